@@ -1,0 +1,206 @@
+/*
+ * libtdse.h -- C-ABI of libtdse, a gfx950 (MI355X) implementation of the
+ * microscopic step of the multiscale high-harmonic-generation model of
+ * arXiv 2507.04115: one independent 1D time-dependent Schrodinger equation
+ * per macroscopic point, soft-core atom, length gauge, Numerov-corrected
+ * Crank-Nicolson with a split-operator field phase, dipole acceleration out.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Atomic units.  Grid of n points x_j = (j - (n-1)/2) dx, j = 0..n-1,
+ *    Dirichlet outside; time grid t_i = i dt, i = 0..nt (the paper's grids,
+ *    section "1D-TSDE Implementation (CTDSE)", shifted to start at t = 0).
+ *  - Wavefunctions are complex128 stored interleaved (re, im) as double[2n].
+ *  - Field and output series are row-major double[batch][nt+1].
+ *  - "dev" pointers are HIP device pointers (16-byte aligned); "host"
+ *    pointers are ordinary host memory.  The caller owns every buffer.
+ *  - Calls that take a `stream` (a hipStream_t passed as void*, NULL = the
+ *    null stream) are asynchronous and stream-ordered unless stated; argument
+ *    errors are reported before anything is launched.
+ *  - Every call returns a tdse_status; on failure a thread-local detail
+ *    string is available from tdse_last_error().
+ *
+ * No entry point allocates device memory except tdse_plan_create (which
+ * sizes every workspace it will ever need), tdse_ground_state and
+ * tdse_soft_core_for_ip (both synchronous set-up calls).
+ */
+#ifndef LIBTDSE_H
+#define LIBTDSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef int32_t tdse_status;
+#define TDSE_OK 0
+#define TDSE_E_INVALID (-1)     /* bad argument; nothing was launched         */
+#define TDSE_E_NOMEM (-2)       /* device or host allocation failed           */
+#define TDSE_E_DEVICE (-3)      /* a HIP runtime call failed                  */
+#define TDSE_E_NOCONV (-4)      /* ground state / soft-core fit not converged */
+#define TDSE_E_UNSUPPORTED (-5) /* size or device outside what is built       */
+#define TDSE_E_NONFINITE (-6)   /* a non-finite value was produced            */
+
+/* Per-system status words written by the propagation calls (sys_status). */
+#define TDSE_SYS_OK 0
+#define TDSE_SYS_NONFINITE 1    /* an observable became NaN/Inf               */
+#define TDSE_SYS_NORM_GROWTH 2  /* norm exceeded its initial value by >1e-8   */
+
+const char* tdse_version(void);
+const char* tdse_status_string(tdse_status s);
+/* Detail of the last failing call on this thread ("" if none). */
+const char* tdse_last_error(void);
+
+/* ---------------------------------------------------------------- params */
+/* Physical and numerical parameters of one batch.
+ *  dx, dt          grid spacing and time step (> 0)
+ *  a, charge_z     soft-core potential V(x) = -charge_z / sqrt(x^2 + a^2)
+ *                  (section "Microscopic Response in XUV regime (TDSE)",
+ *                  Eq. SC potential); charge_z = 0 gives a free particle
+ *  mask_fraction   absorber on the outer fraction of each side (0 disables);
+ *                  m(x) = cos(pi/2 (|x|-x_a)/(x_max-x_a))^mask_power for
+ *                  x_a < |x| < x_max, x_a = (1-mask_fraction) x_max, 1 inside
+ *                  and 0 at the two outermost points.  The paper's solver has
+ *                  no absorber; this one is applied after the field substep.
+ *  mask_power      exponent of the absorber (e.g. 0.125)
+ *  nt              number of time steps; every series has nt+1 samples
+ *  flags           reserved, must be 0 */
+typedef struct {
+    double dx;
+    double dt;
+    double a;
+    double charge_z;
+    double mask_fraction;
+    double mask_power;
+    int32_t nt;
+    uint32_t flags;
+} tdse_params;
+
+/* ------------------------------------------------------ ground state, fit */
+/* Imaginary-time relaxation (dt -> -i dtau in the Crank-Nicolson step, with
+ * renormalisation to dx sum |psi|^2 = 1) of the field-free Hamiltonian
+ * H0 = p^2/2 + V_C on the n-point grid of `p` (p->a, p->charge_z, p->dx;
+ * the absorber and p->dt, p->nt are ignored).  The paper fixes a so that the
+ * ground-state energy matches the atom's (section "Microscopic Response in
+ * XUV regime (TDSE)", text after Eq. SC potential).
+ *   dtau       imaginary time step, 0 < dtau < 2/|E_g| (e.g. 1.0)
+ *   max_iter   iteration cap; tol: stop when successive normalised iterates
+ *              differ by less than tol (dx-weighted L2)
+ *   psi_out    dev, 2n doubles: real, positive at the centre
+ *   energy_out host, may be NULL: ground-state energy E_g
+ * Synchronous on `stream`.  TDSE_E_NOCONV if max_iter is reached. */
+tdse_status tdse_ground_state(const tdse_params* p, int32_t n, double dtau, int32_t max_iter,
+                              double tol, double* psi_out, double* energy_out, void* stream);
+
+/* Soft-core parameter a in [a_lo, a_hi] whose ground-state energy on the
+ * n-point grid of spacing dx equals -ip (E_g increases with a).  Multisection:
+ * each round evaluates a batch of candidates on the device.
+ *   tol        stop when |E_g(a) + ip| < tol
+ *   a_out      host; e_out host, may be NULL.  Synchronous. */
+tdse_status tdse_soft_core_for_ip(double ip, int32_t n, double dx, double dtau, double tol,
+                                  double a_lo, double a_hi, double* a_out, double* e_out);
+
+/* ------------------------------------------------------------------ plan */
+typedef struct tdse_plan_s* tdse_plan;
+
+/* Plan options (bit flags). */
+#define TDSE_OPT_NONE 0u
+#define TDSE_OPT_PLAIN 1u     /* propagate one system per launch (no queue)   */
+#define TDSE_OPT_NO_GRAPH 2u  /* launch directly instead of replaying a graph */
+#define TDSE_OPT_AUTOTUNE 4u  /* time the candidate layouts at plan creation  */
+
+/* Creates a plan for `batch` systems of sizes n_per_system[0..batch-1]
+ * (host array, each 16 <= n <= 16384) sharing the parameters `p`.  The plan
+ * precomputes, per distinct n, the grid tables and the factorisation of the
+ * constant Crank-Nicolson matrix (section "1D-TSDE Implementation (CTDSE)":
+ * the field is split off, so the tridiagonal left-hand side never changes),
+ * computes the ground state for each distinct n (used when psi0 is NULL),
+ * chooses a lane layout per n, and allocates every workspace the
+ * propagation and adjoint calls need.  Synchronous (device 0 of the calling
+ * thread's current device).  The plan is immutable; one plan must not be
+ * used by two threads at once.
+ *   adjoint_k  checkpoint interval of the adjoint (>= 1; 0 = 256) */
+tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t* n_per_system,
+                             uint32_t options, int32_t adjoint_k, tdse_plan* out);
+tdse_status tdse_plan_destroy(tdse_plan plan);
+
+/* Offsets (in complex elements) of each system's wavefunction inside a
+ * ragged psi buffer: offsets[0] = 0, offsets[b+1] = offsets[b] + n_b.
+ * host, batch+1 entries. */
+tdse_status tdse_plan_psi_offsets(tdse_plan plan, int64_t* offsets);
+
+/* Layout chosen for size n: points per lane, lanes per system, scan levels
+ * (host outputs, any may be NULL). */
+tdse_status tdse_plan_layout(tdse_plan plan, int32_t n, int32_t* points_per_lane,
+                             int32_t* lanes, int32_t* scan_levels);
+
+/* Device copy of the plan's ground state for size n (dev, 2n doubles) and its
+ * energy (host, may be NULL).  Synchronous. */
+tdse_status tdse_plan_ground_state(tdse_plan plan, int32_t n, double* psi_out,
+                                   double* energy_out);
+
+/* --------------------------------------------------------------- forward */
+/* Propagates every system of the plan over nt steps (section "1D-TSDE
+ * Implementation (CTDSE)", the three substeps: Crank-Nicolson right-hand
+ * side, tridiagonal solve, field phase exp(-i dt E(t_i) x_j)), followed by
+ * the absorber, and records at every sample i = 0..nt
+ *   accel[b][i] = dx sum_j |psi_j|^2 (dV/dx_j + E_i)   (dipole acceleration,
+ *                 section "Microscopic Response in XUV regime (TDSE)",
+ *                 Eq. dipole acceleration)
+ *   xexp[b][i]  = dx sum_j x_j |psi_j|^2,   norm[b][i] = dx sum_j |psi_j|^2
+ * computed from psi^(i) (before step i).
+ *   E          dev [batch][nt+1]: field samples E(t_i) of every system
+ *   psi0       dev ragged complex (tdse_plan_psi_offsets), or NULL = the
+ *              plan's ground states
+ *   accel      dev [batch][nt+1], required; xexp, norm: same, may be NULL
+ *   psi_final  dev ragged complex, may be NULL
+ *   sys_status dev int32[batch], may be NULL (TDSE_SYS_* codes)
+ * Asynchronous on `stream`. */
+tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* psi0,
+                                 double* accel, double* xexp, double* norm, double* psi_final,
+                                 int32_t* sys_status, void* stream);
+
+/* --------------------------------------------------------------- adjoint */
+/* Gradient of a loss l(accel) with respect to every field sample.  Given
+ * accel_bar[b][i] = dl/d accel[b][i], writes grad_E[b][i] = dl/dE_b(t_i).
+ * The gradient is the exact discrete adjoint of tdse_propagate_batch (the
+ * paper has no adjoint; its derivation from the forward recursion is in the
+ * design notes): the costate is propagated backward in time with the
+ * adjoint of each substep, the forward wavefunction being recomputed from
+ * checkpoints stored every plan->adjoint_k steps.
+ *   E, psi0    as for tdse_propagate_batch
+ *   accel_bar  dev [batch][nt+1]; rows that are entirely zero are skipped
+ *              (their grad_E row is zero)
+ *   grad_E     dev [batch][nt+1], overwritten
+ *   accel      dev [batch][nt+1], may be NULL: forward accelerations
+ *   sys_status dev int32[batch], may be NULL
+ * Asynchronous on `stream`. */
+tdse_status tdse_adjoint_batch(tdse_plan plan, const double* E, const double* psi0,
+                               const double* accel_bar, double* grad_E, double* accel,
+                               int32_t* sys_status, void* stream);
+
+/* ------------------------------------------------------- harmonic yield */
+/* Windowed harmonic yield of each series and its gradient.  With
+ * w_i = sin^2(pi i/nt), A_k = dt sum_i w_i a_i exp(-i omega_k t_i),
+ * omega_k = 2 pi k/((nt+1) dt), domega = 2 pi/((nt+1) dt):
+ *   yield[b]     = sum_{k: h_lo omega0 <= omega_k <= h_hi omega0} domega |A_k|^2
+ *   accel_bar[b][i] = d yield[b] / d a_b,i
+ * The discrete Fourier transform of the acceleration is the quantity the
+ * paper feeds to its XUV propagation (section "XUV Propagation (Spectral
+ * Approach)"); the Hann window keeps the periodic-boundary caveat of the
+ * appendix "Microscopic source terms" small.
+ *   accel      dev [batch][nt+1]; yield dev double[batch];
+ *   accel_bar  dev [batch][nt+1], may be NULL
+ *   row_weight dev double[batch] or NULL (= 1): yield and gradient of row b
+ *              are multiplied by row_weight[b] (0 drops the row)
+ * Asynchronous on `stream`. */
+tdse_status tdse_harmonic_yield(int32_t batch, int32_t nt, double dt, double omega0, double h_lo,
+                                double h_hi, const double* accel, const double* row_weight,
+                                double* yield, double* accel_bar, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBTDSE_H */

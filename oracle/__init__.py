@@ -1,0 +1,235 @@
+"""CPU oracle for the 1D-TDSE microscopic step (arXiv 2507.04115).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The product path (the
+HIP library and its Python binding) never imports, loads or calls it, and the
+two share no code: the numerical core is the plain C file ``tdse_ref.c``
+(serial, fp64, Thomas algorithm, matrices rebuilt from their definitions),
+the harmonic-yield loss below is a direct discrete Fourier sum in numpy.
+
+Parity status: every function here is pinned by the CPU tests in
+``tests/test_oracle_*.py`` against closed forms, dense textbook linear algebra
+(numpy/scipy), physical invariants or finite differences; none is "parity
+unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b  # noqa: WPS433 (local build of the C oracle)
+
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    d, i = ctypes.c_double, ctypes.c_int
+    lib.ref_grid.argtypes = [i, d, d, d, _dp, _dp, _dp]
+    lib.ref_mask.argtypes = [i, d, d, d, _dp]
+    lib.ref_propagate.argtypes = [i, d, d, d, d, d, d, i, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.ref_propagate_batch.argtypes = [i, _ip, _i64p, d, d, d, d, d, d, i, _dp, _dp, _dp,
+                                        _dp, _dp, i]
+    lib.ref_ground_state.argtypes = [i, d, d, d, d, i, d, _dp, _dp, _ip]
+    lib.ref_soft_core_for_ip.argtypes = [d, i, d, d, d, i, d, d, d, _dp, _dp]
+    lib.ref_adjoint.argtypes = [i, d, d, d, d, d, d, i, _dp, _dp, _dp, i, _dp, _dp]
+    lib.ref_step.argtypes = [i, d, d, d, d, d, d, d, _dp]
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_dp)
+
+
+def _check(st, what):
+    if st != 0:
+        raise OracleError(f"{what} failed with status {st}")
+
+
+def _c128(psi, n):
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    if psi.shape != (n,):
+        raise ValueError(f"psi must have shape ({n},), got {psi.shape}")
+    return psi
+
+
+# --------------------------------------------------------------------------
+# grid, potential, mask
+# --------------------------------------------------------------------------
+
+def grid(n, dx, a=1.0, z=1.0):
+    """x_j, V_j = -z/sqrt(x^2+a^2) and dV/dx on the N-point centred grid."""
+    x = np.empty(n)
+    v = np.empty(n)
+    dv = np.empty(n)
+    _check(_load().ref_grid(n, dx, a, z, _ptr(x), _ptr(v), _ptr(dv)), "ref_grid")
+    return x, v, dv
+
+
+def mask(n, dx, frac=0.1, power=0.125):
+    m = np.empty(n)
+    _check(_load().ref_mask(n, dx, frac, power, _ptr(m)), "ref_mask")
+    return m
+
+
+# --------------------------------------------------------------------------
+# propagation
+# --------------------------------------------------------------------------
+
+def step(psi, dx, dt, a, z, e, mask_frac=0.0, mask_pow=0.125):
+    """One Crank-Nicolson + field step psi^(i) -> psi^(i+1) with E(t_i) = e."""
+    n = len(psi)
+    out = _c128(psi, n).copy()
+    _check(_load().ref_step(n, dx, dt, a, z, mask_frac, mask_pow, e,
+                            out.ctypes.data_as(_dp)), "ref_step")
+    return out
+
+
+def propagate(efield, psi0, dx, dt, a, z=1.0, mask_frac=0.1, mask_pow=0.125,
+              want_psi=False):
+    """Forward solve. Returns dict with accel, xexp, norm (nt+1 samples each)
+    and optionally psi_final."""
+    efield = np.ascontiguousarray(efield, dtype=np.float64)
+    nt = efield.shape[0] - 1
+    n = len(psi0)
+    psi0 = _c128(psi0, n)
+    acc = np.empty(nt + 1)
+    xe = np.empty(nt + 1)
+    nr = np.empty(nt + 1)
+    pf = np.empty(n, dtype=np.complex128) if want_psi else None
+    st = _load().ref_propagate(n, dx, dt, a, z, mask_frac, mask_pow, nt, _ptr(efield),
+                               psi0.ctypes.data_as(_dp), _ptr(acc), _ptr(xe), _ptr(nr),
+                               pf.ctypes.data_as(_dp) if pf is not None else None)
+    _check(st, "ref_propagate")
+    out = {"accel": acc, "xexp": xe, "norm": nr}
+    if want_psi:
+        out["psi_final"] = pf
+    return out
+
+
+def propagate_batch(efield, psi0_list, dx, dt, a, z=1.0, mask_frac=0.1, mask_pow=0.125,
+                    nthreads=1):
+    """Forward solve of a batch on host threads. efield: [P, nt+1]."""
+    efield = np.ascontiguousarray(efield, dtype=np.float64)
+    batch, ntp1 = efield.shape
+    n_per = np.array([len(p) for p in psi0_list], dtype=np.int32)
+    off = np.zeros(batch + 1, dtype=np.int64)
+    off[1:] = np.cumsum(n_per)
+    psi0 = np.ascontiguousarray(np.concatenate([np.asarray(p, np.complex128)
+                                                for p in psi0_list]))
+    acc = np.empty((batch, ntp1))
+    xe = np.empty((batch, ntp1))
+    nr = np.empty((batch, ntp1))
+    st = _load().ref_propagate_batch(batch, n_per.ctypes.data_as(_ip), off.ctypes.data_as(_i64p),
+                                     dx, dt, a, z, mask_frac, mask_pow, ntp1 - 1, _ptr(efield),
+                                     psi0.ctypes.data_as(_dp), _ptr(acc), _ptr(xe), _ptr(nr),
+                                     nthreads)
+    _check(st, "ref_propagate_batch")
+    return {"accel": acc, "xexp": xe, "norm": nr}
+
+
+# --------------------------------------------------------------------------
+# ground state and soft-core fit
+# --------------------------------------------------------------------------
+
+def ground_state(n, dx, a, z=1.0, dtau=1.0, max_iter=20000, tol=1e-13):
+    """Imaginary-time relaxation. Returns (psi0 complex128, energy, iterations)."""
+    psi = np.empty(n, dtype=np.complex128)
+    e = ctypes.c_double()
+    it = ctypes.c_int()
+    st = _load().ref_ground_state(n, dx, a, z, dtau, max_iter, tol, psi.ctypes.data_as(_dp),
+                                  ctypes.byref(e), ctypes.byref(it))
+    _check(st, "ref_ground_state")
+    return psi, e.value, it.value
+
+
+def soft_core_for_ip(ip, n, dx, dtau=1.0, gs_tol=1e-13, gs_max_iter=20000, tol=1e-13,
+                     a_lo=0.5, a_hi=3.0):
+    """Bisection on a so that the ground-state energy equals -ip.
+    Returns (a, E_g(a))."""
+    a = ctypes.c_double()
+    e = ctypes.c_double()
+    st = _load().ref_soft_core_for_ip(ip, n, dx, dtau, gs_tol, gs_max_iter, tol, a_lo, a_hi,
+                                      ctypes.byref(a), ctypes.byref(e))
+    _check(st, "ref_soft_core_for_ip")
+    return a.value, e.value
+
+
+# --------------------------------------------------------------------------
+# adjoint
+# --------------------------------------------------------------------------
+
+def adjoint(efield, psi0, abar, dx, dt, a, z=1.0, mask_frac=0.1, mask_pow=0.125, k=256):
+    """Gradient dl/dE_i of a loss l(a_0..a_nt) given abar_i = dl/da_i.
+    Returns (grad, accel)."""
+    efield = np.ascontiguousarray(efield, dtype=np.float64)
+    abar = np.ascontiguousarray(abar, dtype=np.float64)
+    nt = efield.shape[0] - 1
+    if abar.shape != efield.shape:
+        raise ValueError("abar must match efield")
+    n = len(psi0)
+    psi0 = _c128(psi0, n)
+    grad = np.empty(nt + 1)
+    acc = np.empty(nt + 1)
+    st = _load().ref_adjoint(n, dx, dt, a, z, mask_frac, mask_pow, nt, _ptr(efield),
+                             psi0.ctypes.data_as(_dp), _ptr(abar), k, _ptr(grad), _ptr(acc))
+    _check(st, "ref_adjoint")
+    return grad, acc
+
+
+# --------------------------------------------------------------------------
+# harmonic-yield loss (direct band DFT)
+# --------------------------------------------------------------------------
+
+def band_bins(ntp1, dt, omega0, h_lo, h_hi):
+    """Indices k with h_lo*omega0 <= omega_k <= h_hi*omega0, where
+    omega_k = 2 pi k / (ntp1 dt) are the DFT frequencies of ntp1 samples."""
+    dw = 2.0 * np.pi / (ntp1 * dt)
+    k = np.arange(ntp1 // 2 + 1)
+    w = k * dw
+    return k[(w >= h_lo * omega0) & (w <= h_hi * omega0)]
+
+
+def harmonic_yield(accel, dt, omega0, h_lo, h_hi):
+    """Windowed harmonic yield of each row of ``accel`` ([P, nt+1]) and its
+    gradient with respect to the samples.
+
+      w_i   = sin^2(pi i / nt)                       (symmetric Hann window)
+      A_k   = dt sum_i w_i a_i exp(-i omega_k t_i),  t_i = i dt
+      l     = sum_{k in band} domega |A_k|^2,        domega = 2 pi / ((nt+1) dt)
+      dl/da_i = 2 domega dt w_i sum_{k in band} Re(conj(A_k) exp(-i omega_k t_i))
+
+    Returns (l per row, dl/da [P, nt+1])."""
+    accel = np.atleast_2d(np.asarray(accel, dtype=np.float64))
+    ntp1 = accel.shape[1]
+    nt = ntp1 - 1
+    i = np.arange(ntp1)
+    w = np.sin(np.pi * i / nt) ** 2
+    kb = band_bins(ntp1, dt, omega0, h_lo, h_hi)
+    dw = 2.0 * np.pi / (ntp1 * dt)
+    # exp(-i omega_k t_i) with omega_k t_i = 2 pi (k i mod ntp1) / ntp1
+    ph = np.exp(-2j * np.pi * (np.outer(kb, i) % ntp1) / ntp1)  # [K, ntp1]
+    amp = dt * (accel * w) @ ph.T                                # [P, K]
+    loss = dw * np.sum(np.abs(amp) ** 2, axis=1)
+    abar = 2.0 * dw * dt * w * np.real(np.conj(amp) @ ph)        # [P, ntp1]
+    return loss, abar
