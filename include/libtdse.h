@@ -121,7 +121,8 @@ typedef struct tdse_plan_s* tdse_plan;
  * propagation and adjoint calls need.  Synchronous (device 0 of the calling
  * thread's current device).  The plan is immutable; one plan must not be
  * used by two threads at once.
- *   adjoint_k  checkpoint interval of the adjoint (>= 1; 0 = 256) */
+ *   adjoint_k  checkpoint interval of the adjoint in steps (>= 1); 0 creates a
+ *              forward-only plan without the adjoint workspace */
 tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t* n_per_system,
                              uint32_t options, int32_t adjoint_k, tdse_plan* out);
 tdse_status tdse_plan_destroy(tdse_plan plan);
@@ -184,21 +185,26 @@ tdse_status tdse_adjoint_batch(tdse_plan plan, const double* E, const double* ps
 /* ------------------------------------------------------- harmonic yield */
 /* Windowed harmonic yield of each series and its gradient.  With
  * w_i = sin^2(pi i/nt), A_k = dt sum_i w_i a_i exp(-i omega_k t_i),
- * omega_k = 2 pi k/((nt+1) dt), domega = 2 pi/((nt+1) dt):
- *   yield[b]     = sum_{k: h_lo omega0 <= omega_k <= h_hi omega0} domega |A_k|^2
+ * omega_k = 2 pi k/((nt+1) dt), domega = 2 pi/((nt+1) dt) and the band
+ * B = {k <= (nt+1)/2 : h_lo omega0 <= omega_k <= h_hi omega0}:
+ *   yield[b]        = row_weight[b] sum_{k in B} domega |A_k|^2
  *   accel_bar[b][i] = d yield[b] / d a_b,i
- * The discrete Fourier transform of the acceleration is the quantity the
- * paper feeds to its XUV propagation (section "XUV Propagation (Spectral
- * Approach)"); the Hann window keeps the periodic-boundary caveat of the
- * appendix "Microscopic source terms" small.
- *   accel      dev [batch][nt+1]; yield dev double[batch];
- *   accel_bar  dev [batch][nt+1], may be NULL
- *   row_weight dev double[batch] or NULL (= 1): yield and gradient of row b
- *              are multiplied by row_weight[b] (0 drops the row)
+ * The Fourier transform of the acceleration is the quantity the paper feeds
+ * to its XUV propagation (section "XUV Propagation (Spectral Approach)");
+ * the Hann window keeps the periodic-boundary caveat of the appendix
+ * "Microscopic source terms" small.
+ *
+ * tdse_harmonic_band returns the band as bins k_lo .. k_lo+nk-1 (host).
+ *   accel      dev [batch][nt+1]
+ *   row_weight dev double[batch] or NULL (= 1)
+ *   work       dev, 2*batch*max(nk,1) doubles of scratch owned by the caller
+ *   yield      dev double[batch]; accel_bar dev [batch][nt+1] or NULL
  * Asynchronous on `stream`. */
+tdse_status tdse_harmonic_band(int32_t nt, double dt, double omega0, double h_lo, double h_hi,
+                               int32_t* k_lo, int32_t* nk);
 tdse_status tdse_harmonic_yield(int32_t batch, int32_t nt, double dt, double omega0, double h_lo,
                                 double h_hi, const double* accel, const double* row_weight,
-                                double* yield, double* accel_bar, void* stream);
+                                double* work, double* yield, double* accel_bar, void* stream);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,233 @@
+"""ctypes binding of libtdse (include/libtdse.h): same entry points, argument
+marshalling only.  Device buffers are torch tensors on the current HIP
+device (float64 / int32, contiguous); streams are torch streams.  Every call
+raises TDSEError with the library's own message on failure.
+
+The HIP library must be built (``python -m paper_2507_04115_amd.build``);
+loading fails loudly otherwise -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtdse.so")
+
+TDSE_OK = 0
+TDSE_E_INVALID = -1
+TDSE_E_NOMEM = -2
+TDSE_E_DEVICE = -3
+TDSE_E_NOCONV = -4
+TDSE_E_UNSUPPORTED = -5
+TDSE_E_NONFINITE = -6
+
+TDSE_SYS_OK = 0
+TDSE_SYS_NONFINITE = 1
+TDSE_SYS_NORM_GROWTH = 2
+
+TDSE_OPT_NONE = 0
+TDSE_OPT_PLAIN = 1
+TDSE_OPT_NO_GRAPH = 2
+TDSE_OPT_AUTOTUNE = 4
+
+_lib = None
+
+
+class TDSEError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__(f"{what}: {detail} (status {status})")
+        self.status = status
+
+
+class tdse_params(ctypes.Structure):
+    _fields_ = [("dx", ctypes.c_double), ("dt", ctypes.c_double), ("a", ctypes.c_double),
+                ("charge_z", ctypes.c_double), ("mask_fraction", ctypes.c_double),
+                ("mask_power", ctypes.c_double), ("nt", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+_vp = ctypes.c_void_p
+_d = ctypes.c_double
+_i32 = ctypes.c_int32
+_PROTOS = {
+    "tdse_version": (ctypes.c_char_p, []),
+    "tdse_status_string": (ctypes.c_char_p, [_i32]),
+    "tdse_last_error": (ctypes.c_char_p, []),
+    "tdse_ground_state": (_i32, [ctypes.POINTER(tdse_params), _i32, _d, _i32, _d, _vp,
+                                 ctypes.POINTER(_d), _vp]),
+    "tdse_soft_core_for_ip": (_i32, [_d, _i32, _d, _d, _d, _d, _d, ctypes.POINTER(_d),
+                                     ctypes.POINTER(_d)]),
+    "tdse_plan_create": (_i32, [ctypes.POINTER(tdse_params), _i32, ctypes.POINTER(_i32),
+                                ctypes.c_uint32, _i32, ctypes.POINTER(_vp)]),
+    "tdse_plan_destroy": (_i32, [_vp]),
+    "tdse_plan_psi_offsets": (_i32, [_vp, ctypes.POINTER(ctypes.c_int64)]),
+    "tdse_plan_layout": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                ctypes.POINTER(_i32)]),
+    "tdse_plan_ground_state": (_i32, [_vp, _i32, _vp, ctypes.POINTER(_d)]),
+    "tdse_propagate_batch": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tdse_adjoint_batch": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tdse_harmonic_band": (_i32, [_i32, _d, _d, _d, _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "tdse_harmonic_yield": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
+}
+
+
+def exported_names() -> Sequence[str]:
+    return tuple(_PROTOS)
+
+
+def load(path: str = LIB_PATH):
+    """Loads the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libtdse is not built: {path} is missing "
+                          "(run python -m paper_2507_04115_amd.build)")
+    # torch brings its own HIP runtime (same SONAME as ROCm's); loading it
+    # first makes libtdse bind to that runtime, so the process has exactly
+    # one HIP/HSA runtime and torch buffers and streams are valid here.
+    import torch  # noqa: F401
+
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _PROTOS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int, what: str):
+    if st != TDSE_OK:
+        detail = load().tdse_last_error().decode()
+        raise TDSEError(st, what, detail or load().tdse_status_string(st).decode())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("device buffers must be torch tensors")
+    if not t.is_cuda:
+        raise ValueError("device buffers must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def make_params(dx: float, dt: float, a: float, nt: int, charge_z: float = 1.0,
+                mask_fraction: float = 0.1, mask_power: float = 0.125) -> tdse_params:
+    return tdse_params(dx, dt, a, charge_z, mask_fraction, mask_power, int(nt), 0)
+
+
+def tdse_version() -> str:
+    return load().tdse_version().decode()
+
+
+def tdse_ground_state(p: tdse_params, n: int, dtau: float, max_iter: int, tol: float, psi_out,
+                      stream=None) -> float:
+    e = _d()
+    _check(load().tdse_ground_state(ctypes.byref(p), n, dtau, max_iter, tol, _ptr(psi_out),
+                                    ctypes.byref(e), _stream(stream)), "tdse_ground_state")
+    return e.value
+
+
+def tdse_soft_core_for_ip(ip: float, n: int, dx: float, dtau: float = 1.0, tol: float = 1e-13,
+                          a_lo: float = 0.5, a_hi: float = 3.0):
+    a = _d()
+    e = _d()
+    _check(load().tdse_soft_core_for_ip(ip, n, dx, dtau, tol, a_lo, a_hi, ctypes.byref(a),
+                                        ctypes.byref(e)), "tdse_soft_core_for_ip")
+    return a.value, e.value
+
+
+@dataclass
+class Layout:
+    points_per_lane: int
+    lanes: int
+    scan_levels: int
+
+
+class Plan:
+    """Owns a tdse_plan handle (tdse_plan_create / tdse_plan_destroy)."""
+
+    def __init__(self, p: tdse_params, n_per_system: Sequence[int], options: int = 0,
+                 adjoint_k: int = 0):
+        self.params = p
+        self.n_per = [int(v) for v in n_per_system]
+        self.batch = len(self.n_per)
+        arr = (_i32 * self.batch)(*self.n_per)
+        h = _vp()
+        _check(load().tdse_plan_create(ctypes.byref(p), self.batch, arr, options, adjoint_k,
+                                       ctypes.byref(h)), "tdse_plan_create")
+        self.handle = h
+        self.options = options
+        self.adjoint_k = adjoint_k
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().tdse_plan_destroy(self.handle), "tdse_plan_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def psi_offsets(self):
+        off = (ctypes.c_int64 * (self.batch + 1))()
+        _check(load().tdse_plan_psi_offsets(self.handle, off), "tdse_plan_psi_offsets")
+        return list(off)
+
+    def layout(self, n: int) -> Layout:
+        c, t, l = _i32(), _i32(), _i32()
+        _check(load().tdse_plan_layout(self.handle, n, ctypes.byref(c), ctypes.byref(t),
+                                       ctypes.byref(l)), "tdse_plan_layout")
+        return Layout(c.value, t.value, l.value)
+
+    def ground_state(self, n: int, psi_out) -> float:
+        e = _d()
+        _check(load().tdse_plan_ground_state(self.handle, n, _ptr(psi_out), ctypes.byref(e)),
+               "tdse_plan_ground_state")
+        return e.value
+
+
+def tdse_propagate_batch(plan: Plan, E, psi0, accel, xexp=None, norm=None, psi_final=None,
+                         sys_status=None, stream=None):
+    _check(load().tdse_propagate_batch(plan.handle, _ptr(E), _ptr(psi0), _ptr(accel), _ptr(xexp),
+                                       _ptr(norm), _ptr(psi_final), _ptr(sys_status),
+                                       _stream(stream)), "tdse_propagate_batch")
+
+
+def tdse_adjoint_batch(plan: Plan, E, psi0, accel_bar, grad_E, accel=None, sys_status=None,
+                       stream=None):
+    _check(load().tdse_adjoint_batch(plan.handle, _ptr(E), _ptr(psi0), _ptr(accel_bar),
+                                     _ptr(grad_E), _ptr(accel), _ptr(sys_status), _stream(stream)),
+           "tdse_adjoint_batch")
+
+
+def tdse_harmonic_band(nt: int, dt: float, omega0: float, h_lo: float, h_hi: float):
+    k_lo, nk = _i32(), _i32()
+    _check(load().tdse_harmonic_band(nt, dt, omega0, h_lo, h_hi, ctypes.byref(k_lo),
+                                     ctypes.byref(nk)), "tdse_harmonic_band")
+    return k_lo.value, nk.value
+
+
+def tdse_harmonic_yield(batch: int, nt: int, dt: float, omega0: float, h_lo: float, h_hi: float,
+                        accel, row_weight, work, yield_out, accel_bar=None, stream=None):
+    _check(load().tdse_harmonic_yield(batch, nt, dt, omega0, h_lo, h_hi, _ptr(accel),
+                                      _ptr(row_weight), _ptr(work), _ptr(yield_out),
+                                      _ptr(accel_bar), _stream(stream)), "tdse_harmonic_yield")

@@ -1,0 +1,981 @@
+// libtdse.cpp -- host side of the libtdse C-ABI (include/libtdse.h): argument
+// validation, plans (size classes, device tables, ground states, work
+// queues, workspaces), hipGraph capture and replay, the ground-state and
+// soft-core-fit drivers.  All numerical work runs in the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/libtdse.h"
+#include "tdse_internal.hpp"
+#include "tdse_kernels.hpp"
+
+using namespace tdse;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tdse_status fail(tdse_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(TDSE_E_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                            \
+    } while (0)
+
+constexpr double kTruncEps = 1.3877787807814457e-17;  // 2^-56
+constexpr int kMaxN = 16384;
+constexpr int kMinN = 16;
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int num_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+// ------------------------------------------------------------ device arena
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0, used = 0;
+    template <class T>
+    T* take(size_t count)
+    {
+        size_t bytes = (sizeof(T) * count + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base + used);
+        used += bytes;
+        return p;
+    }
+};
+
+// Lane layout for a grid of n points: C points per lane, T lanes.
+struct Layout {
+    int C, T;
+};
+
+Layout default_layout(int n)
+{
+    int C = n > 2048 ? 16 : (n > 512 ? 8 : 4);
+    int T = ((n + C - 1) / C + kWave - 1) / kWave * kWave;
+    if (T < kWave) T = kWave;
+    return {C, T};
+}
+
+size_t class_bytes(const Layout& L)
+{
+    const size_t np = (size_t)L.C * L.T, T = L.T;
+    size_t b = 0;
+    auto add = [&](size_t bytes) { b += (bytes + 255) & ~size_t(255); };
+    for (int i = 0; i < 3; ++i) add(np * sizeof(double));
+    for (int i = 0; i < 5; ++i) add(np * sizeof(cd));
+    for (int i = 0; i < 6; ++i) add(T * sizeof(double));
+    for (int i = 0; i < 2; ++i) add(T * sizeof(cd));
+    for (int i = 0; i < 2; ++i) add(kMaxLevels * T * sizeof(cd));
+    for (int i = 0; i < 2; ++i) add(T * sizeof(cd));
+    add(T * sizeof(int32_t));
+    return b;
+}
+
+void carve_class(Arena& ar, SizeClass& sc)
+{
+    const size_t np = (size_t)sc.C * sc.T, T = sc.T;
+    sc.pt.v = ar.take<double>(np);
+    sc.pt.dv = ar.take<double>(np);
+    sc.pt.m = ar.take<double>(np);
+    sc.pt.alpha = ar.take<cd>(np);
+    sc.pt.at = ar.take<cd>(np);
+    sc.pt.q = ar.take<cd>(np);
+    sc.pt.beta = ar.take<cd>(np);
+    sc.pt.bt = ar.take<cd>(np);
+    sc.lt.vl = ar.take<double>(T);
+    sc.lt.vr = ar.take<double>(T);
+    sc.lt.ml = ar.take<double>(T);
+    sc.lt.mr = ar.take<double>(T);
+    sc.lt.dvl = ar.take<double>(T);
+    sc.lt.dvr = ar.take<double>(T);
+    sc.lt.ql = ar.take<cd>(T);
+    sc.lt.bl = ar.take<cd>(T);
+    sc.lt.pa = ar.take<cd>(kMaxLevels * T);
+    sc.lt.qb = ar.take<cd>(kMaxLevels * T);
+    sc.lt.pw = ar.take<cd>(T);
+    sc.lt.qw = ar.take<cd>(T);
+    sc.lt.hasmask = ar.take<int32_t>(T);
+}
+
+// A set of size classes with their device tables.
+struct ClassSet {
+    std::vector<SizeClass> h;
+    SizeClass* d = nullptr;
+    char* mem = nullptr;
+
+    void release()
+    {
+        if (d) (void)hipFree(d);
+        if (mem) (void)hipFree(mem);
+        d = nullptr;
+        mem = nullptr;
+        h.clear();
+    }
+};
+
+// Builds tables for every entry of `params`/`layouts` and picks the scan
+// depth of each class from the measured decay of the carry products.
+tdse_status build_classes(ClassSet& cs, const std::vector<int>& ns,
+                          const std::vector<Layout>& layouts, const std::vector<TableParams>& params,
+                          hipStream_t st)
+{
+    const int ncls = (int)ns.size();
+    cs.h.assign(ncls, SizeClass{});
+    size_t total = 0;
+    int max_t = 0;
+    for (int c = 0; c < ncls; ++c) {
+        total += class_bytes(layouts[c]);
+        max_t = std::max(max_t, layouts[c].T);
+    }
+    const size_t scratch_bytes = (size_t)ncls * 2 * max_t * sizeof(cd);
+    const size_t metric_bytes = (size_t)ncls * 2 * (kMaxLevels + 1) * sizeof(double);
+    const size_t param_bytes = (size_t)ncls * sizeof(TableParams);
+    HIP_TRY(hipMalloc(&cs.mem, total + 3 * 256));
+    Arena ar{cs.mem, total, 0};
+    for (int c = 0; c < ncls; ++c) {
+        SizeClass& sc = cs.h[c];
+        sc.n = ns[c];
+        sc.C = layouts[c].C;
+        sc.T = layouts[c].T;
+        sc.levels = kMaxLevels;
+        sc.xwaves = sc.T / kWave;
+        sc.dx = params[c].dx;
+        sc.x0 = -0.5 * (double)(sc.n - 1) * sc.dx;
+        carve_class(ar, sc);
+    }
+    HIP_TRY(hipMalloc(&cs.d, sizeof(SizeClass) * ncls));
+    char* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, scratch_bytes + metric_bytes + param_bytes + 3 * 256));
+    cd* d_scratch = reinterpret_cast<cd*>(tmp);
+    double* d_metrics = reinterpret_cast<double*>(tmp + ((scratch_bytes + 255) & ~size_t(255)));
+    TableParams* d_params = reinterpret_cast<TableParams*>(
+        tmp + ((scratch_bytes + 255) & ~size_t(255)) + ((metric_bytes + 255) & ~size_t(255)));
+    tdse_status rc = TDSE_OK;
+    std::vector<double> metrics((size_t)ncls * 2 * (kMaxLevels + 1));
+    do {
+        if (hipMemcpyAsync(cs.d, cs.h.data(), sizeof(SizeClass) * ncls, hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(d_params, params.data(), param_bytes, hipMemcpyHostToDevice, st) !=
+                hipSuccess) {
+            rc = fail(TDSE_E_DEVICE, "copy of table parameters failed");
+            break;
+        }
+        if (launch_build_tables(cs.d, d_params, ncls, d_metrics, d_scratch, max_t, st) !=
+            hipSuccess) {
+            rc = fail(TDSE_E_DEVICE, "table kernel launch failed");
+            break;
+        }
+        if (hipMemcpyAsync(metrics.data(), d_metrics, metric_bytes, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = fail(TDSE_E_DEVICE, "table kernel failed: %s", hipGetErrorString(hipGetLastError()));
+            break;
+        }
+        for (int c = 0; c < ncls; ++c) {
+            SizeClass& sc = cs.h[c];
+            const double* mA = &metrics[(size_t)(c * 2 + 0) * (kMaxLevels + 1)];
+            const double* mB = &metrics[(size_t)(c * 2 + 1) * (kMaxLevels + 1)];
+            int lev = -1;
+            for (int l = 0; l <= kMaxLevels; ++l) {
+                if (mA[l] < kTruncEps && mB[l] < kTruncEps) {
+                    lev = l;
+                    break;
+                }
+            }
+            if (lev >= 0 && lev <= kMaxLevels) {
+                sc.levels = std::min(lev, kMaxLevels);
+                sc.xwaves = 1;
+            } else {
+                sc.levels = kMaxLevels;  // exact scan: every carry kept
+                sc.xwaves = sc.T / kWave;
+            }
+            if (!std::isfinite(mA[0]) || !std::isfinite(mB[0])) {
+                rc = fail(TDSE_E_NONFINITE, "non-finite factorisation for n=%d", sc.n);
+                break;
+            }
+        }
+        if (rc != TDSE_OK) break;
+        if (hipMemcpyAsync(cs.d, cs.h.data(), sizeof(SizeClass) * ncls, hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(TDSE_E_DEVICE, "copy of size classes failed");
+    } while (0);
+    (void)hipFree(tmp);
+    return rc;
+}
+
+TableParams real_time_params(const tdse_params* p)
+{
+    TableParams t;
+    t.dx = p->dx;
+    t.a = p->a;
+    t.z = p->charge_z;
+    t.mask_frac = p->mask_fraction;
+    t.mask_pow = p->mask_power;
+    t.h = cd{0.0, 0.5 * p->dt};
+    return t;
+}
+
+TableParams imag_time_params(double dx, double a, double z, double dtau)
+{
+    TableParams t;
+    t.dx = dx;
+    t.a = a;
+    t.z = z;
+    t.mask_frac = 0.0;
+    t.mask_pow = 1.0;
+    t.h = cd{0.5 * dtau, 0.0};
+    return t;
+}
+
+// Runs the ground-state kernel for candidates that all share one layout.
+tdse_status run_ground_states(const ClassSet& cs, const std::vector<int>& cls_of, double dtau,
+                              int max_iter, double tol, double* d_psi, const int64_t* h_psi_off,
+                              std::vector<double>& energy, std::vector<int>& iters, hipStream_t st)
+{
+    const int nc = (int)cls_of.size();
+    char* tmp = nullptr;
+    const size_t b_cls = ((sizeof(int32_t) * nc + 255) & ~size_t(255));
+    const size_t b_off = ((sizeof(int64_t) * nc + 255) & ~size_t(255));
+    const size_t b_e = ((sizeof(double) * nc + 255) & ~size_t(255));
+    HIP_TRY(hipMalloc(&tmp, b_cls + b_off + b_e + sizeof(int32_t) * nc));
+    int32_t* d_cls = reinterpret_cast<int32_t*>(tmp);
+    int64_t* d_off = reinterpret_cast<int64_t*>(tmp + b_cls);
+    double* d_e = reinterpret_cast<double*>(tmp + b_cls + b_off);
+    int32_t* d_it = reinterpret_cast<int32_t*>(tmp + b_cls + b_off + b_e);
+    tdse_status rc = TDSE_OK;
+    std::vector<int32_t> c32(cls_of.begin(), cls_of.end());
+    energy.assign(nc, 0.0);
+    iters.assign(nc, 0);
+    std::vector<int32_t> it32(nc);
+    do {
+        if (hipMemcpyAsync(d_cls, c32.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(d_off, h_psi_off, sizeof(int64_t) * nc, hipMemcpyHostToDevice, st) !=
+                hipSuccess) {
+            rc = fail(TDSE_E_DEVICE, "ground-state argument copy failed");
+            break;
+        }
+        GsArgs g{};
+        g.classes = cs.d;
+        g.cls_of = d_cls;
+        g.ncand = nc;
+        g.dtau = dtau;
+        g.max_iter = max_iter;
+        g.tol = tol;
+        g.psi_out = d_psi;
+        g.psi_off = d_off;
+        g.energy = d_e;
+        g.iters = d_it;
+        const SizeClass& s0 = cs.h[cls_of[0]];
+        if (launch_ground_state(s0.C, g, s0.T, st) != hipSuccess) {
+            rc = fail(TDSE_E_DEVICE, "ground-state launch failed");
+            break;
+        }
+        if (hipMemcpyAsync(energy.data(), d_e, sizeof(double) * nc, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(it32.data(), d_it, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = fail(TDSE_E_DEVICE, "ground-state kernel failed: %s",
+                      hipGetErrorString(hipGetLastError()));
+            break;
+        }
+        for (int i = 0; i < nc; ++i) iters[i] = it32[i];
+    } while (0);
+    (void)hipFree(tmp);
+    return rc;
+}
+
+tdse_status check_params(const tdse_params* p, bool need_time)
+{
+    if (!p) return fail(TDSE_E_INVALID, "params is NULL");
+    if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(TDSE_E_INVALID, "dx must be > 0");
+    if (need_time && (!(p->dt > 0.0) || !std::isfinite(p->dt)))
+        return fail(TDSE_E_INVALID, "dt must be > 0");
+    if (!std::isfinite(p->a) || (p->charge_z != 0.0 && !(p->a > 0.0)))
+        return fail(TDSE_E_INVALID, "soft-core a must be > 0");
+    if (!std::isfinite(p->charge_z)) return fail(TDSE_E_INVALID, "charge_z must be finite");
+    if (need_time && (!(p->mask_fraction >= 0.0) || p->mask_fraction >= 1.0))
+        return fail(TDSE_E_INVALID, "mask_fraction must be in [0, 1)");
+    if (need_time && p->mask_fraction > 0.0 && !(p->mask_power > 0.0))
+        return fail(TDSE_E_INVALID, "mask_power must be > 0");
+    if (need_time && p->nt < 0) return fail(TDSE_E_INVALID, "nt must be >= 0");
+    if (p->flags != 0) return fail(TDSE_E_INVALID, "flags must be 0");
+    return TDSE_OK;
+}
+
+}  // namespace
+
+// ==================================================================== plan
+struct tdse_plan_s {
+    tdse_params p{};
+    int batch = 0;
+    uint32_t options = 0;
+    int adjoint_k = 0;
+    std::vector<int> n_per;
+    std::vector<int64_t> psi_off;
+    std::vector<int> cls_of;            // per system
+    ClassSet cls;                       // real-time tables, one class per distinct n
+    std::map<int, int> cls_of_n;
+    std::vector<double> gs_energy;      // per class
+    std::vector<int64_t> gs_off;        // per class
+    double* d_gs = nullptr;
+    int64_t* d_gs_off = nullptr;
+    SysDesc* d_sys = nullptr;
+    // launch groups: systems sharing one lane layout (C, T)
+    struct Group {
+        int C, T, count, grid;
+        int32_t* d_order;
+    };
+    std::vector<Group> groups;
+    int32_t* d_order_all = nullptr;
+    int32_t* d_counters = nullptr;      // groups.size() + batch (plain mode)
+    int32_t* d_ident = nullptr;
+    std::vector<int> plain_group;       // per system: its group
+    // graph replay
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> branch;
+    std::vector<hipEvent_t> ev;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<const void*> gkey;
+    // adjoint workspace
+    double* d_adj = nullptr;
+    size_t adj_bytes = 0;
+    std::vector<int64_t> adj_slot_ckpt, adj_slot_seg;
+    std::vector<int> adj_grid;
+    std::vector<int64_t> adj_off;       // per group: offset of its workspace (doubles)
+};
+
+namespace {
+
+void plan_free(tdse_plan pl)
+{
+    if (!pl) return;
+    if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
+    for (auto e : pl->ev) (void)hipEventDestroy(e);
+    for (auto s : pl->branch) (void)hipStreamDestroy(s);
+    if (pl->cap) (void)hipStreamDestroy(pl->cap);
+    pl->cls.release();
+    if (pl->d_gs) (void)hipFree(pl->d_gs);
+    if (pl->d_gs_off) (void)hipFree(pl->d_gs_off);
+    if (pl->d_sys) (void)hipFree(pl->d_sys);
+    if (pl->d_order_all) (void)hipFree(pl->d_order_all);
+    if (pl->d_counters) (void)hipFree(pl->d_counters);
+    if (pl->d_ident) (void)hipFree(pl->d_ident);
+    if (pl->d_adj) (void)hipFree(pl->d_adj);
+    delete pl;
+}
+
+constexpr double kGsDtau = 0.5;
+constexpr double kGsTol = 1e-12;
+constexpr int kGsMaxIter = 100000;
+
+// Ground states of every class of a plan (imaginary-time tables built on the
+// side with the plan's a and charge, mask off).
+tdse_status plan_ground_states(tdse_plan pl, hipStream_t st)
+{
+    const int ncls = (int)pl->cls.h.size();
+    std::vector<int> ns(ncls);
+    std::vector<Layout> lay(ncls);
+    std::vector<TableParams> prm(ncls);
+    pl->gs_off.assign(ncls + 1, 0);
+    for (int c = 0; c < ncls; ++c) {
+        ns[c] = pl->cls.h[c].n;
+        lay[c] = {pl->cls.h[c].C, pl->cls.h[c].T};
+        prm[c] = imag_time_params(pl->p.dx, pl->p.a, pl->p.charge_z, kGsDtau);
+        pl->gs_off[c + 1] = pl->gs_off[c] + ns[c];
+    }
+    HIP_TRY(hipMalloc(&pl->d_gs, sizeof(double) * 2 * (size_t)pl->gs_off[ncls]));
+    HIP_TRY(hipMalloc(&pl->d_gs_off, sizeof(int64_t) * (ncls + 1)));
+    HIP_TRY(hipMemcpy(pl->d_gs_off, pl->gs_off.data(), sizeof(int64_t) * (ncls + 1),
+                      hipMemcpyHostToDevice));
+    ClassSet im;
+    tdse_status rc = build_classes(im, ns, lay, prm, st);
+    pl->gs_energy.assign(ncls, 0.0);
+    if (rc == TDSE_OK) {
+        // one launch per distinct layout (the kernel is specialised on C)
+        for (int c = 0; c < ncls && rc == TDSE_OK; ++c) {
+            std::vector<int> one{c};
+            std::vector<double> e;
+            std::vector<int> it;
+            rc = run_ground_states(im, one, kGsDtau, kGsMaxIter, kGsTol, pl->d_gs,
+                                   &pl->gs_off[c], e, it, st);
+            if (rc == TDSE_OK && it[0] <= 0)
+                rc = fail(TDSE_E_NOCONV, "ground state for n=%d did not converge", ns[c]);
+            if (rc == TDSE_OK) pl->gs_energy[c] = e[0];
+        }
+    }
+    im.release();
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tdse_version(void) { return "libtdse 0.1.0 (gfx950, fp64)"; }
+
+const char* tdse_status_string(tdse_status s)
+{
+    switch (s) {
+        case TDSE_OK: return "ok";
+        case TDSE_E_INVALID: return "invalid argument";
+        case TDSE_E_NOMEM: return "out of memory";
+        case TDSE_E_DEVICE: return "device error";
+        case TDSE_E_NOCONV: return "not converged";
+        case TDSE_E_UNSUPPORTED: return "unsupported";
+        case TDSE_E_NONFINITE: return "non-finite value";
+        default: return "unknown status";
+    }
+}
+
+const char* tdse_last_error(void) { return g_last_error.c_str(); }
+
+tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t* n_per_system,
+                             uint32_t options, int32_t adjoint_k, tdse_plan* out)
+{
+    g_last_error.clear();
+    if (!out) return fail(TDSE_E_INVALID, "out is NULL");
+    *out = nullptr;
+    tdse_status st = check_params(p, true);
+    if (st != TDSE_OK) return st;
+    if (batch < 1) return fail(TDSE_E_INVALID, "batch must be >= 1");
+    if (!n_per_system) return fail(TDSE_E_INVALID, "n_per_system is NULL");
+    if (options & ~(TDSE_OPT_PLAIN | TDSE_OPT_NO_GRAPH | TDSE_OPT_AUTOTUNE))
+        return fail(TDSE_E_INVALID, "unknown option bits 0x%x", options);
+    for (int b = 0; b < batch; ++b) {
+        if (n_per_system[b] < kMinN) return fail(TDSE_E_INVALID, "n[%d] = %d < %d", b, n_per_system[b], kMinN);
+        if (n_per_system[b] > kMaxN)
+            return fail(TDSE_E_UNSUPPORTED, "n[%d] = %d exceeds %d", b, n_per_system[b], kMaxN);
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(TDSE_E_UNSUPPORTED, "device arch %s is not gfx950", prop.gcnArchName);
+
+    tdse_plan pl = new tdse_plan_s();
+    pl->p = *p;
+    pl->batch = batch;
+    pl->options = options;
+    pl->adjoint_k = adjoint_k;
+    pl->n_per.assign(n_per_system, n_per_system + batch);
+    pl->psi_off.assign(batch + 1, 0);
+    for (int b = 0; b < batch; ++b) pl->psi_off[b + 1] = pl->psi_off[b] + pl->n_per[b];
+
+    hipStream_t s0 = nullptr;
+    auto bail = [&](tdse_status rc) {
+        plan_free(pl);
+        return rc;
+    };
+    if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(TDSE_E_DEVICE, "stream creation failed"));
+    s0 = pl->cap;
+
+    // size classes, one per distinct n
+    std::vector<int> ns;
+    for (int b = 0; b < batch; ++b) {
+        if (!pl->cls_of_n.count(pl->n_per[b])) {
+            pl->cls_of_n[pl->n_per[b]] = (int)ns.size();
+            ns.push_back(pl->n_per[b]);
+        }
+    }
+    const int ncls = (int)ns.size();
+    std::vector<Layout> lay(ncls);
+    std::vector<TableParams> prm(ncls, real_time_params(p));
+    for (int c = 0; c < ncls; ++c) {
+        lay[c] = default_layout(ns[c]);
+        if (lay[c].T > 1024 || !layout_supported(lay[c].C))
+            return bail(fail(TDSE_E_UNSUPPORTED, "no lane layout for n=%d", ns[c]));
+    }
+    st = build_classes(pl->cls, ns, lay, prm, s0);
+    if (st != TDSE_OK) return bail(st);
+    st = plan_ground_states(pl, s0);
+    if (st != TDSE_OK) return bail(st);
+
+    // systems and launch groups
+    pl->cls_of.resize(batch);
+    std::vector<SysDesc> sys(batch);
+    std::map<std::pair<int, int>, int> gidx;
+    std::vector<std::vector<int32_t>> gsys;
+    pl->plain_group.resize(batch);
+    for (int b = 0; b < batch; ++b) {
+        const int c = pl->cls_of_n[pl->n_per[b]];
+        pl->cls_of[b] = c;
+        sys[b].cls = c;
+        sys[b].n = pl->n_per[b];
+        sys[b].psi_off = pl->psi_off[b];
+        const auto key = std::make_pair(pl->cls.h[c].C, pl->cls.h[c].T);
+        if (!gidx.count(key)) {
+            gidx[key] = (int)gsys.size();
+            gsys.emplace_back();
+            pl->groups.push_back({key.first, key.second, 0, 0, nullptr});
+        }
+        gsys[gidx[key]].push_back(b);
+        pl->plain_group[b] = gidx[key];
+    }
+    // longest groups first (largest n * lanes of work per system)
+    std::vector<int> gorder(pl->groups.size());
+    for (size_t g = 0; g < gorder.size(); ++g) gorder[g] = (int)g;
+    if (hipMalloc(&pl->d_sys, sizeof(SysDesc) * batch) != hipSuccess ||
+        hipMalloc(&pl->d_order_all, sizeof(int32_t) * batch) != hipSuccess ||
+        hipMalloc(&pl->d_counters, sizeof(int32_t) * (pl->groups.size() + batch)) != hipSuccess ||
+        hipMalloc(&pl->d_ident, sizeof(int32_t) * batch) != hipSuccess)
+        return bail(fail(TDSE_E_NOMEM, "plan allocation failed"));
+    std::vector<int32_t> order_all;
+    for (size_t g = 0; g < pl->groups.size(); ++g) {
+        auto& G = pl->groups[g];
+        G.count = (int)gsys[g].size();
+        G.d_order = pl->d_order_all + order_all.size();
+        order_all.insert(order_all.end(), gsys[g].begin(), gsys[g].end());
+        const int occ = forward_occupancy(G.C, G.T);
+        if (occ <= 0) return bail(fail(TDSE_E_UNSUPPORTED, "layout C=%d T=%d does not fit", G.C, G.T));
+        G.grid = std::min(G.count, occ * num_cus());
+    }
+    std::vector<int32_t> ident(batch);
+    for (int b = 0; b < batch; ++b) ident[b] = b;
+    if (hipMemcpy(pl->d_sys, sys.data(), sizeof(SysDesc) * batch, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->d_order_all, order_all.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(pl->d_ident, ident.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice) !=
+            hipSuccess)
+        return bail(fail(TDSE_E_DEVICE, "plan upload failed"));
+
+    // graph branches
+    const int nbr = std::min<int>(4, (int)pl->groups.size());
+    for (int i = 0; i < nbr; ++i) {
+        hipStream_t s;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(TDSE_E_DEVICE, "stream creation failed"));
+        pl->branch.push_back(s);
+    }
+    for (int i = 0; i < nbr + 1; ++i) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(TDSE_E_DEVICE, "event creation failed"));
+        pl->ev.push_back(e);
+    }
+
+    // adjoint workspace
+    if (adjoint_k > 0) {
+        const int64_t nt = p->nt;
+        int64_t total = 0;
+        for (size_t g = 0; g < pl->groups.size(); ++g) {
+            auto& G = pl->groups[g];
+            const int occ = adjoint_occupancy(G.C, G.T);
+            if (occ <= 0) return bail(fail(TDSE_E_UNSUPPORTED, "adjoint layout C=%d T=%d does not fit", G.C, G.T));
+            const int grid = std::min(G.count, occ * num_cus());
+            const int64_t np = (int64_t)(G.C + 2) * G.T;  // chunk values and two ghosts per lane
+            const int64_t nseg = nt / adjoint_k + 1;
+            const int64_t ck = 2 * np * nseg;
+            const int64_t sg = 2 * np * (int64_t)(adjoint_k + 1) + (nt + 1);
+            pl->adj_grid.push_back(grid);
+            pl->adj_slot_ckpt.push_back(ck);
+            pl->adj_slot_seg.push_back(sg);
+            pl->adj_off.push_back(total);
+            total += (ck + sg) * grid;
+        }
+        pl->adj_bytes = sizeof(double) * (size_t)total;
+        if (hipMalloc(&pl->d_adj, pl->adj_bytes) != hipSuccess)
+            return bail(fail(TDSE_E_NOMEM, "adjoint workspace of %.1f GB not available",
+                             pl->adj_bytes / 1e9));
+    }
+    *out = pl;
+    return TDSE_OK;
+}
+
+tdse_status tdse_plan_destroy(tdse_plan plan)
+{
+    if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
+    (void)hipDeviceSynchronize();
+    plan_free(plan);
+    return TDSE_OK;
+}
+
+tdse_status tdse_plan_psi_offsets(tdse_plan plan, int64_t* offsets)
+{
+    if (!plan || !offsets) return fail(TDSE_E_INVALID, "NULL argument");
+    std::memcpy(offsets, plan->psi_off.data(), sizeof(int64_t) * (plan->batch + 1));
+    return TDSE_OK;
+}
+
+tdse_status tdse_plan_layout(tdse_plan plan, int32_t n, int32_t* points_per_lane, int32_t* lanes,
+                             int32_t* scan_levels)
+{
+    if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
+    auto it = plan->cls_of_n.find(n);
+    if (it == plan->cls_of_n.end()) return fail(TDSE_E_INVALID, "n=%d is not in the plan", n);
+    const SizeClass& sc = plan->cls.h[it->second];
+    if (points_per_lane) *points_per_lane = sc.C;
+    if (lanes) *lanes = sc.T;
+    if (scan_levels) *scan_levels = sc.xwaves > 1 ? -sc.levels : sc.levels;
+    return TDSE_OK;
+}
+
+tdse_status tdse_plan_ground_state(tdse_plan plan, int32_t n, double* psi_out, double* energy_out)
+{
+    if (!plan || !psi_out) return fail(TDSE_E_INVALID, "NULL argument");
+    auto it = plan->cls_of_n.find(n);
+    if (it == plan->cls_of_n.end()) return fail(TDSE_E_INVALID, "n=%d is not in the plan", n);
+    const int c = it->second;
+    HIP_TRY(hipMemcpy(psi_out, plan->d_gs + 2 * plan->gs_off[c], sizeof(double) * 2 * n,
+                      hipMemcpyDeviceToDevice));
+    if (energy_out) *energy_out = plan->gs_energy[c];
+    return TDSE_OK;
+}
+
+static tdse_status fill_fwd_args(tdse_plan pl, FwdArgs& a, const double* E, const double* psi0,
+                                 double* accel, double* xexp, double* norm, double* psi_final,
+                                 int32_t* sys_status)
+{
+    a = FwdArgs{};
+    a.classes = pl->cls.d;
+    a.sys = pl->d_sys;
+    a.nt = pl->p.nt;
+    a.dt = pl->p.dt;
+    a.E = E;
+    a.psi0 = psi0;
+    a.gs = pl->d_gs;
+    a.gs_off = pl->d_gs_off;
+    a.accel = accel;
+    a.xexp = xexp;
+    a.norm = norm;
+    a.psi_final = psi_final;
+    a.status = sys_status;
+    return TDSE_OK;
+}
+
+static tdse_status enqueue_forward(tdse_plan pl, const FwdArgs& base, hipStream_t st, bool branches)
+{
+    const int ng = (int)pl->groups.size();
+    if (launch_reset_counters(pl->d_counters, ng, st) != hipSuccess)
+        return fail(TDSE_E_DEVICE, "counter reset launch failed");
+    if (!branches || pl->branch.size() <= 1) {
+        for (int g = 0; g < ng; ++g) {
+            const auto& G = pl->groups[g];
+            FwdArgs a = base;
+            a.order = G.d_order;
+            a.count = G.count;
+            a.queue = pl->d_counters + g;
+            if (launch_forward(G.C, a, G.T, G.grid, st) != hipSuccess)
+                return fail(TDSE_E_DEVICE, "forward launch failed: %s",
+                            hipGetErrorString(hipGetLastError()));
+        }
+        return TDSE_OK;
+    }
+    // fork the groups over the branch streams (captured as parallel graph branches)
+    const int nb = (int)pl->branch.size();
+    HIP_TRY(hipEventRecord(pl->ev[0], st));
+    for (int b = 0; b < nb; ++b) HIP_TRY(hipStreamWaitEvent(pl->branch[b], pl->ev[0], 0));
+    for (int g = 0; g < ng; ++g) {
+        const auto& G = pl->groups[g];
+        FwdArgs a = base;
+        a.order = G.d_order;
+        a.count = G.count;
+        a.queue = pl->d_counters + g;
+        if (launch_forward(G.C, a, G.T, G.grid, pl->branch[g % nb]) != hipSuccess)
+            return fail(TDSE_E_DEVICE, "forward launch failed");
+    }
+    for (int b = 0; b < nb; ++b) {
+        HIP_TRY(hipEventRecord(pl->ev[b + 1], pl->branch[b]));
+        HIP_TRY(hipStreamWaitEvent(st, pl->ev[b + 1], 0));
+    }
+    return TDSE_OK;
+}
+
+tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* psi0,
+                                 double* accel, double* xexp, double* norm, double* psi_final,
+                                 int32_t* sys_status, void* stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
+    if (!E || !accel) return fail(TDSE_E_INVALID, "E and accel are required");
+    const void* ptrs[] = {E, psi0, accel, xexp, norm, psi_final, sys_status};
+    for (const void* q : ptrs)
+        if (q && !aligned16(q)) return fail(TDSE_E_INVALID, "device pointers must be 16-byte aligned");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    FwdArgs base;
+    fill_fwd_args(plan, base, E, psi0, accel, xexp, norm, psi_final, sys_status);
+
+    if (plan->options & TDSE_OPT_PLAIN) {
+        // one system per launch, serially on the caller's stream
+        const int ng = (int)plan->groups.size();
+        if (launch_reset_counters(plan->d_counters + ng, plan->batch, st) != hipSuccess)
+            return fail(TDSE_E_DEVICE, "counter reset launch failed");
+        for (int b = 0; b < plan->batch; ++b) {
+            const auto& G = plan->groups[plan->plain_group[b]];
+            FwdArgs a = base;
+            a.order = plan->d_ident + b;
+            a.count = 1;
+            a.queue = plan->d_counters + ng + b;
+            if (launch_forward(G.C, a, G.T, 1, st) != hipSuccess)
+                return fail(TDSE_E_DEVICE, "forward launch failed");
+        }
+        return TDSE_OK;
+    }
+    if (plan->options & TDSE_OPT_NO_GRAPH) return enqueue_forward(plan, base, st, false);
+
+    std::vector<const void*> key{E, psi0, accel, xexp, norm, psi_final, sys_status};
+    if (!plan->gexec || key != plan->gkey) {
+        if (plan->gexec) {
+            (void)hipGraphExecDestroy(plan->gexec);
+            plan->gexec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal));
+        tdse_status rc = enqueue_forward(plan, base, plan->cap, true);
+        hipError_t ec = hipStreamEndCapture(plan->cap, &graph);
+        if (rc != TDSE_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ec != hipSuccess) return fail(TDSE_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+        ec = hipGraphInstantiate(&plan->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ec != hipSuccess) {
+            plan->gexec = nullptr;
+            return fail(TDSE_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ec));
+        }
+        plan->gkey = key;
+    }
+    HIP_TRY(hipGraphLaunch(plan->gexec, st));
+    return TDSE_OK;
+}
+
+// ------------------------------------------------------------ ground state
+tdse_status tdse_ground_state(const tdse_params* p, int32_t n, double dtau, int32_t max_iter,
+                              double tol, double* psi_out, double* energy_out, void* stream)
+{
+    g_last_error.clear();
+    tdse_status st = check_params(p, false);
+    if (st != TDSE_OK) return st;
+    if (n < kMinN || n > kMaxN) return fail(n > kMaxN ? TDSE_E_UNSUPPORTED : TDSE_E_INVALID, "n=%d out of range", n);
+    if (!(dtau > 0.0) || max_iter < 1 || !(tol > 0.0) || !psi_out)
+        return fail(TDSE_E_INVALID, "dtau > 0, max_iter >= 1, tol > 0 and psi_out are required");
+    if (!aligned16(psi_out)) return fail(TDSE_E_INVALID, "psi_out must be 16-byte aligned");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    ClassSet cs;
+    std::vector<int> ns{n};
+    std::vector<Layout> lay{default_layout(n)};
+    std::vector<TableParams> prm{imag_time_params(p->dx, p->a, p->charge_z, dtau)};
+    st = build_classes(cs, ns, lay, prm, hs);
+    if (st == TDSE_OK) {
+        std::vector<int> one{0};
+        int64_t off = 0;
+        std::vector<double> e;
+        std::vector<int> it;
+        st = run_ground_states(cs, one, dtau, max_iter, tol, psi_out, &off, e, it, hs);
+        if (st == TDSE_OK) {
+            if (energy_out) *energy_out = e[0];
+            if (it[0] <= 0) st = fail(TDSE_E_NOCONV, "not converged after %d iterations", -it[0]);
+            else if (!std::isfinite(e[0])) st = fail(TDSE_E_NONFINITE, "non-finite energy");
+        }
+    }
+    cs.release();
+    return st;
+}
+
+tdse_status tdse_soft_core_for_ip(double ip, int32_t n, double dx, double dtau, double tol,
+                                  double a_lo, double a_hi, double* a_out, double* e_out)
+{
+    g_last_error.clear();
+    if (!(ip > 0.0) || !(dx > 0.0) || !(dtau > 0.0) || !(tol > 0.0) || !a_out)
+        return fail(TDSE_E_INVALID, "ip, dx, dtau, tol > 0 and a_out are required");
+    if (!(a_lo > 0.0) || !(a_hi > a_lo)) return fail(TDSE_E_INVALID, "need 0 < a_lo < a_hi");
+    if (n < kMinN || n > kMaxN) return fail(TDSE_E_INVALID, "n=%d out of range", n);
+    const int K = 31;  // candidates per round (plus the two bracket ends in round 0)
+    const Layout L = default_layout(n);
+    double* d_psi = nullptr;
+    HIP_TRY(hipMalloc(&d_psi, sizeof(double) * 2 * (size_t)n * (K + 2)));
+    tdse_status st = TDSE_OK;
+    double lo = a_lo, hi = a_hi, best_a = 0.5 * (a_lo + a_hi), best_e = 0.0;
+    bool first = true, done = false;
+    for (int round = 0; round < 40 && st == TDSE_OK && !done; ++round) {
+        std::vector<double> cand;
+        if (first) {
+            cand.push_back(lo);
+            cand.push_back(hi);
+        }
+        for (int k = 1; k <= K; ++k) cand.push_back(lo + (hi - lo) * k / (K + 1));
+        const int nc = (int)cand.size();
+        std::vector<int> ns(nc, n), cls(nc);
+        std::vector<Layout> lay(nc, L);
+        std::vector<TableParams> prm(nc);
+        std::vector<int64_t> off(nc);
+        for (int c = 0; c < nc; ++c) {
+            prm[c] = imag_time_params(dx, cand[c], 1.0, dtau);
+            cls[c] = c;
+            off[c] = (int64_t)c * n;
+        }
+        ClassSet cs;
+        st = build_classes(cs, ns, lay, prm, nullptr);
+        std::vector<double> e;
+        std::vector<int> it;
+        if (st == TDSE_OK) st = run_ground_states(cs, cls, dtau, kGsMaxIter, kGsTol, d_psi, off.data(), e, it, nullptr);
+        cs.release();
+        if (st != TDSE_OK) break;
+        for (int c = 0; c < nc; ++c) {
+            if (it[c] <= 0 || !std::isfinite(e[c])) {
+                st = fail(TDSE_E_NOCONV, "ground state at a=%.17g did not converge", cand[c]);
+                break;
+            }
+        }
+        if (st != TDSE_OK) break;
+        if (first) {
+            if (!(e[0] < -ip && e[1] > -ip)) {
+                st = fail(TDSE_E_INVALID, "-ip is not bracketed: E(a_lo)=%.6f E(a_hi)=%.6f", e[0], e[1]);
+                break;
+            }
+            first = false;
+        }
+        // closest candidate and the new bracket
+        double new_lo = lo, new_hi = hi;
+        for (int c = 0; c < nc; ++c) {
+            if (std::fabs(e[c] + ip) < std::fabs(best_e + ip) || round == 0 && c == 0) {
+                best_a = cand[c];
+                best_e = e[c];
+            }
+            if (e[c] < -ip && cand[c] > new_lo) new_lo = cand[c];
+            if (e[c] > -ip && cand[c] < new_hi) new_hi = cand[c];
+        }
+        lo = new_lo;
+        hi = new_hi;
+        if (std::fabs(best_e + ip) < tol) done = true;
+        else if (hi - lo <= 4.0 * std::numeric_limits<double>::epsilon() * hi) {
+            st = fail(TDSE_E_NOCONV, "bracket collapsed at |E+ip| = %.3g", std::fabs(best_e + ip));
+        }
+    }
+    (void)hipFree(d_psi);
+    if (st == TDSE_OK && !done) st = fail(TDSE_E_NOCONV, "soft-core fit did not reach tol");
+    *a_out = best_a;
+    if (e_out) *e_out = best_e;
+    return st;
+}
+
+tdse_status tdse_adjoint_batch(tdse_plan plan, const double* E, const double* psi0,
+                               const double* accel_bar, double* grad_E, double* accel,
+                               int32_t* sys_status, void* stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
+    if (plan->adjoint_k <= 0 || !plan->d_adj)
+        return fail(TDSE_E_INVALID, "plan was created without adjoint support (adjoint_k <= 0)");
+    if (!E || !accel_bar || !grad_E) return fail(TDSE_E_INVALID, "E, accel_bar and grad_E are required");
+    const void* ptrs[] = {E, psi0, accel_bar, grad_E, accel, sys_status};
+    for (const void* q : ptrs)
+        if (q && !aligned16(q)) return fail(TDSE_E_INVALID, "device pointers must be 16-byte aligned");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    FwdArgs base;
+    fill_fwd_args(plan, base, E, psi0, accel, nullptr, nullptr, nullptr, sys_status);
+    base.abar = accel_bar;
+    base.grad = grad_E;
+    base.k_ckpt = plan->adjoint_k;
+    const int ng = (int)plan->groups.size();
+    if (launch_reset_counters(plan->d_counters, ng, st) != hipSuccess)
+        return fail(TDSE_E_DEVICE, "counter reset launch failed");
+    for (int g = 0; g < ng; ++g) {
+        const auto& G = plan->groups[g];
+        FwdArgs a = base;
+        a.order = G.d_order;
+        a.count = G.count;
+        a.queue = plan->d_counters + g;
+        a.ckpt = plan->d_adj + plan->adj_off[g];
+        a.slot_stride_ckpt = plan->adj_slot_ckpt[g] + plan->adj_slot_seg[g];
+        if (launch_adjoint(G.C, a, G.T, plan->adj_grid[g], st) != hipSuccess)
+            return fail(TDSE_E_DEVICE, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    return TDSE_OK;
+}
+
+static void band_of(int32_t nt, double dt, double omega0, double h_lo, double h_hi, int32_t* k_lo,
+                    int32_t* nk)
+{
+    const int64_t M = (int64_t)nt + 1;
+    const double dw = 2.0 * M_PI / ((double)M * dt);
+    int64_t lo = -1, hi = -2;
+    for (int64_t k = 0; k <= M / 2; ++k) {
+        const double w = (double)k * dw;
+        if (w >= h_lo * omega0 && w <= h_hi * omega0) {
+            if (lo < 0) lo = k;
+            hi = k;
+        }
+    }
+    *k_lo = (int32_t)std::max<int64_t>(lo, 0);
+    *nk = lo < 0 ? 0 : (int32_t)(hi - lo + 1);
+}
+
+tdse_status tdse_harmonic_band(int32_t nt, double dt, double omega0, double h_lo, double h_hi,
+                               int32_t* k_lo, int32_t* nk)
+{
+    g_last_error.clear();
+    if (nt < 1 || !(dt > 0.0) || !(omega0 > 0.0) || !(h_hi >= h_lo) || h_lo < 0.0 || !k_lo || !nk)
+        return fail(TDSE_E_INVALID, "need nt >= 1, dt > 0, omega0 > 0, 0 <= h_lo <= h_hi");
+    band_of(nt, dt, omega0, h_lo, h_hi, k_lo, nk);
+    return TDSE_OK;
+}
+
+tdse_status tdse_harmonic_yield(int32_t batch, int32_t nt, double dt, double omega0, double h_lo,
+                                double h_hi, const double* accel, const double* row_weight,
+                                double* work, double* yield, double* accel_bar, void* stream)
+{
+    g_last_error.clear();
+    if (batch < 1 || nt < 1 || !(dt > 0.0) || !(omega0 > 0.0) || !(h_hi >= h_lo) || h_lo < 0.0)
+        return fail(TDSE_E_INVALID, "need batch >= 1, nt >= 1, dt > 0, omega0 > 0, 0 <= h_lo <= h_hi");
+    if (!accel || !yield || !work) return fail(TDSE_E_INVALID, "accel, work and yield are required");
+    const void* ptrs[] = {accel, row_weight, work, yield, accel_bar};
+    for (const void* q : ptrs)
+        if (q && !aligned16(q)) return fail(TDSE_E_INVALID, "device pointers must be 16-byte aligned");
+    YieldArgs a{};
+    band_of(nt, dt, omega0, h_lo, h_hi, &a.k_lo, &a.nk);
+    a.batch = batch;
+    a.nt = nt;
+    a.dt = dt;
+    a.omega0 = omega0;
+    a.h_lo = h_lo;
+    a.h_hi = h_hi;
+    a.accel = accel;
+    a.row_weight = row_weight;
+    a.amp = work;
+    a.yield = yield;
+    a.abar = accel_bar;
+    HIP_TRY(launch_yield(a, reinterpret_cast<hipStream_t>(stream)));
+    return TDSE_OK;
+}
+
+}  // extern "C"

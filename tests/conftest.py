@@ -24,7 +24,7 @@ def gpu_available() -> bool:
 @pytest.fixture(scope="session")
 def lib():
     """The HIP library binding (GPU tests only)."""
-    from paper_2507_04115_amd import libtdse as L
+    from paper_2507_04115_amd import binding as L
 
     L.load()
     return L

@@ -1,0 +1,79 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/libtdse.h; argument validation runs on the host (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2507_04115_amd import binding as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "libtdse.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdse_[a-z_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = L.load()
+    names = _declared()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.exported_names())
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in L.tdse_version()
+    lib = L.load()
+    for st in range(0, -7, -1):
+        assert lib.tdse_status_string(st)
+    assert lib.tdse_status_string(-99) == b"unknown status"
+
+
+def _create(p, ns, out=True):
+    lib = L.load()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int32 * len(ns))(*ns)
+    return lib.tdse_plan_create(ctypes.byref(p), len(ns), arr, 0, 0,
+                                ctypes.byref(h) if out else None)
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("dx", 0.0, "dx"), ("dt", -1.0, "dt"), ("a", -1.0, "soft-core"),
+    ("mask_fraction", 1.5, "mask_fraction"), ("nt", -3, "nt"), ("flags", 1, "flags"),
+])
+def test_plan_create_rejects_bad_params_before_touching_the_device(field, value, msg):
+    p = L.make_params(0.2, 0.05, 1.2, 100)
+    setattr(p, field, value)
+    assert _create(p, [256]) == L.TDSE_E_INVALID
+    assert msg in L.load().tdse_last_error().decode()
+
+
+def test_plan_create_rejects_bad_sizes():
+    p = L.make_params(0.2, 0.05, 1.2, 100)
+    assert _create(p, [8]) == L.TDSE_E_INVALID
+    assert _create(p, [20000]) == L.TDSE_E_UNSUPPORTED
+    assert _create(p, [256], out=False) == L.TDSE_E_INVALID
+
+
+def test_yield_and_propagate_validation():
+    lib = L.load()
+    assert lib.tdse_harmonic_yield(0, 100, 0.05, 0.057, 21, 31, 16, None, 16, 16, None, None) == L.TDSE_E_INVALID
+    assert lib.tdse_harmonic_yield(1, 100, 0.05, 0.057, 31, 21, 16, None, 16, 16, None, None) == L.TDSE_E_INVALID
+    assert lib.tdse_harmonic_yield(1, 100, 0.05, 0.057, 21, 31, 8, None, 16, 16, None, None) == L.TDSE_E_INVALID
+    assert "aligned" in lib.tdse_last_error().decode()
+    assert lib.tdse_propagate_batch(None, 16, None, 16, None, None, None, None, None) == L.TDSE_E_INVALID
+    assert lib.tdse_adjoint_batch(None, 16, None, 16, 16, None, None, None) == L.TDSE_E_INVALID
+
+
+def test_harmonic_band_matches_definition():
+    k_lo, nk = L.tdse_harmonic_band(22047, 0.05, 0.057, 21, 31)
+    import numpy as np
+    dw = 2 * np.pi / (22048 * 0.05)
+    k = np.arange(22048 // 2 + 1)
+    sel = k[(k * dw >= 21 * 0.057) & (k * dw <= 31 * 0.057)]
+    assert (k_lo, nk) == (sel[0], len(sel))

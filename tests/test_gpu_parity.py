@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle on the
+same seeded inputs.  Bar: relative L2 <= 1e-9 on the dipole acceleration
+(and <norm>, <x>), <= 1e-5 on gradients."""
+import numpy as np
+import pytest
+
+import oracle
+import tdse_inputs as ti
+
+pytestmark = pytest.mark.gpu
+
+A_AR = 1.1891671
+TOL_ACC = 1e-9
+TOL_GRAD = 1e-5
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0")
+
+
+def _to_dev(torch, dev, x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+
+def _c2d(psi):
+    return np.ascontiguousarray(np.asarray(psi, np.complex128)).view(np.float64)
+
+
+def test_ground_state_matches_oracle(lib, torch_dev):
+    torch, dev = torch_dev
+    for n, dx, a in [(2048, 0.2, A_AR), (700, 0.3, 0.9)]:
+        print(f"ground state n={n} dx={dx} a={a}", flush=True)
+        p = lib.make_params(dx, 0.05, a, 0)
+        psi = torch.empty(2 * n, dtype=torch.float64, device=dev)
+        e = lib.tdse_ground_state(p, n, 1.0, 20000, 1e-13, psi)
+        ref, e_ref, _ = oracle.ground_state(n, dx, a, dtau=1.0, tol=1e-13)
+        got = psi.cpu().numpy().view(np.complex128)
+        assert abs(e - e_ref) < 1e-12
+        assert np.max(np.abs(got - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_soft_core_fit_reaches_ip(lib, torch_dev):
+    print("soft-core fit n=2048", flush=True)
+    a, e = lib.tdse_soft_core_for_ip(ti.IP_ARGON, 2048, 0.2, dtau=1.0, tol=1e-13)
+    assert abs(e + ti.IP_ARGON) < 1e-13
+    _, e_ref, _ = oracle.ground_state(2048, 0.2, a, dtau=1.0, tol=1e-13)
+    assert abs(e_ref + ti.IP_ARGON) < 1e-12
+
+
+def _run_forward(lib, torch, dev, ns, efield, dx, dt, a, psi0_list=None, mask=0.1, options=0,
+                 want=True):
+    nt = efield.shape[1] - 1
+    p = lib.make_params(dx, dt, a, nt, mask_fraction=mask)
+    plan = lib.Plan(p, ns, options=options)
+    E = _to_dev(torch, dev, efield)
+    acc = torch.empty_like(E)
+    xe = torch.empty_like(E) if want else None
+    nr = torch.empty_like(E) if want else None
+    st = torch.full((len(ns),), -1, dtype=torch.int32, device=dev)
+    psi0 = None
+    if psi0_list is not None:
+        psi0 = _to_dev(torch, dev, np.concatenate([_c2d(x) for x in psi0_list]))
+    pf = torch.empty(2 * sum(ns), dtype=torch.float64, device=dev)
+    lib.tdse_propagate_batch(plan, E, psi0, acc, xe, nr, pf, st)
+    torch.cuda.synchronize()
+    out = dict(accel=acc.cpu().numpy(), status=st.cpu().numpy(), psi_final=pf.cpu().numpy())
+    if want:
+        out.update(xexp=xe.cpu().numpy(), norm=nr.cpu().numpy())
+    return plan, out
+
+
+def test_forward_ragged_small_batch_vs_oracle(lib, torch_dev):
+    """Several sizes in one batch (several tiles, ragged tails), explicit psi0."""
+    torch, dev = torch_dev
+    ns = [100, 256, 300, 777, 1024, 2048, 2500, 4096]
+    dx, dt = 0.2, 0.05
+    om, nc = 0.057, 1
+    nt = ti.n_steps(om, nc, dt)
+    e0 = np.linspace(0.03, 0.09, len(ns))
+    efield = ti.sin2_pulse(e0, om, nc, dt, nt=nt)
+    psi0 = [ti.random_state(n, 11 + i, width=min(10.0, n * dx / 8), k0=0.3, dx=dx)
+            for i, n in enumerate(ns)]
+    print(f"forward ragged ns={ns} nt={nt}", flush=True)
+    plan, out = _run_forward(lib, torch, dev, ns, efield, dx, dt, A_AR, psi0)
+    off = plan.psi_offsets()
+    pf = out["psi_final"].view(np.complex128)
+    for b, n in enumerate(ns):
+        ref = oracle.propagate(efield[b], psi0[b], dx, dt, A_AR, mask_frac=0.1, want_psi=True)
+        assert out["status"][b] == 0
+        assert rel(out["accel"][b], ref["accel"]) < TOL_ACC, (n, rel(out["accel"][b], ref["accel"]))
+        assert rel(out["xexp"][b], ref["xexp"]) < TOL_ACC
+        assert rel(out["norm"][b], ref["norm"]) < TOL_ACC
+        assert rel(pf[off[b]:off[b + 1]], ref["psi_final"]) < TOL_ACC
+
+
+def test_forward_single_2048_full_pulse(lib, torch_dev):
+    """Single-system workload: N = 2048, dx = 0.2, dt = 0.05, 10-cycle 800 nm
+    pulse at 1.5e14 W/cm^2 (22 047 steps), plan ground state."""
+    torch, dev = torch_dev
+    w = ti.cfg1_single()
+    efield = w.efield()
+    print(f"forward single-2048 nt={w.nt}", flush=True)
+    plan, out = _run_forward(lib, torch, dev, [2048], efield, w.dx, w.dt, A_AR)
+    psi0 = torch.empty(2 * 2048, dtype=torch.float64, device=dev)
+    plan.ground_state(2048, psi0)
+    ref = oracle.propagate(efield[0], psi0.cpu().numpy().view(np.complex128), w.dx, w.dt, A_AR,
+                           mask_frac=0.1)
+    r = rel(out["accel"][0], ref["accel"])
+    print(f"  accel rel-L2 {r:.3e}", flush=True)
+    assert r < TOL_ACC
+    assert rel(out["norm"][0], ref["norm"]) < TOL_ACC
+
+
+def test_plan_ground_state_matches_oracle(lib, torch_dev):
+    torch, dev = torch_dev
+    p = lib.make_params(0.2, 0.05, A_AR, 10)
+    plan = lib.Plan(p, [2048, 1000])
+    for n in (2048, 1000):
+        psi = torch.empty(2 * n, dtype=torch.float64, device=dev)
+        e = plan.ground_state(n, psi)
+        ref, e_ref, _ = oracle.ground_state(n, 0.2, A_AR, dtau=1.0, tol=1e-13)
+        assert abs(e - e_ref) < 1e-12
+        assert np.max(np.abs(psi.cpu().numpy().view(np.complex128) - ref)) < 1e-9
+
+
+def test_plain_graph_direct_identical(lib, torch_dev):
+    """Plain (one launch per system), direct launches and graph replays give
+    bitwise identical outputs; repeated graph replays too."""
+    torch, dev = torch_dev
+    ns = [512, 512, 1024, 300]
+    nt = 300
+    rng = np.random.default_rng(3)
+    efield = 0.05 * rng.standard_normal((len(ns), nt + 1))
+    outs = []
+    for opt in (lib.TDSE_OPT_PLAIN, lib.TDSE_OPT_NO_GRAPH, 0):
+        print(f"options={opt}", flush=True)
+        outs.append(_run_forward(lib, torch, dev, ns, efield, 0.2, 0.05, A_AR, options=opt)[1])
+    for o in outs[1:]:
+        assert np.array_equal(o["accel"], outs[0]["accel"])
+        assert np.array_equal(o["psi_final"], outs[0]["psi_final"])
+    p = lib.make_params(0.2, 0.05, A_AR, nt)
+    plan = lib.Plan(p, ns)
+    E = _to_dev(torch, dev, efield)
+    accs = []
+    for rep in range(3):
+        acc = torch.empty_like(E) if rep == 0 else accs[0][1]
+        lib.tdse_propagate_batch(plan, E, None, acc)
+        torch.cuda.synchronize()
+        accs.append((acc.cpu().numpy().copy(), acc))
+        torch.cuda.synchronize()
+    for a_, _ in accs[1:]:
+        assert np.array_equal(a_, accs[0][0])
+    assert np.array_equal(accs[0][0], outs[0]["accel"])
+
+
+def test_nonfinite_field_is_flagged(lib, torch_dev):
+    torch, dev = torch_dev
+    nt = 100
+    efield = np.zeros((2, nt + 1))
+    efield[1, 40] = np.nan
+    _, out = _run_forward(lib, torch, dev, [256, 256], efield, 0.2, 0.05, A_AR)
+    assert out["status"][0] == 0
+    assert out["status"][1] & lib.TDSE_SYS_NONFINITE
+
+
+def test_harmonic_yield_matches_oracle(lib, torch_dev):
+    torch, dev = torch_dev
+    rng = np.random.default_rng(4)
+    nt, dt, om = 4000, 0.05, 0.057
+    t = np.arange(nt + 1) * dt
+    acc = np.sin(0.057 * 25 * t)[None, :] * rng.uniform(0.5, 1.5, (3, 1)) + 1e-3 * rng.standard_normal((3, nt + 1))
+    w = np.array([1.0, 0.0, 2.0])
+    k_lo, nk = lib.tdse_harmonic_band(nt, dt, om, 21, 31)
+    A = _to_dev(torch, dev, acc)
+    Wt = _to_dev(torch, dev, w)
+    work = torch.empty(2 * 3 * max(nk, 1), dtype=torch.float64, device=dev)
+    y = torch.empty(3, dtype=torch.float64, device=dev)
+    ab = torch.empty_like(A)
+    lib.tdse_harmonic_yield(3, nt, dt, om, 21, 31, A, Wt, work, y, ab)
+    torch.cuda.synchronize()
+    l_ref, ab_ref = oracle.harmonic_yield(acc, dt, om, 21, 31)
+    assert np.allclose(y.cpu().numpy(), w * l_ref, rtol=1e-11, atol=0)
+    got = ab.cpu().numpy()
+    for b in (0, 2):
+        assert rel(got[b], w[b] * ab_ref[b]) < 1e-10
+    assert np.all(got[1] == 0.0)
+
+
+def test_adjoint_matches_oracle_and_fd(lib, torch_dev):
+    torch, dev = torch_dev
+    ns = [256, 256, 400]
+    dx, dt, a = 0.4, 0.05, 1.1
+    om, nc = 0.25, 3
+    nt = ti.n_steps(om, nc, dt)
+    e0 = np.array([0.1, 0.12, 0.0])
+    efield = ti.sin2_pulse(e0, om, nc, dt, nt=nt)
+    efield[2] = 0.05 * np.random.default_rng(7).standard_normal(nt + 1)
+    p = lib.make_params(dx, dt, a, nt, mask_fraction=0.2)
+    for k in (37, 256):
+        print(f"adjoint ns={ns} nt={nt} K={k}", flush=True)
+        plan = lib.Plan(p, ns, adjoint_k=k)
+        E = _to_dev(torch, dev, efield)
+        acc = torch.empty_like(E)
+        lib.tdse_propagate_batch(plan, E, None, acc)
+        torch.cuda.synchronize()
+        _, abar = oracle.harmonic_yield(acc.cpu().numpy(), dt, om, 3, 9)
+        abar[1] = 0.0                      # an all-zero row is skipped
+        AB = _to_dev(torch, dev, abar)
+        grad = torch.full_like(E, 7.0)
+        acc2 = torch.empty_like(E)
+        st = torch.full((3,), -1, dtype=torch.int32, device=dev)
+        lib.tdse_adjoint_batch(plan, E, None, AB, grad, acc2, st)
+        torch.cuda.synchronize()
+        g = grad.cpu().numpy()
+        assert np.array_equal(acc2.cpu().numpy(), acc.cpu().numpy())
+        assert np.all(st.cpu().numpy() == 0)
+        assert np.all(g[1] == 0.0)
+        for b in (0, 2):
+            psi0 = torch.empty(2 * ns[b], dtype=torch.float64, device=dev)
+            plan.ground_state(ns[b], psi0)
+            g_ref, _ = oracle.adjoint(efield[b], psi0.cpu().numpy().view(np.complex128), abar[b],
+                                      dx, dt, a, mask_frac=0.2, k=k)
+            r = rel(g[b], g_ref)
+            print(f"  grad rel-L2 system {b}: {r:.3e}", flush=True)
+            assert r < 1e-9
+        plan.close()
