@@ -1,0 +1,227 @@
+"""Benchmark of the batched 1D-TDSE microscopic step on one MI355X.
+
+Workload (default): the 32 r x 32 z Gaussian-beam focus -- 1024 independent
+systems, N = 4096 points (dx = 0.2), dt = 0.05, 20-cycle 800 nm sin^2 pulse,
+peak 2e14 W/cm^2 at w0 = 50 um, soft-core argon (Ip = 0.5792), cos^(1/8)
+absorber.  Inputs are synthetic and generated on the device.
+
+One timed step = one batched forward solve of the whole batch through
+tdse_propagate_batch (graph replay of the persistent kernel): every system
+propagated over all Nt steps with the dipole acceleration, <x> and norm
+recorded at every sample.  The plan (soft-core fit, tables, ground states)
+is built once before the timed region.
+
+Besides the headline `value` (grid-point-steps/s = sum_p N_p Nt / time), the
+JSON line carries
+  plain       the same kernel launched once per system, serially (subset)
+  adjoint     time per gradient of the H21-H31 yield of the 256-system
+              adjoint batch (forward + checkpointed reverse sweep)
+  roofline    achieved FP64 rate of the forward kernel (52 algorithmic flops
+              per grid-point-step) against the 78.6 TFLOP/s vector peak
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload
+  parity      rel-L2 of the sampled GPU accelerations against that oracle run
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_POINT_STEP = 52.0        # algorithmic FP64 flops per grid-point-step
+FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="focus", choices=["focus", "single", "uneven"])
+    ap.add_argument("--plain-systems", type=int, default=8)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(systems are independent; sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import tdse_inputs as ti
+    from paper_2507_04115_amd import binding as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L.load()
+
+    w = {"focus": ti.cfg2_focus, "single": ti.cfg1_single, "uneven": ti.cfg3_uneven}[args.workload]()
+    a_sc, e_g = L.tdse_soft_core_for_ip(w.ip, 2048, w.dx, dtau=1.0, tol=1e-13)
+    log(f"workload {w.name}: P={w.batch} nt={w.nt} soft-core a={a_sc:.10f} (E_g={e_g:.13f})")
+    p = L.make_params(w.dx, w.dt, a_sc, w.nt, mask_fraction=w.mask_frac, mask_power=w.mask_pow)
+    t0 = time.time()
+    plan = L.Plan(p, w.n_per)
+    log(f"plan built in {time.time() - t0:.2f} s; layout {plan.layout(w.n_per[0])}")
+    E = w.efield(xp={"device": dev}).contiguous()
+    acc = torch.empty_like(E)
+    xe = torch.empty_like(E)
+    nr = torch.empty_like(E)
+    status = torch.empty(w.batch, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    point_steps = float(sum(w.n_per)) * w.nt
+
+    for _ in range(args.warmup):
+        L.tdse_propagate_batch(plan, E, None, acc, xe, nr, None, status)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        L.tdse_propagate_batch(plan, E, None, acc, xe, nr, None, status)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    value = point_steps / (ms_step * 1e-3)
+    st = status.cpu().numpy()
+    log(f"batched: {ms_step:.1f} ms/step, {value:.4e} grid-point-steps/s (wall {t_wall:.2f} s); "
+        f"status nonzero: {int(np.count_nonzero(st))}")
+    achieved = FLOPS_PER_POINT_STEP * value / 1e12
+
+    out = {
+        "metric": "TDSE grid-point-steps/s FP64, batched vs plain; adjoint grad time at 1e-9 err",
+        "value": value,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "systems": w.batch, "grid_points": int(w.n_per[0]) if len(set(w.n_per)) == 1 else "ragged",
+                   "nt": w.nt, "dx": w.dx, "dt": w.dt, "grid_point_steps": point_steps,
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": None,
+                     "kernel": "forward_kernel (graph replay incl. counter reset)",
+                     "flops_per_grid_point_step": FLOPS_PER_POINT_STEP},
+    }
+
+    # ---------------------------------------------------------- plain form
+    if not args.no_plain:
+        m = min(args.plain_systems, w.batch)
+        rows = list(range(m))
+        pp = L.Plan(p, [w.n_per[r] for r in rows], options=L.TDSE_OPT_PLAIN)
+        Ep = E[:m].contiguous()
+        ap_ = torch.empty_like(Ep)
+        L.tdse_propagate_batch(pp, Ep, None, ap_)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        L.tdse_propagate_batch(pp, Ep, None, ap_)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_plain = ev0.elapsed_time(ev1)
+        ps_plain = float(sum(w.n_per[r] for r in rows)) * w.nt
+        v_plain = ps_plain / (ms_plain * 1e-3)
+        same = bool(torch.equal(ap_, acc[:m]))
+        out["plain"] = {"value": v_plain, "unit": "grid-point-steps/s", "systems_timed": m,
+                        "ms": ms_plain, "batched_over_plain": value / v_plain,
+                        "bitwise_equal_to_batched": same}
+        log(f"plain: {v_plain:.4e} grid-point-steps/s on {m} systems; batched/plain = {value / v_plain:.1f}")
+        pp.close()
+
+    # ------------------------------------------------------------ adjoint
+    if not args.no_adjoint:
+        wa = ti.cfg4_adjoint()
+        pa = L.make_params(wa.dx, wa.dt, a_sc, wa.nt, mask_fraction=wa.mask_frac,
+                           mask_power=wa.mask_pow)
+        plan_a = L.Plan(pa, wa.n_per, adjoint_k=256)
+        Ea = wa.efield(xp={"device": dev}).contiguous()
+        acc_a = torch.empty_like(Ea)
+        h_lo, h_hi = wa.meta["band"]
+        k_lo, nk = L.tdse_harmonic_band(wa.nt, wa.dt, wa.omega, h_lo, h_hi)
+        work = torch.empty(2 * wa.batch * max(nk, 1), dtype=torch.float64, device=dev)
+        yld = torch.empty(wa.batch, dtype=torch.float64, device=dev)
+        abar = torch.empty_like(Ea)
+        grad = torch.empty_like(Ea)
+
+        def gradient():
+            L.tdse_propagate_batch(plan_a, Ea, None, acc_a)
+            L.tdse_harmonic_yield(wa.batch, wa.nt, wa.dt, wa.omega, h_lo, h_hi, acc_a, None, work,
+                                  yld, abar)
+            L.tdse_adjoint_batch(plan_a, Ea, None, abar, grad)
+
+        gradient()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        gradient()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_grad = ev0.elapsed_time(ev1)
+        out["adjoint"] = {"workload": wa.name, "systems": wa.batch, "nt": wa.nt, "checkpoint_k": 256,
+                          "time_per_gradient_s": ms_grad * 1e-3,
+                          "forward_grid_point_steps": float(sum(wa.n_per)) * wa.nt,
+                          "loss": f"sum of H{h_lo}-H{h_hi} Hann-windowed yields"}
+        log(f"adjoint: {ms_grad * 1e-3:.3f} s per gradient ({wa.batch} systems)")
+        plan_a.close()
+
+    # ------------------------------------------------------- CPU baseline
+    if not args.no_cpu:
+        import oracle
+
+        nth = args.cpu_threads or min(16, os.cpu_count() or 1)
+        rows = np.linspace(0, w.batch - 1, nth).round().astype(int)
+        gs = {}
+        psi_list = []
+        for r in rows:
+            n = w.n_per[r]
+            if n not in gs:
+                buf = torch.empty(2 * n, dtype=torch.float64, device=dev)
+                plan.ground_state(n, buf)
+                gs[n] = buf.cpu().numpy().view(np.complex128).copy()
+            psi_list.append(gs[n])
+        e_rows = E[torch.as_tensor(rows, device=dev)].cpu().numpy()
+        t0 = time.perf_counter()
+        ref = oracle.propagate_batch(e_rows, psi_list, w.dx, w.dt, a_sc, mask_frac=w.mask_frac,
+                                     mask_pow=w.mask_pow, nthreads=nth)
+        t_cpu = time.perf_counter() - t0
+        ps_cpu = float(sum(w.n_per[r] for r in rows)) * w.nt
+        out["cpu_baseline"] = {"value": ps_cpu / t_cpu, "unit": "grid-point-steps/s", "cores": nth,
+                               "kind": "oracle",
+                               "sample": f"{len(rows)} systems of the same batch (rows {rows[0]}..{rows[-1]}), "
+                                         f"full {w.nt} steps, one thread per system, {t_cpu:.1f} s"}
+        got = acc[torch.as_tensor(rows, device=dev)].cpu().numpy()
+        errs = [float(np.linalg.norm(got[i] - ref["accel"][i]) / np.linalg.norm(ref["accel"][i]))
+                for i in range(len(rows))]
+        out["parity"] = {"accel_rel_l2_max": max(errs), "systems_checked": len(rows),
+                         "tolerance": 1e-9}
+        log(f"cpu oracle: {ps_cpu / t_cpu:.3e} grid-point-steps/s on {nth} threads; "
+            f"parity max rel-L2 {max(errs):.2e}")
+
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -15,7 +15,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/libtdse.h"
+#include "libtdse.h"
 #include "tdse_internal.hpp"
 #include "tdse_kernels.hpp"
 
@@ -82,9 +82,19 @@ struct Layout {
     int C, T;
 };
 
+int env_int(const char* name, int dflt)
+{
+    const char* v = std::getenv(name);
+    return (v && *v) ? std::atoi(v) : dflt;
+}
+
 Layout default_layout(int n)
 {
-    int C = n > 2048 ? 16 : (n > 512 ? 8 : 4);
+    // measured on MI355X: 8 points per lane with two systems per workgroup
+    // beats 16 points (register spills) and 4 (per-lane overheads)
+    int C = n > 8192 ? 16 : (n > 512 ? 8 : 4);
+    const int fc = env_int("TDSE_LAYOUT_C", 0);  // experiment override
+    if (fc == 4 || fc == 8 || fc == 16) C = fc;
     int T = ((n + C - 1) / C + kWave - 1) / kWave * kWave;
     if (T < kWave) T = kWave;
     return {C, T};
@@ -95,10 +105,9 @@ size_t class_bytes(const Layout& L)
     const size_t np = (size_t)L.C * L.T, T = L.T;
     size_t b = 0;
     auto add = [&](size_t bytes) { b += (bytes + 255) & ~size_t(255); };
-    for (int i = 0; i < 3; ++i) add(np * sizeof(double));
-    for (int i = 0; i < 5; ++i) add(np * sizeof(cd));
-    for (int i = 0; i < 6; ++i) add(T * sizeof(double));
-    for (int i = 0; i < 2; ++i) add(T * sizeof(cd));
+    for (int i = 0; i < 4; ++i) add(np * sizeof(double));
+    for (int i = 0; i < 3; ++i) add(np * sizeof(cd));
+    add(T * sizeof(LaneConst));
     for (int i = 0; i < 2; ++i) add(kMaxLevels * T * sizeof(cd));
     for (int i = 0; i < 2; ++i) add(T * sizeof(cd));
     add(T * sizeof(int32_t));
@@ -109,21 +118,13 @@ void carve_class(Arena& ar, SizeClass& sc)
 {
     const size_t np = (size_t)sc.C * sc.T, T = sc.T;
     sc.pt.v = ar.take<double>(np);
+    sc.pt.om = ar.take<double>(np);
     sc.pt.dv = ar.take<double>(np);
     sc.pt.m = ar.take<double>(np);
-    sc.pt.alpha = ar.take<cd>(np);
-    sc.pt.at = ar.take<cd>(np);
     sc.pt.q = ar.take<cd>(np);
+    sc.pt.alpha = ar.take<cd>(np);
     sc.pt.beta = ar.take<cd>(np);
-    sc.pt.bt = ar.take<cd>(np);
-    sc.lt.vl = ar.take<double>(T);
-    sc.lt.vr = ar.take<double>(T);
-    sc.lt.ml = ar.take<double>(T);
-    sc.lt.mr = ar.take<double>(T);
-    sc.lt.dvl = ar.take<double>(T);
-    sc.lt.dvr = ar.take<double>(T);
-    sc.lt.ql = ar.take<cd>(T);
-    sc.lt.bl = ar.take<cd>(T);
+    sc.lt.k = ar.take<LaneConst>(T);
     sc.lt.pa = ar.take<cd>(kMaxLevels * T);
     sc.lt.qb = ar.take<cd>(kMaxLevels * T);
     sc.lt.pw = ar.take<cd>(T);
@@ -174,7 +175,7 @@ tdse_status build_classes(ClassSet& cs, const std::vector<int>& ns,
         sc.levels = kMaxLevels;
         sc.xwaves = sc.T / kWave;
         sc.dx = params[c].dx;
-        sc.x0 = -0.5 * (double)(sc.n - 1) * sc.dx;
+        sc.habs = std::sqrt(params[c].h.re * params[c].h.re + params[c].h.im * params[c].h.im);
         carve_class(ar, sc);
     }
     HIP_TRY(hipMalloc(&cs.d, sizeof(SizeClass) * ncls));
@@ -342,6 +343,22 @@ tdse_status check_params(const tdse_params* p, bool need_time)
 }  // namespace
 
 // ==================================================================== plan
+// ==================================================================== plan
+// One launch of the persistent kernels: the systems of one size class.
+struct Launch {
+    int cls;
+    int C, T, S;          // points per lane, lanes per system, systems per workgroup
+    bool lds;             // point tables staged in LDS
+    int count, grid;
+    int32_t* d_order;     // the class's systems
+    // adjoint
+    int aS = 1, agrid = 0;
+    bool alds = false;
+    int64_t slot_doubles = 0;
+    int64_t work_off = 0;  // doubles into the adjoint workspace
+    int32_t* d_order_adj = nullptr;
+};
+
 struct tdse_plan_s {
     tdse_params p{};
     int batch = 0;
@@ -357,16 +374,11 @@ struct tdse_plan_s {
     double* d_gs = nullptr;
     int64_t* d_gs_off = nullptr;
     SysDesc* d_sys = nullptr;
-    // launch groups: systems sharing one lane layout (C, T)
-    struct Group {
-        int C, T, count, grid;
-        int32_t* d_order;
-    };
-    std::vector<Group> groups;
-    int32_t* d_order_all = nullptr;
-    int32_t* d_counters = nullptr;      // groups.size() + batch (plain mode)
+    std::vector<Launch> launches;       // one per class, longest work first
+    std::vector<int> launch_of_cls;
+    int32_t* d_order_all = nullptr;     // 2*batch: forward order, adjoint order
+    int32_t* d_counters = nullptr;      // launches + batch (plain mode) + 2*launches (compaction)
     int32_t* d_ident = nullptr;
-    std::vector<int> plain_group;       // per system: its group
     // graph replay
     hipStream_t cap = nullptr;
     std::vector<hipStream_t> branch;
@@ -376,9 +388,6 @@ struct tdse_plan_s {
     // adjoint workspace
     double* d_adj = nullptr;
     size_t adj_bytes = 0;
-    std::vector<int64_t> adj_slot_ckpt, adj_slot_seg;
-    std::vector<int> adj_grid;
-    std::vector<int64_t> adj_off;       // per group: offset of its workspace (doubles)
 };
 
 namespace {
@@ -399,6 +408,33 @@ void plan_free(tdse_plan pl)
     if (pl->d_ident) (void)hipFree(pl->d_ident);
     if (pl->d_adj) (void)hipFree(pl->d_adj);
     delete pl;
+}
+
+// Systems per workgroup and table placement for a class: as many systems as
+// fit in 1024 lanes whose registers and LDS fit one workgroup per CU, point
+// tables in LDS whenever they fit.  Returns false if nothing fits.
+bool choose_packing(int C, int T, int count, bool adjoint, int* S_out, bool* lds_out, int* occ_out)
+{
+    int smax = std::max(1, std::min(1024 / T, count));
+    const int fs = env_int("TDSE_PACK_S", 0);          // experiment overrides
+    const int fl = env_int("TDSE_PACK_LDS", -1);
+    if (fs > 0) smax = std::min(smax, fs);
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool lds = pass == 0;
+        if ((fl == 0 && lds) || (fl == 1 && !lds)) continue;
+        for (int S = smax; S >= 1; --S) {
+            const size_t sh = adjoint ? adjoint_smem_bytes(C, T, S, lds) : forward_smem_bytes(C, T, S, lds);
+            if (sh > (size_t)kMaxLds) continue;
+            const int occ = adjoint ? adjoint_occupancy(C, T, S, lds) : forward_occupancy(C, T, S, lds);
+            if (occ >= 1) {
+                *S_out = S;
+                *lds_out = lds;
+                *occ_out = occ;
+                return true;
+            }
+        }
+    }
+    return false;
 }
 
 constexpr double kGsDtau = 0.5;
@@ -448,7 +484,7 @@ tdse_status plan_ground_states(tdse_plan pl, hipStream_t st)
 
 extern "C" {
 
-const char* tdse_version(void) { return "libtdse 0.1.0 (gfx950, fp64)"; }
+const char* tdse_version(void) { return "libtdse 0.2.0 (gfx950, fp64)"; }
 
 const char* tdse_status_string(tdse_status s)
 {
@@ -478,6 +514,7 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     if (!n_per_system) return fail(TDSE_E_INVALID, "n_per_system is NULL");
     if (options & ~(TDSE_OPT_PLAIN | TDSE_OPT_NO_GRAPH | TDSE_OPT_AUTOTUNE))
         return fail(TDSE_E_INVALID, "unknown option bits 0x%x", options);
+    if (adjoint_k < 0) return fail(TDSE_E_INVALID, "adjoint_k must be >= 0");
     for (int b = 0; b < batch; ++b) {
         if (n_per_system[b] < kMinN) return fail(TDSE_E_INVALID, "n[%d] = %d < %d", b, n_per_system[b], kMinN);
         if (n_per_system[b] > kMaxN)
@@ -499,14 +536,13 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     pl->psi_off.assign(batch + 1, 0);
     for (int b = 0; b < batch; ++b) pl->psi_off[b + 1] = pl->psi_off[b] + pl->n_per[b];
 
-    hipStream_t s0 = nullptr;
     auto bail = [&](tdse_status rc) {
         plan_free(pl);
         return rc;
     };
     if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(TDSE_E_DEVICE, "stream creation failed"));
-    s0 = pl->cap;
+    hipStream_t s0 = pl->cap;
 
     // size classes, one per distinct n
     std::vector<int> ns;
@@ -529,44 +565,62 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     st = plan_ground_states(pl, s0);
     if (st != TDSE_OK) return bail(st);
 
-    // systems and launch groups
+    // systems and launches (one per class)
     pl->cls_of.resize(batch);
     std::vector<SysDesc> sys(batch);
-    std::map<std::pair<int, int>, int> gidx;
-    std::vector<std::vector<int32_t>> gsys;
-    pl->plain_group.resize(batch);
+    std::vector<std::vector<int32_t>> csys(ncls);
     for (int b = 0; b < batch; ++b) {
         const int c = pl->cls_of_n[pl->n_per[b]];
         pl->cls_of[b] = c;
         sys[b].cls = c;
         sys[b].n = pl->n_per[b];
         sys[b].psi_off = pl->psi_off[b];
-        const auto key = std::make_pair(pl->cls.h[c].C, pl->cls.h[c].T);
-        if (!gidx.count(key)) {
-            gidx[key] = (int)gsys.size();
-            gsys.emplace_back();
-            pl->groups.push_back({key.first, key.second, 0, 0, nullptr});
-        }
-        gsys[gidx[key]].push_back(b);
-        pl->plain_group[b] = gidx[key];
+        csys[c].push_back(b);
     }
-    // longest groups first (largest n * lanes of work per system)
-    std::vector<int> gorder(pl->groups.size());
-    for (size_t g = 0; g < gorder.size(); ++g) gorder[g] = (int)g;
+    // longest work first: classes by (n_pad * count) descending
+    std::vector<int> corder(ncls);
+    for (int c = 0; c < ncls; ++c) corder[c] = c;
+    std::stable_sort(corder.begin(), corder.end(), [&](int x, int y) {
+        const double wx = (double)lay[x].C * lay[x].T * csys[x].size();
+        const double wy = (double)lay[y].C * lay[y].T * csys[y].size();
+        return wx > wy;
+    });
+    const int nl = ncls;
     if (hipMalloc(&pl->d_sys, sizeof(SysDesc) * batch) != hipSuccess ||
-        hipMalloc(&pl->d_order_all, sizeof(int32_t) * batch) != hipSuccess ||
-        hipMalloc(&pl->d_counters, sizeof(int32_t) * (pl->groups.size() + batch)) != hipSuccess ||
+        hipMalloc(&pl->d_order_all, sizeof(int32_t) * 2 * batch) != hipSuccess ||
+        hipMalloc(&pl->d_counters, sizeof(int32_t) * (3 * nl + batch)) != hipSuccess ||
         hipMalloc(&pl->d_ident, sizeof(int32_t) * batch) != hipSuccess)
         return bail(fail(TDSE_E_NOMEM, "plan allocation failed"));
     std::vector<int32_t> order_all;
-    for (size_t g = 0; g < pl->groups.size(); ++g) {
-        auto& G = pl->groups[g];
-        G.count = (int)gsys[g].size();
-        G.d_order = pl->d_order_all + order_all.size();
-        order_all.insert(order_all.end(), gsys[g].begin(), gsys[g].end());
-        const int occ = forward_occupancy(G.C, G.T);
-        if (occ <= 0) return bail(fail(TDSE_E_UNSUPPORTED, "layout C=%d T=%d does not fit", G.C, G.T));
-        G.grid = std::min(G.count, occ * num_cus());
+    pl->launch_of_cls.assign(ncls, -1);
+    const int64_t nt = p->nt;
+    int64_t adj_total = 0;
+    for (int c : corder) {
+        Launch L{};
+        L.cls = c;
+        L.C = lay[c].C;
+        L.T = lay[c].T;
+        L.count = (int)csys[c].size();
+        L.d_order = pl->d_order_all + order_all.size();
+        L.d_order_adj = pl->d_order_all + batch + order_all.size();
+        order_all.insert(order_all.end(), csys[c].begin(), csys[c].end());
+        int occ = 0;
+        if (!choose_packing(L.C, L.T, L.count, false, &L.S, &L.lds, &occ))
+            return bail(fail(TDSE_E_UNSUPPORTED, "layout C=%d T=%d does not fit", L.C, L.T));
+        L.grid = std::min((L.count + L.S - 1) / L.S, occ * num_cus());
+        if (adjoint_k > 0) {
+            int aocc = 0;
+            if (!choose_packing(L.C, L.T, L.count, true, &L.aS, &L.alds, &aocc))
+                return bail(fail(TDSE_E_UNSUPPORTED, "adjoint layout C=%d T=%d does not fit", L.C, L.T));
+            L.agrid = std::min((L.count + L.aS - 1) / L.aS, aocc * num_cus());
+            const int64_t rec = 2 * (int64_t)(L.C + 2) * L.T;   // one state record
+            const int64_t nseg = nt / adjoint_k + 1;
+            L.slot_doubles = (rec * (nseg + adjoint_k + 1) + (nt + 1) + 1) & ~int64_t(1);
+            L.work_off = adj_total;
+            adj_total += L.slot_doubles * (int64_t)L.agrid * L.aS;
+        }
+        pl->launch_of_cls[c] = (int)pl->launches.size();
+        pl->launches.push_back(L);
     }
     std::vector<int32_t> ident(batch);
     for (int b = 0; b < batch; ++b) ident[b] = b;
@@ -578,7 +632,7 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         return bail(fail(TDSE_E_DEVICE, "plan upload failed"));
 
     // graph branches
-    const int nbr = std::min<int>(4, (int)pl->groups.size());
+    const int nbr = std::min<int>(4, nl);
     for (int i = 0; i < nbr; ++i) {
         hipStream_t s;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
@@ -592,26 +646,8 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         pl->ev.push_back(e);
     }
 
-    // adjoint workspace
     if (adjoint_k > 0) {
-        const int64_t nt = p->nt;
-        int64_t total = 0;
-        for (size_t g = 0; g < pl->groups.size(); ++g) {
-            auto& G = pl->groups[g];
-            const int occ = adjoint_occupancy(G.C, G.T);
-            if (occ <= 0) return bail(fail(TDSE_E_UNSUPPORTED, "adjoint layout C=%d T=%d does not fit", G.C, G.T));
-            const int grid = std::min(G.count, occ * num_cus());
-            const int64_t np = (int64_t)(G.C + 2) * G.T;  // chunk values and two ghosts per lane
-            const int64_t nseg = nt / adjoint_k + 1;
-            const int64_t ck = 2 * np * nseg;
-            const int64_t sg = 2 * np * (int64_t)(adjoint_k + 1) + (nt + 1);
-            pl->adj_grid.push_back(grid);
-            pl->adj_slot_ckpt.push_back(ck);
-            pl->adj_slot_seg.push_back(sg);
-            pl->adj_off.push_back(total);
-            total += (ck + sg) * grid;
-        }
-        pl->adj_bytes = sizeof(double) * (size_t)total;
+        pl->adj_bytes = sizeof(double) * (size_t)adj_total;
         if (hipMalloc(&pl->d_adj, pl->adj_bytes) != hipSuccess)
             return bail(fail(TDSE_E_NOMEM, "adjoint workspace of %.1f GB not available",
                              pl->adj_bytes / 1e9));
@@ -660,9 +696,9 @@ tdse_status tdse_plan_ground_state(tdse_plan plan, int32_t n, double* psi_out, d
     return TDSE_OK;
 }
 
-static tdse_status fill_fwd_args(tdse_plan pl, FwdArgs& a, const double* E, const double* psi0,
-                                 double* accel, double* xexp, double* norm, double* psi_final,
-                                 int32_t* sys_status)
+static void fill_fwd_args(tdse_plan pl, FwdArgs& a, const double* E, const double* psi0,
+                          double* accel, double* xexp, double* norm, double* psi_final,
+                          int32_t* sys_status)
 {
     a = FwdArgs{};
     a.classes = pl->cls.d;
@@ -678,39 +714,39 @@ static tdse_status fill_fwd_args(tdse_plan pl, FwdArgs& a, const double* E, cons
     a.norm = norm;
     a.psi_final = psi_final;
     a.status = sys_status;
-    return TDSE_OK;
 }
 
 static tdse_status enqueue_forward(tdse_plan pl, const FwdArgs& base, hipStream_t st, bool branches)
 {
-    const int ng = (int)pl->groups.size();
-    if (launch_reset_counters(pl->d_counters, ng, st) != hipSuccess)
+    const int nl = (int)pl->launches.size();
+    if (launch_reset_counters(pl->d_counters, nl, st) != hipSuccess)
         return fail(TDSE_E_DEVICE, "counter reset launch failed");
+    auto one = [&](int l, hipStream_t s) -> tdse_status {
+        const Launch& L = pl->launches[l];
+        FwdArgs a = base;
+        a.order = L.d_order;
+        a.count = L.count;
+        a.cls = L.cls;
+        a.queue = pl->d_counters + l;
+        a.sub_bytes = (int64_t)sub_smem_bytes(L.T / kWave);
+        if (launch_forward(L.C, L.lds, a, L.T, L.S, L.grid, s) != hipSuccess)
+            return fail(TDSE_E_DEVICE, "forward launch failed: %s", hipGetErrorString(hipGetLastError()));
+        return TDSE_OK;
+    };
     if (!branches || pl->branch.size() <= 1) {
-        for (int g = 0; g < ng; ++g) {
-            const auto& G = pl->groups[g];
-            FwdArgs a = base;
-            a.order = G.d_order;
-            a.count = G.count;
-            a.queue = pl->d_counters + g;
-            if (launch_forward(G.C, a, G.T, G.grid, st) != hipSuccess)
-                return fail(TDSE_E_DEVICE, "forward launch failed: %s",
-                            hipGetErrorString(hipGetLastError()));
+        for (int l = 0; l < nl; ++l) {
+            tdse_status rc = one(l, st);
+            if (rc != TDSE_OK) return rc;
         }
         return TDSE_OK;
     }
-    // fork the groups over the branch streams (captured as parallel graph branches)
+    // fork the classes over the branch streams (captured as parallel graph branches)
     const int nb = (int)pl->branch.size();
     HIP_TRY(hipEventRecord(pl->ev[0], st));
     for (int b = 0; b < nb; ++b) HIP_TRY(hipStreamWaitEvent(pl->branch[b], pl->ev[0], 0));
-    for (int g = 0; g < ng; ++g) {
-        const auto& G = pl->groups[g];
-        FwdArgs a = base;
-        a.order = G.d_order;
-        a.count = G.count;
-        a.queue = pl->d_counters + g;
-        if (launch_forward(G.C, a, G.T, G.grid, pl->branch[g % nb]) != hipSuccess)
-            return fail(TDSE_E_DEVICE, "forward launch failed");
+    for (int l = 0; l < nl; ++l) {
+        tdse_status rc = one(l, pl->branch[l % nb]);
+        if (rc != TDSE_OK) return rc;
     }
     for (int b = 0; b < nb; ++b) {
         HIP_TRY(hipEventRecord(pl->ev[b + 1], pl->branch[b]));
@@ -735,16 +771,19 @@ tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* 
 
     if (plan->options & TDSE_OPT_PLAIN) {
         // one system per launch, serially on the caller's stream
-        const int ng = (int)plan->groups.size();
-        if (launch_reset_counters(plan->d_counters + ng, plan->batch, st) != hipSuccess)
+        const int nl = (int)plan->launches.size();
+        int32_t* ctr = plan->d_counters + 3 * nl;
+        if (launch_reset_counters(ctr, plan->batch, st) != hipSuccess)
             return fail(TDSE_E_DEVICE, "counter reset launch failed");
         for (int b = 0; b < plan->batch; ++b) {
-            const auto& G = plan->groups[plan->plain_group[b]];
+            const Launch& L = plan->launches[plan->launch_of_cls[plan->cls_of[b]]];
             FwdArgs a = base;
             a.order = plan->d_ident + b;
             a.count = 1;
-            a.queue = plan->d_counters + ng + b;
-            if (launch_forward(G.C, a, G.T, 1, st) != hipSuccess)
+            a.cls = L.cls;
+            a.queue = ctr + b;
+            a.sub_bytes = (int64_t)sub_smem_bytes(L.T / kWave);
+            if (launch_forward(L.C, L.lds, a, L.T, 1, 1, st) != hipSuccess)
                 return fail(TDSE_E_DEVICE, "forward launch failed");
         }
         return TDSE_OK;
@@ -895,7 +934,7 @@ tdse_status tdse_adjoint_batch(tdse_plan plan, const double* E, const double* ps
     g_last_error.clear();
     if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
     if (plan->adjoint_k <= 0 || !plan->d_adj)
-        return fail(TDSE_E_INVALID, "plan was created without adjoint support (adjoint_k <= 0)");
+        return fail(TDSE_E_INVALID, "plan was created without adjoint support (adjoint_k = 0)");
     if (!E || !accel_bar || !grad_E) return fail(TDSE_E_INVALID, "E, accel_bar and grad_E are required");
     const void* ptrs[] = {E, psi0, accel_bar, grad_E, accel, sys_status};
     for (const void* q : ptrs)
@@ -906,18 +945,23 @@ tdse_status tdse_adjoint_batch(tdse_plan plan, const double* E, const double* ps
     base.abar = accel_bar;
     base.grad = grad_E;
     base.k_ckpt = plan->adjoint_k;
-    const int ng = (int)plan->groups.size();
-    if (launch_reset_counters(plan->d_counters, ng, st) != hipSuccess)
+    const int nl = (int)plan->launches.size();
+    if (launch_reset_counters(plan->d_counters, 3 * nl, st) != hipSuccess)
         return fail(TDSE_E_DEVICE, "counter reset launch failed");
-    for (int g = 0; g < ng; ++g) {
-        const auto& G = plan->groups[g];
+    for (int l = 0; l < nl; ++l) {
+        const Launch& L = plan->launches[l];
+        if (launch_compact_rows(accel_bar, plan->p.nt, L.d_order, L.count, L.d_order_adj,
+                                plan->d_counters + nl + 2 * l, st) != hipSuccess)
+            return fail(TDSE_E_DEVICE, "row compaction launch failed");
         FwdArgs a = base;
-        a.order = G.d_order;
-        a.count = G.count;
-        a.queue = plan->d_counters + g;
-        a.ckpt = plan->d_adj + plan->adj_off[g];
-        a.slot_stride_ckpt = plan->adj_slot_ckpt[g] + plan->adj_slot_seg[g];
-        if (launch_adjoint(G.C, a, G.T, plan->adj_grid[g], st) != hipSuccess)
+        a.order = L.d_order_adj;
+        a.count = L.count;
+        a.cls = L.cls;
+        a.queue = plan->d_counters + l;
+        a.sub_bytes = (int64_t)sub_smem_bytes(L.T / kWave);
+        a.work = plan->d_adj + L.work_off;
+        a.slot_doubles = L.slot_doubles;
+        if (launch_adjoint(L.C, L.alds, a, L.T, L.aS, L.agrid, st) != hipSuccess)
             return fail(TDSE_E_DEVICE, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
     return TDSE_OK;

@@ -27,12 +27,6 @@ namespace tdse {
 
 namespace {
 
-__host__ __device__ inline size_t adj_smem_bytes(int W)
-{
-    return sizeof(cd) * 2 * kMaxWaves + sizeof(double) * 2 * kMaxWaves +
-           sizeof(double) * kRing * W * 3 + 8 * sizeof(int);
-}
-
 // State record: chunk values and the two ghosts, [C+2][T] complex.
 template <int C>
 __device__ __forceinline__ void store_state(double* base, int T, int t, const cd (&v)[C], cd gl,
@@ -61,35 +55,11 @@ __device__ __forceinline__ void load_state(const double* base, int T, int t, cd 
     gr = mkc(x.x, x.y);
 }
 
-template <int C>
-__device__ __forceinline__ void observe_a(const cd (&v)[C], const SizeClass& sc, const LaneCtx& lc,
-                                          double xs, double* slot)
+__device__ __forceinline__ void flush_norm(int a0, int a1, int t, int T, const double* ring,
+                                           int W, double dx, const double* erow, double* acc_row,
+                                           double* n_row, int* flag)
 {
-    double sn = 0.0, sk = 0.0, sv = 0.0;
-    const int t = opaque(lc.t);
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const double p = cabs2(v[k]);
-        sn += p;
-        sk = fma((double)k, p, sk);
-        sv = fma(sc.pt.dv[k * sc.T + t], p, sv);
-    }
-    double sx = fma(xs, sn, sc.dx * sk);
-    sn = wave_sum(sn);
-    sx = wave_sum(sx);
-    sv = wave_sum(sv);
-    if (lc.lane == 0) {
-        slot[lc.wave * 3 + 0] = sv;
-        slot[lc.wave * 3 + 1] = sx;
-        slot[lc.wave * 3 + 2] = sn;
-    }
-}
-
-__device__ __forceinline__ void flush_fwd(int a0, int a1, const double* ring, int W, double dx,
-                                          const double* erow, double* acc_row, double* n_row,
-                                          int* flag)
-{
-    for (int smp = a0 + (int)threadIdx.x; smp <= a1; smp += blockDim.x) {
+    for (int smp = a0 + t; smp <= a1; smp += T) {
         const double* r = ring + (smp % kRing) * W * 3;
         double sv = 0.0, sn = 0.0;
         for (int w = 0; w < W; ++w) {
@@ -104,11 +74,11 @@ __device__ __forceinline__ void flush_fwd(int a0, int a1, const double* ring, in
 }
 
 // grad_i = abar_i n_i + dt * sum_w partial_w(i) for i in [a0, a1]
-__device__ __forceinline__ void flush_grad(int a0, int a1, const double* ring, int W, double dt,
-                                           const double* abar, const double* n_row, double* g_row,
-                                           int* flag)
+__device__ __forceinline__ void flush_grad(int a0, int a1, int t, int T, const double* ring,
+                                           int W, double dt, const double* abar,
+                                           const double* n_row, double* g_row, int* flag)
 {
-    for (int smp = a0 + (int)threadIdx.x; smp <= a1; smp += blockDim.x) {
+    for (int smp = a0 + t; smp <= a1; smp += T) {
         const double* r = ring + (smp % kRing) * W;
         double s = 0.0;
         for (int w = 0; w < W; ++w) s += r[w];
@@ -131,187 +101,252 @@ __device__ __forceinline__ void grad_partial(const cd (&kap)[C], const cd (&psi)
         s1 = fma((double)k, im, s1);
     }
     double g = wave_sum(fma(xs, s0, dx * s1));
-    if (lc.lane == 0) slot[lc.wave] = g;
+    if (lc.lane == kSumLane) slot[lc.wave] = g;
+}
+
+// kappa += c_j conj(psi_j) with c_j = ci (V'_j + e), on the chunk and ghosts.
+template <int C, class TV>
+__device__ __forceinline__ void add_source(cd (&kap)[C], cd& kgl, cd& kgr, const cd (&psi)[C],
+                                           cd gl, cd gr, double ci, double e, const TV& tb,
+                                           int T, const LaneCtx& lc)
+{
+    const int b0 = opaque(pbase(lc.t, C));
+#pragma unroll
+    for (int k = 0; k < C; ++k) kap[k] = cadd(kap[k], cscale(ci * (tb.dv(b0 + 64 * k) + e), cconj(psi[k])));
+    kgl = cadd(kgl, cscale(ci * (lc.dvl() + e), cconj(gl)));
+    kgr = cadd(kgr, cscale(ci * (lc.dvr() + e), cconj(gr)));
 }
 
 }  // namespace
 
-template <int C>
-__global__ void __launch_bounds__(256) adjoint_kernel(FwdArgs a)
+template <int C, bool LDSTAB>
+__global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
 {
     extern __shared__ double smem_raw[];
-    const int tid = threadIdx.x;
-    const int W = blockDim.x / kWave;
-    cd* lds_f = reinterpret_cast<cd*>(smem_raw);
-    cd* lds_b = lds_f + kMaxWaves;
-    double* ring = reinterpret_cast<double*>(lds_b + kMaxWaves) + 2 * kMaxWaves;
-    int* misc = reinterpret_cast<int*>(ring + kRing * W * 3);
-
+    const SizeClass sc = uniform_load(a.classes + a.cls);
+    const int T = sc.T, W = T / kWave, np = C * T;
+    const int S = blockDim.x / T;
+    const int tid = threadIdx.x, sub = tid / T, t = tid - sub * T;
+    const size_t sb = a.sub_bytes;
+    char* per = reinterpret_cast<char*>(smem_raw + (LDSTAB ? 4 * np : 0));
+    const SubSmem sm = carve_sub(per + sub * sb, W);
+    int* wg_item = reinterpret_cast<int*>(per + S * sb);
+    TableSource<LDSTAB>::make(sc, smem_raw);  // stages the tables once per workgroup
+    const double dx = sc.dx;
+    const int n = sc.n, s = t * C;
+    const SizeClass* const clsp = a.classes + a.cls;
     const int nt = a.nt, K = a.k_ckpt;
     const int nseg = nt / K + 1;
-    double* slot_base = a.ckpt + (size_t)blockIdx.x * (size_t)a.slot_stride_ckpt;
+    const size_t np2 = 2 * (size_t)(C + 2) * T;  // doubles per state record
+    double* ckpt = a.work + ((size_t)blockIdx.x * S + sub) * (size_t)a.slot_doubles;
+    double* seg = ckpt + np2 * nseg;
+    double* n_row = seg + np2 * (K + 1);
+    double* ring = sm.ring;
+    int* flag = sm.misc + 1;
 
     for (;;) {
         if (tid == 0) {
-            misc[0] = atomicAdd(a.queue, 1);
-            misc[1] = 0;
-            misc[2] = 0;
+            wg_item[0] = atomicAdd(a.queue, S);
+            wg_item[1] = 0;
+        }
+        if (t == 0) {
+            sm.misc[1] = 0;
+            sm.misc[2] = 0;
         }
         __syncthreads();
-        const int item = uniform(misc[0]);
-        if (item >= a.count) break;
-        const int p = uniform(a.order[item]);
+        const int base = uniform(wg_item[0]);
+        if (base >= a.count) break;
+        const int item = base + sub;
+        const bool active = item < a.count;  // uniform within the subgroup
+        const int p = active ? uniform(a.order[item]) : 0;
         const SysDesc d = uniform_load(a.sys + p);
-        const SizeClass sc = uniform_load(a.classes + d.cls);
-        const int T = sc.T;
-        const size_t np2 = 2 * (size_t)(C + 2) * T;  // doubles per state record
-        double* ckpt = slot_base;
-        double* seg = ckpt + np2 * nseg;
-        double* n_row = seg + np2 * (K + 1);
         const size_t row = (size_t)p * (size_t)(nt + 1);
         const double* erow = a.E + row;
         const double* abar = a.abar + row;
         double* g_row = a.grad + row;
-        double* acc_row = a.accel ? a.accel + row : nullptr;
+        double* acc_row = (active && a.accel) ? a.accel + row : nullptr;
+        const double* src = a.psi0 ? a.psi0 + 2 * d.psi_off : a.gs + 2 * a.gs_off[a.cls];
 
-        // rows with an all-zero abar have a zero gradient
-        for (int i = tid; i <= nt; i += blockDim.x)
-            if (abar[i] != 0.0) misc[2] = 1;
+        // rows with an all-zero abar have a zero gradient and need no reverse sweep
+        if (active)
+            for (int i = t; i <= nt; i += T)
+                if (abar[i] != 0.0) {
+                    sm.misc[2] = 1;
+                    wg_item[1] = 1;
+                }
         __syncthreads();
-        if (misc[2] == 0 && acc_row == nullptr) {
-            for (int i = tid; i <= nt; i += blockDim.x) g_row[i] = 0.0;
-            if (tid == 0 && a.status) a.status[p] = 0;
-            __syncthreads();
-            continue;
-        }
-        const bool need_grad = misc[2] != 0;
-
-        const LaneCtx lc = make_lane_ctx(sc, tid);
-        const RhsCoef rc = make_rhs_coef(0.5 * a.dt, sc.dx);
-        const double dx = sc.dx;
-        const int n = sc.n, s = lc.s;
-        const double xs = ((double)s - 0.5 * (double)(n - 1)) * dx;
-        const double xl = ((double)(s - 1) - 0.5 * (double)(n - 1)) * dx;
-        const double* src = a.psi0 ? a.psi0 + 2 * d.psi_off : a.gs + 2 * a.gs_off[d.cls];
+        const bool need_grad = uniform(sm.misc[2]) != 0;
+        const bool wg_need = uniform(wg_item[1]) != 0;  // uniform over the workgroup
 
         // ---------------- forward pass: outputs, norms, checkpoints
         cd v[C];
 #pragma unroll
-        for (int k = 0; k < C; ++k) v[k] = (s + k < n) ? ld_psi(src, s + k) : czero();
-        cd gl = (s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
-        cd gr = (s + C < n) ? ld_psi(src, s + C) : czero();
+        for (int k = 0; k < C; ++k) v[k] = (active && s + k < n) ? ld_psi(src, s + k) : czero();
+        cd gl = (active && s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
+        cd gr = (active && s + C < n) ? ld_psi(src, s + C) : czero();
         int flushed = 0;
-        for (int i = 0; i <= nt; ++i) {
-            if (i % K == 0) store_state<C>(ckpt + np2 * (i / K), T, tid, v, gl, gr);
-            observe_a<C>(v, sc, lc, xs, ring + (i % kRing) * W * 3);
+        const int nfwd = (wg_need || a.accel) ? nt : -1;  // uniform
+        for (int i = 0; i <= nfwd; ++i) {
+            const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
+            if (i % K == 0) store_state<C>(ckpt + np2 * (i / K), T, t, v, gl, gr);
+            observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, ring + (i % kRing) * W * 3);
             if (i == nt) break;
-            forward_step<C>(v, gl, gr, erow[i], a.dt, xl, sc, lc, rc, lds_f, lds_b);
+            forward_step<C>(v, gl, gr, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f,
+                            sm.lds_b);
             if ((i + 1) % kFlush == 0) {
                 __syncthreads();
-                flush_fwd(i + 1 - kFlush, i, ring, W, dx, erow, acc_row, n_row, misc + 1);
+                if (active) flush_norm(i + 1 - kFlush, i, t, T, ring, W, dx, erow, acc_row, n_row, flag);
                 flushed = i + 1;
             }
         }
         __syncthreads();
-        flush_fwd(flushed, nt, ring, W, dx, erow, acc_row, n_row, misc + 1);
+        if (active && nfwd >= 0) flush_norm(flushed, nt, t, T, ring, W, dx, erow, acc_row, n_row, flag);
         __syncthreads();
 
-        if (!need_grad) {
-            for (int i = tid; i <= nt; i += blockDim.x) g_row[i] = 0.0;
-        } else {
-            // ---------------- backward pass
-            if (tid == 0) g_row[nt] = abar[nt] * n_row[nt];
-            cd kap[C], kgl = czero(), kgr = czero();
-            bool started = false;
-            for (int sidx = nseg - 1; sidx >= 0; --sidx) {
-                const int s0 = sidx * K;
-                const int s1 = min(s0 + K, nt);
-                // recompute psi^{s0..s1} into the segment buffer
-                load_state<C>(ckpt + np2 * sidx, T, tid, v, gl, gr);
-                store_state<C>(seg, T, tid, v, gl, gr);
-                for (int i = s0; i < s1; ++i) {
-                    forward_step<C>(v, gl, gr, erow[i], a.dt, xl, sc, lc, rc, lds_f, lds_b);
-                    store_state<C>(seg + np2 * (i - s0 + 1), T, tid, v, gl, gr);
-                }
-                if (!started) {
-                    // kappa^nt = 2 abar_nt dx (V' + E_nt) conj(psi^nt); psi^nt = v
-                    const double cn = 2.0 * abar[nt] * dx;
-                    const double en = erow[nt];
+        // ---------------- reverse sweep (every subgroup runs it, so barriers
+        // stay uniform; subgroups without a gradient write nothing)
+        if (active && need_grad && t == 0) g_row[nt] = abar[nt] * n_row[nt];
+        cd kap[C];
 #pragma unroll
-                    for (int k = 0; k < C; ++k)
-                        kap[k] = cscale(cn * (sc.pt.dv[k * T + tid] + en), cconj(v[k]));
-                    kgl = cscale(cn * (lc.dvl + en), cconj(gl));
-                    kgr = cscale(cn * (lc.dvr + en), cconj(gr));
-                    if (nt > 0) grad_partial<C>(kap, v, xs, dx, lc, ring + ((nt - 1) % kRing) * W);
-                    started = true;
-                    if (nt > 0 && (nt - 1) % kFlush == 0) {
+        for (int k = 0; k < C; ++k) kap[k] = czero();
+        cd kgl = czero(), kgr = czero();
+        bool started = false;
+        for (int sidx = wg_need ? nseg - 1 : -1; sidx >= 0; --sidx) {
+            const int s0 = sidx * K;
+            const int s1 = min(s0 + K, nt);
+            // recompute psi^{s0..s1} into the segment buffer
+            load_state<C>(ckpt + np2 * sidx, T, t, v, gl, gr);
+            store_state<C>(seg, T, t, v, gl, gr);
+            for (int i = s0; i < s1; ++i) {
+                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
+                forward_step<C>(v, gl, gr, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
+                                sm.lds_f, sm.lds_b);
+                store_state<C>(seg + np2 * (i - s0 + 1), T, t, v, gl, gr);
+            }
+            if (!started) {
+                // kappa^nt = 2 abar_nt dx (V' + E_nt) conj(psi^nt); psi^nt = v
+                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
+                add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[nt] * dx, erow[nt], sv.tb, T,
+                              sv.lc);
+                if (nt > 0) grad_partial<C>(kap, v, sv.xs, dx, sv.lc, ring + ((nt - 1) % kRing) * W);
+                started = true;
+                if (nt > 0 && (nt - 1) % kFlush == 0) {
+                    __syncthreads();
+                    if (active && need_grad)
+                        flush_grad(nt - 1, nt - 1, t, T, ring, W, a.dt, abar, n_row, g_row, flag);
+                }
+            }
+            for (int i = s1 - 1; i >= s0; --i) {
+                // kappa <- U (D_i kappa)
+                const double e = erow[i];
+                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
+                phase_mask<C>(kap, kgl, kgr, e, a.dt, sv.xl, dx, sv.sc, sv.lc);
+                cd cf, cb;
+                cn_apply<C, true>(kap, kgl, kgr, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b, cf,
+                                  cb);
+                kgl = cmad(sv.lc.ql(), cf, cmul(sv.lc.bl(), kap[0]));
+                kgr = cb;
+                // + 2 abar_i dx (V' + E_i) conj(psi^i)
+                load_state<C>(seg + np2 * (i - s0), T, t, v, gl, gr);
+                add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[i] * dx, e, sv.tb, T, sv.lc);
+                if (i > 0) {
+                    // partial of grad_{i-1} from kappa^i and psi^i
+                    grad_partial<C>(kap, v, sv.xs, dx, sv.lc, ring + ((i - 1) % kRing) * W);
+                    if ((i - 1) % kFlush == 0) {
                         __syncthreads();
-                        flush_grad(nt - 1, nt - 1, ring, W, a.dt, abar, n_row, g_row, misc + 1);
-                    }
-                }
-                for (int i = s1 - 1; i >= s0; --i) {
-                    // kappa <- U (D_i kappa)
-                    const double e = erow[i];
-                    phase_mask<C>(kap, kgl, kgr, e, a.dt, xl, dx, sc, lc);
-                    cd cf, cb;
-                    cn_apply<C, true>(kap, kgl, kgr, sc, lc, rc, lds_f, lds_b, cf, cb);
-                    kgl = cmad(lc.ql, cf, cmul(lc.bl, kap[0]));
-                    kgr = cb;
-                    // + 2 abar_i dx (V' + E_i) conj(psi^i)
-                    load_state<C>(seg + np2 * (i - s0), T, tid, v, gl, gr);
-                    const double ci = 2.0 * abar[i] * dx;
-                    const int to = opaque(tid);
-#pragma unroll
-                    for (int k = 0; k < C; ++k)
-                        kap[k] = cadd(kap[k], cscale(ci * (sc.pt.dv[k * T + to] + e), cconj(v[k])));
-                    kgl = cadd(kgl, cscale(ci * (lc.dvl + e), cconj(gl)));
-                    kgr = cadd(kgr, cscale(ci * (lc.dvr + e), cconj(gr)));
-                    if (i > 0) {
-                        // partial of grad_{i-1} from kappa^i and psi^i
-                        grad_partial<C>(kap, v, xs, dx, lc, ring + ((i - 1) % kRing) * W);
-                        if ((i - 1) % kFlush == 0) {
-                            __syncthreads();
-                            flush_grad(i - 1, min(i - 1 + kFlush - 1, nt - 1), ring, W, a.dt, abar,
-                                       n_row, g_row, misc + 1);
-                        }
+                        if (active && need_grad)
+                            flush_grad(i - 1, min(i - 1 + kFlush - 1, nt - 1), t, T, ring, W, a.dt,
+                                       abar, n_row, g_row, flag);
                     }
                 }
             }
         }
+        if (active && !need_grad)
+            for (int i = t; i <= nt; i += T) g_row[i] = 0.0;
         __syncthreads();
-        if (tid == 0 && a.status) a.status[p] = misc[1];
+        if (active && t == 0 && a.status) a.status[p] = sm.misc[1];
     }
 }
 
-template <int C>
-static int occ_adj(int T)
+size_t adjoint_smem_bytes(int C, int T, int S, bool lds_tables)
+{
+    return (lds_tables ? sizeof(double) * 4 * (size_t)C * T : 0) + S * sub_smem_bytes(T / kWave) +
+           16;
+}
+
+template <int C, bool L>
+static int occ_adj(int threads, size_t sh)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, adjoint_kernel<C>, T,
-                                                     adj_smem_bytes(T / kWave)) != hipSuccess)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(adjoint_kernel<C, L>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, adjoint_kernel<C, L>, threads, sh) !=
+        hipSuccess)
         return 0;
     return nb;
 }
 
-int adjoint_occupancy(int C, int T)
+int adjoint_occupancy(int C, int T, int S, bool lds_tables)
 {
-    switch (C) {
-        case 4: return occ_adj<4>(T);
-        case 8: return occ_adj<8>(T);
-        case 16: return occ_adj<16>(T);
+    const size_t sh = adjoint_smem_bytes(C, T, S, lds_tables);
+    if (sh > (size_t)kMaxLds) return 0;
+    const int th = S * T;
+    switch (C * 2 + (lds_tables ? 1 : 0)) {
+        case 8: return occ_adj<4, false>(th, sh);
+        case 9: return occ_adj<4, true>(th, sh);
+        case 16: return occ_adj<8, false>(th, sh);
+        case 17: return occ_adj<8, true>(th, sh);
+        case 32: return occ_adj<16, false>(th, sh);
+        case 33: return occ_adj<16, true>(th, sh);
         default: return 0;
     }
 }
 
-hipError_t launch_adjoint(int C, const FwdArgs& a, int T, int grid, hipStream_t st)
+hipError_t launch_adjoint(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
+                          hipStream_t st)
 {
-    const size_t sh = adj_smem_bytes(T / kWave);
-    switch (C) {
-        case 4: hipLaunchKernelGGL(adjoint_kernel<4>, dim3(grid), dim3(T), sh, st, a); break;
-        case 8: hipLaunchKernelGGL(adjoint_kernel<8>, dim3(grid), dim3(T), sh, st, a); break;
-        case 16: hipLaunchKernelGGL(adjoint_kernel<16>, dim3(grid), dim3(T), sh, st, a); break;
+    const size_t sh = adjoint_smem_bytes(C, T, S, lds_tables);
+    const dim3 b(T * S);
+    switch (C * 2 + (lds_tables ? 1 : 0)) {
+        case 8: hipLaunchKernelGGL((adjoint_kernel<4, false>), dim3(grid), b, sh, st, a); break;
+        case 9: hipLaunchKernelGGL((adjoint_kernel<4, true>), dim3(grid), b, sh, st, a); break;
+        case 16: hipLaunchKernelGGL((adjoint_kernel<8, false>), dim3(grid), b, sh, st, a); break;
+        case 17: hipLaunchKernelGGL((adjoint_kernel<8, true>), dim3(grid), b, sh, st, a); break;
+        case 32: hipLaunchKernelGGL((adjoint_kernel<16, false>), dim3(grid), b, sh, st, a); break;
+        case 33: hipLaunchKernelGGL((adjoint_kernel<16, true>), dim3(grid), b, sh, st, a); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// Reorders the systems of one launch so that rows with a non-zero abar come
+// first and all-zero rows last (one workgroup per row); a workgroup of the
+// adjoint kernel whose systems all have zero rows then skips the reverse
+// sweep.  The order within each part depends on scheduling, the per-row
+// results do not.
+__global__ void __launch_bounds__(256) compact_rows_kernel(const double* abar, int nt,
+                                                           const int32_t* order_in, int count,
+                                                           int32_t* order_out, int32_t* counters)
+{
+    __shared__ int nz;
+    if (threadIdx.x == 0) nz = 0;
+    __syncthreads();
+    const int p = order_in[blockIdx.x];
+    const double* row = abar + (size_t)p * (size_t)(nt + 1);
+    for (int i = threadIdx.x; i <= nt; i += blockDim.x)
+        if (row[i] != 0.0) nz = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (nz) order_out[atomicAdd(counters, 1)] = p;
+        else order_out[count - 1 - atomicAdd(counters + 1, 1)] = p;
+    }
+}
+
+hipError_t launch_compact_rows(const double* abar, int nt, const int32_t* order_in, int count,
+                               int32_t* order_out, int32_t* counters, hipStream_t st)
+{
+    hipLaunchKernelGGL(compact_rows_kernel, dim3(count), dim3(256), 0, st, abar, nt, order_in,
+                       count, order_out, counters);
     return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 // tdse_device.hpp -- device-side building blocks shared by the gfx950 kernels:
-// complex fp64 arithmetic, wavefront shuffles and reductions, the cross-lane
-// carry scans of the partitioned tridiagonal solve, and the Crank-Nicolson
-// core that every kernel (forward, ground state, adjoint) runs per time step.
+// complex fp64 arithmetic, wavefront shuffles and reductions, a reduced-range
+// sincos, the cross-lane carry scans of the partitioned tridiagonal solve,
+// and the Crank-Nicolson core that every kernel (forward, ground state,
+// adjoint) runs once per time step.
 #pragma once
 #include "tdse_internal.hpp"
 
@@ -34,23 +35,66 @@ __device__ __forceinline__ cd cinv(cd a)
     double s = 1.0 / fma(a.re, a.re, a.im * a.im);
     return mkc(a.re * s, -a.im * s);
 }
+__device__ __forceinline__ cd ld_psi(const double* p, int64_t j) { return mkc(p[2 * j], p[2 * j + 1]); }
 
-__device__ __forceinline__ cd ld(const cd* p) { return *p; }
+// -(1 + h' w) q with h' = i (real time) or 1 (imaginary time): the
+// elimination factors alpha, beta of the tridiagonal solve.
+template <bool RT>
+__device__ __forceinline__ cd elim(double w, cd q)
+{
+    if (RT) return mkc(fma(w, q.im, -q.re), fma(-w, q.re, -q.im));
+    const double f = -(1.0 + w);
+    return mkc(f * q.re, f * q.im);
+}
+
+// Load through the global address space.  Pointers that come out of
+// structures are generic to the compiler, which would emit FLAT loads; those
+// count against the LDS wait counter as well, so every LDS wait in the time
+// loop would also wait for the L2.  (No volatile here: on gfx950 a volatile
+// load is issued at system scope and bypasses the caches.)
+__device__ __forceinline__ double ldg(const double* p)
+{
+    typedef const __attribute__((address_space(1))) double* gptr;
+    return *(gptr)(p);
+}
+__device__ __forceinline__ int ldg(const int* p)
+{
+    typedef const __attribute__((address_space(1))) int* gptr;
+    return *(gptr)(p);
+}
+__device__ __forceinline__ cd ldg(const cd* p)
+{
+    typedef double dvec2 __attribute__((ext_vector_type(2)));
+    typedef const __attribute__((address_space(1))) dvec2* gptr;
+    const dvec2 v = *(gptr)(p);
+    return mkc(v.x, v.y);
+}
 
 // Returns x unchanged but hides its value from the optimiser.  Table indices
-// are passed through it once per time step so that the loop-invariant table
-// loads stay inside the time loop (streamed from cache) instead of being
-// hoisted into hundreds of registers and spilled.
+// pass through it once per time step so that loop-invariant table loads stay
+// inside the time loop instead of being hoisted into registers and spilled.
 __device__ __forceinline__ int opaque(int x)
 {
     asm volatile("" : "+v"(x));
     return x;
 }
-__device__ __forceinline__ cd ld_psi(const double* p, int64_t j) { return mkc(p[2 * j], p[2 * j + 1]); }
 
-// Loads a workgroup-uniform record and moves it into scalar registers.  Work
-// items arrive through LDS, so the compiler cannot prove the record uniform
-// on its own; without this every table pointer would occupy vector registers.
+// Hides a wave-uniform pointer from the optimiser (kept in SGPRs).
+template <class T>
+__device__ __forceinline__ T* launder_s(T* p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Keeps the scheduler from hoisting the independent work of later grid
+// points of an unrolled chunk loop above the current one: with four waves
+// per SIMD latency is hidden across waves, and hoisting would only raise
+// register pressure (and force spills).
+#define TDSE_POINT_FENCE() __builtin_amdgcn_sched_barrier(0)
+
+// Loads a wave-uniform record into scalar registers.  Work items arrive
+// through LDS, so the compiler cannot prove the record uniform on its own.
 template <class T>
 __device__ __forceinline__ T uniform_load(const T* p)
 {
@@ -64,7 +108,101 @@ __device__ __forceinline__ T uniform_load(const T* p)
 }
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// A double constant materialised by two scalar moves where it is used.  FP64
+// literals do not fit in a VALU instruction, so the compiler otherwise keeps
+// every constant of the time loop in registers across the whole loop.
+template <unsigned long long B>
+__device__ __forceinline__ double kconst()
+{
+    int lo, hi;
+    asm volatile("s_mov_b32 %0, %2\n\ts_mov_b32 %1, %3"
+                 : "=s"(lo), "=s"(hi)
+                 : "i"((int)(unsigned)(B & 0xffffffffull)), "i"((int)(unsigned)(B >> 32)));
+    return __hiloint2double(hi, lo);
+}
+#define TDSE_K(x) ::tdse::kconst<__builtin_bit_cast(unsigned long long, (double)(x))>()
+
+// ------------------------------------------------------------ sincos
+// sin and cos of x by Cody-Waite reduction to |r| <= pi/4 (x = k pi/2 + r,
+// pi/2 split into a 32-bit head and two tails so k*head is exact for
+// |k| < 2^20) and the Taylor series of sin r and cos r through r^17 and r^16
+// (truncation below 4e-18 on |r| <= pi/4), evaluated by Horner in r^2.
+__device__ __forceinline__ void sincos_rr(double x, double* s, double* c)
+{
+    const double two_over_pi = TDSE_K(0.63661977236758134308);
+    const double p1 = TDSE_K(1.5707963267341256);      // pi/2 rounded to 32 significant bits
+    const double p2 = TDSE_K(6.077100506506192e-11);   // pi/2 - p1 rounded to double
+    const double p3 = TDSE_K(3.5215598651832e-27);     // pi/2 - p1 - p2
+    const double k = rint(x * two_over_pi);
+    double r = fma(-k, p1, x);
+    r = fma(-k, p2, r);
+    r = fma(-k, p3, r);
+    const double r2 = r * r;
+    // sin r = r (1 - r^2/3! + r^4/5! - ... + r^16/17!)
+    double ps = TDSE_K(2.8114572543455207632e-15);                       // 1/17!
+    ps = fma(ps, r2, TDSE_K(-7.6471637318198164759e-13));                 // -1/15!
+    ps = fma(ps, r2, TDSE_K(1.6059043836821614599e-10));                  // 1/13!
+    ps = fma(ps, r2, TDSE_K(-2.5052108385441718775e-08));                 // -1/11!
+    ps = fma(ps, r2, TDSE_K(2.7557319223985890653e-06));                  // 1/9!
+    ps = fma(ps, r2, TDSE_K(-1.9841269841269841270e-04));                 // -1/7!
+    ps = fma(ps, r2, TDSE_K(8.3333333333333333333e-03));                  // 1/5!
+    ps = fma(ps, r2, TDSE_K(-1.6666666666666666667e-01));                 // -1/3!
+    const double sr = fma(ps * r2, r, r);
+    // cos r = 1 - r^2/2! + r^4/4! - ... + r^16/16!
+    double pc = TDSE_K(4.7794773323873852974e-14);                       // 1/16!
+    pc = fma(pc, r2, TDSE_K(-1.1470745597729724714e-11));                 // -1/14!
+    pc = fma(pc, r2, TDSE_K(2.0876756987868098979e-09));                  // 1/12!
+    pc = fma(pc, r2, TDSE_K(-2.7557319223985890653e-07));                 // -1/10!
+    pc = fma(pc, r2, TDSE_K(2.4801587301587301587e-05));                  // 1/8!
+    pc = fma(pc, r2, TDSE_K(-1.3888888888888888889e-03));                 // -1/6!
+    pc = fma(pc, r2, TDSE_K(4.1666666666666666667e-02));                  // 1/4!
+    pc = fma(pc, r2, -0.5);                                       // -1/2!
+    const double cr = fma(pc, r2, 1.0);
+    const int q = ((int)k) & 3;
+    const double ss = (q & 1) ? cr : sr;
+    const double cc = (q & 1) ? sr : cr;
+    *s = (q & 2) ? -ss : ss;
+    *c = ((q + 1) & 2) ? -cc : cc;
+}
+
+// sin and cos of the per-point phase increment dt E dx, which is tiny
+// (|x| < 0.05 always holds for sensible grids): Taylor series through x^9 and
+// x^10 (truncation below 1e-19); larger arguments take the general path.
+// The branch is uniform across the wavefront.
+__device__ __forceinline__ void sincos_step(double x, double* s, double* c)
+{
+    if (fabs(x) > 0.05) {
+        sincos_rr(x, s, c);
+        return;
+    }
+    const double x2 = x * x;
+    double ps = fma(x2, TDSE_K(2.7557319223985890653e-06), TDSE_K(-1.9841269841269841270e-04));   // 1/9!, -1/7!
+    ps = fma(ps, x2, TDSE_K(8.3333333333333333333e-03));                                   // 1/5!
+    ps = fma(ps, x2, TDSE_K(-1.6666666666666666667e-01));                                  // -1/3!
+    *s = fma(ps * x2, x, x);
+    double pc = fma(x2, TDSE_K(-2.7557319223985890653e-07), TDSE_K(2.4801587301587301587e-05));    // -1/10!, 1/8!
+    pc = fma(pc, x2, TDSE_K(-1.3888888888888888889e-03));                                  // -1/6!
+    pc = fma(pc, x2, TDSE_K(4.1666666666666666667e-02));                                   // 1/4!
+    pc = fma(pc, x2, -0.5);                                                        // -1/2!
+    *c = fma(pc, x2, 1.0);
+}
+
 // ------------------------------------------------------------ wavefront ops
+// DPP moves of the two halves of a double; lanes without a source (or in a
+// masked row) read 0.  Controls: row_shr:n = 0x110+n, wave_shl:1 = 0x130,
+// wave_shr:1 = 0x138, row_bcast:15 = 0x142, row_bcast:31 = 0x143.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+// lane i receives lane i-1 (lane 0 receives 0)
+__device__ __forceinline__ cd wave_shr1(cd a) { return mkc(dpp_d<0x138>(a.re), dpp_d<0x138>(a.im)); }
+// lane i receives lane i+1 (lane 63 receives 0)
+__device__ __forceinline__ cd wave_shl1(cd a) { return mkc(dpp_d<0x130>(a.re), dpp_d<0x130>(a.im)); }
+
 __device__ __forceinline__ cd shfl_up_c(cd a, int d)
 {
     return mkc(__shfl_up(a.re, d), __shfl_up(a.im, d));
@@ -73,58 +211,70 @@ __device__ __forceinline__ cd shfl_down_c(cd a, int d)
 {
     return mkc(__shfl_down(a.re, d), __shfl_down(a.im, d));
 }
-// Butterfly sum over the 64 lanes.  Every lane ends with a sum; lane 0's
-// association order is fixed, and only lane 0's value is ever stored, so
-// results are bitwise reproducible.
-__device__ __forceinline__ double wave_sum(double v)
+// Sum over the 64 lanes by DPP: inclusive scans within rows of 16
+// (row_shr 1, 2, 4, 8), then the row totals are folded in with row
+// broadcasts.  The total is valid in lane 63 only; the association order is
+// fixed, so results are bitwise reproducible.
+__device__ __forceinline__ double wave_sum(double x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    x += dpp_d<0x111>(x);
+    x += dpp_d<0x112>(x);
+    x += dpp_d<0x114>(x);
+    x += dpp_d<0x118>(x);
+    x += dpp_d<0x142, 0xa>(x);
+    x += dpp_d<0x143, 0xc>(x);
+    return x;
 }
+constexpr int kSumLane = kWave - 1;  // lane holding wave_sum's result
 
-// Workgroup sum in fixed order (waves 0..W-1).  `slots` holds kMaxWaves
-// doubles of LDS; the caller alternates slot arrays between consecutive
-// reductions so one barrier per reduction suffices.
-__device__ __forceinline__ double block_sum(double v, double* slots, int lane, int wave, int W)
-{
-    v = wave_sum(v);
-    if (lane == 0) slots[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int w = 0; w < W; ++w) s += slots[w];
-    return s;
-}
+// ------------------------------------------------------------ table views
+// Point tables seen through LDS (shared by every system of a workgroup) or
+// directly in global memory (grids too large for LDS).
+template <bool GLOBAL>
+struct TabViewT {
+    const double* om_;
+    const cd* q_;
+    const double* dv_;
+    __device__ __forceinline__ double om(int i) const { return GLOBAL ? ldg(om_ + i) : om_[i]; }
+    __device__ __forceinline__ cd q(int i) const { return GLOBAL ? ldg(q_ + i) : q_[i]; }
+    __device__ __forceinline__ double dv(int i) const { return GLOBAL ? ldg(dv_ + i) : dv_[i]; }
+};
+using TabLds = TabViewT<false>;
+using TabGlobal = TabViewT<true>;
 
 // ------------------------------------------------------------ lane context
+// Lane coordinates plus accessors for the per-lane constants of a size
+// class.  The constants are read where they are used (L1-resident, a few
+// loads per step) rather than pinned in registers for the whole time loop.
 struct LaneCtx {
     int lane;   // lane in wavefront
-    int wave;   // wavefront in workgroup
+    int wave;   // wavefront within the system's subgroup
     int W;      // wavefronts per system
     int t;      // lane index within the system (0..T-1)
     int s;      // first grid point of the lane's chunk
-    double vl, vr, ml, mr, dvl, dvr;
-    cd ql, bl;
+    const LaneConst* kk;
     int hasmask;
+    __device__ __forceinline__ const LaneConst* K() const { return kk + opaque(t); }
+    __device__ __forceinline__ double oml() const { return ldg(&K()->oml); }
+    __device__ __forceinline__ double omr() const { return ldg(&K()->omr); }
+    __device__ __forceinline__ double ml() const { return ldg(&K()->ml); }
+    __device__ __forceinline__ double mr() const { return ldg(&K()->mr); }
+    __device__ __forceinline__ double dvl() const { return ldg(&K()->dvl); }
+    __device__ __forceinline__ double dvr() const { return ldg(&K()->dvr); }
+    __device__ __forceinline__ cd ql() const { return ldg(&K()->ql); }
+    __device__ __forceinline__ cd bl() const { return ldg(&K()->bl); }
 };
 
-__device__ __forceinline__ LaneCtx make_lane_ctx(const SizeClass& sc, int tid)
+__device__ __forceinline__ LaneCtx make_lane_ctx(const SizeClass& sc, int t)
 {
     LaneCtx c;
-    c.lane = tid & (kWave - 1);
-    c.wave = tid / kWave;
+    c.lane = t & (kWave - 1);
+    c.wave = t / kWave;
     c.W = sc.T / kWave;
-    c.t = tid;
-    c.s = tid * sc.C;
-    c.vl = sc.lt.vl[tid];
-    c.vr = sc.lt.vr[tid];
-    c.ml = sc.lt.ml[tid];
-    c.mr = sc.lt.mr[tid];
-    c.dvl = sc.lt.dvl[tid];
-    c.dvr = sc.lt.dvr[tid];
-    c.ql = sc.lt.ql[tid];
-    c.bl = sc.lt.bl[tid];
-    c.hasmask = sc.lt.hasmask[tid];
+    c.t = t;
+    c.s = t * sc.C;
+    c.kk = sc.lt.k;
+    c.hasmask = sc.lt.hasmask[t];
     return c;
 }
 
@@ -137,13 +287,17 @@ __device__ __forceinline__ LaneCtx make_lane_ctx(const SizeClass& sc, int tid)
 // only when the host has verified that their products are below 2^-56.
 __device__ __forceinline__ cd scan_fwd(cd z, const SizeClass& sc, const LaneCtx& lc, cd* lds)
 {
-    const int T = sc.T;
+    const int T = sc.T, t = opaque(lc.t);
+    // levels 0 and 1 shift by whole-wave DPP moves (lanes below the shift
+    // receive 0, which leaves them unchanged); deeper levels use bpermute
+    if (sc.levels > 0) z = cmad(ldg(sc.lt.pa + t), wave_shr1(z), z);
+    if (sc.levels > 1) z = cmad(ldg(sc.lt.pa + T + t), wave_shr1(wave_shr1(z)), z);
 #pragma unroll
-    for (int lev = 0; lev < kMaxLevels; ++lev) {
+    for (int lev = 2; lev < kMaxLevels; ++lev) {
         if (lev < sc.levels) {
             const int d = 1 << lev;
             cd zs = shfl_up_c(z, d);
-            if (lc.lane >= d) z = cmad(ld(sc.lt.pa + lev * T + lc.t), zs, z);
+            if (lc.lane >= d) z = cmad(ldg(sc.lt.pa + lev * T + t), zs, z);
         }
     }
     cd prev = czero();
@@ -151,10 +305,10 @@ __device__ __forceinline__ cd scan_fwd(cd z, const SizeClass& sc, const LaneCtx&
         if (lc.lane == kWave - 1) lds[lc.wave] = z;
         __syncthreads();
         const int v0 = max(0, lc.wave - sc.xwaves);
-        for (int w = v0; w < lc.wave; ++w) prev = cmad(ld(sc.lt.pw + w * kWave + kWave - 1), prev, lds[w]);
-        if (lc.lane < (1 << sc.levels)) z = cmad(ld(sc.lt.pw + lc.t), prev, z);
+        for (int w = v0; w < lc.wave; ++w) prev = cmad(ldg(sc.lt.pw + w * kWave + kWave - 1), prev, lds[w]);
+        if (lc.lane < (1 << sc.levels)) z = cmad(ldg(sc.lt.pw + t), prev, z);
     }
-    cd up = shfl_up_c(z, 1);
+    const cd up = wave_shr1(z);
     return lc.lane == 0 ? prev : up;
 }
 
@@ -162,13 +316,15 @@ __device__ __forceinline__ cd scan_fwd(cd z, const SizeClass& sc, const LaneCtx&
 // at the point just after the lane's chunk.
 __device__ __forceinline__ cd scan_bwd(cd y, const SizeClass& sc, const LaneCtx& lc, cd* lds)
 {
-    const int T = sc.T;
+    const int T = sc.T, t = opaque(lc.t);
+    if (sc.levels > 0) y = cmad(ldg(sc.lt.qb + t), wave_shl1(y), y);
+    if (sc.levels > 1) y = cmad(ldg(sc.lt.qb + T + t), wave_shl1(wave_shl1(y)), y);
 #pragma unroll
-    for (int lev = 0; lev < kMaxLevels; ++lev) {
+    for (int lev = 2; lev < kMaxLevels; ++lev) {
         if (lev < sc.levels) {
             const int d = 1 << lev;
             cd ys = shfl_down_c(y, d);
-            if (lc.lane + d < kWave) y = cmad(ld(sc.lt.qb + lev * T + lc.t), ys, y);
+            if (lc.lane + d < kWave) y = cmad(ldg(sc.lt.qb + lev * T + t), ys, y);
         }
     }
     cd next = czero();
@@ -176,108 +332,135 @@ __device__ __forceinline__ cd scan_bwd(cd y, const SizeClass& sc, const LaneCtx&
         if (lc.lane == 0) lds[lc.wave] = y;
         __syncthreads();
         const int v1 = min(lc.W - 1, lc.wave + sc.xwaves);
-        for (int w = v1; w > lc.wave; --w) next = cmad(ld(sc.lt.qw + w * kWave), next, lds[w]);
-        if (lc.lane > kWave - 1 - (1 << sc.levels)) y = cmad(ld(sc.lt.qw + lc.t), next, y);
+        for (int w = v1; w > lc.wave; --w) next = cmad(ldg(sc.lt.qw + w * kWave), next, lds[w]);
+        if (lc.lane > kWave - 1 - (1 << sc.levels)) y = cmad(ldg(sc.lt.qw + t), next, y);
     }
-    cd dn = shfl_down_c(y, 1);
+    const cd dn = wave_shl1(y);
     return lc.lane == kWave - 1 ? next : dn;
 }
 
 // ------------------------------------------------------------ CN core
-// Coefficients of the right-hand side 12 R psi with R = M2 - h A,
-// A = -D2/2 + M2 diag(V):
+// Right-hand side 12 R psi with R = M2 - h A, A = -D2/2 + M2 diag(V):
 //   12 R psi_j = (psi_{j-1} + 10 psi_j + psi_{j+1})
-//                - h' (w(V_{j-1}) psi_{j-1} + d(V_j) psi_j + w(V_{j+1}) psi_{j+1})
-// with w(V) = kw_a V + kw_b = 12 |h| (V/12 - 1/(2 dx^2)),
-//      d(V) = kd_a V + kd_b = 12 |h| (1/dx^2 + 10 V/12),
-// and h' = i (real time, h = i dt/2) or 1 (imaginary time, h = dtau/2).
+//                - h' (om_{j-1} psi_{j-1} + d_j psi_j + om_{j+1} psi_{j+1})
+// with om as in PointTables and d_j = 12|h| (1/dx^2 + 10 V_j/12)
+// = 10 om_j + dofs, dofs = 72 |h| / dx^2 (the diagonal of 12|h| A).
 struct RhsCoef {
-    double kw_a, kw_b, kd_a, kd_b;
+    double dofs;
 };
-
 __host__ __device__ inline RhsCoef make_rhs_coef(double habs, double dx)
 {
     RhsCoef c;
-    const double k = 12.0 * habs;
-    c.kw_a = k / 12.0;
-    c.kw_b = -k / (2.0 * dx * dx);
-    c.kd_a = k * 10.0 / 12.0;
-    c.kd_b = k / (dx * dx);
+    c.dofs = 72.0 * habs / (dx * dx);
     return c;
 }
 
 // Applies psi <- L^{-1} R psi (before the field phase and absorber) to the
 // lane's chunk v[0..C-1] whose neighbours are gl = psi_{s-1}, gr = psi_{s+C}.
-// Returns the carries cf = z_{s-1} and cb = y_{s+C} (both exact), from which
+// Four sweeps over the chunk: right-hand side fused with the forward
+// recurrence from a zero carry (chunk-end value only); forward recurrence
+// from the exact carry with the pivot scaling; backward recurrence from a
+// zero carry (chunk-start value only); backward recurrence from the exact
+// carry.  Returns the exact carries cf = z_{s-1} and cb = y_{s+C}, from which
 // the caller rebuilds the ghost values of the next step without exchanging
 // data between lanes:  y_{s+C} = cb,  y_{s-1} = q_{s-1} cf + beta_{s-1} y_s.
-template <int C, bool REALTIME>
-__device__ __forceinline__ void cn_apply(cd (&v)[C], cd gl, cd gr, const SizeClass& sc,
-                                         const LaneCtx& lc, const RhsCoef rc, cd* lds_f,
-                                         cd* lds_b, cd& cf, cd& cb)
+template <int C, bool RT, class TV>
+__device__ __forceinline__ void cn_apply(cd (&v)[C], cd gl, cd gr, const TV& tb,
+                                         const SizeClass& sc, const LaneCtx& lc, const RhsCoef rc,
+                                         cd* lds_f, cd* lds_b, cd& cf, cd& cb)
 {
-    const int T = sc.T, t = opaque(lc.t);
-    // 1. right-hand side, in place
+    // A. right-hand side in place, chunk-end value of z with zero carry-in.
+    // Each sweep re-derives its table addresses from an opaque lane index so
+    // the compiler does not keep 2C addresses alive across sweeps.
+    cd ze = czero();
     {
+        const int b0 = opaque(pbase(lc.t, C));
         cd prev = gl;
-        double wprev = fma(lc.vl, rc.kw_a, rc.kw_b);
-        double v0 = sc.pt.v[t];
-        double wcur = fma(v0, rc.kw_a, rc.kw_b);
-        double dcur = fma(v0, rc.kd_a, rc.kd_b);
+        double wprev = lc.oml();
+        double wcur = tb.om(b0);
+        cd qprev = czero();
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             const cd cur = v[k];
             const cd nxt = (k + 1 < C) ? v[k + 1] : gr;
-            const double vn = (k + 1 < C) ? sc.pt.v[(k + 1) * T + t] : lc.vr;
-            const double wn = fma(vn, rc.kw_a, rc.kw_b);
-            const double dn = fma(vn, rc.kd_a, rc.kd_b);
+            const double wn = (k + 1 < C) ? tb.om(b0 + 64 * (k + 1)) : lc.omr();
+            const double dk = fma(10.0, wcur, rc.dofs);
             double re = fma(10.0, cur.re, prev.re + nxt.re);
             double im = fma(10.0, cur.im, prev.im + nxt.im);
-            if (REALTIME) {
+            if (RT) {  // r = S - i s
                 re = fma(wprev, prev.im, re);
-                re = fma(dcur, cur.im, re);
+                re = fma(dk, cur.im, re);
                 re = fma(wn, nxt.im, re);
                 im = fma(-wprev, prev.re, im);
-                im = fma(-dcur, cur.re, im);
+                im = fma(-dk, cur.re, im);
                 im = fma(-wn, nxt.re, im);
-            } else {
+            } else {   // r = S - s
                 re = fma(-wprev, prev.re, re);
-                re = fma(-dcur, cur.re, re);
+                re = fma(-dk, cur.re, re);
                 re = fma(-wn, nxt.re, re);
                 im = fma(-wprev, prev.im, im);
-                im = fma(-dcur, cur.im, im);
+                im = fma(-dk, cur.im, im);
                 im = fma(-wn, nxt.im, im);
             }
-            v[k] = mkc(re, im);
+            const cd r = mkc(re, im);
+            v[k] = r;
+            ze = (k == 0) ? r : cmad(elim<RT>(wprev, qprev), ze, r);
+            qprev = tb.q(b0 + 64 * k);
             prev = cur;
             wprev = wcur;
             wcur = wn;
-            dcur = dn;
+            TDSE_POINT_FENCE();
         }
     }
-    // 2. forward recurrence with zero carry-in
+    cf = scan_fwd(ze, sc, lc, lds_f);
+    // B. forward recurrence from the exact carry, w = q z
+    {
+        const int b0 = opaque(pbase(lc.t, C));
+        cd z = cf;
+        double wp = lc.oml();
+        cd qp = lc.ql();
 #pragma unroll
-    for (int k = 1; k < C; ++k) v[k] = cmad(ld(sc.pt.alpha + k * T + t), v[k - 1], v[k]);
-    // 3. carry-in across lanes
-    cf = scan_fwd(v[C - 1], sc, lc, lds_f);
-    // 4. carry fix-up and pivot scaling
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const cd z = cmad(ld(sc.pt.at + k * T + t), cf, v[k]);
-        v[k] = cmul(ld(sc.pt.q + k * T + t), z);
+        for (int k = 0; k < C; ++k) {
+            z = cmad(elim<RT>(wp, qp), z, v[k]);
+            const cd qk = tb.q(b0 + 64 * k);
+            v[k] = cmul(qk, z);
+            wp = tb.om(b0 + 64 * k);
+            qp = qk;
+            TDSE_POINT_FENCE();
+        }
     }
-    // 5. backward recurrence with zero carry-in
+    // C. chunk-start value of y with zero carry-in
+    cd yb = czero();
+    {
+        const int b0 = opaque(pbase(lc.t, C));
+        double wn = lc.omr();
 #pragma unroll
-    for (int k = C - 2; k >= 0; --k) v[k] = cmad(ld(sc.pt.beta + k * T + t), v[k + 1], v[k]);
-    // 6. carry-in from the right
-    cb = scan_bwd(v[0], sc, lc, lds_b);
-    // 7. carry fix-up
+        for (int k = C - 1; k >= 0; --k) {
+            const cd qk = tb.q(b0 + 64 * k);
+            yb = (k == C - 1) ? v[k] : cmad(elim<RT>(wn, qk), yb, v[k]);
+            wn = tb.om(b0 + 64 * k);
+            TDSE_POINT_FENCE();
+        }
+    }
+    cb = scan_bwd(yb, sc, lc, lds_b);
+    // D. backward recurrence from the exact carry
+    {
+        const int b0 = opaque(pbase(lc.t, C));
+        cd y = cb;
+        double wn = lc.omr();
 #pragma unroll
-    for (int k = 0; k < C; ++k) v[k] = cmad(ld(sc.pt.bt + k * T + t), cb, v[k]);
+        for (int k = C - 1; k >= 0; --k) {
+            const cd qk = tb.q(b0 + 64 * k);
+            y = cmad(elim<RT>(wn, qk), y, v[k]);
+            v[k] = y;
+            wn = tb.om(b0 + 64 * k);
+            TDSE_POINT_FENCE();
+        }
+    }
 }
 
-// Field substep exp(-i dt E x_j) and absorber m_j applied to the chunk and to
-// its two ghost points (x_{s-1} = xl).  The phase advances along the chunk by
+// Field substep exp(-i dt E x_j) and absorber m_j on the chunk and its two
+// ghost points (x_{s-1} = xl).  The phase advances along the chunk by
 // multiplication with exp(-i dt E dx); each lane starts from its own sincos.
 template <int C>
 __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e, double dt,
@@ -285,41 +468,205 @@ __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e,
                                            const LaneCtx& lc)
 {
     double s0, c0, s1, c1;
-    sincos(-dt * e * xl, &s0, &c0);
-    sincos(-dt * e * dx, &s1, &c1);
+    sincos_rr(-dt * e * xl, &s0, &c0);
+    sincos_step(-dt * e * dx, &s1, &c1);
     cd ph = mkc(c0, s0);
     const cd w1 = mkc(c1, s1);
-    gl = cscale(lc.ml, cmul(ph, gl));
+    gl = cscale(lc.ml(), cmul(ph, gl));
     ph = cmul(ph, w1);
     if (lc.hasmask) {
-        const int t = opaque(lc.t);
+        const int b0 = opaque(pbase(lc.t, C));
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            v[k] = cscale(sc.pt.m[k * sc.T + t], cmul(ph, v[k]));
+            v[k] = cscale(ldg(sc.pt.m + b0 + 64 * k), cmul(ph, v[k]));
             ph = cmul(ph, w1);
+            TDSE_POINT_FENCE();
         }
     } else {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             v[k] = cmul(ph, v[k]);
             ph = cmul(ph, w1);
+            TDSE_POINT_FENCE();
         }
     }
-    gr = cscale(lc.mr, cmul(ph, gr));
+    gr = cscale(lc.mr(), cmul(ph, gr));
 }
 
 // One full step psi^(i) -> psi^(i+1) (CN right-hand side, partitioned solve,
 // ghost rebuild, field phase and absorber).
-template <int C>
+template <int C, class TV>
 __device__ __forceinline__ void forward_step(cd (&v)[C], cd& gl, cd& gr, double e, double dt,
-                                             double xl, const SizeClass& sc, const LaneCtx& lc,
-                                             const RhsCoef rc, cd* lds_f, cd* lds_b)
+                                             double xl, const TV& tb, const SizeClass& sc,
+                                             const LaneCtx& lc, const RhsCoef rc, cd* lds_f,
+                                             cd* lds_b)
 {
     cd cf, cb;
-    cn_apply<C, true>(v, gl, gr, sc, lc, rc, lds_f, lds_b, cf, cb);
-    gl = cmad(lc.ql, cf, cmul(lc.bl, v[0]));
+    cn_apply<C, true, TV>(v, gl, gr, tb, sc, lc, rc, lds_f, lds_b, cf, cb);
+    gl = cmad(lc.ql(), cf, cmul(lc.bl(), v[0]));
     gr = cb;
     phase_mask<C>(v, gl, gr, e, dt, xl, sc.dx, sc, lc);
+}
+
+// Copies the point tables of a size class into LDS (om, q, dV of np points):
+// 32 bytes per point, shared by every system the workgroup propagates.
+__device__ __forceinline__ TabLds stage_tables(const SizeClass& sc, double* lds)
+{
+    const int np = sc.C * sc.T;
+    double* om = lds;
+    cd* q = reinterpret_cast<cd*>(lds + np);
+    double* dv = lds + 3 * np;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        om[i] = sc.pt.om[i];
+        q[i] = sc.pt.q[i];
+        dv[i] = sc.pt.dv[i];
+    }
+    __syncthreads();
+    TabLds tv;
+    tv.om_ = om;
+    tv.q_ = q;
+    tv.dv_ = dv;
+    return tv;
+}
+
+__device__ __forceinline__ TabGlobal global_tables(const SizeClass& sc)
+{
+    TabGlobal tv;
+    tv.om_ = sc.pt.om;
+    tv.q_ = sc.pt.q;
+    tv.dv_ = sc.pt.dv;
+    return tv;
+}
+
+template <bool LDSTAB>
+struct TableSource;
+template <>
+struct TableSource<true> {
+    using type = TabLds;
+    static __device__ __forceinline__ TabLds make(const SizeClass& sc, double* lds) { return stage_tables(sc, lds); }
+    static __device__ __forceinline__ TabLds view(const SizeClass& sc, double* lds)
+    {
+        const int np = sc.C * sc.T;
+        TabLds tv;
+        tv.om_ = lds;
+        tv.q_ = reinterpret_cast<cd*>(lds + np);
+        tv.dv_ = lds + 3 * np;
+        return tv;
+    }
+};
+template <>
+struct TableSource<false> {
+    using type = TabGlobal;
+    static __device__ __forceinline__ TabGlobal make(const SizeClass& sc, double*) { return global_tables(sc); }
+    static __device__ __forceinline__ TabGlobal view(const SizeClass& sc, double*) { return global_tables(sc); }
+};
+
+// Everything one time step needs to know about its size class.  The time
+// loops rebuild it at the top of every step from a class address that the
+// optimiser cannot see through: otherwise the addresses, lane predicates and
+// coordinates derived from the class are hoisted out of the loop and kept
+// live across it, far beyond the register budget of four waves per SIMD.
+// Rebuilding costs a few scalar loads and integer operations per step.
+template <bool LDSTAB>
+struct StepView {
+    SizeClass sc;
+    LaneCtx lc;
+    typename TableSource<LDSTAB>::type tb;
+    RhsCoef rc;
+    double xs;  // x of the lane's first point
+    double xl;  // x of the point before it
+};
+
+template <bool LDSTAB>
+__device__ __forceinline__ StepView<LDSTAB> step_view(const SizeClass* cls, int t, double* smem)
+{
+    StepView<LDSTAB> v;
+    v.sc = uniform_load(launder_s(cls));
+    v.lc = make_lane_ctx(v.sc, opaque(t));
+    v.tb = TableSource<LDSTAB>::view(v.sc, smem);
+    v.rc = make_rhs_coef(v.sc.habs, v.sc.dx);
+    const double c = 0.5 * (double)(v.sc.n - 1);
+    v.xs = ((double)v.lc.s - c) * v.sc.dx;
+    v.xl = ((double)(v.lc.s - 1) - c) * v.sc.dx;
+    return v;
+}
+
+// ------------------------------------------------------------ time-loop helpers
+// Per-subgroup LDS block: forward and backward carry slots, two reduction
+// slot arrays, the observables ring, a few flags.
+struct SubSmem {
+    cd* lds_f;
+    cd* lds_b;
+    double* red0;
+    double* red1;
+    double* ring;
+    int* misc;
+};
+
+__device__ __forceinline__ SubSmem carve_sub(char* base, int W)
+{
+    SubSmem s;
+    s.lds_f = reinterpret_cast<cd*>(base);
+    s.lds_b = s.lds_f + kMaxWaves;
+    s.red0 = reinterpret_cast<double*>(s.lds_b + kMaxWaves);
+    s.red1 = s.red0 + kMaxWaves;
+    s.ring = s.red1 + kMaxWaves;
+    s.misc = reinterpret_cast<int*>(s.ring + kRing * W * 3);
+    return s;
+}
+
+// Per-lane partial sums of the observables of the current state, reduced over
+// the wavefront; lane 0 stores (sum V'|psi|^2, sum x|psi|^2, sum |psi|^2).
+template <int C, class TV>
+__device__ __forceinline__ void observe(const cd (&v)[C], const TV& tb, int T,
+                                        const LaneCtx& lc, double xs, double dx, double* slot)
+{
+    double sn = 0.0, sk = 0.0, sv = 0.0;
+    const int b0 = opaque(pbase(lc.t, C));
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const double p = cabs2(v[k]);
+        sn += p;
+        sk = fma((double)k, p, sk);
+        sv = fma(tb.dv(b0 + 64 * k), p, sv);
+        TDSE_POINT_FENCE();
+    }
+    double sx = fma(xs, sn, dx * sk);
+    sn = wave_sum(sn);
+    sx = wave_sum(sx);
+    sv = wave_sum(sv);
+    if (lc.lane == kSumLane) {
+        slot[lc.wave * 3 + 0] = sv;
+        slot[lc.wave * 3 + 1] = sx;
+        slot[lc.wave * 3 + 2] = sn;
+    }
+}
+
+// Sums the per-wave partials of samples [a0, a1] in wave order and writes
+//   accel = dx (sum V'|psi|^2 + E sum |psi|^2), xexp = dx sum x|psi|^2,
+//   norm = dx sum |psi|^2.
+__device__ __forceinline__ void flush(int a0, int a1, int t, int T, const double* ring, int W,
+                                      double dx, const double* erow, double* acc_row,
+                                      double* x_row, double* n_row, double n0, int* flag)
+{
+    for (int smp = a0 + t; smp <= a1; smp += T) {
+        const double* r = ring + (smp % kRing) * W * 3;
+        double sv = 0.0, sx = 0.0, sn = 0.0;
+        for (int w = 0; w < W; ++w) {
+            sv += r[w * 3 + 0];
+            sx += r[w * 3 + 1];
+            sn += r[w * 3 + 2];
+        }
+        const double nn = dx * sn;
+        const double acc = dx * fma(erow[smp], sn, sv);
+        acc_row[smp] = acc;
+        if (x_row) x_row[smp] = dx * sx;
+        if (n_row) n_row[smp] = nn;
+        int f = 0;
+        if (!isfinite(acc) || !isfinite(nn) || !isfinite(sx)) f |= 1;
+        if (nn > n0 * (1.0 + 1e-8)) f |= 2;
+        if (f) atomicOr(flag, f);
+    }
 }
 
 }  // namespace tdse

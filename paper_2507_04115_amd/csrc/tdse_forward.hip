@@ -1,138 +1,64 @@
 // tdse_forward.hip -- persistent batched forward propagation and the
 // imaginary-time ground state on gfx950.
 //
-// Layout: one workgroup of T = 64 W lanes owns one system at a time; lane t
-// keeps grid points [t C, t C + C) of psi in VGPRs for the whole time loop,
-// plus one ghost value on each side.  Per step (section "1D-TSDE
-// Implementation (CTDSE)", three substeps):
+// Layout: a workgroup holds S subgroups of T = 64 W lanes; each subgroup owns
+// one system at a time and lane t keeps grid points [t C, t C + C) of psi in
+// VGPRs for the whole time loop, plus one ghost value on each side.  All S
+// systems share one copy of the size class's point tables in LDS (32 bytes
+// per point: om, q, dV/dx), staged once per workgroup.  Per step (section
+// "1D-TSDE Implementation (CTDSE)", three substeps):
 //   1. r = 12 R psi in place                      (first substep)
 //   2. L y = r by a partitioned Thomas solve      (second substep):
-//      lane-local recurrences with zero carry, carries across lanes by a
-//      Kogge-Stone scan over the wavefront (DPP/LDS-free shuffles) and one
-//      LDS exchange between wavefronts, then lane-local fix-ups
+//      lane-local recurrences, carries across lanes by a Kogge-Stone scan
+//      within the wavefront and one LDS exchange between wavefronts
 //   3. psi_j = m_j exp(-i dt E_i x_j) y_j         (third substep + absorber)
 //   4. per-lane partial sums of |psi|^2, x|psi|^2, V'|psi|^2, wavefront sums,
 //      a ring of per-wave partials in LDS flushed every 32 samples as
 //      coalesced rows of accel/xexp/norm.
-// Only E_i (8 B per system-step) is read from HBM inside the loop; only the
-// three observables (24 B per system-step) are written.
+// Only E_i (8 B per system-step) is read from HBM inside the loop and only
+// the three observables (24 B per system-step) are written.
 #include "tdse_device.hpp"
 #include "tdse_kernels.hpp"
 
 namespace tdse {
 
-namespace {
-
-struct Smem {
-    cd* lds_f;
-    cd* lds_b;
-    double* red0;
-    double* red1;
-    double* ring;
-    int* misc;
-};
-
-__device__ __forceinline__ Smem carve(double* base, int W)
+size_t sub_smem_bytes(int W)
 {
-    Smem s;
-    s.lds_f = reinterpret_cast<cd*>(base);
-    s.lds_b = s.lds_f + kMaxWaves;
-    s.red0 = reinterpret_cast<double*>(s.lds_b + kMaxWaves);
-    s.red1 = s.red0 + kMaxWaves;
-    s.ring = s.red1 + kMaxWaves;
-    s.misc = reinterpret_cast<int*>(s.ring + kRing * W * 3);
-    return s;
+    size_t b = sizeof(cd) * 2 * kMaxWaves + sizeof(double) * 2 * kMaxWaves +
+               sizeof(double) * kRing * W * 3 + 4 * sizeof(int);
+    return (b + 15) & ~size_t(15);
 }
-
-__host__ __device__ inline size_t smem_bytes(int W)
-{
-    return sizeof(cd) * 2 * kMaxWaves + sizeof(double) * 2 * kMaxWaves +
-           sizeof(double) * kRing * W * 3 + 4 * sizeof(int);
-}
-
-// Per-lane partial sums of the observables of the current state, reduced over
-// the wavefront; lane 0 stores (sum V'|psi|^2, sum x|psi|^2, sum |psi|^2).
-template <int C>
-__device__ __forceinline__ void observe(const cd (&v)[C], const SizeClass& sc, const LaneCtx& lc,
-                                        double xs, double* slot)
-{
-    double sn = 0.0, sk = 0.0, sv = 0.0;
-    const int t = opaque(lc.t);
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const double p = cabs2(v[k]);
-        sn += p;
-        sk = fma((double)k, p, sk);
-        sv = fma(sc.pt.dv[k * sc.T + t], p, sv);
-    }
-    double sx = fma(xs, sn, sc.dx * sk);
-    sn = wave_sum(sn);
-    sx = wave_sum(sx);
-    sv = wave_sum(sv);
-    if (lc.lane == 0) {
-        slot[lc.wave * 3 + 0] = sv;
-        slot[lc.wave * 3 + 1] = sx;
-        slot[lc.wave * 3 + 2] = sn;
-    }
-}
-
-// Sums the per-wave partials of samples [a0, a1] in wave order and writes
-//   accel = dx (sum V'|psi|^2 + E sum |psi|^2), xexp = dx sum x|psi|^2,
-//   norm = dx sum |psi|^2.
-__device__ __forceinline__ void flush(int a0, int a1, const double* ring, int W, double dx,
-                                      const double* erow, double* acc_row, double* x_row,
-                                      double* n_row, double n0, int* flag)
-{
-    for (int smp = a0 + (int)threadIdx.x; smp <= a1; smp += blockDim.x) {
-        const double* r = ring + (smp % kRing) * W * 3;
-        double sv = 0.0, sx = 0.0, sn = 0.0;
-        for (int w = 0; w < W; ++w) {
-            sv += r[w * 3 + 0];
-            sx += r[w * 3 + 1];
-            sn += r[w * 3 + 2];
-        }
-        const double nn = dx * sn;
-        const double acc = dx * fma(erow[smp], sn, sv);
-        acc_row[smp] = acc;
-        if (x_row) x_row[smp] = dx * sx;
-        if (n_row) n_row[smp] = nn;
-        int f = 0;
-        if (!isfinite(acc) || !isfinite(nn) || !isfinite(sx)) f |= 1;
-        if (nn > n0 * (1.0 + 1e-8)) f |= 2;
-        if (f) atomicOr(flag, f);
-    }
-}
-
-}  // namespace
 
 // -------------------------------------------------------------- forward
-template <int C>
-__global__ void __launch_bounds__(256) forward_kernel(FwdArgs a)
+template <int C, bool LDSTAB>
+__global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
 {
     extern __shared__ double smem_raw[];
-    const int tid = threadIdx.x;
-    const int W = blockDim.x / kWave;
-    const Smem sm = carve(smem_raw, W);
+    const SizeClass sc = uniform_load(a.classes + a.cls);
+    const int T = sc.T, W = T / kWave, np = C * T;
+    const int S = blockDim.x / T;
+    const int tid = threadIdx.x, sub = tid / T, t = tid - sub * T;
+    const size_t sb = a.sub_bytes;
+    char* per = reinterpret_cast<char*>(smem_raw + (LDSTAB ? 4 * np : 0));
+    const SubSmem sm = carve_sub(per + sub * sb, W);
+    int* wg_item = reinterpret_cast<int*>(per + S * sb);
+    TableSource<LDSTAB>::make(sc, smem_raw);  // stages the tables once per workgroup
+    const double dx = sc.dx;
+    const int n = sc.n, s = t * C;
+    const int nt = a.nt;
 
     for (;;) {
-        if (tid == 0) {
-            sm.misc[0] = atomicAdd(a.queue, 1);
-            sm.misc[1] = 0;
-        }
+        if (tid == 0) wg_item[0] = atomicAdd(a.queue, S);
+        if (t == 0) sm.misc[1] = 0;
         __syncthreads();
-        const int item = uniform(sm.misc[0]);
-        if (item >= a.count) break;
-        const int p = uniform(a.order[item]);
+        const int base = uniform(wg_item[0]);
+        if (base >= a.count) break;
+        const int item = base + sub;
+        const bool active = item < a.count;  // uniform within the subgroup
+        const int p = active ? uniform(a.order[item]) : 0;
         const SysDesc d = uniform_load(a.sys + p);
-        const SizeClass sc = uniform_load(a.classes + d.cls);
-        const LaneCtx lc = make_lane_ctx(sc, tid);
-        const RhsCoef rc = make_rhs_coef(0.5 * a.dt, sc.dx);
-        const double dx = sc.dx;
-        const int n = sc.n, s = lc.s, T = sc.T;
-        const double xs = ((double)s - 0.5 * (double)(n - 1)) * dx;
-        const double xl = ((double)(s - 1) - 0.5 * (double)(n - 1)) * dx;
-        const double* src = a.psi0 ? a.psi0 + 2 * d.psi_off : a.gs + 2 * a.gs_off[d.cls];
-        const size_t row = (size_t)p * (size_t)(a.nt + 1);
+        const double* src = a.psi0 ? a.psi0 + 2 * d.psi_off : a.gs + 2 * a.gs_off[a.cls];
+        const size_t row = (size_t)p * (size_t)(nt + 1);
         const double* erow = a.E + row;
         double* acc_row = a.accel + row;
         double* x_row = a.xexp ? a.xexp + row : nullptr;
@@ -140,41 +66,50 @@ __global__ void __launch_bounds__(256) forward_kernel(FwdArgs a)
 
         cd v[C];
 #pragma unroll
-        for (int k = 0; k < C; ++k) v[k] = (s + k < n) ? ld_psi(src, s + k) : czero();
-        cd gl = (s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
-        cd gr = (s + C < n) ? ld_psi(src, s + C) : czero();
+        for (int k = 0; k < C; ++k) v[k] = (active && s + k < n) ? ld_psi(src, s + k) : czero();
+        cd gl = (active && s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
+        cd gr = (active && s + C < n) ? ld_psi(src, s + C) : czero();
 
-        observe<C>(v, sc, lc, xs, sm.ring);
+        {
+            const StepView<LDSTAB> sv = step_view<LDSTAB>(a.classes + a.cls, t, smem_raw);
+            observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, sm.ring);
+        }
         __syncthreads();
         double n0 = 0.0;
         for (int w = 0; w < W; ++w) n0 += sm.ring[w * 3 + 2];
         n0 *= dx;
 
         int flushed = 0;
-        for (int i = 0; i < a.nt; ++i) {
-            forward_step<C>(v, gl, gr, erow[i], a.dt, xl, sc, lc, rc, sm.lds_f, sm.lds_b);
+        for (int i = 0; i < nt; ++i) {
+            const StepView<LDSTAB> sv = step_view<LDSTAB>(a.classes + a.cls, t, smem_raw);
+            forward_step<C>(v, gl, gr, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f,
+                            sm.lds_b);
             if ((i + 1) % kFlush == 0) {
                 __syncthreads();
-                flush(i + 1 - kFlush, i, sm.ring, W, dx, erow, acc_row, x_row, n_row, n0,
-                      sm.misc + 1);
+                if (active)
+                    flush(i + 1 - kFlush, i, t, T, sm.ring, W, dx, erow, acc_row, x_row, n_row, n0,
+                          sm.misc + 1);
                 flushed = i + 1;
             }
-            observe<C>(v, sc, lc, xs, sm.ring + ((i + 1) % kRing) * W * 3);
+            observe<C>(v, sv.tb, sv.sc.T, sv.lc, sv.xs, sv.sc.dx,
+                       sm.ring + ((i + 1) % kRing) * W * 3);
         }
         __syncthreads();
-        flush(flushed, a.nt, sm.ring, W, dx, erow, acc_row, x_row, n_row, n0, sm.misc + 1);
-        if (a.psi_final) {
-            double* dst = a.psi_final + 2 * d.psi_off;
+        if (active) {
+            flush(flushed, nt, t, T, sm.ring, W, dx, erow, acc_row, x_row, n_row, n0, sm.misc + 1);
+            if (a.psi_final) {
+                double* dst = a.psi_final + 2 * d.psi_off;
 #pragma unroll
-            for (int k = 0; k < C; ++k) {
-                if (s + k < n) {
-                    dst[2 * (s + k)] = v[k].re;
-                    dst[2 * (s + k) + 1] = v[k].im;
+                for (int k = 0; k < C; ++k) {
+                    if (s + k < n) {
+                        dst[2 * (s + k)] = v[k].re;
+                        dst[2 * (s + k) + 1] = v[k].im;
+                    }
                 }
             }
         }
         __syncthreads();
-        if (tid == 0 && a.status) a.status[p] = sm.misc[1];
+        if (active && t == 0 && a.status) a.status[p] = sm.misc[1];
     }
 }
 
@@ -183,20 +118,21 @@ __global__ void __launch_bounds__(256) forward_kernel(FwdArgs a)
 // renormalised to dx sum |psi|^2 = 1 each iteration, until successive
 // iterates differ by less than tol.  The energy follows from the growth
 // factor g = ||L_tau^{-1} R_tau psi|| of the converged eigenvector:
-// g = (1 - dtau E/2)/(1 + dtau E/2).  One workgroup per candidate.
+// g = (1 - dtau E/2)/(1 + dtau E/2).  One workgroup per candidate; all
+// candidates of a launch share one lane layout.
 template <int C>
-__global__ void __launch_bounds__(256) gs_kernel(GsArgs a)
+__global__ void __launch_bounds__(1024) gs_kernel(GsArgs a)
 {
     extern __shared__ double smem_raw[];
     const int cand = blockIdx.x;
-    const SizeClass sc = uniform_load(a.classes + uniform(a.cls_of[cand]));
+    const SizeClass* const clsp = a.classes + uniform(a.cls_of[cand]);
+    const SizeClass sc = uniform_load(clsp);
     const int tid = threadIdx.x;
     const int W = sc.T / kWave;
-    const Smem sm = carve(smem_raw, W);
-    const LaneCtx lc = make_lane_ctx(sc, tid);
-    const RhsCoef rc = make_rhs_coef(0.5 * a.dtau, sc.dx);
+    const SubSmem sm = carve_sub(reinterpret_cast<char*>(smem_raw), W);
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
     const double dx = sc.dx;
-    const int n = sc.n, s = lc.s;
+    const int n = sc.n, s = tid * C;
     double* out = a.psi_out + 2 * a.psi_off[cand];
 
     cd v[C];
@@ -210,10 +146,20 @@ __global__ void __launch_bounds__(256) gs_kernel(GsArgs a)
     cd gl = (s > 0 && s - 1 < n) ? mkc(exp(-xl * xl), 0.0) : czero();
     cd gr = (s + C < n) ? mkc(exp(-xr * xr), 0.0) : czero();
 
+    // workgroup sum in fixed wave order; consecutive sums alternate slot arrays
+    auto block_sum = [&](double x, double* slots) {
+        x = wave_sum(x);
+        if (lane == kSumLane) slots[wave] = x;
+        __syncthreads();
+        double r = 0.0;
+        for (int w = 0; w < W; ++w) r += slots[w];
+        return r;
+    };
+
     double loc = 0.0;
 #pragma unroll
     for (int k = 0; k < C; ++k) loc += cabs2(v[k]);
-    double tot = block_sum(loc, sm.red0, lc.lane, lc.wave, W);
+    double tot = block_sum(loc, sm.red0);
     double scl = 1.0 / sqrt(dx * tot);
 #pragma unroll
     for (int k = 0; k < C; ++k) {
@@ -230,14 +176,15 @@ __global__ void __launch_bounds__(256) gs_kernel(GsArgs a)
     bool conv = false;
     double g = 1.0;
     while (it < a.max_iter) {
+        const StepView<false> sv = step_view<false>(clsp, tid, smem_raw);
         cd cf, cb;
-        cn_apply<C, false>(v, gl, gr, sc, lc, rc, sm.lds_f, sm.lds_b, cf, cb);
-        gl = cmad(lc.ql, cf, cmul(lc.bl, v[0]));
+        cn_apply<C, false>(v, gl, gr, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b, cf, cb);
+        gl = cmad(sv.lc.ql(), cf, cmul(sv.lc.bl(), v[0]));
         gr = cb;
         loc = 0.0;
 #pragma unroll
         for (int k = 0; k < C; ++k) loc += cabs2(v[k]);
-        tot = block_sum(loc, sm.red1, lc.lane, lc.wave, W);
+        tot = block_sum(loc, sm.red1);
         g = sqrt(dx * tot);
         scl = 1.0 / g;
         gl = cscale(scl, gl);
@@ -253,7 +200,7 @@ __global__ void __launch_bounds__(256) gs_kernel(GsArgs a)
                 out[2 * (s + k) + 1] = v[k].im;
             }
         }
-        tot = block_sum(loc, sm.red0, lc.lane, lc.wave, W);
+        tot = block_sum(loc, sm.red0);
         ++it;
         if (sqrt(dx * tot) < a.tol) {
             conv = true;
@@ -281,33 +228,52 @@ hipError_t launch_reset_counters(int32_t* counters, int n, hipStream_t st)
 
 bool layout_supported(int C) { return C == 4 || C == 8 || C == 16; }
 
-template <int C>
-static int occ_fwd(int T)
+size_t forward_smem_bytes(int C, int T, int S, bool lds_tables)
+{
+    return (lds_tables ? sizeof(double) * 4 * (size_t)C * T : 0) + S * sub_smem_bytes(T / kWave) +
+           16;
+}
+
+template <int C, bool L>
+static int occ_fwd(int threads, size_t sh)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, forward_kernel<C>, T,
-                                                     smem_bytes(T / kWave)) != hipSuccess)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(forward_kernel<C, L>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, forward_kernel<C, L>, threads, sh) !=
+        hipSuccess)
         return 0;
     return nb;
 }
 
-int forward_occupancy(int C, int T)
+int forward_occupancy(int C, int T, int S, bool lds_tables)
 {
-    switch (C) {
-        case 4: return occ_fwd<4>(T);
-        case 8: return occ_fwd<8>(T);
-        case 16: return occ_fwd<16>(T);
+    const size_t sh = forward_smem_bytes(C, T, S, lds_tables);
+    if (sh > (size_t)kMaxLds) return 0;
+    const int th = S * T;
+    switch (C * 2 + (lds_tables ? 1 : 0)) {
+        case 8: return occ_fwd<4, false>(th, sh);
+        case 9: return occ_fwd<4, true>(th, sh);
+        case 16: return occ_fwd<8, false>(th, sh);
+        case 17: return occ_fwd<8, true>(th, sh);
+        case 32: return occ_fwd<16, false>(th, sh);
+        case 33: return occ_fwd<16, true>(th, sh);
         default: return 0;
     }
 }
 
-hipError_t launch_forward(int C, const FwdArgs& a, int T, int grid, hipStream_t st)
+hipError_t launch_forward(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
+                          hipStream_t st)
 {
-    const size_t sh = smem_bytes(T / kWave);
-    switch (C) {
-        case 4: hipLaunchKernelGGL(forward_kernel<4>, dim3(grid), dim3(T), sh, st, a); break;
-        case 8: hipLaunchKernelGGL(forward_kernel<8>, dim3(grid), dim3(T), sh, st, a); break;
-        case 16: hipLaunchKernelGGL(forward_kernel<16>, dim3(grid), dim3(T), sh, st, a); break;
+    const size_t sh = forward_smem_bytes(C, T, S, lds_tables);
+    const dim3 b(T * S);
+    switch (C * 2 + (lds_tables ? 1 : 0)) {
+        case 8: hipLaunchKernelGGL((forward_kernel<4, false>), dim3(grid), b, sh, st, a); break;
+        case 9: hipLaunchKernelGGL((forward_kernel<4, true>), dim3(grid), b, sh, st, a); break;
+        case 16: hipLaunchKernelGGL((forward_kernel<8, false>), dim3(grid), b, sh, st, a); break;
+        case 17: hipLaunchKernelGGL((forward_kernel<8, true>), dim3(grid), b, sh, st, a); break;
+        case 32: hipLaunchKernelGGL((forward_kernel<16, false>), dim3(grid), b, sh, st, a); break;
+        case 33: hipLaunchKernelGGL((forward_kernel<16, true>), dim3(grid), b, sh, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -315,7 +281,7 @@ hipError_t launch_forward(int C, const FwdArgs& a, int T, int grid, hipStream_t 
 
 hipError_t launch_ground_state(int C, const GsArgs& a, int T, hipStream_t st)
 {
-    const size_t sh = smem_bytes(T / kWave);
+    const size_t sh = sub_smem_bytes(T / kWave) + 16;
     switch (C) {
         case 4: hipLaunchKernelGGL(gs_kernel<4>, dim3(a.ncand), dim3(T), sh, st, a); break;
         case 8: hipLaunchKernelGGL(gs_kernel<8>, dim3(a.ncand), dim3(T), sh, st, a); break;

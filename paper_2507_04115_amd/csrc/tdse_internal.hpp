@@ -1,12 +1,12 @@
 // tdse_internal.hpp -- structures shared by the host API (libtdse.cpp) and the
-// gfx950 kernels (tdse_kernels.hip).  Not part of the public C-ABI.
+// gfx950 kernels.  Not part of the public C-ABI.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace tdse {
 
-struct cd {
+struct alignas(16) cd {
     double re, im;
 };
 
@@ -16,41 +16,55 @@ constexpr int kMaxLevels = 6;   // in-wave Kogge-Stone levels (2^6 = 64 lanes)
 constexpr int kFlush = 32;      // samples per output flush
 constexpr int kRing = 64;       // ring of per-wave partial sums (samples)
 
-// Point tables of one size class, stored lane-interleaved: the value of
-// grid point j = t*C + k (lane t, local index k) lives at [k*T + t], so the
-// k-th loads of consecutive lanes are consecutive in memory.
+__host__ __device__ inline int pbase(int t, int C) { return (t >> 6) * (C * 64) + (t & 63); }
+__host__ __device__ inline int pidx(int t, int k, int C) { return pbase(t, C) + 64 * k; }
+
+// Point tables of one size class, stored lane-interleaved by wavefront: the
+// value of grid point j = t*C + k (lane t, local index k) lives at
+// pidx(t, k, C) = (t/64)*64C + 64k + t%64.  The k-th accesses of the 64 lanes
+// of a wavefront are consecutive (coalesced in HBM, bank-conflict free in
+// LDS) and the offset of point k from the lane's base is the compile-time
+// constant 64k, so every table access in the unrolled chunk loops is an
+// immediate-offset load from one base register.
 //
-// For the left-hand side L = M2 + h A of the Crank-Nicolson step (h = i dt/2
-// in real time, dtau/2 in imaginary time) factorised without pivoting as
-// L = (unit lower, subdiagonal l_j) (upper, pivots p_j, superdiagonal u_j):
-//   alpha_j = -l_j            forward recurrence  z_j = r_j + alpha_j z_{j-1}
-//   q_j     = 1 / (12 p_j)    scaling             w_j = q_j z_j
-//   beta_j  = -u_j / p_j      backward recurrence y_j = w_j + beta_j y_{j+1}
-// (the right-hand side is formed as 12 R psi, hence the 1/12 in q).
-//   at_j    = prod_{m=s..j} alpha_m   within the lane's chunk [s, s+C)
-//   bt_j    = prod_{m=j..s+C-1} beta_m
-// Padding points (j >= n) have every coefficient 0 so they stay 0.
+// The Crank-Nicolson left-hand side L = M2 + h A (h = i dt/2 in real time,
+// dtau/2 in imaginary time) is factorised without pivoting as
+// L = (unit lower, subdiagonal l_{j-1}/p_{j-1}) (upper, pivots p_j,
+// superdiagonal u_j).  With the right-hand side formed as 12 R psi:
+//   om_j  = 12 |h| (V_j/12 - 1/(2 dx^2))   (so 12 l_j = 1 + h' om_j,
+//                                           12 u_j = 1 + h' om_{j+1},
+//                                           h' = i or 1)
+//   q_j   = 1 / (12 p_j)
+//   alpha_j = -(1 + h' om_{j-1}) q_{j-1}    forward  z_j = r_j + alpha_j z_{j-1}
+//   beta_j  = -(1 + h' om_{j+1}) q_j        backward y_j = q_j z_j + beta_j y_{j+1}
+// alpha and beta are kept only to build the lane carry products; the
+// kernels recompute them from om and q (two FMAs each).
+// Padding points (j >= n) have q = 0, V = 0, dV = 0, m = 0, so they stay 0.
 struct PointTables {
     double* v;      // V_j
+    double* om;     // om_j
     double* dv;     // dV/dx_j
     double* m;      // absorber mask m_j (0 on padding)
-    cd* alpha;
-    cd* at;
     cd* q;
+    cd* alpha;
     cd* beta;
-    cd* bt;
+};
+
+// Constants of one lane (the points next to its chunk [s, s+C)).
+struct LaneConst {
+    double oml;    // om at s-1
+    double omr;    // om at s+C
+    double ml;     // mask at s-1 (0 outside)
+    double mr;     // mask at s+C
+    double dvl;    // dV/dx at s-1
+    double dvr;    // dV/dx at s+C
+    cd ql;         // q at s-1 (0 outside)
+    cd bl;         // beta at s-1
 };
 
 // Per-lane constants (arrays of length T).
 struct LaneTables {
-    double* vl;    // V at s-1 (0 outside)
-    double* vr;    // V at s+C
-    double* ml;    // mask at s-1 (0 outside)
-    double* mr;    // mask at s+C
-    double* dvl;   // dV/dx at s-1
-    double* dvr;   // dV/dx at s+C
-    cd* ql;        // q at s-1
-    cd* bl;        // beta at s-1
+    LaneConst* k;  // ghost-point constants
     cd* pa;        // [kMaxLevels][T]: prod of chunk products A over lanes [max(t-2^lev+1, ws), t]
     cd* pw;        // prod of A over [ws, t]   (ws = first lane of t's wave)
     cd* qb;        // [kMaxLevels][T]: prod of chunk products B over lanes [t, min(t+2^lev-1, we)]
@@ -67,7 +81,7 @@ struct SizeClass {
     int32_t xwaves;  // previous/next waves chained in the cross-wave carry
     int32_t pad_;
     double dx;
-    double x0;       // x of grid point 0 = -(n-1)/2 dx
+    double habs;     // |h| of the factorised matrix (dt/2 or dtau/2)
     PointTables pt;
     LaneTables lt;
 };

@@ -4,6 +4,8 @@
 
 namespace tdse {
 
+constexpr int kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+
 // Parameters of one set of plan tables.
 struct TableParams {
     double dx, a, z, mask_frac, mask_pow;
@@ -11,13 +13,16 @@ struct TableParams {
 };
 
 // Arguments of the persistent propagation kernels (forward and adjoint).
+// One launch covers the systems of one size class.
 struct FwdArgs {
     const SizeClass* classes;
     const SysDesc* sys;
     const int32_t* order;   // systems of this launch, in queue order
-    int32_t count;          // number of entries in `order` (all of one lane layout)
+    int32_t count;          // number of entries in `order`
+    int32_t cls;            // size class of every system of this launch
     int32_t* queue;         // work counter, reset to 0 before the launch
     int32_t nt;
+    int64_t sub_bytes;      // LDS bytes per subgroup
     double dt;
     const double* E;        // [batch][nt+1]
     const double* psi0;     // ragged, or NULL
@@ -31,11 +36,8 @@ struct FwdArgs {
     // adjoint only
     const double* abar;     // [batch][nt+1]
     double* grad;           // [batch][nt+1]
-    double* ckpt;           // per workgroup slot checkpoints
-    double* seg;            // per workgroup slot segment states
-    double* nrm_buf;        // per workgroup slot norm series
-    int64_t slot_stride_ckpt;  // doubles per slot
-    int64_t slot_stride_seg;
+    double* work;           // per subgroup slot: checkpoints, segment states, norms
+    int64_t slot_doubles;   // doubles per slot
     int32_t k_ckpt;
 };
 
@@ -66,14 +68,27 @@ struct YieldArgs {
 hipError_t launch_build_tables(const SizeClass* d_classes, const TableParams* d_params, int ncls,
                                double* d_metrics, cd* d_scratch, int max_t, hipStream_t st);
 hipError_t launch_reset_counters(int32_t* counters, int n, hipStream_t st);
-// Occupancy (workgroups per CU) of the forward kernel for points-per-lane C
-// and T lanes; 0 if the configuration is not built.
-int forward_occupancy(int C, int T);
-int adjoint_occupancy(int C, int T);
-hipError_t launch_forward(int C, const FwdArgs& a, int T, int grid, hipStream_t st);
-hipError_t launch_adjoint(int C, const FwdArgs& a, int T, int grid, hipStream_t st);
+bool layout_supported(int C);
+size_t sub_smem_bytes(int W);
+
+// Forward kernel: C points per lane, T lanes per system, S systems per
+// workgroup, point tables in LDS or global memory.  Occupancy is in
+// workgroups per CU (0 when the configuration does not fit).
+size_t forward_smem_bytes(int C, int T, int S, bool lds_tables);
+int forward_occupancy(int C, int T, int S, bool lds_tables);
+hipError_t launch_forward(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
+                          hipStream_t st);
+
+size_t adjoint_smem_bytes(int C, int T, int S, bool lds_tables);
+int adjoint_occupancy(int C, int T, int S, bool lds_tables);
+hipError_t launch_adjoint(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
+                          hipStream_t st);
+
+// Orders the systems of one launch so that rows with a non-zero abar come
+// first; counters (2 ints) must be zero.
+hipError_t launch_compact_rows(const double* abar, int nt, const int32_t* order_in, int count,
+                               int32_t* order_out, int32_t* counters, hipStream_t st);
 hipError_t launch_ground_state(int C, const GsArgs& a, int T, hipStream_t st);
 hipError_t launch_yield(const YieldArgs& a, hipStream_t st);
-bool layout_supported(int C);
 
 }  // namespace tdse

@@ -45,16 +45,21 @@ __global__ void __launch_bounds__(256) build_tables_kernel(const SizeClass* clas
     cd* ca = scratch + (size_t)blockIdx.x * 2 * max_t;  // chunk products of alpha
     cd* cb = ca + max_t;                                 // chunk products of beta
 
-    // 1. potential, slope and absorber at every (padded) point
+    // 1. potential, slope, absorber and om at every (padded) point
+    const double habs = sqrt(P.h.re * P.h.re + P.h.im * P.h.im);
+    const double kw = 12.0 * habs;
     for (int j = threadIdx.x; j < np; j += blockDim.x) {
-        const int idx = (j % C) * T + j / C;
+        const int idx = pidx(j / C, j % C, C);
         if (j < n) {
             const double x = ((double)j - 0.5 * (double)(n - 1)) * dx;
-            sc.pt.v[idx] = soft_core(x, P.a, P.z);
+            const double vj = soft_core(x, P.a, P.z);
+            sc.pt.v[idx] = vj;
+            sc.pt.om[idx] = kw * (vj / 12.0 - 0.5 / (dx * dx));
             sc.pt.dv[idx] = soft_core_slope(x, P.a, P.z);
             sc.pt.m[idx] = absorber(fabs(x), xmax, P.mask_frac, P.mask_pow);
         } else {
             sc.pt.v[idx] = 0.0;
+            sc.pt.om[idx] = 0.0;
             sc.pt.dv[idx] = 0.0;
             sc.pt.m[idx] = 0.0;
         }
@@ -67,7 +72,7 @@ __global__ void __launch_bounds__(256) build_tables_kernel(const SizeClass* clas
         const double inv_dx2 = 1.0 / (dx * dx);
         cd q_prev = czero(), u_prev = czero(), l_prev = czero();
         for (int j = 0; j < np; ++j) {
-            const int idx = (j % C) * T + j / C;
+            const int idx = pidx(j / C, j % C, C);
             cd alpha = czero(), q = czero(), beta = czero();
             if (j < n) {
                 const double vj = sc.pt.v[idx];
@@ -102,48 +107,46 @@ __global__ void __launch_bounds__(256) build_tables_kernel(const SizeClass* clas
     }
     __syncthreads();
 
-    // 3. per lane: in-chunk carry products, chunk products, ghost constants
+    // 3. per lane: chunk products of alpha and beta, ghost constants
     for (int t = threadIdx.x; t < T; t += blockDim.x) {
         cd pr = mkc(1.0, 0.0);
         int has = 0;
         for (int k = 0; k < C; ++k) {
-            pr = cmul(sc.pt.alpha[k * T + t], pr);
-            sc.pt.at[k * T + t] = pr;
-            if (sc.pt.m[k * T + t] != 1.0) has = 1;
+            pr = cmul(sc.pt.alpha[pidx(t, k, C)], pr);
+            if (sc.pt.m[pidx(t, k, C)] != 1.0) has = 1;
         }
         ca[t] = pr;
         pr = mkc(1.0, 0.0);
-        for (int k = C - 1; k >= 0; --k) {
-            pr = cmul(sc.pt.beta[k * T + t], pr);
-            sc.pt.bt[k * T + t] = pr;
-        }
+        for (int k = C - 1; k >= 0; --k) pr = cmul(sc.pt.beta[pidx(t, k, C)], pr);
         cb[t] = pr;
         sc.lt.hasmask[t] = has;
         const int s = t * C;
+        LaneConst kc;
         if (s > 0) {
-            const int il = (C - 1) * T + (t - 1);
-            sc.lt.vl[t] = sc.pt.v[il];
-            sc.lt.ml[t] = sc.pt.m[il];
-            sc.lt.dvl[t] = sc.pt.dv[il];
-            sc.lt.ql[t] = sc.pt.q[il];
-            sc.lt.bl[t] = sc.pt.beta[il];
+            const int il = pidx(t - 1, C - 1, C);
+            kc.oml = sc.pt.om[il];
+            kc.ml = sc.pt.m[il];
+            kc.dvl = sc.pt.dv[il];
+            kc.ql = sc.pt.q[il];
+            kc.bl = sc.pt.beta[il];
         } else {
-            sc.lt.vl[t] = 0.0;
-            sc.lt.ml[t] = 0.0;
-            sc.lt.dvl[t] = 0.0;
-            sc.lt.ql[t] = czero();
-            sc.lt.bl[t] = czero();
+            kc.oml = 0.0;
+            kc.ml = 0.0;
+            kc.dvl = 0.0;
+            kc.ql = czero();
+            kc.bl = czero();
         }
         if (t + 1 < T) {
-            const int ir = t + 1;  // k = 0 of lane t+1
-            sc.lt.vr[t] = sc.pt.v[ir];
-            sc.lt.mr[t] = sc.pt.m[ir];
-            sc.lt.dvr[t] = sc.pt.dv[ir];
+            const int ir = pidx(t + 1, 0, C);
+            kc.omr = sc.pt.om[ir];
+            kc.mr = sc.pt.m[ir];
+            kc.dvr = sc.pt.dv[ir];
         } else {
-            sc.lt.vr[t] = 0.0;
-            sc.lt.mr[t] = 0.0;
-            sc.lt.dvr[t] = 0.0;
+            kc.omr = 0.0;
+            kc.mr = 0.0;
+            kc.dvr = 0.0;
         }
+        sc.lt.k[t] = kc;
     }
     __syncthreads();
 
