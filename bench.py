@@ -36,6 +36,57 @@ sys.path.insert(0, ROOT)
 
 FLOPS_PER_POINT_STEP = 52.0        # algorithmic FP64 flops per grid-point-step
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
+CSRC = os.path.join(ROOT, "paper_2507_04115_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def source_digest() -> str:
+    """sha256 over the kernel sources; HBM counters are valid only for this digest."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def read_traffic(workload: str):
+    """HBM bytes per forward launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, each scaled by the same counter's reading
+    for a plain device copy of known size).  None when the summary is missing
+    or was taken from different kernel sources."""
+    path = os.path.join(PROFILES, f"forward_kernel_{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#") and "=" in line:
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_digest():
+        return None
+    cb = float(kv["copy_bytes"])
+    f_scale = cb / (1024.0 * float(kv["copy_fetch_kib"]))
+    w_scale = cb / (1024.0 * float(kv["copy_write_kib"]))
+    return 1024.0 * (f_scale * float(kv["fetch_kib_per_dispatch"]) +
+                     w_scale * float(kv["write_kib_per_dispatch"]))
+
+
+def calibrate_copy(mib: int):
+    """A plain device-to-device copy of known size, for scaling HBM counters."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8}), flush=True)
 
 
 def log(msg):
@@ -53,11 +104,18 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run one device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
-              "(systems are independent; sharding is described in DESIGN.md)", file=sys.stderr)
+              "(the systems are independent; a multi-GPU run would give each GPU its own "
+              "plan over a share of them)", file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
 
     import torch
 
@@ -123,7 +181,7 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None,
+                     "traffic": read_traffic(w.name),
                      "kernel": "forward_kernel (graph replay incl. counter reset)",
                      "flops_per_grid_point_step": FLOPS_PER_POINT_STEP},
     }
