@@ -1,0 +1,110 @@
+"""torch.autograd.Function wrappers over the HIP forward, adjoint and
+harmonic-yield kernels.  They only marshal tensors into the C-ABI calls of
+``binding``; the forward pass, the reverse (costate) sweep and the loss and
+its gradient all run in libtdse.
+
+    plan  = binding.Plan(params, n_per_system, adjoint_k=256)
+    accel = TDSEFunction.apply(E, plan)                    # [P, nt+1]
+    y     = HarmonicYield.apply(accel, dt, omega0, 21, 31) # [P]
+    y.sum().backward()                                     # E.grad = d sum(y) / dE
+
+The gradient is the exact discrete adjoint of the forward map (the paper
+solves the forward problem only, section "1D-TSDE Implementation (CTDSE)"),
+so it agrees with finite differences of the forward outputs to rounding.
+The initial state is a constant of the map (no gradient with respect to
+psi0).
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import torch
+
+from . import binding as L
+
+__all__ = ["TDSEFunction", "HarmonicYield", "TDSEBatch"]
+
+
+def _check_field(E: torch.Tensor, plan: "L.Plan"):
+    if E.dtype != torch.float64 or not E.is_cuda:
+        raise TypeError("E must be a float64 tensor on the GPU")
+    if E.dim() != 2 or E.shape[0] != plan.batch or E.shape[1] != plan.params.nt + 1:
+        raise ValueError(f"E must have shape [{plan.batch}, {plan.params.nt + 1}], "
+                         f"got {tuple(E.shape)}")
+
+
+class TDSEFunction(torch.autograd.Function):
+    """accel = TDSEFunction.apply(E, plan, psi0=None).
+
+    forward:  tdse_propagate_batch -> dipole acceleration [P, nt+1]
+    backward: tdse_adjoint_batch with accel_bar = grad_output -> dl/dE
+    The plan must have been created with adjoint_k > 0 for backward."""
+
+    @staticmethod
+    def forward(ctx, E: torch.Tensor, plan: "L.Plan", psi0: Optional[torch.Tensor] = None):
+        _check_field(E, plan)
+        E = E.contiguous()
+        accel = torch.empty_like(E)
+        L.tdse_propagate_batch(plan, E, psi0, accel)
+        ctx.plan = plan
+        ctx.psi0 = psi0
+        ctx.save_for_backward(E)
+        return accel
+
+    @staticmethod
+    def backward(ctx, grad_accel: torch.Tensor):
+        (E,) = ctx.saved_tensors
+        if ctx.plan.adjoint_k <= 0:
+            raise RuntimeError("the plan was created without adjoint support (adjoint_k = 0)")
+        grad_E = torch.empty_like(E)
+        L.tdse_adjoint_batch(ctx.plan, E, ctx.psi0, grad_accel.contiguous(), grad_E)
+        return grad_E, None, None
+
+
+class HarmonicYield(torch.autograd.Function):
+    """y = HarmonicYield.apply(accel, dt, omega0, h_lo, h_hi): per-row Hann-
+    windowed yield of harmonics h_lo..h_hi (tdse_harmonic_yield).  backward
+    calls the same kernel with row_weight = grad_output, which returns
+    grad_output[b] * d y[b] / d accel[b]."""
+
+    @staticmethod
+    def forward(ctx, accel: torch.Tensor, dt: float, omega0: float, h_lo: float, h_hi: float):
+        if accel.dtype != torch.float64 or not accel.is_cuda or accel.dim() != 2:
+            raise TypeError("accel must be a 2-D float64 tensor on the GPU")
+        accel = accel.contiguous()
+        batch, n1 = accel.shape
+        _, nk = L.tdse_harmonic_band(n1 - 1, dt, omega0, h_lo, h_hi)
+        work = torch.empty(2 * batch * max(nk, 1), dtype=torch.float64, device=accel.device)
+        y = torch.empty(batch, dtype=torch.float64, device=accel.device)
+        L.tdse_harmonic_yield(batch, n1 - 1, dt, omega0, h_lo, h_hi, accel, None, work, y)
+        ctx.args = (dt, omega0, h_lo, h_hi)
+        ctx.save_for_backward(accel)
+        return y
+
+    @staticmethod
+    def backward(ctx, grad_y: torch.Tensor):
+        (accel,) = ctx.saved_tensors
+        dt, omega0, h_lo, h_hi = ctx.args
+        batch, n1 = accel.shape
+        _, nk = L.tdse_harmonic_band(n1 - 1, dt, omega0, h_lo, h_hi)
+        work = torch.empty(2 * batch * max(nk, 1), dtype=torch.float64, device=accel.device)
+        y = torch.empty(batch, dtype=torch.float64, device=accel.device)
+        abar = torch.empty_like(accel)
+        L.tdse_harmonic_yield(batch, n1 - 1, dt, omega0, h_lo, h_hi, accel,
+                              grad_y.contiguous(), work, y, abar)
+        return abar, None, None, None, None
+
+
+class TDSEBatch:
+    """A batch of systems with a plan that supports the adjoint:
+    ``TDSEBatch(params, n_per)(E)`` is TDSEFunction.apply(E, plan)."""
+
+    def __init__(self, params: "L.tdse_params", n_per_system: Sequence[int], adjoint_k: int = 256,
+                 options: int = 0):
+        self.plan = L.Plan(params, n_per_system, options=options, adjoint_k=adjoint_k)
+
+    def __call__(self, E: torch.Tensor, psi0: Optional[torch.Tensor] = None) -> torch.Tensor:
+        return TDSEFunction.apply(E, self.plan, psi0)
+
+    def close(self):
+        self.plan.close()

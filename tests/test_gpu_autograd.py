@@ -1,0 +1,111 @@
+"""torch.autograd path (paper_2507_04115_amd.autograd) on the GPU: the
+gradient of a harmonic-yield loss through TDSEFunction / HarmonicYield
+against the CPU oracle's adjoint of the same loss and against central
+differences of the GPU forward map (bar: 1e-5 relative)."""
+import numpy as np
+import pytest
+
+import oracle
+import tdse_inputs as ti
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.fixture(scope="module")
+def setup(lib):
+    import torch
+
+    from paper_2507_04115_amd import autograd as AG
+
+    dev = torch.device("cuda:0")
+    ns = [256, 320, 256]
+    dx, dt, a = 0.4, 0.05, 1.1
+    om, nc = 0.25, 3
+    nt = ti.n_steps(om, nc, dt)
+    efield = ti.sin2_pulse(np.array([0.1, 0.08, 0.12]), om, nc, dt, nt=nt)
+    p = lib.make_params(dx, dt, a, nt, mask_fraction=0.2)
+    batch = AG.TDSEBatch(p, ns, adjoint_k=64)
+    yield dict(torch=torch, dev=dev, AG=AG, ns=ns, dx=dx, dt=dt, a=a, om=om, nt=nt,
+               efield=efield, batch=batch)
+    batch.close()
+
+
+def test_yield_gradient_matches_oracle_adjoint(setup, lib):
+    s = setup
+    torch, AG = s["torch"], s["AG"]
+    print(f"autograd yield gradient ns={s['ns']} nt={s['nt']}", flush=True)
+    E = torch.tensor(s["efield"], dtype=torch.float64, device=s["dev"], requires_grad=True)
+    acc = s["batch"](E)
+    w = torch.tensor([1.0, 0.5, 2.0], dtype=torch.float64, device=s["dev"])
+    y = AG.HarmonicYield.apply(acc, s["dt"], s["om"], 3, 9)
+    (w * y).sum().backward()
+    g = E.grad.cpu().numpy()
+    acc_h = acc.detach().cpu().numpy()
+    y_ref, abar = oracle.harmonic_yield(acc_h, s["dt"], s["om"], 3, 9)
+    assert rel(y.detach().cpu().numpy(), y_ref) < 1e-12
+    for b in range(3):
+        psi0 = torch.empty(2 * s["ns"][b], dtype=torch.float64, device=s["dev"])
+        s["batch"].plan.ground_state(s["ns"][b], psi0)
+        g_ref, _ = oracle.adjoint(s["efield"][b], psi0.cpu().numpy().view(np.complex128),
+                                  float(w[b]) * abar[b], s["dx"], s["dt"], s["a"], mask_frac=0.2,
+                                  k=64)
+        r = rel(g[b], g_ref)
+        print(f"  system {b}: grad rel-L2 vs oracle adjoint {r:.3e}", flush=True)
+        assert r < 1e-9
+
+
+def test_gradient_matches_central_differences_of_gpu_forward(setup, lib):
+    s = setup
+    torch, AG = s["torch"], s["AG"]
+    E = torch.tensor(s["efield"], dtype=torch.float64, device=s["dev"], requires_grad=True)
+    loss = AG.HarmonicYield.apply(s["batch"](E), s["dt"], s["om"], 3, 9).sum()
+    loss.backward()
+    g = E.grad.detach()
+    h = 1e-6
+    for d in range(2):
+        v = torch.tensor(ti.probe_directions(E.shape, d), dtype=torch.float64, device=s["dev"])
+        with torch.no_grad():
+            lp = AG.HarmonicYield.apply(s["batch"](E + h * v), s["dt"], s["om"], 3, 9).sum()
+            lm = AG.HarmonicYield.apply(s["batch"](E - h * v), s["dt"], s["om"], 3, 9).sum()
+        fd = float((lp - lm) / (2 * h))
+        ad = float((g * v).sum())
+        print(f"  direction {d}: FD {fd:.10e} adjoint {ad:.10e}", flush=True)
+        assert abs(fd - ad) <= 1e-5 * abs(fd)
+
+
+def test_torch_side_loss_chains_through_adjoint(setup, lib):
+    """A loss written with torch ops on the acceleration: accel_bar comes from
+    torch autograd, the rest from the adjoint kernel."""
+    s = setup
+    torch = s["torch"]
+    E = torch.tensor(s["efield"], dtype=torch.float64, device=s["dev"], requires_grad=True)
+    acc = s["batch"](E)
+    (0.5 * (acc ** 2).sum()).backward()
+    g = E.grad.cpu().numpy()
+    acc_h = acc.detach().cpu().numpy()
+    for b in (0, 2):
+        psi0 = torch.empty(2 * s["ns"][b], dtype=torch.float64, device=s["dev"])
+        s["batch"].plan.ground_state(s["ns"][b], psi0)
+        g_ref, _ = oracle.adjoint(s["efield"][b], psi0.cpu().numpy().view(np.complex128),
+                                  acc_h[b], s["dx"], s["dt"], s["a"], mask_frac=0.2, k=64)
+        r = rel(g[b], g_ref)
+        print(f"  system {b}: grad rel-L2 (torch loss) {r:.3e}", flush=True)
+        assert r < 1e-9
+
+
+def test_backward_without_adjoint_plan_raises(lib):
+    import torch
+
+    from paper_2507_04115_amd import autograd as AG
+
+    p = lib.make_params(0.4, 0.05, 1.1, 20, mask_fraction=0.2)
+    plan = lib.Plan(p, [256])
+    E = torch.zeros(1, 21, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    acc = AG.TDSEFunction.apply(E, plan)
+    with pytest.raises(RuntimeError):
+        acc.sum().backward()
+    plan.close()
