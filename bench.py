@@ -99,7 +99,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="focus",
-                    choices=["focus", "single", "uneven", "uneven-wide", "volume"])
+                    choices=["focus", "single", "uneven", "uneven-wide", "volume", "sweep"])
+    ap.add_argument("--sweep-n", type=int, default=8192, help="grid size of the sweep workload")
     ap.add_argument("--plain-systems", type=int, default=8)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -130,7 +131,8 @@ def main():
 
     w = {"focus": ti.cfg2_focus, "single": ti.cfg1_single, "uneven": ti.cfg3_uneven,
          "uneven-wide": lambda: ti.cfg3_uneven(wide=True),
-         "volume": ti.cfg5_volume}[args.workload]()
+         "volume": ti.cfg5_volume,
+         "sweep": lambda: ti.size_sweep(args.sweep_n)}[args.workload]()
     a_sc, e_g = L.tdse_soft_core_for_ip(w.ip, 2048, w.dx, dtau=1.0, tol=1e-13)
     log(f"workload {w.name}: P={w.batch} nt={w.nt} soft-core a={a_sc:.10f} (E_g={e_g:.13f})")
     p = L.make_params(w.dx, w.dt, a_sc, w.nt, mask_fraction=w.mask_frac, mask_power=w.mask_pow)

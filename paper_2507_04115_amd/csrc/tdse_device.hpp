@@ -92,6 +92,21 @@ __device__ __forceinline__ T* launder_s(T* p)
 // per SIMD latency is hidden across waves, and hoisting would only raise
 // register pressure (and force spills).
 #define TDSE_POINT_FENCE() __builtin_amdgcn_sched_barrier(0)
+__device__ __forceinline__ void point_fence(cd a)
+{
+    asm volatile("" ::"v"(a.re), "v"(a.im));
+    __builtin_amdgcn_sched_barrier(0);
+}
+__device__ __forceinline__ void point_fence(cd a, cd b)
+{
+    asm volatile("" ::"v"(a.re), "v"(a.im), "v"(b.re), "v"(b.im));
+    __builtin_amdgcn_sched_barrier(0);
+}
+__device__ __forceinline__ void point_fence(double a, double b)
+{
+    asm volatile("" ::"v"(a), "v"(b));
+    __builtin_amdgcn_sched_barrier(0);
+}
 
 // Loads a wave-uniform record into scalar registers.  Work items arrive
 // through LDS, so the compiler cannot prove the record uniform on its own.
@@ -409,7 +424,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd gl, cd gr, const TV& tb,
             prev = cur;
             wprev = wcur;
             wcur = wn;
-            TDSE_POINT_FENCE();
+            point_fence(r, ze);
         }
     }
     cf = scan_fwd(ze, sc, lc, lds_f);
@@ -426,7 +441,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd gl, cd gr, const TV& tb,
             v[k] = cmul(qk, z);
             wp = tb.om(b0 + 64 * k);
             qp = qk;
-            TDSE_POINT_FENCE();
+            point_fence(v[k]);
         }
     }
     // C. chunk-start value of y with zero carry-in
@@ -439,7 +454,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd gl, cd gr, const TV& tb,
             const cd qk = tb.q(b0 + 64 * k);
             yb = (k == C - 1) ? v[k] : cmad(elim<RT>(wn, qk), yb, v[k]);
             wn = tb.om(b0 + 64 * k);
-            TDSE_POINT_FENCE();
+            point_fence(yb);
         }
     }
     cb = scan_bwd(yb, sc, lc, lds_b);
@@ -454,7 +469,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd gl, cd gr, const TV& tb,
             y = cmad(elim<RT>(wn, qk), y, v[k]);
             v[k] = y;
             wn = tb.om(b0 + 64 * k);
-            TDSE_POINT_FENCE();
+            point_fence(y);
         }
     }
 }
@@ -480,14 +495,14 @@ __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e,
         for (int k = 0; k < C; ++k) {
             v[k] = cscale(ldg(sc.pt.m + b0 + 64 * k), cmul(ph, v[k]));
             ph = cmul(ph, w1);
-            TDSE_POINT_FENCE();
+            point_fence(v[k], ph);
         }
     } else {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             v[k] = cmul(ph, v[k]);
             ph = cmul(ph, w1);
-            TDSE_POINT_FENCE();
+            point_fence(v[k], ph);
         }
     }
     gr = cscale(lc.mr(), cmul(ph, gr));
@@ -629,7 +644,7 @@ __device__ __forceinline__ void observe(const cd (&v)[C], const TV& tb, int T,
         sn += p;
         sk = fma((double)k, p, sk);
         sv = fma(tb.dv(b0 + 64 * k), p, sv);
-        TDSE_POINT_FENCE();
+        point_fence(sv, sn);
     }
     double sx = fma(xs, sn, dx * sk);
     sn = wave_sum(sn);

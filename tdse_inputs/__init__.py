@@ -148,6 +148,15 @@ def cfg1_single() -> Workload:
                     np.array([field_amplitude(1.5e14)]), np.array([0.0]))
 
 
+def size_sweep(n: int, batch: int = 1024) -> Workload:
+    """Uniform batch of `batch` systems of N = n points with the single-system
+    pulse (dx = 0.2, dt = 0.05, 800 nm, 10 cycles, 1.5e14 W/cm^2): the size
+    sweep N in {2048, 4096, 8192, 16384}."""
+    om, nc, dt = 0.057, 10, 0.05
+    return Workload(f"sweep-{batch}x{n}", 0.2, dt, om, nc, n_steps(om, nc, dt), [n] * batch,
+                    np.full(batch, field_amplitude(1.5e14)), np.zeros(batch))
+
+
 def cfg2_focus(nr: int = 32, nz: int = 32) -> Workload:
     """Gaussian focus, 32 r x 32 z points, w0 = 50 um, 800 nm, 2e14 W/cm^2,
     20 cycles, N = 4096, dx = 0.2, dt = 0.05."""
