@@ -121,6 +121,20 @@ __device__ __forceinline__ T uniform_load(const T* p)
     for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
     return out;
 }
+// Loads a record whose address is wave-uniform (held in SGPRs) through the
+// constant address space, which the compiler turns into scalar loads.
+template <class T>
+__device__ __forceinline__ T scalar_load(const T* p)
+{
+    static_assert(sizeof(T) % 4 == 0, "scalar_load needs a 4-byte multiple");
+    typedef const __attribute__((address_space(4))) int* cptr;
+    const cptr src = (cptr)(p);
+    T out;
+    int* dst = reinterpret_cast<int*>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+    return out;
+}
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // A double constant materialised by two scalar moves where it is used.  FP64
@@ -209,8 +223,15 @@ __device__ __forceinline__ void sincos_step(double x, double* s, double* c)
 template <int CTRL, int ROWMASK = 0xf>
 __device__ __forceinline__ double dpp_d(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    int lo, hi;
+    if (ROWMASK == 0xf) {
+        // every row written; bound_ctrl makes lanes without a source read 0
+        lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+        hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
+        hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    }
     return __hiloint2double(hi, lo);
 }
 // lane i receives lane i-1 (lane 0 receives 0)
@@ -596,7 +617,7 @@ template <bool LDSTAB>
 __device__ __forceinline__ StepView<LDSTAB> step_view(const SizeClass* cls, int t, double* smem)
 {
     StepView<LDSTAB> v;
-    v.sc = uniform_load(launder_s(cls));
+    v.sc = scalar_load(launder_s(cls));
     v.lc = make_lane_ctx(v.sc, opaque(t));
     v.tb = TableSource<LDSTAB>::view(v.sc, smem);
     v.rc = make_rhs_coef(v.sc.habs, v.sc.dx);
