@@ -107,7 +107,6 @@ size_t class_bytes(const Layout& L)
     auto add = [&](size_t bytes) { b += (bytes + 255) & ~size_t(255); };
     for (int i = 0; i < 4; ++i) add(np * sizeof(double));
     for (int i = 0; i < 3; ++i) add(np * sizeof(cd));
-    add(T * sizeof(LaneConst));
     for (int i = 0; i < 2; ++i) add(kMaxLevels * T * sizeof(cd));
     for (int i = 0; i < 2; ++i) add(T * sizeof(cd));
     add(T * sizeof(int32_t));
@@ -124,7 +123,6 @@ void carve_class(Arena& ar, SizeClass& sc)
     sc.pt.q = ar.take<cd>(np);
     sc.pt.alpha = ar.take<cd>(np);
     sc.pt.beta = ar.take<cd>(np);
-    sc.lt.k = ar.take<LaneConst>(T);
     sc.lt.pa = ar.take<cd>(kMaxLevels * T);
     sc.lt.qb = ar.take<cd>(kMaxLevels * T);
     sc.lt.pw = ar.take<cd>(T);

@@ -110,11 +110,12 @@ __device__ __forceinline__ void add_source(cd (&kap)[C], cd& kgl, cd& kgr, const
                                            cd gl, cd gr, double ci, double e, const TV& tb,
                                            int T, const LaneCtx& lc)
 {
-    const int b0 = opaque(pbase(lc.t, C));
 #pragma unroll
-    for (int k = 0; k < C; ++k) kap[k] = cadd(kap[k], cscale(ci * (tb.dv(b0 + 64 * k) + e), cconj(psi[k])));
-    kgl = cadd(kgl, cscale(ci * (lc.dvl() + e), cconj(gl)));
-    kgr = cadd(kgr, cscale(ci * (lc.dvr() + e), cconj(gr)));
+    for (int k = 0; k < C; ++k)
+        kap[k] = cadd(kap[k], cscale(ci * (tb.dv(lc.b0 + 64 * k) + e), cconj(psi[k])));
+    // the clamped neighbour indices of the end lanes meet zero ghost values
+    kgl = cadd(kgl, cscale(ci * (tb.dv(lc.il) + e), cconj(gl)));
+    kgr = cadd(kgr, cscale(ci * (tb.dv(lc.ir) + e), cconj(gr)));
 }
 
 }  // namespace
@@ -128,7 +129,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
     const int S = blockDim.x / T;
     const int tid = threadIdx.x, sub = tid / T, t = tid - sub * T;
     const size_t sb = a.sub_bytes;
-    char* per = reinterpret_cast<char*>(smem_raw + (LDSTAB ? 4 * np : 0));
+    char* per = reinterpret_cast<char*>(smem_raw) + (LDSTAB ? kLdsTableBytes * np : 0);
     const SubSmem sm = carve_sub(per + sub * sb, W);
     int* wg_item = reinterpret_cast<int*>(per + S * sb);
     TableSource<LDSTAB>::make(sc, smem_raw);  // stages the tables once per workgroup
@@ -184,6 +185,11 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
         for (int k = 0; k < C; ++k) v[k] = (active && s + k < n) ? ld_psi(src, s + k) : czero();
         cd gl = (active && s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
         cd gr = (active && s + C < n) ? ld_psi(src, s + C) : czero();
+        LaneFactors<C> f;
+        {
+            const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
+            f = load_factors<C>(sv.sc, sv.lc);
+        }
         int flushed = 0;
         const int nfwd = (wg_need || a.accel) ? nt : -1;  // uniform
         for (int i = 0; i <= nfwd; ++i) {
@@ -191,8 +197,8 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
             if (i % K == 0) store_state<C>(ckpt + np2 * (i / K), T, t, v, gl, gr);
             observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, ring + (i % kRing) * W * 3);
             if (i == nt) break;
-            forward_step<C>(v, gl, gr, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f,
-                            sm.lds_b);
+            forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
+                            sm.lds_f, sm.lds_b);
             if ((i + 1) % kFlush == 0) {
                 __syncthreads();
                 if (active) flush_norm(i + 1 - kFlush, i, t, T, ring, W, dx, erow, acc_row, n_row, flag);
@@ -219,7 +225,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
             store_state<C>(seg, T, t, v, gl, gr);
             for (int i = s0; i < s1; ++i) {
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
-                forward_step<C>(v, gl, gr, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
+                forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
                                 sm.lds_f, sm.lds_b);
                 store_state<C>(seg + np2 * (i - s0 + 1), T, t, v, gl, gr);
             }
@@ -240,12 +246,8 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
                 // kappa <- U (D_i kappa)
                 const double e = erow[i];
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
-                phase_mask<C>(kap, kgl, kgr, e, a.dt, sv.xl, dx, sv.sc, sv.lc);
-                cd cf, cb;
-                cn_apply<C, true>(kap, kgl, kgr, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b, cf,
-                                  cb);
-                kgl = cmad(sv.lc.ql(), cf, cmul(sv.lc.bl(), kap[0]));
-                kgr = cb;
+                phase_mask<C>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc, sv.lc);
+                cn_apply<C, true>(kap, kgl, kgr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
                 // + 2 abar_i dx (V' + E_i) conj(psi^i)
                 load_state<C>(seg + np2 * (i - s0), T, t, v, gl, gr);
                 add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[i] * dx, e, sv.tb, T, sv.lc);
@@ -270,7 +272,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
 
 size_t adjoint_smem_bytes(int C, int T, int S, bool lds_tables)
 {
-    return (lds_tables ? sizeof(double) * 4 * (size_t)C * T : 0) + S * sub_smem_bytes(T / kWave) +
+    return (lds_tables ? (size_t)kLdsTableBytes * C * T : 0) + S * sub_smem_bytes(T / kWave) +
            16;
 }
 

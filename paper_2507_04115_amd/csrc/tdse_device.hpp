@@ -264,54 +264,101 @@ __device__ __forceinline__ double wave_sum(double x)
 constexpr int kSumLane = kWave - 1;  // lane holding wave_sum's result
 
 // ------------------------------------------------------------ table views
-// Point tables seen through LDS (shared by every system of a workgroup) or
-// directly in global memory (grids too large for LDS).
+// om and dV/dx of a size class seen through LDS (staged once per workgroup,
+// shared by its systems) or directly in global memory.  The pivot factors q
+// live in registers instead (LaneFactors).
 template <bool GLOBAL>
 struct TabViewT {
     const double* om_;
-    const cd* q_;
     const double* dv_;
     __device__ __forceinline__ double om(int i) const { return GLOBAL ? ldg(om_ + i) : om_[i]; }
-    __device__ __forceinline__ cd q(int i) const { return GLOBAL ? ldg(q_ + i) : q_[i]; }
     __device__ __forceinline__ double dv(int i) const { return GLOBAL ? ldg(dv_ + i) : dv_[i]; }
 };
 using TabLds = TabViewT<false>;
 using TabGlobal = TabViewT<true>;
 
 // ------------------------------------------------------------ lane context
-// Lane coordinates plus accessors for the per-lane constants of a size
-// class.  The constants are read where they are used (L1-resident, a few
-// loads per step) rather than pinned in registers for the whole time loop.
+// Lane coordinates within the system's subgroup and the table indices of the
+// two points next to the lane's chunk (clamped to the lane's own points at
+// the ends of the grid, where the ghost values they multiply are zero).
 struct LaneCtx {
     int lane;   // lane in wavefront
     int wave;   // wavefront within the system's subgroup
     int W;      // wavefronts per system
     int t;      // lane index within the system (0..T-1)
     int s;      // first grid point of the lane's chunk
-    const LaneConst* kk;
-    int hasmask;
-    __device__ __forceinline__ const LaneConst* K() const { return kk + opaque(t); }
-    __device__ __forceinline__ double oml() const { return ldg(&K()->oml); }
-    __device__ __forceinline__ double omr() const { return ldg(&K()->omr); }
-    __device__ __forceinline__ double ml() const { return ldg(&K()->ml); }
-    __device__ __forceinline__ double mr() const { return ldg(&K()->mr); }
-    __device__ __forceinline__ double dvl() const { return ldg(&K()->dvl); }
-    __device__ __forceinline__ double dvr() const { return ldg(&K()->dvr); }
-    __device__ __forceinline__ cd ql() const { return ldg(&K()->ql); }
-    __device__ __forceinline__ cd bl() const { return ldg(&K()->bl); }
+    int b0;     // table index of the chunk's first point
+    int il;     // table index of point s-1
+    int ir;     // table index of point s+C
 };
 
 __device__ __forceinline__ LaneCtx make_lane_ctx(const SizeClass& sc, int t)
 {
     LaneCtx c;
+    const int C = sc.C;
     c.lane = t & (kWave - 1);
     c.wave = t / kWave;
     c.W = sc.T / kWave;
     c.t = t;
-    c.s = t * sc.C;
-    c.kk = sc.lt.k;
-    c.hasmask = sc.lt.hasmask[t];
+    c.s = t * C;
+    c.b0 = pbase(t, C);
+    c.il = t > 0 ? pidx(t - 1, C - 1, C) : c.b0;
+    c.ir = t + 1 < sc.T ? pidx(t + 1, 0, C) : c.b0;
     return c;
+}
+
+// Pivot factors q are held in registers for a whole propagation when the
+// chunk is short enough (C <= 8: 4C + 4 VGPRs); with 16 points per lane they
+// would not fit beside the chunk itself and are read from global memory
+// (L2-resident) where they are used.
+template <int C>
+struct QInRegs {
+    static constexpr bool value = C <= 8;
+};
+
+// Per-lane factors: q at the C points of the chunk and at the point before
+// it (when held in registers), and the absorber flags (bit 0: a mask value of
+// the chunk differs from 1; bit 1: at s-1; bit 2: at s+C).
+template <int C>
+struct LaneFactors {
+    static constexpr int NQ = QInRegs<C>::value ? C : 1;
+    cd q_[NQ];
+    cd ql_;
+    int mflags;
+    // q at point k of the chunk and at s-1 (zero for the first lane)
+    __device__ __forceinline__ cd q(int k, const SizeClass& sc, const LaneCtx& lc) const
+    {
+        if constexpr (QInRegs<C>::value) return q_[k];
+        else return ldg(sc.pt.q + lc.b0 + 64 * k);
+    }
+    __device__ __forceinline__ cd ql(const SizeClass& sc, const LaneCtx& lc) const
+    {
+        if constexpr (QInRegs<C>::value) return ql_;
+        else return lc.t > 0 ? ldg(sc.pt.q + lc.il) : czero();
+    }
+};
+
+template <int C>
+__device__ __forceinline__ LaneFactors<C> load_factors(const SizeClass& sc, const LaneCtx& lc)
+{
+    LaneFactors<C> f;
+    if constexpr (QInRegs<C>::value) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) f.q_[k] = ldg(sc.pt.q + lc.b0 + 64 * k);
+        f.ql_ = lc.t > 0 ? ldg(sc.pt.q + lc.il) : czero();
+    } else {
+        f.q_[0] = czero();
+        f.ql_ = czero();
+    }
+    f.mflags = ldg(sc.lt.hasmask + lc.t);
+    return f;
+}
+
+// Unsigned byte offset of lane t in a per-lane array of 16-byte records;
+// loads through it use a scalar base register plus one vector offset.
+__device__ __forceinline__ cd ld_lane(const cd* base, unsigned off_bytes)
+{
+    return ldg(reinterpret_cast<const cd*>(reinterpret_cast<const char*>(base) + off_bytes));
 }
 
 // ------------------------------------------------------------ carry scans
@@ -321,28 +368,30 @@ __device__ __forceinline__ LaneCtx make_lane_ctx(const SizeClass& sc, int t)
 // `levels` levels with precomputed window products, then one cross-wave
 // correction through LDS; windows longer than 2^levels lanes are dropped
 // only when the host has verified that their products are below 2^-56.
-__device__ __forceinline__ cd scan_fwd(cd z, const SizeClass& sc, const LaneCtx& lc, cd* lds)
+// a0, a1, aw: the lane's window products of levels 0 and 1 and of the
+// cross-wave correction, loaded by the caller ahead of time.
+__device__ __forceinline__ cd scan_fwd(cd z, cd a0, cd a1, cd aw, const SizeClass& sc,
+                                       const LaneCtx& lc, cd* lds)
 {
-    const int T = sc.T, t = opaque(lc.t);
+    const unsigned off = 16u * (unsigned)lc.t;
     // levels 0 and 1 shift by whole-wave DPP moves (lanes below the shift
     // receive 0, which leaves them unchanged); deeper levels use bpermute
-    if (sc.levels > 0) z = cmad(ldg(sc.lt.pa + t), wave_shr1(z), z);
-    if (sc.levels > 1) z = cmad(ldg(sc.lt.pa + T + t), wave_shr1(wave_shr1(z)), z);
-#pragma unroll
-    for (int lev = 2; lev < kMaxLevels; ++lev) {
-        if (lev < sc.levels) {
-            const int d = 1 << lev;
-            cd zs = shfl_up_c(z, d);
-            if (lc.lane >= d) z = cmad(ldg(sc.lt.pa + lev * T + t), zs, z);
-        }
+    if (sc.levels > 0) z = cmad(a0, wave_shr1(z), z);
+    if (sc.levels > 1) z = cmad(a1, wave_shr1(wave_shr1(z)), z);
+    for (int lev = 2; lev < sc.levels; ++lev) {
+        const int d = 1 << lev;
+        cd zs = shfl_up_c(z, d);
+        const cd p = ld_lane(sc.lt.pa + lev * sc.T, off);
+        if (lc.lane >= d) z = cmad(p, zs, z);
     }
     cd prev = czero();
     if (lc.W > 1) {
         if (lc.lane == kWave - 1) lds[lc.wave] = z;
         __syncthreads();
         const int v0 = max(0, lc.wave - sc.xwaves);
-        for (int w = v0; w < lc.wave; ++w) prev = cmad(ldg(sc.lt.pw + w * kWave + kWave - 1), prev, lds[w]);
-        if (lc.lane < (1 << sc.levels)) z = cmad(ldg(sc.lt.pw + t), prev, z);
+        for (int w = v0; w < lc.wave; ++w)
+            prev = cmad(ldg(sc.lt.pw + w * kWave + kWave - 1), prev, lds[w]);
+        if (lc.lane < (1 << sc.levels)) z = cmad(aw, prev, z);
     }
     const cd up = wave_shr1(z);
     return lc.lane == 0 ? prev : up;
@@ -350,18 +399,17 @@ __device__ __forceinline__ cd scan_fwd(cd z, const SizeClass& sc, const LaneCtx&
 
 // Backward carries of y_j = w_j + beta_j y_{j+1}, mirrored: returns the true y
 // at the point just after the lane's chunk.
-__device__ __forceinline__ cd scan_bwd(cd y, const SizeClass& sc, const LaneCtx& lc, cd* lds)
+__device__ __forceinline__ cd scan_bwd(cd y, cd b0, cd b1, cd bw, const SizeClass& sc,
+                                       const LaneCtx& lc, cd* lds)
 {
-    const int T = sc.T, t = opaque(lc.t);
-    if (sc.levels > 0) y = cmad(ldg(sc.lt.qb + t), wave_shl1(y), y);
-    if (sc.levels > 1) y = cmad(ldg(sc.lt.qb + T + t), wave_shl1(wave_shl1(y)), y);
-#pragma unroll
-    for (int lev = 2; lev < kMaxLevels; ++lev) {
-        if (lev < sc.levels) {
-            const int d = 1 << lev;
-            cd ys = shfl_down_c(y, d);
-            if (lc.lane + d < kWave) y = cmad(ldg(sc.lt.qb + lev * T + t), ys, y);
-        }
+    const unsigned off = 16u * (unsigned)lc.t;
+    if (sc.levels > 0) y = cmad(b0, wave_shl1(y), y);
+    if (sc.levels > 1) y = cmad(b1, wave_shl1(wave_shl1(y)), y);
+    for (int lev = 2; lev < sc.levels; ++lev) {
+        const int d = 1 << lev;
+        cd ys = shfl_down_c(y, d);
+        const cd p = ld_lane(sc.lt.qb + lev * sc.T, off);
+        if (lc.lane + d < kWave) y = cmad(p, ys, y);
     }
     cd next = czero();
     if (lc.W > 1) {
@@ -369,130 +417,128 @@ __device__ __forceinline__ cd scan_bwd(cd y, const SizeClass& sc, const LaneCtx&
         __syncthreads();
         const int v1 = min(lc.W - 1, lc.wave + sc.xwaves);
         for (int w = v1; w > lc.wave; --w) next = cmad(ldg(sc.lt.qw + w * kWave), next, lds[w]);
-        if (lc.lane > kWave - 1 - (1 << sc.levels)) y = cmad(ldg(sc.lt.qw + t), next, y);
+        if (lc.lane > kWave - 1 - (1 << sc.levels)) y = cmad(bw, next, y);
     }
     const cd dn = wave_shl1(y);
     return lc.lane == kWave - 1 ? next : dn;
 }
 
 // ------------------------------------------------------------ CN core
-// Right-hand side 12 R psi with R = M2 - h A, A = -D2/2 + M2 diag(V):
-//   12 R psi_j = (psi_{j-1} + 10 psi_j + psi_{j+1})
-//                - h' (om_{j-1} psi_{j-1} + d_j psi_j + om_{j+1} psi_{j+1})
-// with om as in PointTables and d_j = 12|h| (1/dx^2 + 10 V_j/12)
-// = 10 om_j + dofs, dofs = 72 |h| / dx^2 (the diagonal of 12|h| A).
+// Right-hand side 12 R psi with R = M2 - h A, A = -D2/2 + M2 diag(V), h = h' |h|
+// (h' = i in real time, 1 in imaginary time).  With S the stencil
+// S(x)_j = x_{j-1} + 10 x_j + x_{j+1}, om as in PointTables and
+// dofs = 72 |h| / dx^2 (the diagonal of 12 |h| (-D2/2)):
+//   12 R psi = S(psi) - h' (S(om psi) + dofs psi)
+//            = (g_{j-1} + g_{j+1}) + 10 gh_j,
+//   g_j  = (1 - h' om_j) psi_j,   gh_j = (1 - h' (om_j + dofs/10)) psi_j.
+// om_j + dofs/10 is small where the kinetic and potential parts cancel, so
+// gh is formed from psi directly rather than from g.
 struct RhsCoef {
-    double dofs;
+    double dofs10;  // dofs / 10
 };
 __host__ __device__ inline RhsCoef make_rhs_coef(double habs, double dx)
 {
     RhsCoef c;
-    c.dofs = 72.0 * habs / (dx * dx);
+    c.dofs10 = 7.2 * habs / (dx * dx);
     return c;
 }
 
+// (1 - h' w) x
+template <bool RT>
+__device__ __forceinline__ cd gfac(double w, cd x)
+{
+    if (RT) return mkc(fma(w, x.im, x.re), fma(-w, x.re, x.im));
+    return mkc(fma(-w, x.re, x.re), fma(-w, x.im, x.im));
+}
+
 // Applies psi <- L^{-1} R psi (before the field phase and absorber) to the
-// lane's chunk v[0..C-1] whose neighbours are gl = psi_{s-1}, gr = psi_{s+C}.
-// Four sweeps over the chunk: right-hand side fused with the forward
-// recurrence from a zero carry (chunk-end value only); forward recurrence
-// from the exact carry with the pivot scaling; backward recurrence from a
-// zero carry (chunk-start value only); backward recurrence from the exact
-// carry.  Returns the exact carries cf = z_{s-1} and cb = y_{s+C}, from which
-// the caller rebuilds the ghost values of the next step without exchanging
+// lane's chunk v[0..C-1] whose neighbours are gl = psi_{s-1}, gr = psi_{s+C},
+// and replaces gl, gr by the new neighbour values.  Four sweeps over the
+// chunk: right-hand side fused with the forward recurrence from a zero carry
+// (chunk-end value only); forward recurrence from the exact carry with the
+// pivot scaling; backward recurrence from a zero carry (chunk-start value
+// only); backward recurrence from the exact carry.  The new neighbours follow
+// from the exact carries cf = z_{s-1} and cb = y_{s+C} without exchanging
 // data between lanes:  y_{s+C} = cb,  y_{s-1} = q_{s-1} cf + beta_{s-1} y_s.
 template <int C, bool RT, class TV>
-__device__ __forceinline__ void cn_apply(cd (&v)[C], cd gl, cd gr, const TV& tb,
-                                         const SizeClass& sc, const LaneCtx& lc, const RhsCoef rc,
-                                         cd* lds_f, cd* lds_b, cd& cf, cd& cb)
+__device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneFactors<C>& f,
+                                         const TV& tb, const SizeClass& sc, const LaneCtx& lc,
+                                         const RhsCoef rc, cd* lds_f, cd* lds_b)
 {
-    // A. right-hand side in place, chunk-end value of z with zero carry-in.
-    // Each sweep re-derives its table addresses from an opaque lane index so
-    // the compiler does not keep 2C addresses alive across sweeps.
+    const int b0 = lc.b0;
+    const unsigned off = 16u * (unsigned)lc.t;
+    const double oml = tb.om(lc.il);
+    const double omr = tb.om(lc.ir);
+    // window products of the forward scan, needed after sweep A
+    const cd a0 = sc.levels > 0 ? ld_lane(sc.lt.pa, off) : czero();
+    const cd a1 = sc.levels > 1 ? ld_lane(sc.lt.pa + sc.T, off) : czero();
+    const cd aw = ld_lane(sc.lt.pw, off);
+    // A. right-hand side in place, chunk-end value of z with zero carry-in
     cd ze = czero();
     {
-        const int b0 = opaque(pbase(lc.t, C));
-        cd prev = gl;
-        double wprev = lc.oml();
-        double wcur = tb.om(b0);
-        cd qprev = czero();
+        double om_p = oml;
+        double om_c = tb.om(b0);
+        cd g_p = gfac<RT>(oml, gl);
+        cd g_c = gfac<RT>(om_c, v[0]);
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            const cd cur = v[k];
-            const cd nxt = (k + 1 < C) ? v[k + 1] : gr;
-            const double wn = (k + 1 < C) ? tb.om(b0 + 64 * (k + 1)) : lc.omr();
-            const double dk = fma(10.0, wcur, rc.dofs);
-            double re = fma(10.0, cur.re, prev.re + nxt.re);
-            double im = fma(10.0, cur.im, prev.im + nxt.im);
-            if (RT) {  // r = S - i s
-                re = fma(wprev, prev.im, re);
-                re = fma(dk, cur.im, re);
-                re = fma(wn, nxt.im, re);
-                im = fma(-wprev, prev.re, im);
-                im = fma(-dk, cur.re, im);
-                im = fma(-wn, nxt.re, im);
-            } else {   // r = S - s
-                re = fma(-wprev, prev.re, re);
-                re = fma(-dk, cur.re, re);
-                re = fma(-wn, nxt.re, re);
-                im = fma(-wprev, prev.im, im);
-                im = fma(-dk, cur.im, im);
-                im = fma(-wn, nxt.im, im);
-            }
-            const cd r = mkc(re, im);
+            const double om_n = (k + 1 < C) ? tb.om(b0 + 64 * (k + 1)) : omr;
+            const cd g_n = gfac<RT>(om_n, (k + 1 < C) ? v[k + 1] : gr);
+            const cd gh = gfac<RT>(om_c + rc.dofs10, v[k]);
+            const cd r = mkc(fma(10.0, gh.re, g_p.re + g_n.re), fma(10.0, gh.im, g_p.im + g_n.im));
             v[k] = r;
-            ze = (k == 0) ? r : cmad(elim<RT>(wprev, qprev), ze, r);
-            qprev = tb.q(b0 + 64 * k);
-            prev = cur;
-            wprev = wcur;
-            wcur = wn;
+            ze = (k == 0) ? r : cmad(elim<RT>(om_p, f.q(k - 1, sc, lc)), ze, r);
+            g_p = g_c;
+            g_c = g_n;
+            om_p = om_c;
+            om_c = om_n;
             point_fence(r, ze);
         }
     }
-    cf = scan_fwd(ze, sc, lc, lds_f);
+    const cd cf = scan_fwd(ze, a0, a1, aw, sc, lc, lds_f);
+    const cd b0c = sc.levels > 0 ? ld_lane(sc.lt.qb, off) : czero();
+    const cd b1c = sc.levels > 1 ? ld_lane(sc.lt.qb + sc.T, off) : czero();
+    const cd bw = ld_lane(sc.lt.qw, off);
     // B. forward recurrence from the exact carry, w = q z
     {
-        const int b0 = opaque(pbase(lc.t, C));
         cd z = cf;
-        double wp = lc.oml();
-        cd qp = lc.ql();
+        double om_p = oml;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            z = cmad(elim<RT>(wp, qp), z, v[k]);
-            const cd qk = tb.q(b0 + 64 * k);
-            v[k] = cmul(qk, z);
-            wp = tb.om(b0 + 64 * k);
-            qp = qk;
+            z = cmad(elim<RT>(om_p, k == 0 ? f.ql(sc, lc) : f.q(k - 1, sc, lc)), z, v[k]);
+            v[k] = cmul(f.q(k, sc, lc), z);
+            if (k + 1 < C) om_p = tb.om(b0 + 64 * k);
             point_fence(v[k]);
         }
     }
     // C. chunk-start value of y with zero carry-in
-    cd yb = czero();
+    cd yb = v[C - 1];
     {
-        const int b0 = opaque(pbase(lc.t, C));
-        double wn = lc.omr();
 #pragma unroll
-        for (int k = C - 1; k >= 0; --k) {
-            const cd qk = tb.q(b0 + 64 * k);
-            yb = (k == C - 1) ? v[k] : cmad(elim<RT>(wn, qk), yb, v[k]);
-            wn = tb.om(b0 + 64 * k);
+        for (int k = C - 2; k >= 0; --k) {
+            const double om_n = tb.om(b0 + 64 * (k + 1));
+            yb = cmad(elim<RT>(om_n, f.q(k, sc, lc)), yb, v[k]);
             point_fence(yb);
         }
     }
-    cb = scan_bwd(yb, sc, lc, lds_b);
+    const cd cb = scan_bwd(yb, b0c, b1c, bw, sc, lc, lds_b);
     // D. backward recurrence from the exact carry
+    double om_0;
     {
-        const int b0 = opaque(pbase(lc.t, C));
         cd y = cb;
-        double wn = lc.omr();
+        double om_n = omr;
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
-            const cd qk = tb.q(b0 + 64 * k);
-            y = cmad(elim<RT>(wn, qk), y, v[k]);
+            y = cmad(elim<RT>(om_n, f.q(k, sc, lc)), y, v[k]);
             v[k] = y;
-            wn = tb.om(b0 + 64 * k);
+            om_n = tb.om(b0 + 64 * k);
             point_fence(y);
         }
+        om_0 = om_n;
     }
+    const cd ql = f.ql(sc, lc);
+    gl = cmad(ql, cf, cmul(elim<RT>(om_0, ql), v[0]));
+    gr = cb;
 }
 
 // Field substep exp(-i dt E x_j) and absorber m_j on the chunk and its two
@@ -500,21 +546,21 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd gl, cd gr, const TV& tb,
 // multiplication with exp(-i dt E dx); each lane starts from its own sincos.
 template <int C>
 __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e, double dt,
-                                           double xl, double dx, const SizeClass& sc,
-                                           const LaneCtx& lc)
+                                           double xl, double dx, int mflags,
+                                           const SizeClass& sc, const LaneCtx& lc)
 {
     double s0, c0, s1, c1;
     sincos_rr(-dt * e * xl, &s0, &c0);
     sincos_step(-dt * e * dx, &s1, &c1);
     cd ph = mkc(c0, s0);
     const cd w1 = mkc(c1, s1);
-    gl = cscale(lc.ml(), cmul(ph, gl));
+    gl = cmul(ph, gl);
+    if (mflags & 2) gl = cscale(ldg(sc.pt.m + lc.il), gl);
     ph = cmul(ph, w1);
-    if (lc.hasmask) {
-        const int b0 = opaque(pbase(lc.t, C));
+    if (mflags & 1) {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            v[k] = cscale(ldg(sc.pt.m + b0 + 64 * k), cmul(ph, v[k]));
+            v[k] = cscale(ldg(sc.pt.m + lc.b0 + 64 * k), cmul(ph, v[k]));
             ph = cmul(ph, w1);
             point_fence(v[k], ph);
         }
@@ -526,41 +572,39 @@ __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e,
             point_fence(v[k], ph);
         }
     }
-    gr = cscale(lc.mr(), cmul(ph, gr));
+    gr = cmul(ph, gr);
+    if (mflags & 4) gr = cscale(ldg(sc.pt.m + lc.ir), gr);
 }
 
 // One full step psi^(i) -> psi^(i+1) (CN right-hand side, partitioned solve,
 // ghost rebuild, field phase and absorber).
 template <int C, class TV>
-__device__ __forceinline__ void forward_step(cd (&v)[C], cd& gl, cd& gr, double e, double dt,
-                                             double xl, const TV& tb, const SizeClass& sc,
-                                             const LaneCtx& lc, const RhsCoef rc, cd* lds_f,
-                                             cd* lds_b)
+__device__ __forceinline__ void forward_step(cd (&v)[C], cd& gl, cd& gr, const LaneFactors<C>& f,
+                                             double e, double dt, double xl, const TV& tb,
+                                             const SizeClass& sc, const LaneCtx& lc,
+                                             const RhsCoef rc, cd* lds_f, cd* lds_b)
 {
-    cd cf, cb;
-    cn_apply<C, true, TV>(v, gl, gr, tb, sc, lc, rc, lds_f, lds_b, cf, cb);
-    gl = cmad(lc.ql(), cf, cmul(lc.bl(), v[0]));
-    gr = cb;
-    phase_mask<C>(v, gl, gr, e, dt, xl, sc.dx, sc, lc);
+    cn_apply<C, true, TV>(v, gl, gr, f, tb, sc, lc, rc, lds_f, lds_b);
+    phase_mask<C>(v, gl, gr, e, dt, xl, sc.dx, f.mflags, sc, lc);
 }
 
-// Copies the point tables of a size class into LDS (om, q, dV of np points):
-// 32 bytes per point, shared by every system the workgroup propagates.
+// Bytes of LDS per grid point of the staged tables (om and dV/dx).
+constexpr int kLdsTableBytes = 16;
+
+// Copies the om and dV/dx tables of a size class into LDS: 16 bytes per
+// point, shared by every system the workgroup propagates.
 __device__ __forceinline__ TabLds stage_tables(const SizeClass& sc, double* lds)
 {
     const int np = sc.C * sc.T;
     double* om = lds;
-    cd* q = reinterpret_cast<cd*>(lds + np);
-    double* dv = lds + 3 * np;
+    double* dv = lds + np;
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
         om[i] = sc.pt.om[i];
-        q[i] = sc.pt.q[i];
         dv[i] = sc.pt.dv[i];
     }
     __syncthreads();
     TabLds tv;
     tv.om_ = om;
-    tv.q_ = q;
     tv.dv_ = dv;
     return tv;
 }
@@ -569,7 +613,6 @@ __device__ __forceinline__ TabGlobal global_tables(const SizeClass& sc)
 {
     TabGlobal tv;
     tv.om_ = sc.pt.om;
-    tv.q_ = sc.pt.q;
     tv.dv_ = sc.pt.dv;
     return tv;
 }
@@ -582,11 +625,9 @@ struct TableSource<true> {
     static __device__ __forceinline__ TabLds make(const SizeClass& sc, double* lds) { return stage_tables(sc, lds); }
     static __device__ __forceinline__ TabLds view(const SizeClass& sc, double* lds)
     {
-        const int np = sc.C * sc.T;
         TabLds tv;
         tv.om_ = lds;
-        tv.q_ = reinterpret_cast<cd*>(lds + np);
-        tv.dv_ = lds + 3 * np;
+        tv.dv_ = lds + sc.C * sc.T;
         return tv;
     }
 };
@@ -658,13 +699,12 @@ __device__ __forceinline__ void observe(const cd (&v)[C], const TV& tb, int T,
                                         const LaneCtx& lc, double xs, double dx, double* slot)
 {
     double sn = 0.0, sk = 0.0, sv = 0.0;
-    const int b0 = opaque(pbase(lc.t, C));
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const double p = cabs2(v[k]);
         sn += p;
         sk = fma((double)k, p, sk);
-        sv = fma(tb.dv(b0 + 64 * k), p, sv);
+        sv = fma(tb.dv(lc.b0 + 64 * k), p, sv);
         point_fence(sv, sn);
     }
     double sx = fma(xs, sn, dx * sk);

@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
     const int S = blockDim.x / T;
     const int tid = threadIdx.x, sub = tid / T, t = tid - sub * T;
     const size_t sb = a.sub_bytes;
-    char* per = reinterpret_cast<char*>(smem_raw + (LDSTAB ? 4 * np : 0));
+    char* per = reinterpret_cast<char*>(smem_raw) + (LDSTAB ? kLdsTableBytes * np : 0);
     const SubSmem sm = carve_sub(per + sub * sb, W);
     int* wg_item = reinterpret_cast<int*>(per + S * sb);
     TableSource<LDSTAB>::make(sc, smem_raw);  // stages the tables once per workgroup
@@ -70,8 +70,10 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
         cd gl = (active && s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
         cd gr = (active && s + C < n) ? ld_psi(src, s + C) : czero();
 
+        LaneFactors<C> f;
         {
             const StepView<LDSTAB> sv = step_view<LDSTAB>(a.classes + a.cls, t, smem_raw);
+            f = load_factors<C>(sv.sc, sv.lc);
             observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, sm.ring);
         }
         __syncthreads();
@@ -82,8 +84,8 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
         int flushed = 0;
         for (int i = 0; i < nt; ++i) {
             const StepView<LDSTAB> sv = step_view<LDSTAB>(a.classes + a.cls, t, smem_raw);
-            forward_step<C>(v, gl, gr, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f,
-                            sm.lds_b);
+            forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
+                            sm.lds_f, sm.lds_b);
             if ((i + 1) % kFlush == 0) {
                 __syncthreads();
                 if (active)
@@ -175,12 +177,10 @@ __global__ void __launch_bounds__(1024) gs_kernel(GsArgs a)
     int it = 0;
     bool conv = false;
     double g = 1.0;
+    const LaneFactors<C> f = load_factors<C>(sc, make_lane_ctx(sc, tid));
     while (it < a.max_iter) {
         const StepView<false> sv = step_view<false>(clsp, tid, smem_raw);
-        cd cf, cb;
-        cn_apply<C, false>(v, gl, gr, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b, cf, cb);
-        gl = cmad(sv.lc.ql(), cf, cmul(sv.lc.bl(), v[0]));
-        gr = cb;
+        cn_apply<C, false>(v, gl, gr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
         loc = 0.0;
 #pragma unroll
         for (int k = 0; k < C; ++k) loc += cabs2(v[k]);
@@ -230,7 +230,7 @@ bool layout_supported(int C) { return C == 4 || C == 8 || C == 16; }
 
 size_t forward_smem_bytes(int C, int T, int S, bool lds_tables)
 {
-    return (lds_tables ? sizeof(double) * 4 * (size_t)C * T : 0) + S * sub_smem_bytes(T / kWave) +
+    return (lds_tables ? (size_t)kLdsTableBytes * C * T : 0) + S * sub_smem_bytes(T / kWave) +
            16;
 }
 

@@ -38,7 +38,8 @@ __host__ __device__ inline int pidx(int t, int k, int C) { return pbase(t, C) + 
 //   alpha_j = -(1 + h' om_{j-1}) q_{j-1}    forward  z_j = r_j + alpha_j z_{j-1}
 //   beta_j  = -(1 + h' om_{j+1}) q_j        backward y_j = q_j z_j + beta_j y_{j+1}
 // alpha and beta are kept only to build the lane carry products; the
-// kernels recompute them from om and q (two FMAs each).
+// kernels recompute them from om and q (two FMAs each), with q held in
+// registers and om read from LDS.
 // Padding points (j >= n) have q = 0, V = 0, dV = 0, m = 0, so they stay 0.
 struct PointTables {
     double* v;      // V_j
@@ -50,26 +51,14 @@ struct PointTables {
     cd* beta;
 };
 
-// Constants of one lane (the points next to its chunk [s, s+C)).
-struct LaneConst {
-    double oml;    // om at s-1
-    double omr;    // om at s+C
-    double ml;     // mask at s-1 (0 outside)
-    double mr;     // mask at s+C
-    double dvl;    // dV/dx at s-1
-    double dvr;    // dV/dx at s+C
-    cd ql;         // q at s-1 (0 outside)
-    cd bl;         // beta at s-1
-};
-
 // Per-lane constants (arrays of length T).
 struct LaneTables {
-    LaneConst* k;  // ghost-point constants
     cd* pa;        // [kMaxLevels][T]: prod of chunk products A over lanes [max(t-2^lev+1, ws), t]
     cd* pw;        // prod of A over [ws, t]   (ws = first lane of t's wave)
     cd* qb;        // [kMaxLevels][T]: prod of chunk products B over lanes [t, min(t+2^lev-1, we)]
     cd* qw;        // prod of B over [t, we]
-    int32_t* hasmask;  // 1 if any mask value of the chunk differs from 1
+    int32_t* hasmask;  // absorber flags: bit 0 chunk, bit 1 point s-1, bit 2 point s+C
+                       // (set where a mask value differs from 1)
 };
 
 // One size class: a distinct grid size n with its lane layout.

@@ -107,46 +107,21 @@ __global__ void __launch_bounds__(256) build_tables_kernel(const SizeClass* clas
     }
     __syncthreads();
 
-    // 3. per lane: chunk products of alpha and beta, ghost constants
+    // 3. per lane: chunk products of alpha and beta, absorber flags
     for (int t = threadIdx.x; t < T; t += blockDim.x) {
         cd pr = mkc(1.0, 0.0);
-        int has = 0;
+        int flags = 0;
         for (int k = 0; k < C; ++k) {
             pr = cmul(sc.pt.alpha[pidx(t, k, C)], pr);
-            if (sc.pt.m[pidx(t, k, C)] != 1.0) has = 1;
+            if (sc.pt.m[pidx(t, k, C)] != 1.0) flags |= 1;
         }
         ca[t] = pr;
         pr = mkc(1.0, 0.0);
         for (int k = C - 1; k >= 0; --k) pr = cmul(sc.pt.beta[pidx(t, k, C)], pr);
         cb[t] = pr;
-        sc.lt.hasmask[t] = has;
-        const int s = t * C;
-        LaneConst kc;
-        if (s > 0) {
-            const int il = pidx(t - 1, C - 1, C);
-            kc.oml = sc.pt.om[il];
-            kc.ml = sc.pt.m[il];
-            kc.dvl = sc.pt.dv[il];
-            kc.ql = sc.pt.q[il];
-            kc.bl = sc.pt.beta[il];
-        } else {
-            kc.oml = 0.0;
-            kc.ml = 0.0;
-            kc.dvl = 0.0;
-            kc.ql = czero();
-            kc.bl = czero();
-        }
-        if (t + 1 < T) {
-            const int ir = pidx(t + 1, 0, C);
-            kc.omr = sc.pt.om[ir];
-            kc.mr = sc.pt.m[ir];
-            kc.dvr = sc.pt.dv[ir];
-        } else {
-            kc.omr = 0.0;
-            kc.mr = 0.0;
-            kc.dvr = 0.0;
-        }
-        sc.lt.k[t] = kc;
+        if (t > 0 && sc.pt.m[pidx(t - 1, C - 1, C)] != 1.0) flags |= 2;
+        if (t + 1 < T && sc.pt.m[pidx(t + 1, 0, C)] != 1.0) flags |= 4;
+        sc.lt.hasmask[t] = flags;
     }
     __syncthreads();
 
