@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default lane layouts instead of timing them at plan creation")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -137,8 +139,16 @@ def main():
     log(f"workload {w.name}: P={w.batch} nt={w.nt} soft-core a={a_sc:.10f} (E_g={e_g:.13f})")
     p = L.make_params(w.dx, w.dt, a_sc, w.nt, mask_fraction=w.mask_frac, mask_power=w.mask_pow)
     t0 = time.time()
-    plan = L.Plan(p, w.n_per)
-    log(f"plan built in {time.time() - t0:.2f} s; layout {plan.layout(w.n_per[0])}")
+    plan = L.Plan(p, w.n_per, options=0 if args.no_autotune else L.TDSE_OPT_AUTOTUNE)
+    layouts = {}
+    for n in sorted(set(w.n_per)):
+        lay, info = plan.layout(n), plan.launch_info(n)
+        layouts[n] = {"points_per_lane": lay.points_per_lane, "lanes": lay.lanes,
+                      "scan_levels": lay.scan_levels,
+                      "systems_per_workgroup": info.systems_per_workgroup,
+                      "lds_tables": info.lds_tables}
+    log(f"plan built in {time.time() - t0:.2f} s ({'default layouts' if args.no_autotune else 'autotuned'}); "
+        f"{len(layouts)} sizes, first {next(iter(layouts.items()))}")
     E = w.efield(xp={"device": dev}).contiguous()
     acc = torch.empty_like(E)
     xe = torch.empty_like(E)
@@ -183,7 +193,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "systems": w.batch, "grid_points": int(w.n_per[0]) if len(set(w.n_per)) == 1 else "ragged",
                    "nt": w.nt, "dx": w.dx, "dt": w.dt, "grid_point_steps": point_steps,
-                   "parallelism": "single-gpu"},
+                   "parallelism": "single-gpu", "autotune": not args.no_autotune,
+                   "layout": next(iter(layouts.values())) if len(layouts) == 1 else
+                   f"{len(layouts)} sizes"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": read_traffic(w.name),

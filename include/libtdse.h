@@ -137,6 +137,18 @@ tdse_status tdse_plan_psi_offsets(tdse_plan plan, int64_t* offsets);
 tdse_status tdse_plan_layout(tdse_plan plan, int32_t n, int32_t* points_per_lane,
                              int32_t* lanes, int32_t* scan_levels);
 
+/* Launch parameters chosen for size n (host outputs, any may be NULL):
+ * systems per workgroup, 1 if the point tables are staged in LDS (0: read
+ * from global memory), and the probe rate in grid-point-steps/s measured by
+ * the autotuner (0 when the plan was not created with TDSE_OPT_AUTOTUNE).
+ * The autotuner times, for each distinct n, every lane layout that fits
+ * (points per lane C in {4, 8, 16}, i.e. the length of the lane-local Thomas
+ * chunks against the width of the cross-lane scan; systems per workgroup;
+ * tables in LDS or global memory) on a probe batch that fills the GPU once,
+ * and keeps the fastest.  Results are cached per process. */
+tdse_status tdse_plan_launch_info(tdse_plan plan, int32_t n, int32_t* systems_per_workgroup,
+                                  int32_t* lds_tables, double* tuned_rate);
+
 /* Device copy of the plan's ground state for size n (dev, 2n doubles) and its
  * energy (host, may be NULL).  Synchronous. */
 tdse_status tdse_plan_ground_state(tdse_plan plan, int32_t n, double* psi_out,

@@ -65,6 +65,8 @@ _PROTOS = {
     "tdse_plan_psi_offsets": (_i32, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "tdse_plan_layout": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                 ctypes.POINTER(_i32)]),
+    "tdse_plan_launch_info": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                     ctypes.POINTER(_d)]),
     "tdse_plan_ground_state": (_i32, [_vp, _i32, _vp, ctypes.POINTER(_d)]),
     "tdse_propagate_batch": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tdse_adjoint_batch": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -160,6 +162,13 @@ class Layout:
     scan_levels: int
 
 
+@dataclass
+class LaunchInfo:
+    systems_per_workgroup: int
+    lds_tables: bool
+    tuned_rate: float
+
+
 class Plan:
     """Owns a tdse_plan handle (tdse_plan_create / tdse_plan_destroy)."""
 
@@ -197,6 +206,12 @@ class Plan:
         _check(load().tdse_plan_layout(self.handle, n, ctypes.byref(c), ctypes.byref(t),
                                        ctypes.byref(l)), "tdse_plan_layout")
         return Layout(c.value, t.value, l.value)
+
+    def launch_info(self, n: int) -> LaunchInfo:
+        s_, l_, r_ = _i32(), _i32(), _d()
+        _check(load().tdse_plan_launch_info(self.handle, n, ctypes.byref(s_), ctypes.byref(l_),
+                                            ctypes.byref(r_)), "tdse_plan_launch_info")
+        return LaunchInfo(s_.value, bool(l_.value), r_.value)
 
     def ground_state(self, n: int, psi_out) -> float:
         e = _d()

@@ -12,6 +12,8 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -348,6 +350,7 @@ struct Launch {
     int C, T, S;          // points per lane, lanes per system, systems per workgroup
     bool lds;             // point tables staged in LDS
     int count, grid;
+    double tuned_rate = 0.0;  // autotuner probe rate (0: default layout)
     int32_t* d_order;     // the class's systems
     // adjoint
     int aS = 1, agrid = 0;
@@ -433,6 +436,150 @@ bool choose_packing(int C, int T, int count, bool adjoint, int* S_out, bool* lds
         }
     }
     return false;
+}
+
+// ------------------------------------------------------------ autotuner
+// For one grid size, times the forward kernel over the candidate lane
+// layouts -- points per lane C (the length of the lane-local Thomas chunks
+// against the width of the cross-lane scan), systems per workgroup S, and
+// point tables in LDS or in global memory -- on a probe batch that fills the
+// GPU once, and keeps the fastest.  Results are cached per process.
+struct TuneChoice {
+    int C = 0, T = 0, S = 1;
+    bool lds = true;
+    double rate = 0.0;  // grid-point-steps per second of the probe
+};
+
+using TuneKey = std::tuple<int, int, double, double, double, double, double, double>;
+std::map<TuneKey, TuneChoice> g_tune_cache;
+std::mutex g_tune_mutex;
+
+Layout layout_for(int n, int C)
+{
+    int T = ((n + C - 1) / C + kWave - 1) / kWave * kWave;
+    if (T < kWave) T = kWave;
+    return {C, T};
+}
+
+constexpr int kProbeSteps = 64;
+
+// Rate of one candidate (0 when it does not fit).  Probe inputs are zero:
+// the kernel's instruction stream does not depend on the values.
+tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, bool lds, int count,
+                          hipStream_t st, double* rate)
+{
+    *rate = 0.0;
+    const int occ = forward_occupancy(L.C, L.T, S, lds);
+    if (occ < 1 || forward_smem_bytes(L.C, L.T, S, lds) > (size_t)kMaxLds) return TDSE_OK;
+    const int slots = S * occ * num_cus();
+    const int P = std::max(1, std::min(count, slots));
+    const int nt = kProbeSteps;
+    ClassSet cs;
+    tdse_status rc = build_classes(cs, {n}, {L}, {real_time_params(p)}, st);
+    if (rc != TDSE_OK) {
+        cs.release();
+        return rc;
+    }
+    const size_t b_e = ((sizeof(double) * (size_t)P * (nt + 1) + 255) & ~size_t(255));
+    const size_t b_psi = ((sizeof(double) * 2 * (size_t)P * n + 255) & ~size_t(255));
+    const size_t b_sys = ((sizeof(SysDesc) * (size_t)P + 255) & ~size_t(255));
+    const size_t b_ord = ((sizeof(int32_t) * (size_t)P + 255) & ~size_t(255));
+    char* mem = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    do {
+        if (hipMalloc(&mem, 2 * b_e + b_psi + b_sys + b_ord + 256) != hipSuccess) {
+            rc = fail(TDSE_E_NOMEM, "autotune probe allocation failed");
+            break;
+        }
+        double* E = reinterpret_cast<double*>(mem);
+        double* acc = reinterpret_cast<double*>(mem + b_e);
+        double* psi = reinterpret_cast<double*>(mem + 2 * b_e);
+        SysDesc* sys = reinterpret_cast<SysDesc*>(mem + 2 * b_e + b_psi);
+        int32_t* ord = reinterpret_cast<int32_t*>(mem + 2 * b_e + b_psi + b_sys);
+        int32_t* ctr = reinterpret_cast<int32_t*>(mem + 2 * b_e + b_psi + b_sys + b_ord);
+        std::vector<SysDesc> hs(P);
+        std::vector<int32_t> ho(P);
+        for (int i = 0; i < P; ++i) {
+            hs[i].cls = 0;
+            hs[i].n = n;
+            hs[i].psi_off = (int64_t)i * n;
+            ho[i] = i;
+        }
+        if (hipMemsetAsync(mem, 0, 2 * b_e + b_psi, st) != hipSuccess ||
+            hipMemcpyAsync(sys, hs.data(), sizeof(SysDesc) * P, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(ord, ho.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            rc = fail(TDSE_E_DEVICE, "autotune probe setup failed");
+            break;
+        }
+        FwdArgs a{};
+        a.classes = cs.d;
+        a.sys = sys;
+        a.order = ord;
+        a.count = P;
+        a.cls = 0;
+        a.queue = ctr;
+        a.nt = nt;
+        a.sub_bytes = (int64_t)sub_smem_bytes(L.T / kWave);
+        a.dt = p->dt;
+        a.E = E;
+        a.psi0 = psi;
+        a.accel = acc;
+        const int grid = std::min((P + S - 1) / S, occ * num_cus());
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && rc == TDSE_OK; ++rep) {  // warm-up, then timed
+            if (launch_reset_counters(ctr, 1, st) != hipSuccess ||
+                (rep == 1 && hipEventRecord(e0, st) != hipSuccess) ||
+                launch_forward(L.C, lds, a, L.T, S, grid, st) != hipSuccess ||
+                (rep == 1 && hipEventRecord(e1, st) != hipSuccess) ||
+                hipStreamSynchronize(st) != hipSuccess)
+                rc = fail(TDSE_E_DEVICE, "autotune probe launch failed: %s",
+                          hipGetErrorString(hipGetLastError()));
+        }
+        if (rc == TDSE_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.0f)
+            *rate = (double)P * n * nt / (ms * 1e-3);
+    } while (0);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (mem) (void)hipFree(mem);
+    cs.release();
+    return rc;
+}
+
+tdse_status autotune(const tdse_params* p, int n, int count, hipStream_t st, TuneChoice* out)
+{
+    const TuneKey key{n, count, p->dx, p->dt, p->a, p->charge_z, p->mask_fraction, p->mask_power};
+    {
+        std::lock_guard<std::mutex> g(g_tune_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            return TDSE_OK;
+        }
+    }
+    TuneChoice best;
+    for (int C : {4, 8, 16}) {
+        const Layout L = layout_for(n, C);
+        if (L.T > 1024 || !layout_supported(C)) continue;
+        const int smax = std::max(1, std::min(1024 / L.T, count));
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool lds = pass == 0;
+            int tried = 0;
+            for (int S = smax; S >= 1 && tried < 2; --S) {
+                if (forward_occupancy(C, L.T, S, lds) < 1) continue;
+                double r = 0.0;
+                tdse_status rc = probe_forward(p, n, L, S, lds, count, st, &r);
+                if (rc != TDSE_OK) return rc;
+                ++tried;
+                if (r > best.rate) best = TuneChoice{C, L.T, S, lds, r};
+            }
+        }
+    }
+    if (best.rate <= 0.0) return fail(TDSE_E_UNSUPPORTED, "no lane layout fits n=%d", n);
+    std::lock_guard<std::mutex> g(g_tune_mutex);
+    g_tune_cache[key] = best;
+    *out = best;
+    return TDSE_OK;
 }
 
 constexpr double kGsDtau = 0.5;
@@ -553,8 +700,18 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     const int ncls = (int)ns.size();
     std::vector<Layout> lay(ncls);
     std::vector<TableParams> prm(ncls, real_time_params(p));
+    std::vector<int> ccount(ncls, 0);
+    for (int b = 0; b < batch; ++b) ++ccount[pl->cls_of_n[pl->n_per[b]]];
+    const bool tune = (options & TDSE_OPT_AUTOTUNE) && !(options & TDSE_OPT_PLAIN);
+    std::vector<TuneChoice> tuned(ncls);
     for (int c = 0; c < ncls; ++c) {
-        lay[c] = default_layout(ns[c]);
+        if (tune) {
+            st = autotune(p, ns[c], ccount[c], s0, &tuned[c]);
+            if (st != TDSE_OK) return bail(st);
+            lay[c] = {tuned[c].C, tuned[c].T};
+        } else {
+            lay[c] = default_layout(ns[c]);
+        }
         if (lay[c].T > 1024 || !layout_supported(lay[c].C))
             return bail(fail(TDSE_E_UNSUPPORTED, "no lane layout for n=%d", ns[c]));
     }
@@ -603,8 +760,15 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         L.d_order_adj = pl->d_order_all + batch + order_all.size();
         order_all.insert(order_all.end(), csys[c].begin(), csys[c].end());
         int occ = 0;
-        if (!choose_packing(L.C, L.T, L.count, false, &L.S, &L.lds, &occ))
+        if (tune) {
+            L.S = tuned[c].S;
+            L.lds = tuned[c].lds;
+            L.tuned_rate = tuned[c].rate;
+            occ = forward_occupancy(L.C, L.T, L.S, L.lds);
+            if (occ < 1) return bail(fail(TDSE_E_UNSUPPORTED, "tuned layout does not fit"));
+        } else if (!choose_packing(L.C, L.T, L.count, false, &L.S, &L.lds, &occ)) {
             return bail(fail(TDSE_E_UNSUPPORTED, "layout C=%d T=%d does not fit", L.C, L.T));
+        }
         L.grid = std::min((L.count + L.S - 1) / L.S, occ * num_cus());
         if (adjoint_k > 0) {
             int aocc = 0;
@@ -679,6 +843,19 @@ tdse_status tdse_plan_layout(tdse_plan plan, int32_t n, int32_t* points_per_lane
     if (points_per_lane) *points_per_lane = sc.C;
     if (lanes) *lanes = sc.T;
     if (scan_levels) *scan_levels = sc.xwaves > 1 ? -sc.levels : sc.levels;
+    return TDSE_OK;
+}
+
+tdse_status tdse_plan_launch_info(tdse_plan plan, int32_t n, int32_t* systems_per_workgroup,
+                                  int32_t* lds_tables, double* tuned_rate)
+{
+    if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
+    auto it = plan->cls_of_n.find(n);
+    if (it == plan->cls_of_n.end()) return fail(TDSE_E_INVALID, "n=%d is not in the plan", n);
+    const Launch& L = plan->launches[plan->launch_of_cls[it->second]];
+    if (systems_per_workgroup) *systems_per_workgroup = L.S;
+    if (lds_tables) *lds_tables = L.lds ? 1 : 0;
+    if (tuned_rate) *tuned_rate = L.tuned_rate;
     return TDSE_OK;
 }
 

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
     const SizeClass sc = uniform_load(a.classes + a.cls);
     const int T = sc.T, W = T / kWave, np = C * T;
     const int S = blockDim.x / T;
-    const int tid = threadIdx.x, sub = tid / T, t = tid - sub * T;
+    const int tid = threadIdx.x, sub = uniform(tid / T), t = tid - sub * T;
     const size_t sb = a.sub_bytes;
     char* per = reinterpret_cast<char*>(smem_raw) + (LDSTAB ? kLdsTableBytes * np : 0);
     const SubSmem sm = carve_sub(per + sub * sb, W);

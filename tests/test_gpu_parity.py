@@ -259,3 +259,37 @@ def test_forward_uneven_wide_batch_sampled(lib, torch_dev):
         print(f"  system {b} n={ns[b]} layout={plan.layout(ns[b])}: accel rel-L2 {r:.3e}", flush=True)
         assert r < TOL_ACC
     plan.close()
+
+
+def test_autotuned_plan_matches_oracle(lib, torch_dev):
+    """TDSE_OPT_AUTOTUNE: every size gets a timed layout (C in {4, 8, 16},
+    systems per workgroup, table placement); results stay within the parity
+    bar and agree with the default-layout plan to rounding."""
+    torch, dev = torch_dev
+    ns = [600, 600, 2048, 3000, 5000]
+    dx, dt = 0.2, 0.05
+    nt = 150
+    efield = 0.06 * np.random.default_rng(12).standard_normal((len(ns), nt + 1))
+    print(f"autotune ns={ns} nt={nt}", flush=True)
+    plan_t, out_t = _run_forward(lib, torch, dev, ns, efield, dx, dt, A_AR,
+                                 options=lib.TDSE_OPT_AUTOTUNE, want=False)
+    plan_d, out_d = _run_forward(lib, torch, dev, ns, efield, dx, dt, A_AR, want=False)
+    for n in sorted(set(ns)):
+        lay = plan_t.layout(n)
+        info = plan_t.launch_info(n)
+        print(f"  n={n}: {lay} {info}", flush=True)
+        assert lay.points_per_lane in (4, 8, 16)
+        assert lay.lanes % 64 == 0 and lay.lanes * lay.points_per_lane >= n
+        assert info.systems_per_workgroup * lay.lanes <= 1024
+        assert info.tuned_rate > 0.0
+        assert plan_d.launch_info(n).tuned_rate == 0.0
+    assert np.all(out_t["status"] == 0)
+    for b, n in enumerate(ns):
+        psi0 = torch.empty(2 * n, dtype=torch.float64, device=dev)
+        plan_t.ground_state(n, psi0)
+        ref = oracle.propagate(efield[b], psi0.cpu().numpy().view(np.complex128), dx, dt, A_AR,
+                               mask_frac=0.1)
+        assert rel(out_t["accel"][b], ref["accel"]) < TOL_ACC
+        assert rel(out_t["accel"][b], out_d["accel"][b]) < 1e-11
+    plan_t.close()
+    plan_d.close()
