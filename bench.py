@@ -231,7 +231,9 @@ def main():
         wa = ti.cfg4_adjoint()
         pa = L.make_params(wa.dx, wa.dt, a_sc, wa.nt, mask_fraction=wa.mask_frac,
                            mask_power=wa.mask_pow)
-        plan_a = L.Plan(pa, wa.n_per, adjoint_k=256)
+        plan_a = L.Plan(pa, wa.n_per, adjoint_k=256,
+                        options=0 if args.no_autotune else L.TDSE_OPT_AUTOTUNE)
+        lay_a = plan_a.layout(wa.n_per[0])
         Ea = wa.efield(xp={"device": dev}).contiguous()
         acc_a = torch.empty_like(Ea)
         h_lo, h_hi = wa.meta["band"]
@@ -255,6 +257,7 @@ def main():
         torch.cuda.synchronize()
         ms_grad = ev0.elapsed_time(ev1)
         out["adjoint"] = {"workload": wa.name, "systems": wa.batch, "nt": wa.nt, "checkpoint_k": 256,
+                          "points_per_lane": lay_a.points_per_lane, "lanes": lay_a.lanes,
                           "time_per_gradient_s": ms_grad * 1e-3,
                           "forward_grid_point_steps": float(sum(wa.n_per)) * wa.nt,
                           "loss": f"sum of H{h_lo}-H{h_hi} Hann-windowed yields"}

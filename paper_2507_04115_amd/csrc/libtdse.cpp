@@ -546,9 +546,109 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, b
     return rc;
 }
 
-tdse_status autotune(const tdse_params* p, int n, int count, hipStream_t st, TuneChoice* out)
+// Rate of the adjoint kernel (forward pass, checkpointed recompute and
+// reverse sweep over kProbeSteps steps, checkpoints every 16 steps) for one
+// layout, with its default packing; 0 when it does not fit.
+tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int count, hipStream_t st,
+                          double* rate)
 {
-    const TuneKey key{n, count, p->dx, p->dt, p->a, p->charge_z, p->mask_fraction, p->mask_power};
+    *rate = 0.0;
+    int S = 1, occ = 0;
+    bool lds = false;
+    if (!choose_packing(L.C, L.T, count, true, &S, &lds, &occ)) return TDSE_OK;
+    const int P = std::max(1, std::min(count, S * occ * num_cus()));
+    const int nt = kProbeSteps, K = 16;
+    const int grid = std::min((P + S - 1) / S, occ * num_cus());
+    const int64_t rec = 2 * (int64_t)(L.C + 2) * L.T;
+    const int64_t slot = (rec * (nt / K + 1 + K + 1) + (nt + 1) + 1) & ~int64_t(1);
+    ClassSet cs;
+    tdse_status rc = build_classes(cs, {n}, {L}, {real_time_params(p)}, st);
+    if (rc != TDSE_OK) {
+        cs.release();
+        return rc;
+    }
+    const size_t b_e = ((sizeof(double) * (size_t)P * (nt + 1) + 255) & ~size_t(255));
+    const size_t b_psi = ((sizeof(double) * 2 * (size_t)P * n + 255) & ~size_t(255));
+    const size_t b_sys = ((sizeof(SysDesc) * (size_t)P + 255) & ~size_t(255));
+    const size_t b_ord = ((sizeof(int32_t) * (size_t)P + 255) & ~size_t(255));
+    const size_t b_work = sizeof(double) * (size_t)slot * grid * S;
+    char* mem = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    do {
+        if (hipMalloc(&mem, 3 * b_e + b_psi + b_sys + b_ord + 256 + b_work) != hipSuccess) {
+            rc = fail(TDSE_E_NOMEM, "autotune probe allocation failed");
+            break;
+        }
+        double* E = reinterpret_cast<double*>(mem);
+        double* abar = reinterpret_cast<double*>(mem + b_e);
+        double* grad = reinterpret_cast<double*>(mem + 2 * b_e);
+        double* psi = reinterpret_cast<double*>(mem + 3 * b_e);
+        SysDesc* sys = reinterpret_cast<SysDesc*>(mem + 3 * b_e + b_psi);
+        int32_t* ord = reinterpret_cast<int32_t*>(mem + 3 * b_e + b_psi + b_sys);
+        int32_t* ctr = reinterpret_cast<int32_t*>(mem + 3 * b_e + b_psi + b_sys + b_ord);
+        double* work = reinterpret_cast<double*>(mem + 3 * b_e + b_psi + b_sys + b_ord + 256);
+        std::vector<SysDesc> hs(P);
+        std::vector<int32_t> ho(P);
+        std::vector<double> ha((size_t)P * (nt + 1), 1e-3);  // every row takes the reverse sweep
+        for (int i = 0; i < P; ++i) {
+            hs[i].cls = 0;
+            hs[i].n = n;
+            hs[i].psi_off = (int64_t)i * n;
+            ho[i] = i;
+        }
+        if (hipMemsetAsync(E, 0, b_e, st) != hipSuccess ||
+            hipMemsetAsync(psi, 0, b_psi, st) != hipSuccess ||
+            hipMemcpyAsync(abar, ha.data(), sizeof(double) * ha.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(sys, hs.data(), sizeof(SysDesc) * P, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(ord, ho.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            rc = fail(TDSE_E_DEVICE, "autotune probe setup failed");
+            break;
+        }
+        FwdArgs a{};
+        a.classes = cs.d;
+        a.sys = sys;
+        a.order = ord;
+        a.count = P;
+        a.cls = 0;
+        a.queue = ctr;
+        a.nt = nt;
+        a.sub_bytes = (int64_t)sub_smem_bytes(L.T / kWave);
+        a.dt = p->dt;
+        a.E = E;
+        a.psi0 = psi;
+        a.abar = abar;
+        a.grad = grad;
+        a.work = work;
+        a.slot_doubles = slot;
+        a.k_ckpt = K;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && rc == TDSE_OK; ++rep) {  // warm-up, then timed
+            if (launch_reset_counters(ctr, 1, st) != hipSuccess ||
+                (rep == 1 && hipEventRecord(e0, st) != hipSuccess) ||
+                launch_adjoint(L.C, lds, a, L.T, S, grid, st) != hipSuccess ||
+                (rep == 1 && hipEventRecord(e1, st) != hipSuccess) ||
+                hipStreamSynchronize(st) != hipSuccess)
+                rc = fail(TDSE_E_DEVICE, "autotune adjoint probe failed: %s",
+                          hipGetErrorString(hipGetLastError()));
+        }
+        if (rc == TDSE_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.0f)
+            *rate = (double)P * n * nt / (ms * 1e-3);
+    } while (0);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (mem) (void)hipFree(mem);
+    cs.release();
+    return rc;
+}
+
+// For plans with the adjoint the score is the time of one forward and one
+// adjoint pass per grid-point-step, with the adjoint's own default packing.
+tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, hipStream_t st,
+                     TuneChoice* out)
+{
+    const TuneKey key{n, adjoint ? -count : count, p->dx, p->dt, p->a, p->charge_z,
+                      p->mask_fraction, p->mask_power};
     {
         std::lock_guard<std::mutex> g(g_tune_mutex);
         auto it = g_tune_cache.find(key);
@@ -558,9 +658,18 @@ tdse_status autotune(const tdse_params* p, int n, int count, hipStream_t st, Tun
         }
     }
     TuneChoice best;
+    double best_cost = 0.0;  // seconds per grid-point-step (forward [+ adjoint])
     for (int C : {4, 8, 16}) {
         const Layout L = layout_for(n, C);
         if (L.T > 1024 || !layout_supported(C)) continue;
+        double adj_cost = 0.0;
+        if (adjoint) {
+            double ra = 0.0;
+            tdse_status rc = probe_adjoint(p, n, L, count, st, &ra);
+            if (rc != TDSE_OK) return rc;
+            if (ra <= 0.0) continue;
+            adj_cost = 1.0 / ra;
+        }
         const int smax = std::max(1, std::min(1024 / L.T, count));
         for (int pass = 0; pass < 2; ++pass) {
             const bool lds = pass == 0;
@@ -571,11 +680,16 @@ tdse_status autotune(const tdse_params* p, int n, int count, hipStream_t st, Tun
                 tdse_status rc = probe_forward(p, n, L, S, lds, count, st, &r);
                 if (rc != TDSE_OK) return rc;
                 ++tried;
-                if (r > best.rate) best = TuneChoice{C, L.T, S, lds, r};
+                if (r <= 0.0) continue;
+                const double cost = 1.0 / r + adj_cost;
+                if (best_cost == 0.0 || cost < best_cost) {
+                    best_cost = cost;
+                    best = TuneChoice{C, L.T, S, lds, r};
+                }
             }
         }
     }
-    if (best.rate <= 0.0) return fail(TDSE_E_UNSUPPORTED, "no lane layout fits n=%d", n);
+    if (best_cost <= 0.0) return fail(TDSE_E_UNSUPPORTED, "no lane layout fits n=%d", n);
     std::lock_guard<std::mutex> g(g_tune_mutex);
     g_tune_cache[key] = best;
     *out = best;
@@ -706,7 +820,7 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     std::vector<TuneChoice> tuned(ncls);
     for (int c = 0; c < ncls; ++c) {
         if (tune) {
-            st = autotune(p, ns[c], ccount[c], s0, &tuned[c]);
+            st = autotune(p, ns[c], ccount[c], adjoint_k > 0, s0, &tuned[c]);
             if (st != TDSE_OK) return bail(st);
             lay[c] = {tuned[c].C, tuned[c].T};
         } else {
