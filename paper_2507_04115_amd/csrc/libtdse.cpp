@@ -175,7 +175,9 @@ tdse_status build_classes(ClassSet& cs, const std::vector<int>& ns,
         sc.levels = kMaxLevels;
         sc.xwaves = sc.T / kWave;
         sc.dx = params[c].dx;
-        sc.habs = std::sqrt(params[c].h.re * params[c].h.re + params[c].h.im * params[c].h.im);
+        const double habs =
+            std::sqrt(params[c].h.re * params[c].h.re + params[c].h.im * params[c].h.im);
+        sc.dofs10 = 7.2 * habs / (params[c].dx * params[c].dx);
         carve_class(ar, sc);
     }
     HIP_TRY(hipMalloc(&cs.d, sizeof(SizeClass) * ncls));

@@ -114,8 +114,8 @@ __device__ __forceinline__ void add_source(cd (&kap)[C], cd& kgl, cd& kgr, const
     for (int k = 0; k < C; ++k)
         kap[k] = cadd(kap[k], cscale(ci * (tb.dv(lc.b0 + 64 * k) + e), cconj(psi[k])));
     // the clamped neighbour indices of the end lanes meet zero ghost values
-    kgl = cadd(kgl, cscale(ci * (tb.dv(lc.il) + e), cconj(gl)));
-    kgr = cadd(kgr, cscale(ci * (tb.dv(lc.ir) + e), cconj(gr)));
+    kgl = cadd(kgl, cscale(ci * (tb.dv(lc.il()) + e), cconj(gl)));
+    kgr = cadd(kgr, cscale(ci * (tb.dv(lc.ir()) + e), cconj(gr)));
 }
 
 }  // namespace
@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
     const int T = sc.T, W = T / kWave, np = C * T;
     const int S = blockDim.x / T;
     const int tid = threadIdx.x, sub = uniform(tid / T), t = tid - sub * T;
+    const int wsys = uniform(t / kWave);  // wavefront within the system
     const size_t sb = a.sub_bytes;
     char* per = reinterpret_cast<char*>(smem_raw) + (LDSTAB ? kLdsTableBytes * np : 0);
     const SubSmem sm = carve_sub(per + sub * sb, W);
@@ -187,13 +188,13 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
         cd gr = (active && s + C < n) ? ld_psi(src, s + C) : czero();
         LaneFactors<C> f;
         {
-            const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
+            const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
             f = load_factors<C>(sv.sc, sv.lc);
         }
         int flushed = 0;
         const int nfwd = (wg_need || a.accel) ? nt : -1;  // uniform
         for (int i = 0; i <= nfwd; ++i) {
-            const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
+            const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
             if (i % K == 0) store_state<C>(ckpt + np2 * (i / K), T, t, v, gl, gr);
             observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, ring + (i % kRing) * W * 3);
             if (i == nt) break;
@@ -224,14 +225,14 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
             load_state<C>(ckpt + np2 * sidx, T, t, v, gl, gr);
             store_state<C>(seg, T, t, v, gl, gr);
             for (int i = s0; i < s1; ++i) {
-                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
+                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
                                 sm.lds_f, sm.lds_b);
                 store_state<C>(seg + np2 * (i - s0 + 1), T, t, v, gl, gr);
             }
             if (!started) {
                 // kappa^nt = 2 abar_nt dx (V' + E_nt) conj(psi^nt); psi^nt = v
-                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
+                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[nt] * dx, erow[nt], sv.tb, T,
                               sv.lc);
                 if (nt > 0) grad_partial<C>(kap, v, sv.xs, dx, sv.lc, ring + ((nt - 1) % kRing) * W);
@@ -245,7 +246,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
             for (int i = s1 - 1; i >= s0; --i) {
                 // kappa <- U (D_i kappa)
                 const double e = erow[i];
-                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, t, smem_raw);
+                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 phase_mask<C>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc, sv.lc);
                 cn_apply<C, true>(kap, kgl, kgr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
                 // + 2 abar_i dx (V' + E_i) conj(psi^i)
@@ -282,6 +283,10 @@ static int occ_adj(int threads, size_t sh)
     int nb = 0;
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(adjoint_kernel<C, L>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(adjoint_kernel<C, L>)) != hipSuccess ||
+        threads > fa.maxThreadsPerBlock)
+        return 0;  // beyond the kernel's launch bounds
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, adjoint_kernel<C, L>, threads, sh) !=
         hipSuccess)
         return 0;

@@ -288,8 +288,22 @@ struct LaneCtx {
     int t;      // lane index within the system (0..T-1)
     int s;      // first grid point of the lane's chunk
     int b0;     // table index of the chunk's first point
-    int il;     // table index of point s-1
-    int ir;     // table index of point s+C
+    int C, T;   // points per lane, lanes per system
+    // Table indices of point s-1 (the last point of lane t-1: 64(C-1) - 1
+    // past b0 within a wavefront, b0 - 1 across a wavefront boundary) and of
+    // point s+C (the first point of lane t+1), clamped at the two ends of the
+    // grid.  Formed where they are used (from a fresh copy of t) rather than
+    // kept live across the step.
+    __device__ __forceinline__ int il() const
+    {
+        const int tt = opaque(t), ln = tt & (kWave - 1);
+        return max(pbase(tt, C) - 1 + (ln ? 64 * (C - 1) : 0), 0);
+    }
+    __device__ __forceinline__ int ir() const
+    {
+        const int tt = opaque(t), ln = tt & (kWave - 1);
+        return min(pbase(tt, C) + (ln == kWave - 1 ? 64 * C - 63 : 1), C * T - 1);
+    }
 };
 
 __device__ __forceinline__ LaneCtx make_lane_ctx(const SizeClass& sc, int t)
@@ -302,8 +316,8 @@ __device__ __forceinline__ LaneCtx make_lane_ctx(const SizeClass& sc, int t)
     c.t = t;
     c.s = t * C;
     c.b0 = pbase(t, C);
-    c.il = t > 0 ? pidx(t - 1, C - 1, C) : c.b0;
-    c.ir = t + 1 < sc.T ? pidx(t + 1, 0, C) : c.b0;
+    c.C = C;
+    c.T = sc.T;
     return c;
 }
 
@@ -334,7 +348,7 @@ struct LaneFactors {
     __device__ __forceinline__ cd ql(const SizeClass& sc, const LaneCtx& lc) const
     {
         if constexpr (QInRegs<C>::value) return ql_;
-        else return lc.t > 0 ? ldg(sc.pt.q + lc.il) : czero();
+        else return lc.t > 0 ? ldg(sc.pt.q + lc.il()) : czero();
     }
 };
 
@@ -345,7 +359,7 @@ __device__ __forceinline__ LaneFactors<C> load_factors(const SizeClass& sc, cons
     if constexpr (QInRegs<C>::value) {
 #pragma unroll
         for (int k = 0; k < C; ++k) f.q_[k] = ldg(sc.pt.q + lc.b0 + 64 * k);
-        f.ql_ = lc.t > 0 ? ldg(sc.pt.q + lc.il) : czero();
+        f.ql_ = lc.t > 0 ? ldg(sc.pt.q + lc.il()) : czero();
     } else {
         f.q_[0] = czero();
         f.ql_ = czero();
@@ -434,14 +448,8 @@ __device__ __forceinline__ cd scan_bwd(cd y, cd b0, cd b1, cd bw, const SizeClas
 // om_j + dofs/10 is small where the kinetic and potential parts cancel, so
 // gh is formed from psi directly rather than from g.
 struct RhsCoef {
-    double dofs10;  // dofs / 10
+    double dofs10;  // dofs / 10 (precomputed per size class)
 };
-__host__ __device__ inline RhsCoef make_rhs_coef(double habs, double dx)
-{
-    RhsCoef c;
-    c.dofs10 = 7.2 * habs / (dx * dx);
-    return c;
-}
 
 // (1 - h' w) x
 template <bool RT>
@@ -467,12 +475,10 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
 {
     const int b0 = lc.b0;
     const unsigned off = 16u * (unsigned)lc.t;
-    const double oml = tb.om(lc.il);
-    const double omr = tb.om(lc.ir);
-    // window products of the forward scan, needed after sweep A
-    const cd a0 = sc.levels > 0 ? ld_lane(sc.lt.pa, off) : czero();
-    const cd a1 = sc.levels > 1 ? ld_lane(sc.lt.pa + sc.T, off) : czero();
-    const cd aw = ld_lane(sc.lt.pw, off);
+    const double oml = tb.om(lc.il());
+    const double omr = tb.om(lc.ir());
+    // window products of the forward scan, loaded halfway through sweep A
+    cd a0 = czero(), a1 = czero(), aw = czero();
     // A. right-hand side in place, chunk-end value of z with zero carry-in
     cd ze = czero();
     {
@@ -482,6 +488,11 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
         cd g_c = gfac<RT>(om_c, v[0]);
 #pragma unroll
         for (int k = 0; k < C; ++k) {
+            if (k == C / 2) {
+                if (sc.levels > 0) a0 = ld_lane(sc.lt.pa, off);
+                if (sc.levels > 1) a1 = ld_lane(sc.lt.pa + sc.T, off);
+                aw = ld_lane(sc.lt.pw, off);
+            }
             const double om_n = (k + 1 < C) ? tb.om(b0 + 64 * (k + 1)) : omr;
             const cd g_n = gfac<RT>(om_n, (k + 1 < C) ? v[k + 1] : gr);
             const cd gh = gfac<RT>(om_c + rc.dofs10, v[k]);
@@ -555,7 +566,7 @@ __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e,
     cd ph = mkc(c0, s0);
     const cd w1 = mkc(c1, s1);
     gl = cmul(ph, gl);
-    if (mflags & 2) gl = cscale(ldg(sc.pt.m + lc.il), gl);
+    if (mflags & 2) gl = cscale(ldg(sc.pt.m + lc.il()), gl);
     ph = cmul(ph, w1);
     if (mflags & 1) {
 #pragma unroll
@@ -573,7 +584,7 @@ __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e,
         }
     }
     gr = cmul(ph, gr);
-    if (mflags & 4) gr = cscale(ldg(sc.pt.m + lc.ir), gr);
+    if (mflags & 4) gr = cscale(ldg(sc.pt.m + lc.ir()), gr);
 }
 
 // One full step psi^(i) -> psi^(i+1) (CN right-hand side, partitioned solve,
@@ -654,14 +665,17 @@ struct StepView {
     double xl;  // x of the point before it
 };
 
+// wsys: wave-uniform index of the calling wavefront within its system; the
+// lane index is rebuilt from the hardware lane id, so no per-lane index stays
+// live across the time loop.
 template <bool LDSTAB>
-__device__ __forceinline__ StepView<LDSTAB> step_view(const SizeClass* cls, int t, double* smem)
+__device__ __forceinline__ StepView<LDSTAB> step_view(const SizeClass* cls, int wsys, double* smem)
 {
     StepView<LDSTAB> v;
     v.sc = scalar_load(launder_s(cls));
-    v.lc = make_lane_ctx(v.sc, opaque(t));
+    v.lc = make_lane_ctx(v.sc, wsys * kWave + opaque((int)__lane_id()));
     v.tb = TableSource<LDSTAB>::view(v.sc, smem);
-    v.rc = make_rhs_coef(v.sc.habs, v.sc.dx);
+    v.rc.dofs10 = v.sc.dofs10;
     const double c = 0.5 * (double)(v.sc.n - 1);
     v.xs = ((double)v.lc.s - c) * v.sc.dx;
     v.xl = ((double)(v.lc.s - 1) - c) * v.sc.dx;

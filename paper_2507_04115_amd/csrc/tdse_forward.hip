@@ -38,6 +38,7 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
     const int T = sc.T, W = T / kWave, np = C * T;
     const int S = blockDim.x / T;
     const int tid = threadIdx.x, sub = uniform(tid / T), t = tid - sub * T;
+    const int wsys = uniform(t / kWave);  // wavefront within the system
     const size_t sb = a.sub_bytes;
     char* per = reinterpret_cast<char*>(smem_raw) + (LDSTAB ? kLdsTableBytes * np : 0);
     const SubSmem sm = carve_sub(per + sub * sb, W);
@@ -72,7 +73,7 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
 
         LaneFactors<C> f;
         {
-            const StepView<LDSTAB> sv = step_view<LDSTAB>(a.classes + a.cls, t, smem_raw);
+            const StepView<LDSTAB> sv = step_view<LDSTAB>(a.classes + a.cls, wsys, smem_raw);
             f = load_factors<C>(sv.sc, sv.lc);
             observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, sm.ring);
         }
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
 
         int flushed = 0;
         for (int i = 0; i < nt; ++i) {
-            const StepView<LDSTAB> sv = step_view<LDSTAB>(a.classes + a.cls, t, smem_raw);
+            const StepView<LDSTAB> sv = step_view<LDSTAB>(a.classes + a.cls, wsys, smem_raw);
             forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
                             sm.lds_f, sm.lds_b);
             if ((i + 1) % kFlush == 0) {
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(1024) gs_kernel(GsArgs a)
     double g = 1.0;
     const LaneFactors<C> f = load_factors<C>(sc, make_lane_ctx(sc, tid));
     while (it < a.max_iter) {
-        const StepView<false> sv = step_view<false>(clsp, tid, smem_raw);
+        const StepView<false> sv = step_view<false>(clsp, uniform(tid / kWave), smem_raw);
         cn_apply<C, false>(v, gl, gr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
         loc = 0.0;
 #pragma unroll
@@ -240,6 +241,10 @@ static int occ_fwd(int threads, size_t sh)
     int nb = 0;
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(forward_kernel<C, L>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(forward_kernel<C, L>)) != hipSuccess ||
+        threads > fa.maxThreadsPerBlock)
+        return 0;  // beyond the kernel's launch bounds
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, forward_kernel<C, L>, threads, sh) !=
         hipSuccess)
         return 0;

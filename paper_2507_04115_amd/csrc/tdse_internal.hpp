@@ -70,7 +70,8 @@ struct SizeClass {
     int32_t xwaves;  // previous/next waves chained in the cross-wave carry
     int32_t pad_;
     double dx;
-    double habs;     // |h| of the factorised matrix (dt/2 or dtau/2)
+    double dofs10;   // 7.2 |h| / dx^2 (|h| = dt/2 or dtau/2): a tenth of the
+                     // diagonal of 12 |h| (-D2/2), used by the right-hand side
     PointTables pt;
     LaneTables lt;
 };
