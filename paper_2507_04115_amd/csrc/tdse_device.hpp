@@ -152,6 +152,16 @@ __device__ __forceinline__ double kconst()
 #define TDSE_K(x) ::tdse::kconst<__builtin_bit_cast(unsigned long long, (double)(x))>()
 
 // ------------------------------------------------------------ sincos
+// a * b + k with the constant k in scalar registers.  The compiler would
+// otherwise prefer the two-address v_fmac form and copy k into a vector
+// register pair before every step of a Horner chain.
+__device__ __forceinline__ double fma_s(double a, double b, double k)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(k));
+    return d;
+}
+
 // sin and cos of x by Cody-Waite reduction to |r| <= pi/4 (x = k pi/2 + r,
 // pi/2 split into a 32-bit head and two tails so k*head is exact for
 // |k| < 2^20) and the Taylor series of sin r and cos r through r^17 and r^16
@@ -169,22 +179,22 @@ __device__ __forceinline__ void sincos_rr(double x, double* s, double* c)
     const double r2 = r * r;
     // sin r = r (1 - r^2/3! + r^4/5! - ... + r^16/17!)
     double ps = TDSE_K(2.8114572543455207632e-15);                       // 1/17!
-    ps = fma(ps, r2, TDSE_K(-7.6471637318198164759e-13));                 // -1/15!
-    ps = fma(ps, r2, TDSE_K(1.6059043836821614599e-10));                  // 1/13!
-    ps = fma(ps, r2, TDSE_K(-2.5052108385441718775e-08));                 // -1/11!
-    ps = fma(ps, r2, TDSE_K(2.7557319223985890653e-06));                  // 1/9!
-    ps = fma(ps, r2, TDSE_K(-1.9841269841269841270e-04));                 // -1/7!
-    ps = fma(ps, r2, TDSE_K(8.3333333333333333333e-03));                  // 1/5!
-    ps = fma(ps, r2, TDSE_K(-1.6666666666666666667e-01));                 // -1/3!
+    ps = fma_s(ps, r2, TDSE_K(-7.6471637318198164759e-13));                 // -1/15!
+    ps = fma_s(ps, r2, TDSE_K(1.6059043836821614599e-10));                  // 1/13!
+    ps = fma_s(ps, r2, TDSE_K(-2.5052108385441718775e-08));                 // -1/11!
+    ps = fma_s(ps, r2, TDSE_K(2.7557319223985890653e-06));                  // 1/9!
+    ps = fma_s(ps, r2, TDSE_K(-1.9841269841269841270e-04));                 // -1/7!
+    ps = fma_s(ps, r2, TDSE_K(8.3333333333333333333e-03));                  // 1/5!
+    ps = fma_s(ps, r2, TDSE_K(-1.6666666666666666667e-01));                 // -1/3!
     const double sr = fma(ps * r2, r, r);
     // cos r = 1 - r^2/2! + r^4/4! - ... + r^16/16!
     double pc = TDSE_K(4.7794773323873852974e-14);                       // 1/16!
-    pc = fma(pc, r2, TDSE_K(-1.1470745597729724714e-11));                 // -1/14!
-    pc = fma(pc, r2, TDSE_K(2.0876756987868098979e-09));                  // 1/12!
-    pc = fma(pc, r2, TDSE_K(-2.7557319223985890653e-07));                 // -1/10!
-    pc = fma(pc, r2, TDSE_K(2.4801587301587301587e-05));                  // 1/8!
-    pc = fma(pc, r2, TDSE_K(-1.3888888888888888889e-03));                 // -1/6!
-    pc = fma(pc, r2, TDSE_K(4.1666666666666666667e-02));                  // 1/4!
+    pc = fma_s(pc, r2, TDSE_K(-1.1470745597729724714e-11));                 // -1/14!
+    pc = fma_s(pc, r2, TDSE_K(2.0876756987868098979e-09));                  // 1/12!
+    pc = fma_s(pc, r2, TDSE_K(-2.7557319223985890653e-07));                 // -1/10!
+    pc = fma_s(pc, r2, TDSE_K(2.4801587301587301587e-05));                  // 1/8!
+    pc = fma_s(pc, r2, TDSE_K(-1.3888888888888888889e-03));                 // -1/6!
+    pc = fma_s(pc, r2, TDSE_K(4.1666666666666666667e-02));                  // 1/4!
     pc = fma(pc, r2, -0.5);                                       // -1/2!
     const double cr = fma(pc, r2, 1.0);
     const int q = ((int)k) & 3;
@@ -206,12 +216,12 @@ __device__ __forceinline__ void sincos_step(double x, double* s, double* c)
     }
     const double x2 = x * x;
     double ps = fma(x2, TDSE_K(2.7557319223985890653e-06), TDSE_K(-1.9841269841269841270e-04));   // 1/9!, -1/7!
-    ps = fma(ps, x2, TDSE_K(8.3333333333333333333e-03));                                   // 1/5!
-    ps = fma(ps, x2, TDSE_K(-1.6666666666666666667e-01));                                  // -1/3!
+    ps = fma_s(ps, x2, TDSE_K(8.3333333333333333333e-03));                                   // 1/5!
+    ps = fma_s(ps, x2, TDSE_K(-1.6666666666666666667e-01));                                  // -1/3!
     *s = fma(ps * x2, x, x);
     double pc = fma(x2, TDSE_K(-2.7557319223985890653e-07), TDSE_K(2.4801587301587301587e-05));    // -1/10!, 1/8!
-    pc = fma(pc, x2, TDSE_K(-1.3888888888888888889e-03));                                  // -1/6!
-    pc = fma(pc, x2, TDSE_K(4.1666666666666666667e-02));                                   // 1/4!
+    pc = fma_s(pc, x2, TDSE_K(-1.3888888888888888889e-03));                                  // -1/6!
+    pc = fma_s(pc, x2, TDSE_K(4.1666666666666666667e-02));                                   // 1/4!
     pc = fma(pc, x2, -0.5);                                                        // -1/2!
     *c = fma(pc, x2, 1.0);
 }
