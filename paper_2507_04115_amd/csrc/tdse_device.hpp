@@ -248,6 +248,23 @@ __device__ __forceinline__ double dpp_d(double v)
 __device__ __forceinline__ cd wave_shr1(cd a) { return mkc(dpp_d<0x138>(a.re), dpp_d<0x138>(a.im)); }
 // lane i receives lane i+1 (lane 63 receives 0)
 __device__ __forceinline__ cd wave_shl1(cd a) { return mkc(dpp_d<0x130>(a.re), dpp_d<0x130>(a.im)); }
+// The same shifts, with the lane that has no source (lane 0, resp. 63)
+// receiving `edge` instead of 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_keep(double v, double edge)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(edge), __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(edge), __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ cd wave_shr1_keep(cd a, cd edge)
+{
+    return mkc(dpp_keep<0x138>(a.re, edge.re), dpp_keep<0x138>(a.im, edge.im));
+}
+__device__ __forceinline__ cd wave_shl1_keep(cd a, cd edge)
+{
+    return mkc(dpp_keep<0x130>(a.re, edge.re), dpp_keep<0x130>(a.im, edge.im));
+}
 
 __device__ __forceinline__ cd shfl_up_c(cd a, int d)
 {
@@ -316,12 +333,14 @@ struct LaneCtx {
     }
 };
 
-__device__ __forceinline__ LaneCtx make_lane_ctx(const SizeClass& sc, int t)
+// wave: the wavefront index t / 64, passed separately so that the compiler
+// can keep it in a scalar register (it is uniform across the wavefront).
+__device__ __forceinline__ LaneCtx make_lane_ctx(const SizeClass& sc, int t, int wave)
 {
     LaneCtx c;
     const int C = sc.C;
     c.lane = t & (kWave - 1);
-    c.wave = t / kWave;
+    c.wave = wave;
     c.W = sc.T / kWave;
     c.t = t;
     c.s = t * C;
@@ -412,13 +431,15 @@ __device__ __forceinline__ cd scan_fwd(cd z, cd a0, cd a1, cd aw, const SizeClas
     if (lc.W > 1) {
         if (lc.lane == kWave - 1) lds[lc.wave] = z;
         __syncthreads();
-        const int v0 = max(0, lc.wave - sc.xwaves);
-        for (int w = v0; w < lc.wave; ++w)
-            prev = cmad(ldg(sc.lt.pw + w * kWave + kWave - 1), prev, lds[w]);
-        if (lc.lane < (1 << sc.levels)) z = cmad(aw, prev, z);
+        const int v0 = max(0, lc.wave - sc.xwaves);  // wave-uniform
+        if (v0 < lc.wave) {
+            prev = lds[v0];
+            for (int w = v0 + 1; w < lc.wave; ++w)
+                prev = cmad(ldg(sc.lt.pw + w * kWave + kWave - 1), prev, lds[w]);
+        }
+        z = cmad(aw, prev, z);  // aw = 0 in lanes past the scan's reach
     }
-    const cd up = wave_shr1(z);
-    return lc.lane == 0 ? prev : up;
+    return wave_shr1_keep(z, prev);
 }
 
 // Backward carries of y_j = w_j + beta_j y_{j+1}, mirrored: returns the true y
@@ -439,12 +460,14 @@ __device__ __forceinline__ cd scan_bwd(cd y, cd b0, cd b1, cd bw, const SizeClas
     if (lc.W > 1) {
         if (lc.lane == 0) lds[lc.wave] = y;
         __syncthreads();
-        const int v1 = min(lc.W - 1, lc.wave + sc.xwaves);
-        for (int w = v1; w > lc.wave; --w) next = cmad(ldg(sc.lt.qw + w * kWave), next, lds[w]);
-        if (lc.lane > kWave - 1 - (1 << sc.levels)) y = cmad(bw, next, y);
+        const int v1 = min(lc.W - 1, lc.wave + sc.xwaves);  // wave-uniform
+        if (v1 > lc.wave) {
+            next = lds[v1];
+            for (int w = v1 - 1; w > lc.wave; --w) next = cmad(ldg(sc.lt.qw + w * kWave), next, lds[w]);
+        }
+        y = cmad(bw, next, y);  // bw = 0 in lanes past the scan's reach
     }
-    const cd dn = wave_shl1(y);
-    return lc.lane == kWave - 1 ? next : dn;
+    return wave_shl1_keep(y, next);
 }
 
 // ------------------------------------------------------------ CN core
@@ -501,7 +524,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
             if (k == C / 2) {
                 if (sc.levels > 0) a0 = ld_lane(sc.lt.pa, off);
                 if (sc.levels > 1) a1 = ld_lane(sc.lt.pa + sc.T, off);
-                aw = ld_lane(sc.lt.pw, off);
+                if (lc.lane < (1 << sc.levels)) aw = ld_lane(sc.lt.pw, off);
             }
             const double om_n = (k + 1 < C) ? tb.om(b0 + 64 * (k + 1)) : omr;
             const cd g_n = gfac<RT>(om_n, (k + 1 < C) ? v[k + 1] : gr);
@@ -519,7 +542,8 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
     const cd cf = scan_fwd(ze, a0, a1, aw, sc, lc, lds_f);
     const cd b0c = sc.levels > 0 ? ld_lane(sc.lt.qb, off) : czero();
     const cd b1c = sc.levels > 1 ? ld_lane(sc.lt.qb + sc.T, off) : czero();
-    const cd bw = ld_lane(sc.lt.qw, off);
+    cd bw = czero();
+    if (lc.lane > kWave - 1 - (1 << sc.levels)) bw = ld_lane(sc.lt.qw, off);
     // B. forward recurrence from the exact carry, w = q z
     {
         cd z = cf;
@@ -683,7 +707,7 @@ __device__ __forceinline__ StepView<LDSTAB> step_view(const SizeClass* cls, int 
 {
     StepView<LDSTAB> v;
     v.sc = scalar_load(launder_s(cls));
-    v.lc = make_lane_ctx(v.sc, wsys * kWave + opaque((int)__lane_id()));
+    v.lc = make_lane_ctx(v.sc, wsys * kWave + opaque((int)__lane_id()), wsys);
     v.tb = TableSource<LDSTAB>::view(v.sc, smem);
     v.rc.dofs10 = v.sc.dofs10;
     const double c = 0.5 * (double)(v.sc.n - 1);

@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(1024) gs_kernel(GsArgs a)
     int it = 0;
     bool conv = false;
     double g = 1.0;
-    const LaneFactors<C> f = load_factors<C>(sc, make_lane_ctx(sc, tid));
+    const LaneFactors<C> f = load_factors<C>(sc, make_lane_ctx(sc, tid, uniform(tid / kWave)));
     while (it < a.max_iter) {
         const StepView<false> sv = step_view<false>(clsp, uniform(tid / kWave), smem_raw);
         cn_apply<C, false>(v, gl, gr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
