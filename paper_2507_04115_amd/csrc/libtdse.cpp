@@ -463,7 +463,7 @@ Layout layout_for(int n, int C)
     return {C, T};
 }
 
-constexpr int kProbeSteps = 64;
+constexpr int kProbeSteps = 128;
 
 // Rate of one candidate (0 when it does not fit).  Probe inputs are zero:
 // the kernel's instruction stream does not depend on the values.
@@ -528,18 +528,20 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, b
         a.psi0 = psi;
         a.accel = acc;
         const int grid = std::min((P + S - 1) / S, occ * num_cus());
-        float ms = 0.0f;
-        for (int rep = 0; rep < 2 && rc == TDSE_OK; ++rep) {  // warm-up, then timed
+        float best_ms = 0.0f;
+        for (int rep = 0; rep < 3 && rc == TDSE_OK; ++rep) {  // warm-up, then best of two
+            float ms = 0.0f;
             if (launch_reset_counters(ctr, 1, st) != hipSuccess ||
-                (rep == 1 && hipEventRecord(e0, st) != hipSuccess) ||
+                hipEventRecord(e0, st) != hipSuccess ||
                 launch_forward(L.C, lds, a, L.T, S, grid, st) != hipSuccess ||
-                (rep == 1 && hipEventRecord(e1, st) != hipSuccess) ||
-                hipStreamSynchronize(st) != hipSuccess)
+                hipEventRecord(e1, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                 rc = fail(TDSE_E_DEVICE, "autotune probe launch failed: %s",
                           hipGetErrorString(hipGetLastError()));
+            else if (rep > 0 && ms > 0.0f && (best_ms == 0.0f || ms < best_ms))
+                best_ms = ms;
         }
-        if (rc == TDSE_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.0f)
-            *rate = (double)P * n * nt / (ms * 1e-3);
+        if (rc == TDSE_OK && best_ms > 0.0f) *rate = (double)P * n * nt / (best_ms * 1e-3);
     } while (0);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
