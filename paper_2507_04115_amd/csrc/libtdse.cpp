@@ -391,6 +391,22 @@ struct tdse_plan_s {
     // adjoint workspace
     double* d_adj = nullptr;
     size_t adj_bytes = 0;
+    // forward: one persistent launch per lane layout over workgroup bins
+    struct FwdGroup {
+        int C = 0;
+        bool lds = true;
+        int threads = 0;  // workgroup size = bin capacity in lanes
+        size_t smem = 0;  // LDS bytes per workgroup
+        int nbins = 0, grid = 0;
+        BinDesc* d_bins = nullptr;
+    };
+    std::vector<FwdGroup> fgroups;
+    std::vector<int> fgroup_of_cls;
+    BinDesc* d_bins = nullptr;             // every group's bins, then one bin per system (plain)
+    std::vector<int> plain_threads;        // per system
+    std::vector<size_t> plain_smem;
+    int ncls_real = 0;                     // classes [0, ncls_real) are real, the rest padding
+    int ctr_plain = 0, ctr_fwd = 0;        // offsets into d_counters
 };
 
 namespace {
@@ -410,7 +426,18 @@ void plan_free(tdse_plan pl)
     if (pl->d_counters) (void)hipFree(pl->d_counters);
     if (pl->d_ident) (void)hipFree(pl->d_ident);
     if (pl->d_adj) (void)hipFree(pl->d_adj);
+    if (pl->d_bins) (void)hipFree(pl->d_bins);
     delete pl;
+}
+
+// LDS bytes of a forward workgroup holding S systems of one class.
+size_t fwd_smem(int C, int T, int S, bool lds)
+{
+    return (lds ? (size_t)kLdsTableBytes * C * T : 0) + S * sub_smem_bytes(T / kWave) + 16;
+}
+int fwd_occupancy(int C, int T, int S, bool lds)
+{
+    return forward_occupancy(C, S * T, fwd_smem(C, T, S, lds), lds);
 }
 
 // Systems per workgroup and table placement for a class: as many systems as
@@ -426,9 +453,9 @@ bool choose_packing(int C, int T, int count, bool adjoint, int* S_out, bool* lds
         const bool lds = pass == 0;
         if ((fl == 0 && lds) || (fl == 1 && !lds)) continue;
         for (int S = smax; S >= 1; --S) {
-            const size_t sh = adjoint ? adjoint_smem_bytes(C, T, S, lds) : forward_smem_bytes(C, T, S, lds);
+            const size_t sh = adjoint ? adjoint_smem_bytes(C, T, S, lds) : fwd_smem(C, T, S, lds);
             if (sh > (size_t)kMaxLds) continue;
-            const int occ = adjoint ? adjoint_occupancy(C, T, S, lds) : forward_occupancy(C, T, S, lds);
+            const int occ = adjoint ? adjoint_occupancy(C, T, S, lds) : fwd_occupancy(C, T, S, lds);
             if (occ >= 1) {
                 *S_out = S;
                 *lds_out = lds;
@@ -438,6 +465,132 @@ bool choose_packing(int C, int T, int count, bool adjoint, int* S_out, bool* lds
         }
     }
     return false;
+}
+
+// ------------------------------------------------------------ workgroup bins
+// The forward kernel takes one bin per queue item: systems of one lane layout
+// packed into the lanes of a workgroup (first fit decreasing in lanes, within
+// the LDS budget).  Lanes no system needs go to padding subgroups of padding
+// classes, each no wider than the bin's widest system: a padding subgroup
+// stages no tables of its own but reads (and discards the results of) the
+// staged tables of that widest system's class, which are long enough.
+struct PackItem {
+    int p, cls, T;
+};
+
+struct HostBin {
+    std::vector<PackItem> subs;
+    std::vector<int> classes;  // distinct classes, in order of appearance
+    int lanes = 0;
+    int tmax = 0;              // widest subgroup (lanes)
+    size_t tab_bytes = 0, sub_bytes = 0;
+};
+
+// Lane counts of the padding subgroups of a bin of `cap` lanes.
+std::vector<int> pad_chunks(const HostBin& b, int cap)
+{
+    std::vector<int> out;
+    for (int idle = cap - b.lanes; idle > 0;) {
+        const int t = std::min(idle, b.tmax);
+        out.push_back(t);
+        idle -= t;
+    }
+    return out;
+}
+
+// LDS bytes of a bin (staged tables of its classes, the scratch blocks of all
+// subgroups, the queue slot) and its subgroup count, padding included.
+size_t bin_total(const HostBin& b, int cap, int* nsub)
+{
+    size_t bytes = b.tab_bytes + b.sub_bytes + 16;
+    const std::vector<int> pad = pad_chunks(b, cap);
+    for (int t : pad) bytes += sub_smem_bytes(t / kWave);
+    *nsub = (int)(b.subs.size() + pad.size());
+    return bytes;
+}
+
+bool bin_try_add(HostBin& b, const PackItem& it, int cap, int C, bool lds)
+{
+    if (b.lanes + it.T > cap) return false;
+    HostBin t = b;
+    t.subs.push_back(it);
+    t.lanes += it.T;
+    t.tmax = std::max(t.tmax, it.T);
+    if (std::find(t.classes.begin(), t.classes.end(), it.cls) == t.classes.end()) {
+        t.classes.push_back(it.cls);
+        if (lds) t.tab_bytes += (size_t)kLdsTableBytes * C * it.T;
+    }
+    t.sub_bytes += sub_smem_bytes(it.T / kWave);
+    int nsub = 0;
+    if (bin_total(t, cap, &nsub) > (size_t)kMaxLds || nsub > kMaxSubs) return false;
+    b = std::move(t);
+    return true;
+}
+
+// Packs items into bins of `cap` lanes; fails if an item alone does not fit.
+bool pack_bins(std::vector<PackItem> items, int cap, int C, bool lds, std::vector<HostBin>& bins)
+{
+    std::stable_sort(items.begin(), items.end(),
+                     [](const PackItem& x, const PackItem& y) { return x.T > y.T; });
+    bins.clear();
+    size_t first_open = 0;  // bins before this one are full
+    for (const PackItem& it : items) {
+        bool placed = false;
+        for (size_t i = first_open; i < bins.size() && !placed; ++i) placed = bin_try_add(bins[i], it, cap, C, lds);
+        if (!placed) {
+            bins.emplace_back();
+            if (!bin_try_add(bins.back(), it, cap, C, lds)) return false;
+        }
+        while (first_open < bins.size() && bins[first_open].lanes == cap) ++first_open;
+    }
+    return true;
+}
+
+// Device descriptor of a bin.  pad_cls(lanes) gives the padding class of a
+// padding subgroup.  Returns the LDS bytes the bin uses (queue slot included).
+template <class PadCls>
+size_t make_bin_desc(const HostBin& b, int cap, int C, bool lds, const std::vector<SizeClass>& cls,
+                     PadCls pad_cls, BinDesc* d)
+{
+    std::memset(d, 0, sizeof(BinDesc));
+    size_t off = 0;
+    std::vector<size_t> tab(b.classes.size(), 0);
+    size_t wide_tab = 0;  // tables of the widest class, read by padding subgroups
+    int wide_T = 0;
+    if (lds)
+        for (size_t k = 0; k < b.classes.size(); ++k) {
+            tab[k] = off;
+            const int T = cls[b.classes[k]].T;
+            if (T > wide_T) {
+                wide_T = T;
+                wide_tab = off;
+            }
+            off += (size_t)kLdsTableBytes * C * T;
+        }
+    int wave = 0, j = 0;
+    std::vector<int> staged;
+    auto add = [&](int p, int c, int T, size_t toff, bool stage) {
+        BinSub& u = d->sub[j];
+        u.p = p;
+        u.cls = c;
+        u.wave0 = wave;
+        u.tab_off = (int32_t)toff;
+        u.sub_off = (int32_t)off;
+        u.stage = stage ? 1 : 0;
+        off += sub_smem_bytes(T / kWave);
+        for (int w = 0; w < T / kWave; ++w) d->sub_of_wave[wave + w] = j;
+        wave += T / kWave;
+        ++j;
+    };
+    for (const PackItem& it : b.subs) {
+        const size_t k = std::find(b.classes.begin(), b.classes.end(), it.cls) - b.classes.begin();
+        const bool first = std::find(staged.begin(), staged.end(), it.cls) == staged.end();
+        if (first) staged.push_back(it.cls);
+        add(it.p, it.cls, it.T, lds ? tab[k] : 0, lds && first);
+    }
+    for (int t : pad_chunks(b, cap)) add(-1, pad_cls(t), t, wide_tab, false);
+    d->nsub = j;
+    return off + 16;
 }
 
 // ------------------------------------------------------------ autotuner
@@ -466,15 +619,17 @@ Layout layout_for(int n, int C)
 constexpr int kProbeSteps = 128;
 
 // Rate of one candidate (0 when it does not fit).  Probe inputs are zero:
-// the kernel's instruction stream does not depend on the values.
+// the kernel's instruction stream does not depend on the values.  The probe
+// batch fills every workgroup slot once with bins of S systems.
 tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, bool lds, int count,
                           hipStream_t st, double* rate)
 {
     *rate = 0.0;
-    const int occ = forward_occupancy(L.C, L.T, S, lds);
-    if (occ < 1 || forward_smem_bytes(L.C, L.T, S, lds) > (size_t)kMaxLds) return TDSE_OK;
-    const int slots = S * occ * num_cus();
-    const int P = std::max(1, std::min(count, slots));
+    const size_t smem = fwd_smem(L.C, L.T, S, lds);
+    const int occ = forward_occupancy(L.C, S * L.T, smem, lds);
+    if (occ < 1 || smem > (size_t)kMaxLds || count < S) return TDSE_OK;
+    const int nb = std::max(1, std::min(count / S, occ * num_cus()));
+    const int P = nb * S;
     const int nt = kProbeSteps;
     ClassSet cs;
     tdse_status rc = build_classes(cs, {n}, {L}, {real_time_params(p)}, st);
@@ -485,11 +640,11 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, b
     const size_t b_e = ((sizeof(double) * (size_t)P * (nt + 1) + 255) & ~size_t(255));
     const size_t b_psi = ((sizeof(double) * 2 * (size_t)P * n + 255) & ~size_t(255));
     const size_t b_sys = ((sizeof(SysDesc) * (size_t)P + 255) & ~size_t(255));
-    const size_t b_ord = ((sizeof(int32_t) * (size_t)P + 255) & ~size_t(255));
+    const size_t b_bin = ((sizeof(BinDesc) * (size_t)nb + 255) & ~size_t(255));
     char* mem = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     do {
-        if (hipMalloc(&mem, 2 * b_e + b_psi + b_sys + b_ord + 256) != hipSuccess) {
+        if (hipMalloc(&mem, 2 * b_e + b_psi + b_sys + b_bin + 256) != hipSuccess) {
             rc = fail(TDSE_E_NOMEM, "autotune probe allocation failed");
             break;
         }
@@ -497,19 +652,34 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, b
         double* acc = reinterpret_cast<double*>(mem + b_e);
         double* psi = reinterpret_cast<double*>(mem + 2 * b_e);
         SysDesc* sys = reinterpret_cast<SysDesc*>(mem + 2 * b_e + b_psi);
-        int32_t* ord = reinterpret_cast<int32_t*>(mem + 2 * b_e + b_psi + b_sys);
-        int32_t* ctr = reinterpret_cast<int32_t*>(mem + 2 * b_e + b_psi + b_sys + b_ord);
+        BinDesc* bins = reinterpret_cast<BinDesc*>(mem + 2 * b_e + b_psi + b_sys);
+        int32_t* ctr = reinterpret_cast<int32_t*>(mem + 2 * b_e + b_psi + b_sys + b_bin);
         std::vector<SysDesc> hs(P);
-        std::vector<int32_t> ho(P);
         for (int i = 0; i < P; ++i) {
             hs[i].cls = 0;
             hs[i].n = n;
             hs[i].psi_off = (int64_t)i * n;
-            ho[i] = i;
+        }
+        std::vector<BinDesc> hb(nb);
+        size_t used = 0;
+        bool packed = true;
+        for (int k = 0; k < nb && packed; ++k) {
+            HostBin hbin;
+            for (int i = 0; i < S && packed; ++i)
+                packed = bin_try_add(hbin, PackItem{k * S + i, 0, L.T}, S * L.T, L.C, lds);
+            used = std::max(used, make_bin_desc(hbin, S * L.T, L.C, lds, cs.h, [](int) { return 0; }, &hb[k]));
+        }
+        if (!packed) {
+            rc = fail(TDSE_E_UNSUPPORTED, "autotune probe: %d systems of n=%d do not fit a workgroup", S, n);
+            break;
+        }
+        if (used > smem) {
+            rc = fail(TDSE_E_UNSUPPORTED, "autotune probe bins need %zu B of LDS, %zu planned", used, smem);
+            break;
         }
         if (hipMemsetAsync(mem, 0, 2 * b_e + b_psi, st) != hipSuccess ||
             hipMemcpyAsync(sys, hs.data(), sizeof(SysDesc) * P, hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(ord, ho.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(bins, hb.data(), sizeof(BinDesc) * nb, hipMemcpyHostToDevice, st) != hipSuccess ||
             hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
             rc = fail(TDSE_E_DEVICE, "autotune probe setup failed");
             break;
@@ -517,23 +687,22 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, b
         FwdArgs a{};
         a.classes = cs.d;
         a.sys = sys;
-        a.order = ord;
-        a.count = P;
-        a.cls = 0;
+        a.bins = bins;
+        a.nbins = nb;
+        a.item_off = (int32_t)(smem - 16);
         a.queue = ctr;
         a.nt = nt;
-        a.sub_bytes = (int64_t)sub_smem_bytes(L.T / kWave);
         a.dt = p->dt;
         a.E = E;
         a.psi0 = psi;
         a.accel = acc;
-        const int grid = std::min((P + S - 1) / S, occ * num_cus());
+        const int grid = std::min(nb, occ * num_cus());
         float best_ms = 0.0f;
         for (int rep = 0; rep < 3 && rc == TDSE_OK; ++rep) {  // warm-up, then best of two
             float ms = 0.0f;
             if (launch_reset_counters(ctr, 1, st) != hipSuccess ||
                 hipEventRecord(e0, st) != hipSuccess ||
-                launch_forward(L.C, lds, a, L.T, S, grid, st) != hipSuccess ||
+                launch_forward(L.C, lds, a, S * L.T, smem, grid, st) != hipSuccess ||
                 hipEventRecord(e1, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess ||
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                 rc = fail(TDSE_E_DEVICE, "autotune probe launch failed: %s",
@@ -679,7 +848,7 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, hipSt
             const bool lds = pass == 0;
             int tried = 0;
             for (int S = smax; S >= 1 && tried < 2; --S) {
-                if (forward_occupancy(C, L.T, S, lds) < 1) continue;
+                if (fwd_occupancy(C, L.T, S, lds) < 1) continue;
                 double r = 0.0;
                 tdse_status rc = probe_forward(p, n, L, S, lds, count, st, &r);
                 if (rc != TDSE_OK) return rc;
@@ -708,7 +877,7 @@ constexpr int kGsMaxIter = 100000;
 // side with the plan's a and charge, mask off).
 tdse_status plan_ground_states(tdse_plan pl, hipStream_t st)
 {
-    const int ncls = (int)pl->cls.h.size();
+    const int ncls = pl->ncls_real;  // padding classes need no ground state
     std::vector<int> ns(ncls);
     std::vector<Layout> lay(ncls);
     std::vector<TableParams> prm(ncls);
@@ -833,12 +1002,8 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         if (lay[c].T > 1024 || !layout_supported(lay[c].C))
             return bail(fail(TDSE_E_UNSUPPORTED, "no lane layout for n=%d", ns[c]));
     }
-    st = build_classes(pl->cls, ns, lay, prm, s0);
-    if (st != TDSE_OK) return bail(st);
-    st = plan_ground_states(pl, s0);
-    if (st != TDSE_OK) return bail(st);
-
-    // systems and launches (one per class)
+    // systems of each class
+    pl->ncls_real = ncls;
     pl->cls_of.resize(batch);
     std::vector<SysDesc> sys(batch);
     std::vector<std::vector<int32_t>> csys(ncls);
@@ -850,7 +1015,124 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         sys[b].psi_off = pl->psi_off[b];
         csys[c].push_back(b);
     }
-    // longest work first: classes by (n_pad * count) descending
+
+    // forward packing of each class: systems per workgroup, table placement
+    std::vector<int> cS(ncls, 1);
+    std::vector<char> clds(ncls, 1);
+    for (int c = 0; c < ncls; ++c) {
+        if (tune) {
+            cS[c] = tuned[c].S;
+            clds[c] = tuned[c].lds;
+        } else {
+            int S = 1, occ = 0;
+            bool l = true;
+            if (!choose_packing(lay[c].C, lay[c].T, ccount[c], false, &S, &l, &occ))
+                return bail(fail(TDSE_E_UNSUPPORTED, "layout C=%d T=%d does not fit", lay[c].C, lay[c].T));
+            cS[c] = S;
+            clds[c] = l;
+        }
+    }
+    // one persistent forward launch per (C, table placement): a single class
+    // keeps its own packing, several classes share 1024-lane workgroups
+    std::map<std::pair<int, int>, std::vector<int>> gcls;
+    for (int c = 0; c < ncls; ++c) gcls[{lay[c].C, (int)clds[c]}].push_back(c);
+    struct GroupBins {
+        int C;
+        bool lds;
+        int cap;
+        std::vector<HostBin> bins;
+    };
+    std::vector<GroupBins> gbins;
+    std::map<std::pair<int, int>, int> pad_cls;  // (C, lanes) -> padding class
+    pl->fgroup_of_cls.assign(ncls, -1);
+    auto add_group = [&](const std::vector<int>& classes, int C, bool lds, int cap) -> bool {
+        GroupBins g;
+        g.C = C;
+        g.lds = lds;
+        g.cap = cap;
+        std::vector<PackItem> items;
+        for (int c : classes)
+            for (int32_t b : csys[c]) items.push_back(PackItem{b, c, lay[c].T});
+        if (!pack_bins(items, g.cap, g.C, g.lds, g.bins)) return false;
+        for (int c : classes) pl->fgroup_of_cls[c] = (int)gbins.size();
+        for (const HostBin& hb : g.bins)
+            for (int t : pad_chunks(hb, g.cap)) pad_cls[{g.C, t}] = 0;
+        gbins.push_back(std::move(g));
+        return true;
+    };
+    for (const auto& kv : gcls) {
+        const int C = kv.first.first;
+        const bool lds = kv.first.second != 0;
+        // several classes share full workgroups when their staged tables and a
+        // padding subgroup fit the LDS; otherwise each class keeps its own
+        bool ok = kv.second.size() > 1 && add_group(kv.second, C, lds, 1024);
+        if (!ok)
+            for (int c : kv.second)
+                if (!add_group({c}, C, lds, cS[c] * lay[c].T))
+                    return bail(fail(TDSE_E_UNSUPPORTED, "systems of n=%d do not fit a workgroup", ns[c]));
+    }
+    // padding classes (16 points, the needed lane counts) after the real ones
+    std::vector<int> ns_all = ns;
+    std::vector<Layout> lay_all = lay;
+    std::vector<TableParams> prm_all = prm;
+    for (auto& kv : pad_cls) {
+        kv.second = (int)ns_all.size();
+        ns_all.push_back(kMinN);
+        lay_all.push_back(Layout{kv.first.first, kv.first.second});
+        prm_all.push_back(real_time_params(p));
+    }
+    st = build_classes(pl->cls, ns_all, lay_all, prm_all, s0);
+    if (st != TDSE_OK) return bail(st);
+    st = plan_ground_states(pl, s0);
+    if (st != TDSE_OK) return bail(st);
+
+    // bin descriptors: each group's bins, then one bin per system (plain form)
+    std::vector<BinDesc> hbins;
+    std::vector<size_t> goff;
+    for (const GroupBins& g : gbins) {
+        tdse_plan_s::FwdGroup fg;
+        fg.C = g.C;
+        fg.lds = g.lds;
+        fg.threads = g.cap;
+        fg.nbins = (int)g.bins.size();
+        goff.push_back(hbins.size());
+        for (const HostBin& hb : g.bins) {
+            hbins.emplace_back();
+            const size_t used = make_bin_desc(hb, g.cap, g.C, g.lds, pl->cls.h,
+                                              [&](int t) { return pad_cls[{g.C, t}]; },
+                                              &hbins.back());
+            fg.smem = std::max(fg.smem, used);
+        }
+        const int occ = forward_occupancy(fg.C, fg.threads, fg.smem, fg.lds);
+        if (occ < 1)
+            return bail(fail(TDSE_E_UNSUPPORTED, "forward workgroup of %d lanes with %zu B of LDS does not fit",
+                             fg.threads, fg.smem));
+        fg.grid = std::min(fg.nbins, occ * num_cus());
+        pl->fgroups.push_back(fg);
+    }
+    const size_t plain0 = hbins.size();
+    pl->plain_threads.assign(batch, 0);
+    pl->plain_smem.assign(batch, 0);
+    for (int b = 0; b < batch; ++b) {
+        const int c = pl->cls_of[b];
+        HostBin hb;
+        if (!bin_try_add(hb, PackItem{b, c, lay[c].T}, lay[c].T, lay[c].C, clds[c]))
+            return bail(fail(TDSE_E_UNSUPPORTED, "system %d does not fit a workgroup", b));
+        hbins.emplace_back();
+        pl->plain_smem[b] = make_bin_desc(hb, lay[c].T, lay[c].C, clds[c], pl->cls.h,
+                                          [](int) { return 0; }, &hbins.back());
+        pl->plain_threads[b] = lay[c].T;
+    }
+    if (hipMalloc(&pl->d_bins, sizeof(BinDesc) * hbins.size()) != hipSuccess)
+        return bail(fail(TDSE_E_NOMEM, "plan allocation failed"));
+    for (size_t g = 0; g < pl->fgroups.size(); ++g) pl->fgroups[g].d_bins = pl->d_bins + goff[g];
+    if (hipMemcpy(pl->d_bins, hbins.data(), sizeof(BinDesc) * hbins.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return bail(fail(TDSE_E_DEVICE, "plan upload failed"));
+    (void)plain0;
+
+    // adjoint launches, one per class, longest work first: classes by
+    // (n_pad * count) descending
     std::vector<int> corder(ncls);
     for (int c = 0; c < ncls; ++c) corder[c] = c;
     std::stable_sort(corder.begin(), corder.end(), [&](int x, int y) {
@@ -859,9 +1141,12 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         return wx > wy;
     });
     const int nl = ncls;
+    const int ng = (int)pl->fgroups.size();
+    pl->ctr_plain = 3 * nl;
+    pl->ctr_fwd = 3 * nl + batch;
     if (hipMalloc(&pl->d_sys, sizeof(SysDesc) * batch) != hipSuccess ||
         hipMalloc(&pl->d_order_all, sizeof(int32_t) * 2 * batch) != hipSuccess ||
-        hipMalloc(&pl->d_counters, sizeof(int32_t) * (3 * nl + batch)) != hipSuccess ||
+        hipMalloc(&pl->d_counters, sizeof(int32_t) * (3 * nl + batch + ng)) != hipSuccess ||
         hipMalloc(&pl->d_ident, sizeof(int32_t) * batch) != hipSuccess)
         return bail(fail(TDSE_E_NOMEM, "plan allocation failed"));
     std::vector<int32_t> order_all;
@@ -877,17 +1162,11 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         L.d_order = pl->d_order_all + order_all.size();
         L.d_order_adj = pl->d_order_all + batch + order_all.size();
         order_all.insert(order_all.end(), csys[c].begin(), csys[c].end());
-        int occ = 0;
-        if (tune) {
-            L.S = tuned[c].S;
-            L.lds = tuned[c].lds;
-            L.tuned_rate = tuned[c].rate;
-            occ = forward_occupancy(L.C, L.T, L.S, L.lds);
-            if (occ < 1) return bail(fail(TDSE_E_UNSUPPORTED, "tuned layout does not fit"));
-        } else if (!choose_packing(L.C, L.T, L.count, false, &L.S, &L.lds, &occ)) {
-            return bail(fail(TDSE_E_UNSUPPORTED, "layout C=%d T=%d does not fit", L.C, L.T));
-        }
-        L.grid = std::min((L.count + L.S - 1) / L.S, occ * num_cus());
+        const tdse_plan_s::FwdGroup& fg = pl->fgroups[pl->fgroup_of_cls[c]];
+        L.S = std::max(1, fg.threads / L.T);
+        L.lds = fg.lds;
+        L.grid = fg.grid;
+        if (tune) L.tuned_rate = tuned[c].rate;
         if (adjoint_k > 0) {
             int aocc = 0;
             if (!choose_packing(L.C, L.T, L.count, true, &L.aS, &L.alds, &aocc))
@@ -911,8 +1190,8 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
             hipSuccess)
         return bail(fail(TDSE_E_DEVICE, "plan upload failed"));
 
-    // graph branches
-    const int nbr = std::min<int>(4, nl);
+    // graph branches (forward groups run concurrently)
+    const int nbr = std::min<int>(4, ng);
     for (int i = 0; i < nbr; ++i) {
         hipStream_t s;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
@@ -1011,34 +1290,34 @@ static void fill_fwd_args(tdse_plan pl, FwdArgs& a, const double* E, const doubl
 
 static tdse_status enqueue_forward(tdse_plan pl, const FwdArgs& base, hipStream_t st, bool branches)
 {
-    const int nl = (int)pl->launches.size();
-    if (launch_reset_counters(pl->d_counters, nl, st) != hipSuccess)
+    const int ng = (int)pl->fgroups.size();
+    int32_t* ctr = pl->d_counters + pl->ctr_fwd;
+    if (launch_reset_counters(ctr, ng, st) != hipSuccess)
         return fail(TDSE_E_DEVICE, "counter reset launch failed");
-    auto one = [&](int l, hipStream_t s) -> tdse_status {
-        const Launch& L = pl->launches[l];
+    auto one = [&](int g, hipStream_t s) -> tdse_status {
+        const tdse_plan_s::FwdGroup& G = pl->fgroups[g];
         FwdArgs a = base;
-        a.order = L.d_order;
-        a.count = L.count;
-        a.cls = L.cls;
-        a.queue = pl->d_counters + l;
-        a.sub_bytes = (int64_t)sub_smem_bytes(L.T / kWave);
-        if (launch_forward(L.C, L.lds, a, L.T, L.S, L.grid, s) != hipSuccess)
+        a.bins = G.d_bins;
+        a.nbins = G.nbins;
+        a.item_off = (int32_t)(G.smem - 16);
+        a.queue = ctr + g;
+        if (launch_forward(G.C, G.lds, a, G.threads, G.smem, G.grid, s) != hipSuccess)
             return fail(TDSE_E_DEVICE, "forward launch failed: %s", hipGetErrorString(hipGetLastError()));
         return TDSE_OK;
     };
     if (!branches || pl->branch.size() <= 1) {
-        for (int l = 0; l < nl; ++l) {
-            tdse_status rc = one(l, st);
+        for (int g = 0; g < ng; ++g) {
+            tdse_status rc = one(g, st);
             if (rc != TDSE_OK) return rc;
         }
         return TDSE_OK;
     }
-    // fork the classes over the branch streams (captured as parallel graph branches)
+    // fork the groups over the branch streams (captured as parallel graph branches)
     const int nb = (int)pl->branch.size();
     HIP_TRY(hipEventRecord(pl->ev[0], st));
     for (int b = 0; b < nb; ++b) HIP_TRY(hipStreamWaitEvent(pl->branch[b], pl->ev[0], 0));
-    for (int l = 0; l < nl; ++l) {
-        tdse_status rc = one(l, pl->branch[l % nb]);
+    for (int g = 0; g < ng; ++g) {
+        tdse_status rc = one(g, pl->branch[g % nb]);
         if (rc != TDSE_OK) return rc;
     }
     for (int b = 0; b < nb; ++b) {
@@ -1064,19 +1343,21 @@ tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* 
 
     if (plan->options & TDSE_OPT_PLAIN) {
         // one system per launch, serially on the caller's stream
-        const int nl = (int)plan->launches.size();
-        int32_t* ctr = plan->d_counters + 3 * nl;
+        int32_t* ctr = plan->d_counters + plan->ctr_plain;
         if (launch_reset_counters(ctr, plan->batch, st) != hipSuccess)
             return fail(TDSE_E_DEVICE, "counter reset launch failed");
+        const BinDesc* pb = plan->d_bins;
+        size_t off = 0;
+        for (const auto& G : plan->fgroups) off += G.nbins;
         for (int b = 0; b < plan->batch; ++b) {
             const Launch& L = plan->launches[plan->launch_of_cls[plan->cls_of[b]]];
             FwdArgs a = base;
-            a.order = plan->d_ident + b;
-            a.count = 1;
-            a.cls = L.cls;
+            a.bins = pb + off + b;
+            a.nbins = 1;
+            a.item_off = (int32_t)(plan->plain_smem[b] - 16);
             a.queue = ctr + b;
-            a.sub_bytes = (int64_t)sub_smem_bytes(L.T / kWave);
-            if (launch_forward(L.C, L.lds, a, L.T, 1, 1, st) != hipSuccess)
+            if (launch_forward(L.C, L.lds, a, plan->plain_threads[b], plan->plain_smem[b], 1, st) !=
+                hipSuccess)
                 return fail(TDSE_E_DEVICE, "forward launch failed");
         }
         return TDSE_OK;

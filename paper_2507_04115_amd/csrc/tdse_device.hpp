@@ -428,9 +428,11 @@ __device__ __forceinline__ cd scan_fwd(cd z, cd a0, cd a1, cd aw, const SizeClas
         if (lc.lane >= d) z = cmad(p, zs, z);
     }
     cd prev = czero();
+    // The barrier is taken even by single-wavefront systems: subgroups of
+    // different sizes share a workgroup and must take the same barriers.
+    if (lc.W > 1 && lc.lane == kWave - 1) lds[lc.wave] = z;
+    __syncthreads();
     if (lc.W > 1) {
-        if (lc.lane == kWave - 1) lds[lc.wave] = z;
-        __syncthreads();
         const int v0 = max(0, lc.wave - sc.xwaves);  // wave-uniform
         if (v0 < lc.wave) {
             prev = lds[v0];
@@ -457,9 +459,9 @@ __device__ __forceinline__ cd scan_bwd(cd y, cd b0, cd b1, cd bw, const SizeClas
         if (lc.lane + d < kWave) y = cmad(p, ys, y);
     }
     cd next = czero();
+    if (lc.W > 1 && lc.lane == 0) lds[lc.wave] = y;
+    __syncthreads();
     if (lc.W > 1) {
-        if (lc.lane == 0) lds[lc.wave] = y;
-        __syncthreads();
         const int v1 = min(lc.W - 1, lc.wave + sc.xwaves);  // wave-uniform
         if (v1 > lc.wave) {
             next = lds[v1];
@@ -632,9 +634,6 @@ __device__ __forceinline__ void forward_step(cd (&v)[C], cd& gl, cd& gr, const L
     cn_apply<C, true, TV>(v, gl, gr, f, tb, sc, lc, rc, lds_f, lds_b);
     phase_mask<C>(v, gl, gr, e, dt, xl, sc.dx, f.mflags, sc, lc);
 }
-
-// Bytes of LDS per grid point of the staged tables (om and dV/dx).
-constexpr int kLdsTableBytes = 16;
 
 // Copies the om and dV/dx tables of a size class into LDS: 16 bytes per
 // point, shared by every system the workgroup propagates.

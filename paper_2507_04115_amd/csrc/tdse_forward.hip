@@ -30,35 +30,52 @@ size_t sub_smem_bytes(int W)
 }
 
 // -------------------------------------------------------------- forward
+// Persistent: each workgroup takes bins from the queue.  A bin is a set of
+// systems of one lane layout that together fill the workgroup's lanes (plus a
+// padding system where they do not); every subgroup runs the whole time loop
+// of its system with the same barrier sequence as the others.
 template <int C, bool LDSTAB>
 __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
 {
     extern __shared__ double smem_raw[];
-    const SizeClass sc = uniform_load(a.classes + a.cls);
-    const int T = sc.T, W = T / kWave, np = C * T;
-    const int S = blockDim.x / T;
-    const int tid = threadIdx.x, sub = uniform(tid / T), t = tid - sub * T;
-    const int wsys = uniform(t / kWave);  // wavefront within the system
-    const size_t sb = a.sub_bytes;
-    char* per = reinterpret_cast<char*>(smem_raw) + (LDSTAB ? kLdsTableBytes * np : 0);
-    const SubSmem sm = carve_sub(per + sub * sb, W);
-    int* wg_item = reinterpret_cast<int*>(per + S * sb);
-    TableSource<LDSTAB>::make(sc, smem_raw);  // stages the tables once per workgroup
-    const double dx = sc.dx;
-    const int n = sc.n, s = t * C;
+    char* const smem = reinterpret_cast<char*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int wv = uniform(tid / kWave);  // wavefront within the workgroup
+    int* wg_item = reinterpret_cast<int*>(smem + a.item_off);
     const int nt = a.nt;
 
     for (;;) {
-        if (tid == 0) wg_item[0] = atomicAdd(a.queue, S);
+        if (tid == 0) wg_item[0] = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int b = uniform(wg_item[0]);
+        if (b >= a.nbins) break;
+        const BinDesc* bd = a.bins + b;
+        const int j = scalar_load(bd->sub_of_wave + wv);
+        const BinSub bs = scalar_load(bd->sub + j);
+        const SizeClass* const clsp = a.classes + bs.cls;
+        const SizeClass sc = scalar_load(clsp);
+        const int T = sc.T, W = T / kWave;
+        const int wsys = wv - bs.wave0;  // wavefront within the system
+        const int t = wsys * kWave + (tid & (kWave - 1));
+        double* const tab = reinterpret_cast<double*>(smem + bs.tab_off);
+        const SubSmem sm = carve_sub(smem + bs.sub_off, W);
+        const bool active = bs.p >= 0;  // uniform within the subgroup
+        const int p = active ? bs.p : 0;
+        const double dx = sc.dx;
+        const int n = sc.n, s = t * C;
+        if (LDSTAB && bs.stage) {
+            const int np = C * T;
+            for (int i = t; i < np; i += T) {
+                tab[i] = sc.pt.om[i];
+                tab[np + i] = sc.pt.dv[i];
+            }
+        }
         if (t == 0) sm.misc[1] = 0;
         __syncthreads();
-        const int base = uniform(wg_item[0]);
-        if (base >= a.count) break;
-        const int item = base + sub;
-        const bool active = item < a.count;  // uniform within the subgroup
-        const int p = active ? uniform(a.order[item]) : 0;
+
         const SysDesc d = uniform_load(a.sys + p);
-        const double* src = a.psi0 ? a.psi0 + 2 * d.psi_off : a.gs + 2 * a.gs_off[a.cls];
+        const double* src = nullptr;
+        if (active) src = a.psi0 ? a.psi0 + 2 * d.psi_off : a.gs + 2 * a.gs_off[bs.cls];
         const size_t row = (size_t)p * (size_t)(nt + 1);
         const double* erow = a.E + row;
         double* acc_row = a.accel + row;
@@ -73,7 +90,7 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
 
         LaneFactors<C> f;
         {
-            const StepView<LDSTAB> sv = step_view<LDSTAB>(a.classes + a.cls, wsys, smem_raw);
+            const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, tab);
             f = load_factors<C>(sv.sc, sv.lc);
             observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, sm.ring);
         }
@@ -84,7 +101,7 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
 
         int flushed = 0;
         for (int i = 0; i < nt; ++i) {
-            const StepView<LDSTAB> sv = step_view<LDSTAB>(a.classes + a.cls, wsys, smem_raw);
+            const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, tab);
             forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
                             sm.lds_f, sm.lds_b);
             if ((i + 1) % kFlush == 0) {
@@ -229,12 +246,6 @@ hipError_t launch_reset_counters(int32_t* counters, int n, hipStream_t st)
 
 bool layout_supported(int C) { return C == 4 || C == 8 || C == 16; }
 
-size_t forward_smem_bytes(int C, int T, int S, bool lds_tables)
-{
-    return (lds_tables ? (size_t)kLdsTableBytes * C * T : 0) + S * sub_smem_bytes(T / kWave) +
-           16;
-}
-
 template <int C, bool L>
 static int occ_fwd(int threads, size_t sh)
 {
@@ -251,34 +262,34 @@ static int occ_fwd(int threads, size_t sh)
     return nb;
 }
 
-int forward_occupancy(int C, int T, int S, bool lds_tables)
+int forward_occupancy(int C, int threads, size_t smem, bool lds_tables)
 {
-    const size_t sh = forward_smem_bytes(C, T, S, lds_tables);
-    if (sh > (size_t)kMaxLds) return 0;
-    const int th = S * T;
+    if (smem > (size_t)kMaxLds || threads < kWave || threads > 1024 || threads % kWave) return 0;
     switch (C * 2 + (lds_tables ? 1 : 0)) {
-        case 8: return occ_fwd<4, false>(th, sh);
-        case 9: return occ_fwd<4, true>(th, sh);
-        case 16: return occ_fwd<8, false>(th, sh);
-        case 17: return occ_fwd<8, true>(th, sh);
-        case 32: return occ_fwd<16, false>(th, sh);
-        case 33: return occ_fwd<16, true>(th, sh);
+        case 8: return occ_fwd<4, false>(threads, smem);
+        case 9: return occ_fwd<4, true>(threads, smem);
+        case 16: return occ_fwd<8, false>(threads, smem);
+        case 17: return occ_fwd<8, true>(threads, smem);
+        case 32: return occ_fwd<16, false>(threads, smem);
+        case 33: return occ_fwd<16, true>(threads, smem);
         default: return 0;
     }
 }
 
-hipError_t launch_forward(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
-                          hipStream_t st)
+hipError_t launch_forward(int C, bool lds_tables, const FwdArgs& a, int threads, size_t smem,
+                          int grid, hipStream_t st)
 {
-    const size_t sh = forward_smem_bytes(C, T, S, lds_tables);
-    const dim3 b(T * S);
+    if (smem > (size_t)kMaxLds || threads < kWave || threads > 1024 || threads % kWave ||
+        (size_t)a.item_off + 16 > smem)
+        return hipErrorInvalidValue;
+    const dim3 b(threads);
     switch (C * 2 + (lds_tables ? 1 : 0)) {
-        case 8: hipLaunchKernelGGL((forward_kernel<4, false>), dim3(grid), b, sh, st, a); break;
-        case 9: hipLaunchKernelGGL((forward_kernel<4, true>), dim3(grid), b, sh, st, a); break;
-        case 16: hipLaunchKernelGGL((forward_kernel<8, false>), dim3(grid), b, sh, st, a); break;
-        case 17: hipLaunchKernelGGL((forward_kernel<8, true>), dim3(grid), b, sh, st, a); break;
-        case 32: hipLaunchKernelGGL((forward_kernel<16, false>), dim3(grid), b, sh, st, a); break;
-        case 33: hipLaunchKernelGGL((forward_kernel<16, true>), dim3(grid), b, sh, st, a); break;
+        case 8: hipLaunchKernelGGL((forward_kernel<4, false>), dim3(grid), b, smem, st, a); break;
+        case 9: hipLaunchKernelGGL((forward_kernel<4, true>), dim3(grid), b, smem, st, a); break;
+        case 16: hipLaunchKernelGGL((forward_kernel<8, false>), dim3(grid), b, smem, st, a); break;
+        case 17: hipLaunchKernelGGL((forward_kernel<8, true>), dim3(grid), b, smem, st, a); break;
+        case 32: hipLaunchKernelGGL((forward_kernel<16, false>), dim3(grid), b, smem, st, a); break;
+        case 33: hipLaunchKernelGGL((forward_kernel<16, true>), dim3(grid), b, smem, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -15,6 +15,8 @@ constexpr int kMaxWaves = 16;   // lanes per system <= 1024
 constexpr int kMaxLevels = 6;   // in-wave Kogge-Stone levels (2^6 = 64 lanes)
 constexpr int kFlush = 32;      // samples per output flush
 constexpr int kRing = 64;       // ring of per-wave partial sums (samples)
+constexpr int kLdsTableBytes = 16;  // LDS bytes per grid point of the staged
+                                    // tables (om and dV/dx)
 
 __host__ __device__ inline int pbase(int t, int C) { return (t >> 6) * (C * 64) + (t & 63); }
 __host__ __device__ inline int pidx(int t, int k, int C) { return pbase(t, C) + 64 * k; }
@@ -74,6 +76,32 @@ struct SizeClass {
                      // diagonal of 12 |h| (-D2/2), used by the right-hand side
     PointTables pt;
     LaneTables lt;
+};
+
+// One workgroup's worth of work for the forward kernel: up to kMaxSubs
+// systems of one lane layout, each on a contiguous run of wavefronts
+// (a subgroup of T = 64 W lanes).  Lanes that no system needs run a padding
+// system (p = -1) of a padding class with exactly that many lanes, so every
+// wavefront takes the same sequence of barriers.  Packing systems of
+// different sizes into full workgroups is what lets one persistent launch
+// keep every SIMD busy on an uneven batch.
+constexpr int kMaxSubs = 16;
+
+struct BinSub {
+    int32_t p;        // system, or -1 for padding
+    int32_t cls;      // size class
+    int32_t wave0;    // first wavefront of the subgroup in the workgroup
+    int32_t tab_off;  // byte offset of the class's staged tables in LDS
+    int32_t sub_off;  // byte offset of the subgroup's scratch block in LDS
+    int32_t stage;    // 1: this subgroup copies its class's tables into LDS
+    int32_t pad_[2];
+};
+
+struct BinDesc {
+    int32_t nsub;
+    int32_t pad_[3];
+    int32_t sub_of_wave[kMaxSubs];  // subgroup of each wavefront
+    BinSub sub[kMaxSubs];
 };
 
 // Kernel-side description of one system of a batch.

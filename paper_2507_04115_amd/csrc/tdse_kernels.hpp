@@ -17,6 +17,11 @@ struct TableParams {
 struct FwdArgs {
     const SizeClass* classes;
     const SysDesc* sys;
+    // forward: workgroup bins (one queue item each)
+    const BinDesc* bins;
+    int32_t nbins;
+    int32_t item_off;       // LDS byte offset of the workgroup's queue slot
+    // adjoint: the systems of one size class, one subgroup each
     const int32_t* order;   // systems of this launch, in queue order
     int32_t count;          // number of entries in `order`
     int32_t cls;            // size class of every system of this launch
@@ -71,13 +76,13 @@ hipError_t launch_reset_counters(int32_t* counters, int n, hipStream_t st);
 bool layout_supported(int C);
 size_t sub_smem_bytes(int W);
 
-// Forward kernel: C points per lane, T lanes per system, S systems per
-// workgroup, point tables in LDS or global memory.  Occupancy is in
-// workgroups per CU (0 when the configuration does not fit).
-size_t forward_smem_bytes(int C, int T, int S, bool lds_tables);
-int forward_occupancy(int C, int T, int S, bool lds_tables);
-hipError_t launch_forward(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
-                          hipStream_t st);
+// Forward kernel over workgroup bins: C points per lane, `threads` lanes per
+// workgroup, `smem` bytes of LDS (staged tables of the bin's classes, the
+// subgroups' scratch blocks, the queue slot), point tables in LDS or global
+// memory.  Occupancy is in workgroups per CU (0 when it does not fit).
+int forward_occupancy(int C, int threads, size_t smem, bool lds_tables);
+hipError_t launch_forward(int C, bool lds_tables, const FwdArgs& a, int threads, size_t smem,
+                          int grid, hipStream_t st);
 
 size_t adjoint_smem_bytes(int C, int T, int S, bool lds_tables);
 int adjoint_occupancy(int C, int T, int S, bool lds_tables);

@@ -293,3 +293,29 @@ def test_autotuned_plan_matches_oracle(lib, torch_dev):
         assert rel(out_t["accel"][b], out_d["accel"][b]) < 1e-11
     plan_t.close()
     plan_d.close()
+
+
+def test_mixed_sizes_share_workgroups(lib, torch_dev):
+    """Systems of several sizes and one layout are packed together into
+    1024-lane workgroups (with padding subgroups where they do not fill one);
+    every system matches the oracle and the packed result equals the
+    one-system-per-launch result bitwise."""
+    torch, dev = torch_dev
+    ns = [2048] * 5 + [2304] * 3 + [3328] * 2 + [600]
+    dx, dt = 0.2, 0.05
+    nt = 120
+    efield = 0.05 * np.random.default_rng(21).standard_normal((len(ns), nt + 1))
+    print(f"mixed sizes ns={ns} nt={nt}", flush=True)
+    plan, out = _run_forward(lib, torch, dev, ns, efield, dx, dt, A_AR, want=False)
+    _, out_p = _run_forward(lib, torch, dev, ns, efield, dx, dt, A_AR, options=lib.TDSE_OPT_PLAIN,
+                            want=False)
+    assert np.all(out["status"] == 0)
+    assert np.array_equal(out["accel"], out_p["accel"])
+    assert np.array_equal(out["psi_final"], out_p["psi_final"])
+    for b in (0, 5, 8, 10):
+        psi0 = torch.empty(2 * ns[b], dtype=torch.float64, device=dev)
+        plan.ground_state(ns[b], psi0)
+        ref = oracle.propagate(efield[b], psi0.cpu().numpy().view(np.complex128), dx, dt, A_AR,
+                               mask_frac=0.1)
+        assert rel(out["accel"][b], ref["accel"]) < TOL_ACC
+    plan.close()
