@@ -523,7 +523,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
         cd g_c = gfac<RT>(om_c, v[0]);
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            if (k == C / 2) {
+            if (k == (QInRegs<C>::value ? C / 2 : C - 1)) {
                 if (sc.levels > 0) a0 = ld_lane(sc.lt.pa, off);
                 if (sc.levels > 1) a1 = ld_lane(sc.lt.pa + sc.T, off);
                 if (lc.lane < (1 << sc.levels)) aw = ld_lane(sc.lt.pw, off);
@@ -542,10 +542,15 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
         }
     }
     const cd cf = scan_fwd(ze, a0, a1, aw, sc, lc, lds_f);
-    const cd b0c = sc.levels > 0 ? ld_lane(sc.lt.qb, off) : czero();
-    const cd b1c = sc.levels > 1 ? ld_lane(sc.lt.qb + sc.T, off) : czero();
-    cd bw = czero();
-    if (lc.lane > kWave - 1 - (1 << sc.levels)) bw = ld_lane(sc.lt.qw, off);
+    // window products of the backward scan: loaded ahead of sweep B when the
+    // registers allow, else just before the scan
+    cd b0c = czero(), b1c = czero(), bw = czero();
+    auto load_bwd_windows = [&]() {
+        if (sc.levels > 0) b0c = ld_lane(sc.lt.qb, off);
+        if (sc.levels > 1) b1c = ld_lane(sc.lt.qb + sc.T, off);
+        if (lc.lane > kWave - 1 - (1 << sc.levels)) bw = ld_lane(sc.lt.qw, off);
+    };
+    if constexpr (QInRegs<C>::value) load_bwd_windows();
     // B. forward recurrence from the exact carry, w = q z
     {
         cd z = cf;
@@ -558,16 +563,22 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
             point_fence(v[k]);
         }
     }
-    // C. chunk-start value of y with zero carry-in
+    // C. chunk-start value of y with zero carry-in.  When q is read from
+    // memory, the chunk base is hidden from the optimiser so that sweep C
+    // reloads q and om instead of keeping sweep B's values live in registers.
     cd yb = v[C - 1];
     {
+        LaneCtx lcc = lc;
+        if constexpr (!QInRegs<C>::value) lcc.b0 = opaque(lc.b0);
+        const int bc = lcc.b0;
 #pragma unroll
         for (int k = C - 2; k >= 0; --k) {
-            const double om_n = tb.om(b0 + 64 * (k + 1));
-            yb = cmad(elim<RT>(om_n, f.q(k, sc, lc)), yb, v[k]);
+            const double om_n = tb.om(bc + 64 * (k + 1));
+            yb = cmad(elim<RT>(om_n, f.q(k, sc, lcc)), yb, v[k]);
             point_fence(yb);
         }
     }
+    if constexpr (!QInRegs<C>::value) load_bwd_windows();
     const cd cb = scan_bwd(yb, b0c, b1c, bw, sc, lc, lds_b);
     // D. backward recurrence from the exact carry
     double om_0;
