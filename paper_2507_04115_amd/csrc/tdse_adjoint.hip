@@ -27,32 +27,38 @@ namespace tdse {
 
 namespace {
 
-// State record: chunk values and the two ghosts, [C+2][T] complex.
-template <int C>
-__device__ __forceinline__ void store_state(double* base, int T, int t, const cd (&v)[C], cd gl,
-                                            cd gr)
+// State record: chunk values and the two ghosts, [C+2][T] complex.  The
+// record base is wave-uniform (scalar registers); each access adds the
+// lane's byte offset 16 t, so the loads and stores take one VGPR offset.
+__device__ __forceinline__ void st_lane(double* base, unsigned off_bytes, cd x)
 {
-    double2* b = reinterpret_cast<double2*>(base);
-#pragma unroll
-    for (int k = 0; k < C; ++k) b[k * T + t] = make_double2(v[k].re, v[k].im);
-    b[C * T + t] = make_double2(gl.re, gl.im);
-    b[(C + 1) * T + t] = make_double2(gr.re, gr.im);
+    typedef double dvec2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) dvec2* gptr;
+    dvec2 w;
+    w.x = x.re;
+    w.y = x.im;
+    *(gptr)(reinterpret_cast<char*>(base) + off_bytes) = w;
 }
 
 template <int C>
-__device__ __forceinline__ void load_state(const double* base, int T, int t, cd (&v)[C], cd& gl,
-                                           cd& gr)
+__device__ __forceinline__ void store_state(double* base, int T, unsigned off, const cd (&v)[C],
+                                            cd gl, cd gr)
 {
-    const double2* b = reinterpret_cast<const double2*>(base);
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const double2 x = b[k * T + t];
-        v[k] = mkc(x.x, x.y);
-    }
-    double2 x = b[C * T + t];
-    gl = mkc(x.x, x.y);
-    x = b[(C + 1) * T + t];
-    gr = mkc(x.x, x.y);
+    for (int k = 0; k < C; ++k) st_lane(base + 2 * (size_t)k * T, off, v[k]);
+    st_lane(base + 2 * (size_t)C * T, off, gl);
+    st_lane(base + 2 * (size_t)(C + 1) * T, off, gr);
+}
+
+template <int C>
+__device__ __forceinline__ void load_state(const double* base, int T, unsigned off, cd (&v)[C],
+                                           cd& gl, cd& gr)
+{
+    const cd* b = reinterpret_cast<const cd*>(base);
+#pragma unroll
+    for (int k = 0; k < C; ++k) v[k] = ld_lane(b + (size_t)k * T, off);
+    gl = ld_lane(b + (size_t)C * T, off);
+    gr = ld_lane(b + (size_t)(C + 1) * T, off);
 }
 
 __device__ __forceinline__ void flush_norm(int a0, int a1, int t, int T, const double* ring,
@@ -129,6 +135,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
     const int S = blockDim.x / T;
     const int tid = threadIdx.x, sub = uniform(tid / T), t = tid - sub * T;
     const int wsys = uniform(t / kWave);  // wavefront within the system
+    const unsigned loff = 16u * (unsigned)t;  // lane offset in state records
     const size_t sb = a.sub_bytes;
     char* per = reinterpret_cast<char*>(smem_raw) + (LDSTAB ? kLdsTableBytes * np : 0);
     const SubSmem sm = carve_sub(per + sub * sb, W);
@@ -195,7 +202,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
         const int nfwd = (wg_need || a.accel) ? nt : -1;  // uniform
         for (int i = 0; i <= nfwd; ++i) {
             const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
-            if (i % K == 0) store_state<C>(ckpt + np2 * (i / K), T, t, v, gl, gr);
+            if (i % K == 0) store_state<C>(ckpt + np2 * (i / K), T, loff, v, gl, gr);
             observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, ring + (i % kRing) * W * 3);
             if (i == nt) break;
             forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
@@ -222,13 +229,13 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
             const int s0 = sidx * K;
             const int s1 = min(s0 + K, nt);
             // recompute psi^{s0..s1} into the segment buffer
-            load_state<C>(ckpt + np2 * sidx, T, t, v, gl, gr);
-            store_state<C>(seg, T, t, v, gl, gr);
+            load_state<C>(ckpt + np2 * sidx, T, loff, v, gl, gr);
+            store_state<C>(seg, T, loff, v, gl, gr);
             for (int i = s0; i < s1; ++i) {
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
                                 sm.lds_f, sm.lds_b);
-                store_state<C>(seg + np2 * (i - s0 + 1), T, t, v, gl, gr);
+                store_state<C>(seg + np2 * (i - s0 + 1), T, loff, v, gl, gr);
             }
             if (!started) {
                 // kappa^nt = 2 abar_nt dx (V' + E_nt) conj(psi^nt); psi^nt = v
@@ -247,10 +254,11 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
                 // kappa <- U (D_i kappa)
                 const double e = erow[i];
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
+                // psi^i is loaded first: its latency overlaps the costate step
+                load_state<C>(seg + np2 * (i - s0), T, loff, v, gl, gr);
                 phase_mask<C>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc, sv.lc);
                 cn_apply<C, true>(kap, kgl, kgr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
                 // + 2 abar_i dx (V' + E_i) conj(psi^i)
-                load_state<C>(seg + np2 * (i - s0), T, t, v, gl, gr);
                 add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[i] * dx, e, sv.tb, T, sv.lc);
                 if (i > 0) {
                     // partial of grad_{i-1} from kappa^i and psi^i
