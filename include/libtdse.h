@@ -110,6 +110,7 @@ typedef struct tdse_plan_s* tdse_plan;
 #define TDSE_OPT_PLAIN 1u     /* propagate one system per launch (no queue)   */
 #define TDSE_OPT_NO_GRAPH 2u  /* launch directly instead of replaying a graph */
 #define TDSE_OPT_AUTOTUNE 4u  /* time the candidate layouts at plan creation  */
+#define TDSE_OPT_STORE_CHECKPOINTS 8u /* forward stores adjoint checkpoints   */
 
 /* Creates a plan for `batch` systems of sizes n_per_system[0..batch-1]
  * (host array, each 16 <= n <= 16384) sharing the parameters `p`.  The plan
@@ -122,7 +123,14 @@ typedef struct tdse_plan_s* tdse_plan;
  * thread's current device).  The plan is immutable; one plan must not be
  * used by two threads at once.
  *   adjoint_k  checkpoint interval of the adjoint in steps (>= 1); 0 creates a
- *              forward-only plan without the adjoint workspace */
+ *              forward-only plan without the adjoint workspace
+ * With TDSE_OPT_STORE_CHECKPOINTS (needs adjoint_k > 0, excludes
+ * TDSE_OPT_PLAIN) the plan also holds, per system, the states at steps
+ * 0, K, 2K, ... and the norm row of the last forward pass: about
+ * 16 (C+2)/C n (nt/K + 1) + 8 (nt+1) bytes per system (C = points per lane).
+ * tdse_propagate_batch then runs the adjoint kernel's forward pass, which
+ * writes the same outputs and the store, and tdse_adjoint_batch_stored can
+ * skip that pass. */
 tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t* n_per_system,
                              uint32_t options, int32_t adjoint_k, tdse_plan* out);
 tdse_status tdse_plan_destroy(tdse_plan plan);
@@ -179,10 +187,12 @@ tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* 
 /* Gradient of a loss l(accel) with respect to every field sample.  Given
  * accel_bar[b][i] = dl/d accel[b][i], writes grad_E[b][i] = dl/dE_b(t_i).
  * The gradient is the exact discrete adjoint of tdse_propagate_batch (the
- * paper has no adjoint; its derivation from the forward recursion is in the
- * design notes): the costate is propagated backward in time with the
- * adjoint of each substep, the forward wavefunction being recomputed from
- * checkpoints stored every plan->adjoint_k steps.
+ * paper has no adjoint; this one follows from differentiating the forward
+ * recursion step by step): the costate is propagated backward in time with
+ * the adjoint of each substep, the forward wavefunction being recomputed
+ * from checkpoints stored every plan->adjoint_k steps during a forward pass
+ * that this call runs first.  On a plan with TDSE_OPT_STORE_CHECKPOINTS that
+ * pass rewrites the plan's store (and advances its generation).
  *   E, psi0    as for tdse_propagate_batch
  *   accel_bar  dev [batch][nt+1]; rows that are entirely zero are skipped
  *              (their grad_E row is zero)
@@ -193,6 +203,26 @@ tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* 
 tdse_status tdse_adjoint_batch(tdse_plan plan, const double* E, const double* psi0,
                                const double* accel_bar, double* grad_E, double* accel,
                                int32_t* sys_status, void* stream);
+
+/* Generation of a plan's checkpoint store (host output): 0 until the first
+ * tdse_propagate_batch, then advanced by every call that rewrites the store
+ * (tdse_propagate_batch and tdse_adjoint_batch on a plan created with
+ * TDSE_OPT_STORE_CHECKPOINTS).  Read it right after the forward call whose
+ * checkpoints a later tdse_adjoint_batch_stored should use. */
+tdse_status tdse_plan_checkpoint_generation(tdse_plan plan, uint64_t* generation);
+
+/* The gradient of tdse_adjoint_batch from the checkpoints that the forward
+ * pass of generation `generation` stored: the reverse sweep only (segment
+ * recompute from the stored checkpoints, then the costate steps).  E must be
+ * the field of that forward pass (the checkpoints already hold its psi0).
+ * Fails with TDSE_E_INVALID, before any launch, when the plan has no store
+ * or the store has been rewritten since (generation mismatch).
+ *   accel_bar, grad_E, sys_status   as for tdse_adjoint_batch
+ * Asynchronous on `stream`, ordered after the forward pass on the same
+ * stream. */
+tdse_status tdse_adjoint_batch_stored(tdse_plan plan, uint64_t generation, const double* E,
+                                      const double* accel_bar, double* grad_E, int32_t* sys_status,
+                                      void* stream);
 
 /* ------------------------------------------------------- harmonic yield */
 /* Windowed harmonic yield of each series and its gradient.  With

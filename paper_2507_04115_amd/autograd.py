@@ -38,7 +38,10 @@ class TDSEFunction(torch.autograd.Function):
 
     forward:  tdse_propagate_batch -> dipole acceleration [P, nt+1]
     backward: tdse_adjoint_batch with accel_bar = grad_output -> dl/dE
-    The plan must have been created with adjoint_k > 0 for backward."""
+    The plan must have been created with adjoint_k > 0 for backward.  On a
+    plan with TDSE_OPT_STORE_CHECKPOINTS, backward uses the checkpoints this
+    forward stored (tdse_adjoint_batch_stored) while no later call has
+    rewritten them, and recomputes the forward pass otherwise."""
 
     @staticmethod
     def forward(ctx, E: torch.Tensor, plan: "L.Plan", psi0: Optional[torch.Tensor] = None):
@@ -48,6 +51,7 @@ class TDSEFunction(torch.autograd.Function):
         L.tdse_propagate_batch(plan, E, psi0, accel)
         ctx.plan = plan
         ctx.psi0 = psi0
+        ctx.generation = plan.checkpoint_generation() if plan.stores_checkpoints else 0
         ctx.save_for_backward(E)
         return accel
 
@@ -57,7 +61,11 @@ class TDSEFunction(torch.autograd.Function):
         if ctx.plan.adjoint_k <= 0:
             raise RuntimeError("the plan was created without adjoint support (adjoint_k = 0)")
         grad_E = torch.empty_like(E)
-        L.tdse_adjoint_batch(ctx.plan, E, ctx.psi0, grad_accel.contiguous(), grad_E)
+        plan = ctx.plan
+        if ctx.generation and plan.checkpoint_generation() == ctx.generation:
+            L.tdse_adjoint_batch_stored(plan, ctx.generation, E, grad_accel.contiguous(), grad_E)
+        else:
+            L.tdse_adjoint_batch(plan, E, ctx.psi0, grad_accel.contiguous(), grad_E)
         return grad_E, None, None
 
 
@@ -100,7 +108,9 @@ class TDSEBatch:
     ``TDSEBatch(params, n_per)(E)`` is TDSEFunction.apply(E, plan)."""
 
     def __init__(self, params: "L.tdse_params", n_per_system: Sequence[int], adjoint_k: int = 256,
-                 options: int = 0):
+                 options: int = 0, store_checkpoints: bool = False):
+        if store_checkpoints:
+            options |= L.TDSE_OPT_STORE_CHECKPOINTS
         self.plan = L.Plan(params, n_per_system, options=options, adjoint_k=adjoint_k)
 
     def __call__(self, E: torch.Tensor, psi0: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -32,6 +32,7 @@ TDSE_OPT_NONE = 0
 TDSE_OPT_PLAIN = 1
 TDSE_OPT_NO_GRAPH = 2
 TDSE_OPT_AUTOTUNE = 4
+TDSE_OPT_STORE_CHECKPOINTS = 8
 
 _lib = None
 
@@ -70,6 +71,8 @@ _PROTOS = {
     "tdse_plan_ground_state": (_i32, [_vp, _i32, _vp, ctypes.POINTER(_d)]),
     "tdse_propagate_batch": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tdse_adjoint_batch": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tdse_plan_checkpoint_generation": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint64)]),
+    "tdse_adjoint_batch_stored": (_i32, [_vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp]),
     "tdse_harmonic_band": (_i32, [_i32, _d, _d, _d, _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "tdse_harmonic_yield": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
 }
@@ -213,6 +216,16 @@ class Plan:
                                             ctypes.byref(r_)), "tdse_plan_launch_info")
         return LaunchInfo(s_.value, bool(l_.value), r_.value)
 
+    @property
+    def stores_checkpoints(self) -> bool:
+        return bool(self.options & TDSE_OPT_STORE_CHECKPOINTS)
+
+    def checkpoint_generation(self) -> int:
+        g = ctypes.c_uint64()
+        _check(load().tdse_plan_checkpoint_generation(self.handle, ctypes.byref(g)),
+               "tdse_plan_checkpoint_generation")
+        return g.value
+
     def ground_state(self, n: int, psi_out) -> float:
         e = _d()
         _check(load().tdse_plan_ground_state(self.handle, n, _ptr(psi_out), ctypes.byref(e)),
@@ -232,6 +245,13 @@ def tdse_adjoint_batch(plan: Plan, E, psi0, accel_bar, grad_E, accel=None, sys_s
     _check(load().tdse_adjoint_batch(plan.handle, _ptr(E), _ptr(psi0), _ptr(accel_bar),
                                      _ptr(grad_E), _ptr(accel), _ptr(sys_status), _stream(stream)),
            "tdse_adjoint_batch")
+
+
+def tdse_adjoint_batch_stored(plan: Plan, generation: int, E, accel_bar, grad_E, sys_status=None,
+                              stream=None):
+    _check(load().tdse_adjoint_batch_stored(plan.handle, generation, _ptr(E), _ptr(accel_bar),
+                                            _ptr(grad_E), _ptr(sys_status), _stream(stream)),
+           "tdse_adjoint_batch_stored")
 
 
 def tdse_harmonic_band(nt: int, dt: float, omega0: float, h_lo: float, h_hi: float):

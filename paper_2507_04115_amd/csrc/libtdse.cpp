@@ -391,6 +391,11 @@ struct tdse_plan_s {
     // adjoint workspace
     double* d_adj = nullptr;
     size_t adj_bytes = 0;
+    // stored checkpoints (TDSE_OPT_STORE_CHECKPOINTS): per system
+    double* d_store = nullptr;
+    int64_t* d_store_off = nullptr;
+    size_t store_bytes = 0;
+    uint64_t ckpt_gen = 0;  // bumped by every call that rewrites the store
     // forward: one persistent launch per lane layout over workgroup bins
     struct FwdGroup {
         int C = 0;
@@ -426,6 +431,8 @@ void plan_free(tdse_plan pl)
     if (pl->d_counters) (void)hipFree(pl->d_counters);
     if (pl->d_ident) (void)hipFree(pl->d_ident);
     if (pl->d_adj) (void)hipFree(pl->d_adj);
+    if (pl->d_store) (void)hipFree(pl->d_store);
+    if (pl->d_store_off) (void)hipFree(pl->d_store_off);
     if (pl->d_bins) (void)hipFree(pl->d_bins);
     delete pl;
 }
@@ -944,9 +951,11 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     if (st != TDSE_OK) return st;
     if (batch < 1) return fail(TDSE_E_INVALID, "batch must be >= 1");
     if (!n_per_system) return fail(TDSE_E_INVALID, "n_per_system is NULL");
-    if (options & ~(TDSE_OPT_PLAIN | TDSE_OPT_NO_GRAPH | TDSE_OPT_AUTOTUNE))
+    if (options & ~(TDSE_OPT_PLAIN | TDSE_OPT_NO_GRAPH | TDSE_OPT_AUTOTUNE | TDSE_OPT_STORE_CHECKPOINTS))
         return fail(TDSE_E_INVALID, "unknown option bits 0x%x", options);
     if (adjoint_k < 0) return fail(TDSE_E_INVALID, "adjoint_k must be >= 0");
+    if ((options & TDSE_OPT_STORE_CHECKPOINTS) && (adjoint_k == 0 || (options & TDSE_OPT_PLAIN)))
+        return fail(TDSE_E_INVALID, "TDSE_OPT_STORE_CHECKPOINTS needs adjoint_k > 0 and no TDSE_OPT_PLAIN");
     for (int b = 0; b < batch; ++b) {
         if (n_per_system[b] < kMinN) return fail(TDSE_E_INVALID, "n[%d] = %d < %d", b, n_per_system[b], kMinN);
         if (n_per_system[b] > kMaxN)
@@ -1153,6 +1162,9 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     pl->launch_of_cls.assign(ncls, -1);
     const int64_t nt = p->nt;
     int64_t adj_total = 0;
+    const bool store = (options & TDSE_OPT_STORE_CHECKPOINTS) != 0;
+    std::vector<int64_t> store_off(batch, 0);
+    int64_t store_total = 0;
     for (int c : corder) {
         Launch L{};
         L.cls = c;
@@ -1174,9 +1186,16 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
             L.agrid = std::min((L.count + L.aS - 1) / L.aS, aocc * num_cus());
             const int64_t rec = 2 * (int64_t)(L.C + 2) * L.T;   // one state record
             const int64_t nseg = nt / adjoint_k + 1;
-            L.slot_doubles = (rec * (nseg + adjoint_k + 1) + (nt + 1) + 1) & ~int64_t(1);
+            const int64_t ck = rec * nseg + ((nt + 2) & ~int64_t(1));  // checkpoints + norm row
+            // a slot holds the segment states, and the checkpoints unless stored per system
+            L.slot_doubles = rec * (adjoint_k + 1) + (store ? 0 : ck);
             L.work_off = adj_total;
             adj_total += L.slot_doubles * (int64_t)L.agrid * L.aS;
+            if (store)
+                for (int32_t b : csys[c]) {
+                    store_off[b] = store_total;
+                    store_total += ck;
+                }
         }
         pl->launch_of_cls[c] = (int)pl->launches.size();
         pl->launches.push_back(L);
@@ -1210,6 +1229,16 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         if (hipMalloc(&pl->d_adj, pl->adj_bytes) != hipSuccess)
             return bail(fail(TDSE_E_NOMEM, "adjoint workspace of %.1f GB not available",
                              pl->adj_bytes / 1e9));
+    }
+    if (store) {
+        pl->store_bytes = sizeof(double) * (size_t)store_total;
+        if (hipMalloc(&pl->d_store, pl->store_bytes) != hipSuccess)
+            return bail(fail(TDSE_E_NOMEM, "checkpoint store of %.1f GB not available",
+                             pl->store_bytes / 1e9));
+        if (hipMalloc(&pl->d_store_off, sizeof(int64_t) * batch) != hipSuccess ||
+            hipMemcpy(pl->d_store_off, store_off.data(), sizeof(int64_t) * batch,
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(TDSE_E_NOMEM, "checkpoint store offsets not available"));
     }
     *out = pl;
     return TDSE_OK;
@@ -1327,6 +1356,42 @@ static tdse_status enqueue_forward(tdse_plan pl, const FwdArgs& base, hipStream_
     return TDSE_OK;
 }
 
+// One adjoint-kernel launch per size class.  With accel_bar, the class's
+// systems are first reordered so that rows needing the reverse sweep come
+// first; the forward-only mode keeps the class order.
+static tdse_status enqueue_adjoint(tdse_plan plan, const FwdArgs& base, const double* accel_bar,
+                                   int32_t mode, hipStream_t st)
+{
+    const int nl = (int)plan->launches.size();
+    if (launch_reset_counters(plan->d_counters, 3 * nl, st) != hipSuccess)
+        return fail(TDSE_E_DEVICE, "counter reset launch failed");
+    for (int l = 0; l < nl; ++l) {
+        const Launch& L = plan->launches[l];
+        FwdArgs a = base;
+        a.abar = accel_bar;
+        a.k_ckpt = plan->adjoint_k;
+        a.mode = mode;
+        a.store = plan->d_store;
+        a.store_off = plan->d_store_off;
+        a.order = L.d_order;
+        if (accel_bar) {
+            if (launch_compact_rows(accel_bar, plan->p.nt, L.d_order, L.count, L.d_order_adj,
+                                    plan->d_counters + nl + 2 * l, st) != hipSuccess)
+                return fail(TDSE_E_DEVICE, "row compaction launch failed");
+            a.order = L.d_order_adj;
+        }
+        a.count = L.count;
+        a.cls = L.cls;
+        a.queue = plan->d_counters + l;
+        a.sub_bytes = (int64_t)sub_smem_bytes(L.T / kWave);
+        a.work = plan->d_adj + L.work_off;
+        a.slot_doubles = L.slot_doubles;
+        if (launch_adjoint(L.C, L.alds, a, L.T, L.aS, L.agrid, st) != hipSuccess)
+            return fail(TDSE_E_DEVICE, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    return TDSE_OK;
+}
+
 tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* psi0,
                                  double* accel, double* xexp, double* norm, double* psi_final,
                                  int32_t* sys_status, void* stream)
@@ -1341,6 +1406,13 @@ tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* 
     FwdArgs base;
     fill_fwd_args(plan, base, E, psi0, accel, xexp, norm, psi_final, sys_status);
 
+    if (plan->d_store) {
+        // the adjoint kernel's forward pass: the same outputs, plus the
+        // checkpoints and norm rows a later tdse_adjoint_batch_stored uses
+        tdse_status rc = enqueue_adjoint(plan, base, nullptr, kAdjForwardOnly, st);
+        if (rc == TDSE_OK) ++plan->ckpt_gen;
+        return rc;
+    }
     if (plan->options & TDSE_OPT_PLAIN) {
         // one system per launch, serially on the caller's stream
         int32_t* ctr = plan->d_counters + plan->ctr_plain;
@@ -1513,32 +1585,41 @@ tdse_status tdse_adjoint_batch(tdse_plan plan, const double* E, const double* ps
     const void* ptrs[] = {E, psi0, accel_bar, grad_E, accel, sys_status};
     for (const void* q : ptrs)
         if (q && !aligned16(q)) return fail(TDSE_E_INVALID, "device pointers must be 16-byte aligned");
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     FwdArgs base;
     fill_fwd_args(plan, base, E, psi0, accel, nullptr, nullptr, nullptr, sys_status);
-    base.abar = accel_bar;
     base.grad = grad_E;
-    base.k_ckpt = plan->adjoint_k;
-    const int nl = (int)plan->launches.size();
-    if (launch_reset_counters(plan->d_counters, 3 * nl, st) != hipSuccess)
-        return fail(TDSE_E_DEVICE, "counter reset launch failed");
-    for (int l = 0; l < nl; ++l) {
-        const Launch& L = plan->launches[l];
-        if (launch_compact_rows(accel_bar, plan->p.nt, L.d_order, L.count, L.d_order_adj,
-                                plan->d_counters + nl + 2 * l, st) != hipSuccess)
-            return fail(TDSE_E_DEVICE, "row compaction launch failed");
-        FwdArgs a = base;
-        a.order = L.d_order_adj;
-        a.count = L.count;
-        a.cls = L.cls;
-        a.queue = plan->d_counters + l;
-        a.sub_bytes = (int64_t)sub_smem_bytes(L.T / kWave);
-        a.work = plan->d_adj + L.work_off;
-        a.slot_doubles = L.slot_doubles;
-        if (launch_adjoint(L.C, L.alds, a, L.T, L.aS, L.agrid, st) != hipSuccess)
-            return fail(TDSE_E_DEVICE, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
-    }
+    tdse_status rc = enqueue_adjoint(plan, base, accel_bar, kAdjFull, reinterpret_cast<hipStream_t>(stream));
+    if (rc == TDSE_OK && plan->d_store) ++plan->ckpt_gen;  // the store now holds this E's pass
+    return rc;
+}
+
+tdse_status tdse_plan_checkpoint_generation(tdse_plan plan, uint64_t* generation)
+{
+    g_last_error.clear();
+    if (!plan || !generation) return fail(TDSE_E_INVALID, "NULL argument");
+    *generation = plan->ckpt_gen;
     return TDSE_OK;
+}
+
+tdse_status tdse_adjoint_batch_stored(tdse_plan plan, uint64_t generation, const double* E,
+                                      const double* accel_bar, double* grad_E, int32_t* sys_status,
+                                      void* stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
+    if (!plan->d_store)
+        return fail(TDSE_E_INVALID, "plan was created without TDSE_OPT_STORE_CHECKPOINTS");
+    if (generation == 0 || generation != plan->ckpt_gen)
+        return fail(TDSE_E_INVALID, "stored checkpoints are of generation %llu, not %llu",
+                    (unsigned long long)plan->ckpt_gen, (unsigned long long)generation);
+    if (!E || !accel_bar || !grad_E) return fail(TDSE_E_INVALID, "E, accel_bar and grad_E are required");
+    const void* ptrs[] = {E, accel_bar, grad_E, sys_status};
+    for (const void* q : ptrs)
+        if (q && !aligned16(q)) return fail(TDSE_E_INVALID, "device pointers must be 16-byte aligned");
+    FwdArgs base;
+    fill_fwd_args(plan, base, E, nullptr, nullptr, nullptr, nullptr, nullptr, sys_status);
+    base.grad = grad_E;
+    return enqueue_adjoint(plan, base, accel_bar, kAdjReverseOnly, reinterpret_cast<hipStream_t>(stream));
 }
 
 static void band_of(int32_t nt, double dt, double omega0, double h_lo, double h_hi, int32_t* k_lo,

@@ -61,22 +61,42 @@ __device__ __forceinline__ void load_state(const double* base, int T, unsigned o
     gr = ld_lane(b + (size_t)(C + 1) * T, off);
 }
 
-__device__ __forceinline__ void flush_norm(int a0, int a1, int t, int T, const double* ring,
-                                           int W, double dx, const double* erow, double* acc_row,
-                                           double* n_row, int* flag)
+// Outputs of the forward pass for samples [a0, a1]: the acceleration, <x> and
+// norm rows the caller asked for, and the norm row the reverse sweep uses.
+// Flags as in the forward kernel: bit 0 non-finite output, bit 1 the norm
+// grew by more than 1e-8 relative to sample 0 (n0 < 0: not known yet).
+__device__ __forceinline__ void flush_fwd(int a0, int a1, int t, int T, const double* ring, int W,
+                                          double dx, const double* erow, double* acc_row,
+                                          double* x_row, double* nu_row, double* n_row, double n0,
+                                          int* flag)
 {
     for (int smp = a0 + t; smp <= a1; smp += T) {
         const double* r = ring + (smp % kRing) * W * 3;
-        double sv = 0.0, sn = 0.0;
+        double sv = 0.0, sx = 0.0, sn = 0.0;
         for (int w = 0; w < W; ++w) {
             sv += r[w * 3 + 0];
+            sx += r[w * 3 + 1];
             sn += r[w * 3 + 2];
         }
+        const double nn = dx * sn;
         const double acc = dx * fma(erow[smp], sn, sv);
         if (acc_row) acc_row[smp] = acc;
-        n_row[smp] = dx * sn;
-        if (!isfinite(acc) || !isfinite(sn)) atomicOr(flag, 1);
+        if (x_row) x_row[smp] = dx * sx;
+        if (nu_row) nu_row[smp] = nn;
+        n_row[smp] = nn;
+        int f = 0;
+        if (!isfinite(acc) || !isfinite(nn) || !isfinite(sx)) f |= 1;
+        if (n0 >= 0.0 && nn > n0 * (1.0 + 1e-8)) f |= 2;
+        if (f) atomicOr(flag, f);
     }
+}
+
+// dx sum |psi|^2 of sample 0 from its ring slot (intact until sample kRing).
+__device__ __forceinline__ double ring_norm0(const double* ring, int W, double dx)
+{
+    double sn = 0.0;
+    for (int w = 0; w < W; ++w) sn += ring[w * 3 + 2];
+    return dx * sn;
 }
 
 // grad_i = abar_i n_i + dt * sum_w partial_w(i) for i in [a0, a1]
@@ -147,9 +167,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
     const int nt = a.nt, K = a.k_ckpt;
     const int nseg = nt / K + 1;
     const size_t np2 = 2 * (size_t)(C + 2) * T;  // doubles per state record
-    double* ckpt = a.work + ((size_t)blockIdx.x * S + sub) * (size_t)a.slot_doubles;
-    double* seg = ckpt + np2 * nseg;
-    double* n_row = seg + np2 * (K + 1);
+    double* const slot = a.work + ((size_t)blockIdx.x * S + sub) * (size_t)a.slot_doubles;
     double* ring = sm.ring;
     int* flag = sm.misc + 1;
 
@@ -171,13 +189,19 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
         const SysDesc d = uniform_load(a.sys + p);
         const size_t row = (size_t)p * (size_t)(nt + 1);
         const double* erow = a.E + row;
-        const double* abar = a.abar + row;
-        double* g_row = a.grad + row;
+        const double* abar = a.abar ? a.abar + row : nullptr;
+        double* g_row = a.grad ? a.grad + row : nullptr;
         double* acc_row = (active && a.accel) ? a.accel + row : nullptr;
+        double* x_row = (active && a.xexp) ? a.xexp + row : nullptr;
+        double* nu_row = (active && a.norm) ? a.norm + row : nullptr;
         const double* src = a.psi0 ? a.psi0 + 2 * d.psi_off : a.gs + 2 * a.gs_off[a.cls];
+        // checkpoints and norm row: the system's own (stored) or the slot's
+        double* ckpt = a.store ? a.store + uniform_load(a.store_off + p) : slot;
+        double* n_row = ckpt + np2 * nseg;
+        double* seg = a.store ? slot : n_row + ((nt + 2) & ~1);
 
         // rows with an all-zero abar have a zero gradient and need no reverse sweep
-        if (active)
+        if (active && a.mode != kAdjForwardOnly)
             for (int i = t; i <= nt; i += T)
                 if (abar[i] != 0.0) {
                     sm.misc[2] = 1;
@@ -199,7 +223,10 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
             f = load_factors<C>(sv.sc, sv.lc);
         }
         int flushed = 0;
-        const int nfwd = (wg_need || a.accel) ? nt : -1;  // uniform
+        // forward pass length (uniform): none when the checkpoints are stored
+        const int nfwd = a.mode == kAdjReverseOnly ? -1
+                         : (a.mode == kAdjForwardOnly || wg_need || a.accel) ? nt : -1;
+        double n0 = -1.0;
         for (int i = 0; i <= nfwd; ++i) {
             const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
             if (i % K == 0) store_state<C>(ckpt + np2 * (i / K), T, loff, v, gl, gr);
@@ -209,12 +236,30 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
                             sm.lds_f, sm.lds_b);
             if ((i + 1) % kFlush == 0) {
                 __syncthreads();
-                if (active) flush_norm(i + 1 - kFlush, i, t, T, ring, W, dx, erow, acc_row, n_row, flag);
+                if (flushed == 0) n0 = ring_norm0(ring, W, dx);
+                if (active)
+                    flush_fwd(i + 1 - kFlush, i, t, T, ring, W, dx, erow, acc_row, x_row, nu_row,
+                              n_row, n0, flag);
                 flushed = i + 1;
             }
         }
         __syncthreads();
-        if (active && nfwd >= 0) flush_norm(flushed, nt, t, T, ring, W, dx, erow, acc_row, n_row, flag);
+        if (nfwd >= 0) {
+            if (flushed == 0) n0 = ring_norm0(ring, W, dx);
+            if (active)
+                flush_fwd(flushed, nt, t, T, ring, W, dx, erow, acc_row, x_row, nu_row, n_row, n0,
+                          flag);
+            if (active && a.psi_final) {
+                double* dst = a.psi_final + 2 * d.psi_off;
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    if (s + k < n) {
+                        dst[2 * (s + k)] = v[k].re;
+                        dst[2 * (s + k) + 1] = v[k].im;
+                    }
+                }
+            }
+        }
         __syncthreads();
 
         // ---------------- reverse sweep (every subgroup runs it, so barriers
@@ -272,7 +317,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
                 }
             }
         }
-        if (active && !need_grad)
+        if (active && !need_grad && a.mode != kAdjForwardOnly)
             for (int i = t; i <= nt; i += T) g_row[i] = 0.0;
         __syncthreads();
         if (active && t == 0 && a.status) a.status[p] = sm.misc[1];

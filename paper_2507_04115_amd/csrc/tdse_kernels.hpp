@@ -41,10 +41,22 @@ struct FwdArgs {
     // adjoint only
     const double* abar;     // [batch][nt+1]
     double* grad;           // [batch][nt+1]
-    double* work;           // per subgroup slot: checkpoints, segment states, norms
+    double* work;           // per subgroup slot: [checkpoints, norm row,] segment states
     int64_t slot_doubles;   // doubles per slot
     int32_t k_ckpt;
+    int32_t mode;           // kAdjFull, kAdjForwardOnly or kAdjReverseOnly
+    // per-system checkpoints and norm rows (stored mode), or NULL: then they
+    // live in the slot
+    double* store;
+    const int64_t* store_off;  // [batch] doubles into store
 };
+
+// Adjoint kernel modes: forward pass then reverse sweep; forward pass only
+// (outputs and stored checkpoints); reverse sweep only, from the stored
+// checkpoints of an earlier forward pass.
+constexpr int32_t kAdjFull = 0;
+constexpr int32_t kAdjForwardOnly = 1;
+constexpr int32_t kAdjReverseOnly = 2;
 
 struct GsArgs {
     const SizeClass* classes;

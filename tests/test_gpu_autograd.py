@@ -97,6 +97,30 @@ def test_torch_side_loss_chains_through_adjoint(setup, lib):
         assert r < 1e-9
 
 
+def test_stored_checkpoints_through_autograd(setup, lib):
+    """Two forwards, then the two backwards in reverse order through a plan
+    that stores checkpoints: the second forward's backward reads the store,
+    the first one's finds it rewritten and recomputes; both equal the
+    gradients of the plan that always recomputes."""
+    s = setup
+    torch, AG = s["torch"], s["AG"]
+    p = lib.make_params(s["dx"], s["dt"], s["a"], s["nt"], mask_fraction=0.2)
+    sb = AG.TDSEBatch(p, s["ns"], adjoint_k=64, store_checkpoints=True)
+    grads = {}
+    for name, batch in (("stored", sb), ("recompute", s["batch"])):
+        E1 = torch.tensor(s["efield"], dtype=torch.float64, device=s["dev"], requires_grad=True)
+        E2 = torch.tensor(1.1 * s["efield"], dtype=torch.float64, device=s["dev"],
+                          requires_grad=True)
+        y1 = AG.HarmonicYield.apply(batch(E1), s["dt"], s["om"], 3, 9).sum()
+        y2 = AG.HarmonicYield.apply(batch(E2), s["dt"], s["om"], 3, 9).sum()
+        y2.backward()
+        y1.backward()
+        grads[name] = (E1.grad.cpu().numpy(), E2.grad.cpu().numpy())
+    for a_, b_ in zip(grads["stored"], grads["recompute"]):
+        assert np.array_equal(a_, b_)
+    sb.close()
+
+
 def test_backward_without_adjoint_plan_raises(lib):
     import torch
 

@@ -234,6 +234,67 @@ def test_adjoint_matches_oracle_and_fd(lib, torch_dev):
         plan.close()
 
 
+def test_stored_checkpoints_match_recomputing_adjoint(lib, torch_dev):
+    """A plan that stores the adjoint checkpoints in its forward pass gives
+    the same forward outputs as a plain plan of the same layouts, its reverse
+    sweep from the stored checkpoints gives the recomputing adjoint's
+    gradient bitwise (and the oracle's), and a stale generation is refused."""
+    torch, dev = torch_dev
+    ns = [256, 400, 256]
+    dx, dt, a = 0.4, 0.05, 1.1
+    om, nc = 0.25, 3
+    nt = ti.n_steps(om, nc, dt)
+    efield = ti.sin2_pulse(np.array([0.1, 0.12, 0.08]), om, nc, dt, nt=nt)
+    p = lib.make_params(dx, dt, a, nt, mask_fraction=0.2)
+    E = _to_dev(torch, dev, efield)
+    print(f"stored checkpoints ns={ns} nt={nt} K=37", flush=True)
+    ref = lib.Plan(p, ns, adjoint_k=37)
+    stp = lib.Plan(p, ns, adjoint_k=37, options=lib.TDSE_OPT_STORE_CHECKPOINTS)
+    assert stp.checkpoint_generation() == 0
+    outs = []
+    for pl in (ref, stp):
+        acc, xe, nr = (torch.empty_like(E) for _ in range(3))
+        pf = torch.empty(2 * sum(ns), dtype=torch.float64, device=dev)
+        status = torch.full((len(ns),), -1, dtype=torch.int32, device=dev)
+        lib.tdse_propagate_batch(pl, E, None, acc, xe, nr, pf, status)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy() for t in (acc, xe, nr, pf, status)])
+    gen = stp.checkpoint_generation()
+    assert gen == 1
+    for x, y in zip(outs[0], outs[1]):
+        assert np.array_equal(x, y)
+    assert np.all(outs[1][4] == 0)
+    _, abar = oracle.harmonic_yield(outs[0][0], dt, om, 3, 9)
+    abar[1] = 0.0                          # an all-zero row is skipped here too
+    AB = _to_dev(torch, dev, abar)
+    g_full = torch.full_like(E, 7.0)
+    lib.tdse_adjoint_batch(ref, E, None, AB, g_full)
+    g_st = torch.full_like(E, 7.0)
+    st = torch.full((len(ns),), -1, dtype=torch.int32, device=dev)
+    lib.tdse_adjoint_batch_stored(stp, gen, E, AB, g_st, st)
+    torch.cuda.synchronize()
+    assert np.array_equal(g_st.cpu().numpy(), g_full.cpu().numpy())
+    assert np.all(st.cpu().numpy() == 0)
+    assert np.all(g_st.cpu().numpy()[1] == 0.0)
+    psi0 = torch.empty(2 * ns[2], dtype=torch.float64, device=dev)
+    stp.ground_state(ns[2], psi0)
+    g_ref, _ = oracle.adjoint(efield[2], psi0.cpu().numpy().view(np.complex128), abar[2], dx, dt, a,
+                              mask_frac=0.2, k=37)
+    assert rel(g_st.cpu().numpy()[2], g_ref) < 1e-9
+    # a later forward pass rewrites the store: the old generation is refused
+    lib.tdse_propagate_batch(stp, E, None, torch.empty_like(E))
+    with pytest.raises(lib.TDSEError):
+        lib.tdse_adjoint_batch_stored(stp, gen, E, AB, g_st)
+    # the recomputing adjoint works on the storing plan and rewrites the store
+    g2 = torch.full_like(E, 7.0)
+    lib.tdse_adjoint_batch(stp, E, None, AB, g2)
+    torch.cuda.synchronize()
+    assert np.array_equal(g2.cpu().numpy(), g_full.cpu().numpy())
+    assert stp.checkpoint_generation() == gen + 2
+    ref.close()
+    stp.close()
+
+
 def test_forward_uneven_wide_batch_sampled(lib, torch_dev):
     """Uneven batch spanning N = 2048..16384 (many size classes, tables in LDS
     and in global memory, 8 and 16 points per lane), first 400 steps of the
