@@ -93,6 +93,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,7 +291,11 @@ def main():
         import oracle
 
         nth = args.cpu_threads or min(16, os.cpu_count() or 1)
-        rows = np.linspace(0, w.batch - 1, nth).round().astype(int)
+        # a stratified sample: rows spread over the batch (two per thread),
+        # plus the smallest and the largest grid
+        by_n = np.argsort(np.asarray(w.n_per), kind="stable")
+        rows = np.array(sorted(set(np.linspace(0, w.batch - 1, 2 * nth).round().astype(int).tolist())
+                               | {int(by_n[0]), int(by_n[-1])}))
         gs = {}
         psi_list = []
         for r in rows:
@@ -297,17 +311,26 @@ def main():
                                      mask_pow=w.mask_pow, nthreads=nth)
         t_cpu = time.perf_counter() - t0
         ps_cpu = float(sum(w.n_per[r] for r in rows)) * w.nt
+        # one core: the first sampled system alone
+        t1 = time.perf_counter()
+        oracle.propagate_batch(e_rows[:1], psi_list[:1], w.dx, w.dt, a_sc, mask_frac=w.mask_frac,
+                               mask_pow=w.mask_pow, nthreads=1)
+        t1 = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": ps_cpu / t_cpu, "unit": "grid-point-steps/s", "cores": nth,
                                "kind": "oracle",
-                               "sample": f"{len(rows)} systems of the same batch (rows {rows[0]}..{rows[-1]}), "
-                                         f"full {w.nt} steps, one thread per system, {t_cpu:.1f} s"}
+                               "sample": f"{len(rows)} systems of the same batch (rows spread over it, "
+                                         f"smallest and largest grid included), full {w.nt} steps, "
+                                         f"one system per thread at a time on {nth} threads, {t_cpu:.1f} s",
+                               "single_core_value": float(w.n_per[rows[0]]) * w.nt / t1,
+                               "cpu_model": cpu_model()}
         got = acc[torch.as_tensor(rows, device=dev)].cpu().numpy()
         errs = [float(np.linalg.norm(got[i] - ref["accel"][i]) / np.linalg.norm(ref["accel"][i]))
                 for i in range(len(rows))]
         out["parity"] = {"accel_rel_l2_max": max(errs), "systems_checked": len(rows),
                          "tolerance": 1e-9}
-        log(f"cpu oracle: {ps_cpu / t_cpu:.3e} grid-point-steps/s on {nth} threads; "
-            f"parity max rel-L2 {max(errs):.2e}")
+        log(f"cpu oracle: {ps_cpu / t_cpu:.3e} grid-point-steps/s on {nth} threads "
+            f"({out['cpu_baseline']['single_core_value']:.3e} on one core, {cpu_model()}); "
+            f"parity max rel-L2 {max(errs):.2e} over {len(rows)} systems")
 
     plan.close()
     print(json.dumps(out), flush=True)

@@ -121,6 +121,51 @@ def test_stored_checkpoints_through_autograd(setup, lib):
     sb.close()
 
 
+def test_spectral_phase_gradient_of_on_axis_yield(lib):
+    """The full-volume workload's optimisation problem, small: the harmonic
+    yield summed over the on-axis points of a 2 r x 3 z focus, as a function
+    of 64 spectral-phase coefficients of the driver.  dl/dc comes from
+    autograd through the FFT map, TDSEFunction's adjoint (off-axis rows have
+    an all-zero accel_bar and are skipped) and HarmonicYield; it must match
+    central differences of the GPU forward map (bar: 1e-5 relative)."""
+    import torch
+
+    from paper_2507_04115_amd import autograd as AG
+    from paper_2507_04115_amd.driver import SpectralPhase
+
+    dev = torch.device("cuda:0")
+    om, nc, dt, dx, a = 0.25, 3, 0.05, 0.4, 1.1
+    nt = ti.n_steps(om, nc, dt)
+    nr, nz = 2, 3
+    e0, ph, r, _ = ti.gaussian_focus(nr, nz, 50.0, 800.0, 2e14)
+    E0 = torch.tensor(ti.sin2_pulse(e0, om, nc, dt, phase=ph, nt=nt), dtype=torch.float64,
+                      device=dev)
+    p = lib.make_params(dx, dt, a, nt, mask_fraction=0.2)
+    batch = AG.TDSEBatch(p, [256] * (nr * nz), adjoint_k=64, store_checkpoints=True)
+    sp = SpectralPhase(E0, 64)
+    on_axis = torch.tensor((r == 0.0).astype(np.float64), device=dev)
+    print(f"spectral phase: {nr}x{nz} focus, nt={nt}, band bins {sp.band}", flush=True)
+
+    def loss(c):
+        return (AG.HarmonicYield.apply(batch(sp(c)), dt, om, 3, 9) * on_axis).sum()
+
+    c = torch.tensor(np.random.default_rng(5).normal(0.0, 0.3, 64), dtype=torch.float64,
+                     device=dev, requires_grad=True)
+    loss(c).backward()
+    g = c.grad.detach()
+    assert torch.count_nonzero(g) > 0
+    h = 1e-6
+    for d in range(2):
+        v = torch.tensor(np.random.default_rng(20 + d).standard_normal(64), dtype=torch.float64,
+                         device=dev)
+        with torch.no_grad():
+            fd = float((loss(c + h * v) - loss(c - h * v)) / (2 * h))
+        ad = float((g * v).sum())
+        print(f"  direction {d}: FD {fd:.10e} adjoint {ad:.10e}", flush=True)
+        assert abs(fd - ad) <= 1e-5 * abs(fd)
+    batch.close()
+
+
 def test_backward_without_adjoint_plan_raises(lib):
     import torch
 
