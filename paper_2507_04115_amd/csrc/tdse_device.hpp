@@ -551,21 +551,24 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
         if (lc.lane > kWave - 1 - (1 << sc.levels)) bw = ld_lane(sc.lt.qw, off);
     };
     if constexpr (QInRegs<C>::value) load_bwd_windows();
-    // B. forward recurrence from the exact carry, w = q z
+    // B. forward recurrence from the exact carry, w = q z.  When q is read
+    // from memory, each sweep hides the chunk base from the optimiser so
+    // that it reloads q and om rather than keeping earlier sweeps' values
+    // live (they would be spilled).
     {
+        LaneCtx lcb = lc;
+        if constexpr (!QInRegs<C>::value) lcb.b0 = opaque(lc.b0);
         cd z = cf;
         double om_p = oml;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            z = cmad(elim<RT>(om_p, k == 0 ? f.ql(sc, lc) : f.q(k - 1, sc, lc)), z, v[k]);
-            v[k] = cmul(f.q(k, sc, lc), z);
-            if (k + 1 < C) om_p = tb.om(b0 + 64 * k);
+            z = cmad(elim<RT>(om_p, k == 0 ? f.ql(sc, lc) : f.q(k - 1, sc, lcb)), z, v[k]);
+            v[k] = cmul(f.q(k, sc, lcb), z);
+            if (k + 1 < C) om_p = tb.om(lcb.b0 + 64 * k);
             point_fence(v[k]);
         }
     }
-    // C. chunk-start value of y with zero carry-in.  When q is read from
-    // memory, the chunk base is hidden from the optimiser so that sweep C
-    // reloads q and om instead of keeping sweep B's values live in registers.
+    // C. chunk-start value of y with zero carry-in
     cd yb = v[C - 1];
     {
         LaneCtx lcc = lc;
@@ -583,13 +586,15 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
     // D. backward recurrence from the exact carry
     double om_0;
     {
+        LaneCtx lcd = lc;
+        if constexpr (!QInRegs<C>::value) lcd.b0 = opaque(lc.b0);
         cd y = cb;
         double om_n = omr;
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
-            y = cmad(elim<RT>(om_n, f.q(k, sc, lc)), y, v[k]);
+            y = cmad(elim<RT>(om_n, f.q(k, sc, lcd)), y, v[k]);
             v[k] = y;
-            om_n = tb.om(b0 + 64 * k);
+            om_n = tb.om(lcd.b0 + 64 * k);
             point_fence(y);
         }
         om_0 = om_n;
@@ -615,7 +620,17 @@ __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e,
     gl = cmul(ph, gl);
     if (mflags & 2) gl = cscale(ldg(sc.pt.m + lc.il()), gl);
     ph = cmul(ph, w1);
-    if (mflags & 1) {
+    if (!QInRegs<C>::value) {
+        // long chunks: the absorber factor is applied to every point (1 away
+        // from the edges); a branch here would make the two paths' results
+        // meet in different registers, which costs spills of the chunk
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            v[k] = cscale(ldg(sc.pt.m + lc.b0 + 64 * k), cmul(ph, v[k]));
+            ph = cmul(ph, w1);
+            point_fence(v[k], ph);
+        }
+    } else if (mflags & 1) {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             v[k] = cscale(ldg(sc.pt.m + lc.b0 + 64 * k), cmul(ph, v[k]));
