@@ -146,14 +146,16 @@ tdse_status tdse_plan_layout(tdse_plan plan, int32_t n, int32_t* points_per_lane
                              int32_t* lanes, int32_t* scan_levels);
 
 /* Launch parameters chosen for size n (host outputs, any may be NULL):
- * systems per workgroup, 1 if the point tables are staged in LDS (0: read
- * from global memory), and the probe rate in grid-point-steps/s measured by
- * the autotuner (0 when the plan was not created with TDSE_OPT_AUTOTUNE).
- * The autotuner times, for each distinct n, every lane layout that fits
- * (points per lane C in {4, 8, 16}, i.e. the length of the lane-local Thomas
- * chunks against the width of the cross-lane scan; systems per workgroup;
- * tables in LDS or global memory) on a probe batch that fills the GPU once,
- * and keeps the fastest.  Results are cached per process. */
+ * systems per workgroup, the placement of the per-point tables (om and
+ * dV/dx) of the forward kernel -- 0 both read from global memory, 1 both
+ * staged in LDS, 2 om staged in LDS and dV/dx read from global memory -- and
+ * the probe rate in grid-point-steps/s measured by the autotuner (0 when
+ * the plan was not created with TDSE_OPT_AUTOTUNE).  The autotuner times,
+ * for each distinct n, every lane layout that fits (points per lane C in
+ * {4, 8, 16}, i.e. the length of the lane-local Thomas chunks against the
+ * width of the cross-lane scan; systems per workgroup; table placement) on
+ * a probe batch that fills the GPU once, and keeps the fastest.  Results are
+ * cached per process. */
 tdse_status tdse_plan_launch_info(tdse_plan plan, int32_t n, int32_t* systems_per_workgroup,
                                   int32_t* lds_tables, double* tuned_rate);
 

@@ -168,7 +168,7 @@ class Layout:
 @dataclass
 class LaunchInfo:
     systems_per_workgroup: int
-    lds_tables: bool
+    lds_tables: int        # 0 global, 1 om and dV/dx in LDS, 2 om in LDS
     tuned_rate: float
 
 
@@ -214,7 +214,7 @@ class Plan:
         s_, l_, r_ = _i32(), _i32(), _d()
         _check(load().tdse_plan_launch_info(self.handle, n, ctypes.byref(s_), ctypes.byref(l_),
                                             ctypes.byref(r_)), "tdse_plan_launch_info")
-        return LaunchInfo(s_.value, bool(l_.value), r_.value)
+        return LaunchInfo(s_.value, int(l_.value), r_.value)
 
     @property
     def stores_checkpoints(self) -> bool:

@@ -350,7 +350,7 @@ tdse_status check_params(const tdse_params* p, bool need_time)
 struct Launch {
     int cls;
     int C, T, S;          // points per lane, lanes per system, systems per workgroup
-    bool lds;             // point tables staged in LDS
+    int tab;              // table placement of the forward launch (kTab*)
     int count, grid;
     double tuned_rate = 0.0;  // autotuner probe rate (0: default layout)
     int32_t* d_order;     // the class's systems
@@ -399,7 +399,7 @@ struct tdse_plan_s {
     // forward: one persistent launch per lane layout over workgroup bins
     struct FwdGroup {
         int C = 0;
-        bool lds = true;
+        int tab = kTabLds;
         int threads = 0;  // workgroup size = bin capacity in lanes
         size_t smem = 0;  // LDS bytes per workgroup
         int nbins = 0, grid = 0;
@@ -438,34 +438,40 @@ void plan_free(tdse_plan pl)
 }
 
 // LDS bytes of a forward workgroup holding S systems of one class.
-size_t fwd_smem(int C, int T, int S, bool lds)
+size_t fwd_smem(int C, int T, int S, int tab)
 {
-    return (lds ? (size_t)kLdsTableBytes * C * T : 0) + S * sub_smem_bytes(T / kWave) + 16;
+    return (size_t)tab_lds_bytes(tab) * C * T + S * sub_smem_bytes(T / kWave) + 16;
 }
-int fwd_occupancy(int C, int T, int S, bool lds)
+int fwd_occupancy(int C, int T, int S, int tab)
 {
-    return forward_occupancy(C, S * T, fwd_smem(C, T, S, lds), lds);
+    if (!forward_tab_supported(C, tab)) return 0;
+    return forward_occupancy(C, S * T, fwd_smem(C, T, S, tab), tab);
 }
+
+// Table placements in order of preference: both tables in LDS, om alone in
+// LDS (forward kernel only), both in global memory.
+constexpr int kTabOrder[3] = {kTabLds, kTabOmLds, kTabGlobal};
 
 // Systems per workgroup and table placement for a class: as many systems as
 // fit in 1024 lanes whose registers and LDS fit one workgroup per CU, point
 // tables in LDS whenever they fit.  Returns false if nothing fits.
-bool choose_packing(int C, int T, int count, bool adjoint, int* S_out, bool* lds_out, int* occ_out)
+bool choose_packing(int C, int T, int count, bool adjoint, int* S_out, int* tab_out, int* occ_out)
 {
     int smax = std::max(1, std::min(1024 / T, count));
     const int fs = env_int("TDSE_PACK_S", 0);          // experiment overrides
     const int fl = env_int("TDSE_PACK_LDS", -1);
     if (fs > 0) smax = std::min(smax, fs);
-    for (int pass = 0; pass < 2; ++pass) {
-        const bool lds = pass == 0;
-        if ((fl == 0 && lds) || (fl == 1 && !lds)) continue;
+    for (int tab : kTabOrder) {
+        if (fl >= 0 && tab != fl) continue;
+        if (adjoint ? tab == kTabOmLds : !forward_tab_supported(C, tab)) continue;
+        const bool lds = tab == kTabLds;
         for (int S = smax; S >= 1; --S) {
-            const size_t sh = adjoint ? adjoint_smem_bytes(C, T, S, lds) : fwd_smem(C, T, S, lds);
+            const size_t sh = adjoint ? adjoint_smem_bytes(C, T, S, lds) : fwd_smem(C, T, S, tab);
             if (sh > (size_t)kMaxLds) continue;
-            const int occ = adjoint ? adjoint_occupancy(C, T, S, lds) : fwd_occupancy(C, T, S, lds);
+            const int occ = adjoint ? adjoint_occupancy(C, T, S, lds) : fwd_occupancy(C, T, S, tab);
             if (occ >= 1) {
                 *S_out = S;
-                *lds_out = lds;
+                *tab_out = tab;
                 *occ_out = occ;
                 return true;
             }
@@ -516,7 +522,7 @@ size_t bin_total(const HostBin& b, int cap, int* nsub)
     return bytes;
 }
 
-bool bin_try_add(HostBin& b, const PackItem& it, int cap, int C, bool lds)
+bool bin_try_add(HostBin& b, const PackItem& it, int cap, int C, int tab)
 {
     if (b.lanes + it.T > cap) return false;
     HostBin t = b;
@@ -525,7 +531,7 @@ bool bin_try_add(HostBin& b, const PackItem& it, int cap, int C, bool lds)
     t.tmax = std::max(t.tmax, it.T);
     if (std::find(t.classes.begin(), t.classes.end(), it.cls) == t.classes.end()) {
         t.classes.push_back(it.cls);
-        if (lds) t.tab_bytes += (size_t)kLdsTableBytes * C * it.T;
+        t.tab_bytes += (size_t)tab_lds_bytes(tab) * C * it.T;
     }
     t.sub_bytes += sub_smem_bytes(it.T / kWave);
     int nsub = 0;
@@ -535,7 +541,7 @@ bool bin_try_add(HostBin& b, const PackItem& it, int cap, int C, bool lds)
 }
 
 // Packs items into bins of `cap` lanes; fails if an item alone does not fit.
-bool pack_bins(std::vector<PackItem> items, int cap, int C, bool lds, std::vector<HostBin>& bins)
+bool pack_bins(std::vector<PackItem> items, int cap, int C, int tab, std::vector<HostBin>& bins)
 {
     std::stable_sort(items.begin(), items.end(),
                      [](const PackItem& x, const PackItem& y) { return x.T > y.T; });
@@ -543,10 +549,10 @@ bool pack_bins(std::vector<PackItem> items, int cap, int C, bool lds, std::vecto
     size_t first_open = 0;  // bins before this one are full
     for (const PackItem& it : items) {
         bool placed = false;
-        for (size_t i = first_open; i < bins.size() && !placed; ++i) placed = bin_try_add(bins[i], it, cap, C, lds);
+        for (size_t i = first_open; i < bins.size() && !placed; ++i) placed = bin_try_add(bins[i], it, cap, C, tab);
         if (!placed) {
             bins.emplace_back();
-            if (!bin_try_add(bins.back(), it, cap, C, lds)) return false;
+            if (!bin_try_add(bins.back(), it, cap, C, tab)) return false;
         }
         while (first_open < bins.size() && bins[first_open].lanes == cap) ++first_open;
     }
@@ -556,23 +562,24 @@ bool pack_bins(std::vector<PackItem> items, int cap, int C, bool lds, std::vecto
 // Device descriptor of a bin.  pad_cls(lanes) gives the padding class of a
 // padding subgroup.  Returns the LDS bytes the bin uses (queue slot included).
 template <class PadCls>
-size_t make_bin_desc(const HostBin& b, int cap, int C, bool lds, const std::vector<SizeClass>& cls,
+size_t make_bin_desc(const HostBin& b, int cap, int C, int tab, const std::vector<SizeClass>& cls,
                      PadCls pad_cls, BinDesc* d)
 {
     std::memset(d, 0, sizeof(BinDesc));
     size_t off = 0;
-    std::vector<size_t> tab(b.classes.size(), 0);
+    const bool lds = tab != kTabGlobal;
+    std::vector<size_t> toff(b.classes.size(), 0);
     size_t wide_tab = 0;  // tables of the widest class, read by padding subgroups
     int wide_T = 0;
     if (lds)
         for (size_t k = 0; k < b.classes.size(); ++k) {
-            tab[k] = off;
+            toff[k] = off;
             const int T = cls[b.classes[k]].T;
             if (T > wide_T) {
                 wide_T = T;
                 wide_tab = off;
             }
-            off += (size_t)kLdsTableBytes * C * T;
+            off += (size_t)tab_lds_bytes(tab) * C * T;
         }
     int wave = 0, j = 0;
     std::vector<int> staged;
@@ -593,7 +600,7 @@ size_t make_bin_desc(const HostBin& b, int cap, int C, bool lds, const std::vect
         const size_t k = std::find(b.classes.begin(), b.classes.end(), it.cls) - b.classes.begin();
         const bool first = std::find(staged.begin(), staged.end(), it.cls) == staged.end();
         if (first) staged.push_back(it.cls);
-        add(it.p, it.cls, it.T, lds ? tab[k] : 0, lds && first);
+        add(it.p, it.cls, it.T, lds ? toff[k] : 0, lds && first);
     }
     for (int t : pad_chunks(b, cap)) add(-1, pad_cls(t), t, wide_tab, false);
     d->nsub = j;
@@ -608,7 +615,7 @@ size_t make_bin_desc(const HostBin& b, int cap, int C, bool lds, const std::vect
 // GPU once, and keeps the fastest.  Results are cached per process.
 struct TuneChoice {
     int C = 0, T = 0, S = 1;
-    bool lds = true;
+    int tab = kTabLds;
     double rate = 0.0;  // grid-point-steps per second of the probe
 };
 
@@ -628,12 +635,13 @@ constexpr int kProbeSteps = 128;
 // Rate of one candidate (0 when it does not fit).  Probe inputs are zero:
 // the kernel's instruction stream does not depend on the values.  The probe
 // batch fills every workgroup slot once with bins of S systems.
-tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, bool lds, int count,
+tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, int tab, int count,
                           hipStream_t st, double* rate)
 {
     *rate = 0.0;
-    const size_t smem = fwd_smem(L.C, L.T, S, lds);
-    const int occ = forward_occupancy(L.C, S * L.T, smem, lds);
+    if (!forward_tab_supported(L.C, tab)) return TDSE_OK;
+    const size_t smem = fwd_smem(L.C, L.T, S, tab);
+    const int occ = forward_occupancy(L.C, S * L.T, smem, tab);
     if (occ < 1 || smem > (size_t)kMaxLds || count < S) return TDSE_OK;
     const int nb = std::max(1, std::min(count / S, occ * num_cus()));
     const int P = nb * S;
@@ -673,8 +681,8 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, b
         for (int k = 0; k < nb && packed; ++k) {
             HostBin hbin;
             for (int i = 0; i < S && packed; ++i)
-                packed = bin_try_add(hbin, PackItem{k * S + i, 0, L.T}, S * L.T, L.C, lds);
-            used = std::max(used, make_bin_desc(hbin, S * L.T, L.C, lds, cs.h, [](int) { return 0; }, &hb[k]));
+                packed = bin_try_add(hbin, PackItem{k * S + i, 0, L.T}, S * L.T, L.C, tab);
+            used = std::max(used, make_bin_desc(hbin, S * L.T, L.C, tab, cs.h, [](int) { return 0; }, &hb[k]));
         }
         if (!packed) {
             rc = fail(TDSE_E_UNSUPPORTED, "autotune probe: %d systems of n=%d do not fit a workgroup", S, n);
@@ -709,7 +717,7 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, b
             float ms = 0.0f;
             if (launch_reset_counters(ctr, 1, st) != hipSuccess ||
                 hipEventRecord(e0, st) != hipSuccess ||
-                launch_forward(L.C, lds, a, S * L.T, smem, grid, st) != hipSuccess ||
+                launch_forward(L.C, tab, a, S * L.T, smem, grid, st) != hipSuccess ||
                 hipEventRecord(e1, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess ||
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                 rc = fail(TDSE_E_DEVICE, "autotune probe launch failed: %s",
@@ -733,9 +741,9 @@ tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int coun
                           double* rate)
 {
     *rate = 0.0;
-    int S = 1, occ = 0;
-    bool lds = false;
-    if (!choose_packing(L.C, L.T, count, true, &S, &lds, &occ)) return TDSE_OK;
+    int S = 1, occ = 0, tab = kTabGlobal;
+    if (!choose_packing(L.C, L.T, count, true, &S, &tab, &occ)) return TDSE_OK;
+    const bool lds = tab == kTabLds;
     const int P = std::max(1, std::min(count, S * occ * num_cus()));
     const int nt = kProbeSteps, K = 16;
     const int grid = std::min((P + S - 1) / S, occ * num_cus());
@@ -851,20 +859,20 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, hipSt
             adj_cost = 1.0 / ra;
         }
         const int smax = std::max(1, std::min(1024 / L.T, count));
-        for (int pass = 0; pass < 2; ++pass) {
-            const bool lds = pass == 0;
+        for (int tab : kTabOrder) {
+            if (!forward_tab_supported(C, tab)) continue;
             int tried = 0;
             for (int S = smax; S >= 1 && tried < 2; --S) {
-                if (fwd_occupancy(C, L.T, S, lds) < 1) continue;
+                if (fwd_occupancy(C, L.T, S, tab) < 1) continue;
                 double r = 0.0;
-                tdse_status rc = probe_forward(p, n, L, S, lds, count, st, &r);
+                tdse_status rc = probe_forward(p, n, L, S, tab, count, st, &r);
                 if (rc != TDSE_OK) return rc;
                 ++tried;
                 if (r <= 0.0) continue;
                 const double cost = 1.0 / r + adj_cost;
                 if (best_cost == 0.0 || cost < best_cost) {
                     best_cost = cost;
-                    best = TuneChoice{C, L.T, S, lds, r};
+                    best = TuneChoice{C, L.T, S, tab, r};
                 }
             }
         }
@@ -1027,42 +1035,41 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
 
     // forward packing of each class: systems per workgroup, table placement
     std::vector<int> cS(ncls, 1);
-    std::vector<char> clds(ncls, 1);
+    std::vector<int> ctab(ncls, kTabLds);
     for (int c = 0; c < ncls; ++c) {
         if (tune) {
             cS[c] = tuned[c].S;
-            clds[c] = tuned[c].lds;
+            ctab[c] = tuned[c].tab;
         } else {
-            int S = 1, occ = 0;
-            bool l = true;
-            if (!choose_packing(lay[c].C, lay[c].T, ccount[c], false, &S, &l, &occ))
+            int S = 1, occ = 0, tb = kTabLds;
+            if (!choose_packing(lay[c].C, lay[c].T, ccount[c], false, &S, &tb, &occ))
                 return bail(fail(TDSE_E_UNSUPPORTED, "layout C=%d T=%d does not fit", lay[c].C, lay[c].T));
             cS[c] = S;
-            clds[c] = l;
+            ctab[c] = tb;
         }
     }
     // one persistent forward launch per (C, table placement): a single class
     // keeps its own packing, several classes share 1024-lane workgroups
     std::map<std::pair<int, int>, std::vector<int>> gcls;
-    for (int c = 0; c < ncls; ++c) gcls[{lay[c].C, (int)clds[c]}].push_back(c);
+    for (int c = 0; c < ncls; ++c) gcls[{lay[c].C, ctab[c]}].push_back(c);
     struct GroupBins {
         int C;
-        bool lds;
+        int tab;
         int cap;
         std::vector<HostBin> bins;
     };
     std::vector<GroupBins> gbins;
     std::map<std::pair<int, int>, int> pad_cls;  // (C, lanes) -> padding class
     pl->fgroup_of_cls.assign(ncls, -1);
-    auto add_group = [&](const std::vector<int>& classes, int C, bool lds, int cap) -> bool {
+    auto add_group = [&](const std::vector<int>& classes, int C, int tab, int cap) -> bool {
         GroupBins g;
         g.C = C;
-        g.lds = lds;
+        g.tab = tab;
         g.cap = cap;
         std::vector<PackItem> items;
         for (int c : classes)
             for (int32_t b : csys[c]) items.push_back(PackItem{b, c, lay[c].T});
-        if (!pack_bins(items, g.cap, g.C, g.lds, g.bins)) return false;
+        if (!pack_bins(items, g.cap, g.C, g.tab, g.bins)) return false;
         for (int c : classes) pl->fgroup_of_cls[c] = (int)gbins.size();
         for (const HostBin& hb : g.bins)
             for (int t : pad_chunks(hb, g.cap)) pad_cls[{g.C, t}] = 0;
@@ -1071,13 +1078,13 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     };
     for (const auto& kv : gcls) {
         const int C = kv.first.first;
-        const bool lds = kv.first.second != 0;
+        const int tab = kv.first.second;
         // several classes share full workgroups when their staged tables and a
         // padding subgroup fit the LDS; otherwise each class keeps its own
-        bool ok = kv.second.size() > 1 && add_group(kv.second, C, lds, 1024);
+        bool ok = kv.second.size() > 1 && add_group(kv.second, C, tab, 1024);
         if (!ok)
             for (int c : kv.second)
-                if (!add_group({c}, C, lds, cS[c] * lay[c].T))
+                if (!add_group({c}, C, tab, cS[c] * lay[c].T))
                     return bail(fail(TDSE_E_UNSUPPORTED, "systems of n=%d do not fit a workgroup", ns[c]));
     }
     // padding classes (16 points, the needed lane counts) after the real ones
@@ -1101,18 +1108,18 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     for (const GroupBins& g : gbins) {
         tdse_plan_s::FwdGroup fg;
         fg.C = g.C;
-        fg.lds = g.lds;
+        fg.tab = g.tab;
         fg.threads = g.cap;
         fg.nbins = (int)g.bins.size();
         goff.push_back(hbins.size());
         for (const HostBin& hb : g.bins) {
             hbins.emplace_back();
-            const size_t used = make_bin_desc(hb, g.cap, g.C, g.lds, pl->cls.h,
+            const size_t used = make_bin_desc(hb, g.cap, g.C, g.tab, pl->cls.h,
                                               [&](int t) { return pad_cls[{g.C, t}]; },
                                               &hbins.back());
             fg.smem = std::max(fg.smem, used);
         }
-        const int occ = forward_occupancy(fg.C, fg.threads, fg.smem, fg.lds);
+        const int occ = forward_occupancy(fg.C, fg.threads, fg.smem, fg.tab);
         if (occ < 1)
             return bail(fail(TDSE_E_UNSUPPORTED, "forward workgroup of %d lanes with %zu B of LDS does not fit",
                              fg.threads, fg.smem));
@@ -1125,10 +1132,10 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     for (int b = 0; b < batch; ++b) {
         const int c = pl->cls_of[b];
         HostBin hb;
-        if (!bin_try_add(hb, PackItem{b, c, lay[c].T}, lay[c].T, lay[c].C, clds[c]))
+        if (!bin_try_add(hb, PackItem{b, c, lay[c].T}, lay[c].T, lay[c].C, ctab[c]))
             return bail(fail(TDSE_E_UNSUPPORTED, "system %d does not fit a workgroup", b));
         hbins.emplace_back();
-        pl->plain_smem[b] = make_bin_desc(hb, lay[c].T, lay[c].C, clds[c], pl->cls.h,
+        pl->plain_smem[b] = make_bin_desc(hb, lay[c].T, lay[c].C, ctab[c], pl->cls.h,
                                           [](int) { return 0; }, &hbins.back());
         pl->plain_threads[b] = lay[c].T;
     }
@@ -1176,13 +1183,15 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         order_all.insert(order_all.end(), csys[c].begin(), csys[c].end());
         const tdse_plan_s::FwdGroup& fg = pl->fgroups[pl->fgroup_of_cls[c]];
         L.S = std::max(1, fg.threads / L.T);
-        L.lds = fg.lds;
+        L.tab = fg.tab;
         L.grid = fg.grid;
         if (tune) L.tuned_rate = tuned[c].rate;
         if (adjoint_k > 0) {
             int aocc = 0;
-            if (!choose_packing(L.C, L.T, L.count, true, &L.aS, &L.alds, &aocc))
+            int atab = kTabGlobal;
+            if (!choose_packing(L.C, L.T, L.count, true, &L.aS, &atab, &aocc))
                 return bail(fail(TDSE_E_UNSUPPORTED, "adjoint layout C=%d T=%d does not fit", L.C, L.T));
+            L.alds = atab == kTabLds;
             L.agrid = std::min((L.count + L.aS - 1) / L.aS, aocc * num_cus());
             const int64_t rec = 2 * (int64_t)(L.C + 2) * L.T;   // one state record
             const int64_t nseg = nt / adjoint_k + 1;
@@ -1280,7 +1289,7 @@ tdse_status tdse_plan_launch_info(tdse_plan plan, int32_t n, int32_t* systems_pe
     if (it == plan->cls_of_n.end()) return fail(TDSE_E_INVALID, "n=%d is not in the plan", n);
     const Launch& L = plan->launches[plan->launch_of_cls[it->second]];
     if (systems_per_workgroup) *systems_per_workgroup = L.S;
-    if (lds_tables) *lds_tables = L.lds ? 1 : 0;
+    if (lds_tables) *lds_tables = L.tab;
     if (tuned_rate) *tuned_rate = L.tuned_rate;
     return TDSE_OK;
 }
@@ -1330,7 +1339,7 @@ static tdse_status enqueue_forward(tdse_plan pl, const FwdArgs& base, hipStream_
         a.nbins = G.nbins;
         a.item_off = (int32_t)(G.smem - 16);
         a.queue = ctr + g;
-        if (launch_forward(G.C, G.lds, a, G.threads, G.smem, G.grid, s) != hipSuccess)
+        if (launch_forward(G.C, G.tab, a, G.threads, G.smem, G.grid, s) != hipSuccess)
             return fail(TDSE_E_DEVICE, "forward launch failed: %s", hipGetErrorString(hipGetLastError()));
         return TDSE_OK;
     };
@@ -1428,7 +1437,7 @@ tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* 
             a.nbins = 1;
             a.item_off = (int32_t)(plan->plain_smem[b] - 16);
             a.queue = ctr + b;
-            if (launch_forward(L.C, L.lds, a, plan->plain_threads[b], plan->plain_smem[b], 1, st) !=
+            if (launch_forward(L.C, L.tab, a, plan->plain_threads[b], plan->plain_smem[b], 1, st) !=
                 hipSuccess)
                 return fail(TDSE_E_DEVICE, "forward launch failed");
         }

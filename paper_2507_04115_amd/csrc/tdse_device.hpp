@@ -294,15 +294,16 @@ constexpr int kSumLane = kWave - 1;  // lane holding wave_sum's result
 // om and dV/dx of a size class seen through LDS (staged once per workgroup,
 // shared by its systems) or directly in global memory.  The pivot factors q
 // live in registers instead (LaneFactors).
-template <bool GLOBAL>
+template <bool OM_GLOBAL, bool DV_GLOBAL>
 struct TabViewT {
     const double* om_;
     const double* dv_;
-    __device__ __forceinline__ double om(int i) const { return GLOBAL ? ldg(om_ + i) : om_[i]; }
-    __device__ __forceinline__ double dv(int i) const { return GLOBAL ? ldg(dv_ + i) : dv_[i]; }
+    __device__ __forceinline__ double om(int i) const { return OM_GLOBAL ? ldg(om_ + i) : om_[i]; }
+    __device__ __forceinline__ double dv(int i) const { return DV_GLOBAL ? ldg(dv_ + i) : dv_[i]; }
 };
-using TabLds = TabViewT<false>;
-using TabGlobal = TabViewT<true>;
+using TabLds = TabViewT<false, false>;
+using TabGlobal = TabViewT<true, true>;
+using TabOmLds = TabViewT<false, true>;
 
 // ------------------------------------------------------------ lane context
 // Lane coordinates within the system's subgroup and the table indices of the
@@ -687,10 +688,10 @@ __device__ __forceinline__ TabGlobal global_tables(const SizeClass& sc)
     return tv;
 }
 
-template <bool LDSTAB>
+template <int TAB>
 struct TableSource;
 template <>
-struct TableSource<true> {
+struct TableSource<kTabLds> {
     using type = TabLds;
     static __device__ __forceinline__ TabLds make(const SizeClass& sc, double* lds) { return stage_tables(sc, lds); }
     static __device__ __forceinline__ TabLds view(const SizeClass& sc, double* lds)
@@ -702,7 +703,18 @@ struct TableSource<true> {
     }
 };
 template <>
-struct TableSource<false> {
+struct TableSource<kTabOmLds> {
+    using type = TabOmLds;
+    static __device__ __forceinline__ TabOmLds view(const SizeClass& sc, double* lds)
+    {
+        TabOmLds tv;
+        tv.om_ = lds;
+        tv.dv_ = sc.pt.dv;
+        return tv;
+    }
+};
+template <>
+struct TableSource<kTabGlobal> {
     using type = TabGlobal;
     static __device__ __forceinline__ TabGlobal make(const SizeClass& sc, double*) { return global_tables(sc); }
     static __device__ __forceinline__ TabGlobal view(const SizeClass& sc, double*) { return global_tables(sc); }
@@ -714,11 +726,11 @@ struct TableSource<false> {
 // coordinates derived from the class are hoisted out of the loop and kept
 // live across it, far beyond the register budget of four waves per SIMD.
 // Rebuilding costs a few scalar loads and integer operations per step.
-template <bool LDSTAB>
+template <int TAB>
 struct StepView {
     SizeClass sc;
     LaneCtx lc;
-    typename TableSource<LDSTAB>::type tb;
+    typename TableSource<TAB>::type tb;
     RhsCoef rc;
     double xs;  // x of the lane's first point
     double xl;  // x of the point before it
@@ -727,13 +739,13 @@ struct StepView {
 // wsys: wave-uniform index of the calling wavefront within its system; the
 // lane index is rebuilt from the hardware lane id, so no per-lane index stays
 // live across the time loop.
-template <bool LDSTAB>
-__device__ __forceinline__ StepView<LDSTAB> step_view(const SizeClass* cls, int wsys, double* smem)
+template <int TAB>
+__device__ __forceinline__ StepView<TAB> step_view(const SizeClass* cls, int wsys, double* smem)
 {
-    StepView<LDSTAB> v;
+    StepView<TAB> v;
     v.sc = scalar_load(launder_s(cls));
     v.lc = make_lane_ctx(v.sc, wsys * kWave + opaque((int)__lane_id()), wsys);
-    v.tb = TableSource<LDSTAB>::view(v.sc, smem);
+    v.tb = TableSource<TAB>::view(v.sc, smem);
     v.rc.dofs10 = v.sc.dofs10;
     const double c = 0.5 * (double)(v.sc.n - 1);
     v.xs = ((double)v.lc.s - c) * v.sc.dx;

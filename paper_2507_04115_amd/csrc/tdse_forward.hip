@@ -34,7 +34,7 @@ size_t sub_smem_bytes(int W)
 // systems of one lane layout that together fill the workgroup's lanes (plus a
 // padding system where they do not); every subgroup runs the whole time loop
 // of its system with the same barrier sequence as the others.
-template <int C, bool LDSTAB>
+template <int C, int TAB>
 __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
 {
     extern __shared__ double smem_raw[];
@@ -63,11 +63,11 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
         const int p = active ? bs.p : 0;
         const double dx = sc.dx;
         const int n = sc.n, s = t * C;
-        if (LDSTAB && bs.stage) {
+        if (TAB != kTabGlobal && bs.stage) {
             const int np = C * T;
             for (int i = t; i < np; i += T) {
                 tab[i] = sc.pt.om[i];
-                tab[np + i] = sc.pt.dv[i];
+                if (TAB == kTabLds) tab[np + i] = sc.pt.dv[i];
             }
         }
         if (t == 0) sm.misc[1] = 0;
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
 
         LaneFactors<C> f;
         {
-            const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, tab);
+            const StepView<TAB> sv = step_view<TAB>(clsp, wsys, tab);
             f = load_factors<C>(sv.sc, sv.lc);
             observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, sm.ring);
         }
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
 
         int flushed = 0;
         for (int i = 0; i < nt; ++i) {
-            const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, tab);
+            const StepView<TAB> sv = step_view<TAB>(clsp, wsys, tab);
             forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
                             sm.lds_f, sm.lds_b);
             if ((i + 1) % kFlush == 0) {
@@ -246,50 +246,61 @@ hipError_t launch_reset_counters(int32_t* counters, int n, hipStream_t st)
 
 bool layout_supported(int C) { return C == 4 || C == 8 || C == 16; }
 
-template <int C, bool L>
+template <int C, int TAB>
 static int occ_fwd(int threads, size_t sh)
 {
     int nb = 0;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(forward_kernel<C, L>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(forward_kernel<C, TAB>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     hipFuncAttributes fa;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(forward_kernel<C, L>)) != hipSuccess ||
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(forward_kernel<C, TAB>)) != hipSuccess ||
         threads > fa.maxThreadsPerBlock)
         return 0;  // beyond the kernel's launch bounds
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, forward_kernel<C, L>, threads, sh) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, forward_kernel<C, TAB>, threads, sh) !=
         hipSuccess)
         return 0;
     return nb;
 }
 
-int forward_occupancy(int C, int threads, size_t smem, bool lds_tables)
+// Instantiated layouts: C in {4, 8, 16} with tables in global memory or in
+// LDS; om alone in LDS only for 16 points per lane (the grids whose full
+// tables do not fit).
+bool forward_tab_supported(int C, int tab)
+{
+    if (!layout_supported(C)) return false;
+    return tab == kTabGlobal || tab == kTabLds || (tab == kTabOmLds && C == 16);
+}
+
+int forward_occupancy(int C, int threads, size_t smem, int tab)
 {
     if (smem > (size_t)kMaxLds || threads < kWave || threads > 1024 || threads % kWave) return 0;
-    switch (C * 2 + (lds_tables ? 1 : 0)) {
-        case 8: return occ_fwd<4, false>(threads, smem);
-        case 9: return occ_fwd<4, true>(threads, smem);
-        case 16: return occ_fwd<8, false>(threads, smem);
-        case 17: return occ_fwd<8, true>(threads, smem);
-        case 32: return occ_fwd<16, false>(threads, smem);
-        case 33: return occ_fwd<16, true>(threads, smem);
+    switch (C * 4 + tab) {
+        case 16: return occ_fwd<4, kTabGlobal>(threads, smem);
+        case 17: return occ_fwd<4, kTabLds>(threads, smem);
+        case 32: return occ_fwd<8, kTabGlobal>(threads, smem);
+        case 33: return occ_fwd<8, kTabLds>(threads, smem);
+        case 64: return occ_fwd<16, kTabGlobal>(threads, smem);
+        case 65: return occ_fwd<16, kTabLds>(threads, smem);
+        case 66: return occ_fwd<16, kTabOmLds>(threads, smem);
         default: return 0;
     }
 }
 
-hipError_t launch_forward(int C, bool lds_tables, const FwdArgs& a, int threads, size_t smem,
-                          int grid, hipStream_t st)
+hipError_t launch_forward(int C, int tab, const FwdArgs& a, int threads, size_t smem, int grid,
+                          hipStream_t st)
 {
     if (smem > (size_t)kMaxLds || threads < kWave || threads > 1024 || threads % kWave ||
         (size_t)a.item_off + 16 > smem)
         return hipErrorInvalidValue;
     const dim3 b(threads);
-    switch (C * 2 + (lds_tables ? 1 : 0)) {
-        case 8: hipLaunchKernelGGL((forward_kernel<4, false>), dim3(grid), b, smem, st, a); break;
-        case 9: hipLaunchKernelGGL((forward_kernel<4, true>), dim3(grid), b, smem, st, a); break;
-        case 16: hipLaunchKernelGGL((forward_kernel<8, false>), dim3(grid), b, smem, st, a); break;
-        case 17: hipLaunchKernelGGL((forward_kernel<8, true>), dim3(grid), b, smem, st, a); break;
-        case 32: hipLaunchKernelGGL((forward_kernel<16, false>), dim3(grid), b, smem, st, a); break;
-        case 33: hipLaunchKernelGGL((forward_kernel<16, true>), dim3(grid), b, smem, st, a); break;
+    switch (C * 4 + tab) {
+        case 16: hipLaunchKernelGGL((forward_kernel<4, kTabGlobal>), dim3(grid), b, smem, st, a); break;
+        case 17: hipLaunchKernelGGL((forward_kernel<4, kTabLds>), dim3(grid), b, smem, st, a); break;
+        case 32: hipLaunchKernelGGL((forward_kernel<8, kTabGlobal>), dim3(grid), b, smem, st, a); break;
+        case 33: hipLaunchKernelGGL((forward_kernel<8, kTabLds>), dim3(grid), b, smem, st, a); break;
+        case 64: hipLaunchKernelGGL((forward_kernel<16, kTabGlobal>), dim3(grid), b, smem, st, a); break;
+        case 65: hipLaunchKernelGGL((forward_kernel<16, kTabLds>), dim3(grid), b, smem, st, a); break;
+        case 66: hipLaunchKernelGGL((forward_kernel<16, kTabOmLds>), dim3(grid), b, smem, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

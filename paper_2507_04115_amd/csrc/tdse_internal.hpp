@@ -18,6 +18,17 @@ constexpr int kRing = 64;       // ring of per-wave partial sums (samples)
 constexpr int kLdsTableBytes = 16;  // LDS bytes per grid point of the staged
                                     // tables (om and dV/dx)
 
+// Placement of a size class's om and dV/dx tables in a workgroup: both read
+// from global memory, both staged in LDS, or om staged in LDS and dV/dx read
+// from global memory (for grids whose full tables do not fit).
+constexpr int kTabGlobal = 0;
+constexpr int kTabLds = 1;
+constexpr int kTabOmLds = 2;
+__host__ __device__ constexpr int tab_lds_bytes(int tab)
+{
+    return tab == kTabLds ? kLdsTableBytes : (tab == kTabOmLds ? 8 : 0);
+}
+
 __host__ __device__ inline int pbase(int t, int C) { return (t >> 6) * (C * 64) + (t & 63); }
 __host__ __device__ inline int pidx(int t, int k, int C) { return pbase(t, C) + 64 * k; }
 

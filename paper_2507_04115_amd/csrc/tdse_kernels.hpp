@@ -90,11 +90,13 @@ size_t sub_smem_bytes(int W);
 
 // Forward kernel over workgroup bins: C points per lane, `threads` lanes per
 // workgroup, `smem` bytes of LDS (staged tables of the bin's classes, the
-// subgroups' scratch blocks, the queue slot), point tables in LDS or global
-// memory.  Occupancy is in workgroups per CU (0 when it does not fit).
-int forward_occupancy(int C, int threads, size_t smem, bool lds_tables);
-hipError_t launch_forward(int C, bool lds_tables, const FwdArgs& a, int threads, size_t smem,
-                          int grid, hipStream_t st);
+// subgroups' scratch blocks, the queue slot), table placement `tab`
+// (kTabGlobal, kTabLds, kTabOmLds).  Occupancy is in workgroups per CU (0
+// when it does not fit or the combination is not instantiated).
+bool forward_tab_supported(int C, int tab);
+int forward_occupancy(int C, int threads, size_t smem, int tab);
+hipError_t launch_forward(int C, int tab, const FwdArgs& a, int threads, size_t smem, int grid,
+                          hipStream_t st);
 
 size_t adjoint_smem_bytes(int C, int T, int S, bool lds_tables);
 int adjoint_occupancy(int C, int T, int S, bool lds_tables);

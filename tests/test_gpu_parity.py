@@ -171,6 +171,42 @@ def test_nonfinite_field_is_flagged(lib, torch_dev):
     assert out["status"][1] & lib.TDSE_SYS_NONFINITE
 
 
+def test_invalid_arguments_are_refused_before_any_launch(lib, torch_dev):
+    """Argument errors come back as TDSE_E_INVALID / TDSE_E_UNSUPPORTED with a
+    detail message, and leave the plan usable."""
+    torch, dev = torch_dev
+    nt = 40
+    p = lib.make_params(0.4, 0.05, 1.1, nt, mask_fraction=0.2)
+
+    def status_of(fn):
+        with pytest.raises(lib.TDSEError) as ei:
+            fn()
+        assert str(ei.value)
+        return ei.value.status
+
+    assert status_of(lambda: lib.Plan(p, [8])) == lib.TDSE_E_INVALID              # n < 16
+    assert status_of(lambda: lib.Plan(p, [20000])) == lib.TDSE_E_UNSUPPORTED      # n > 16384
+    assert status_of(lambda: lib.Plan(p, [256], options=64)) == lib.TDSE_E_INVALID
+    assert status_of(lambda: lib.Plan(p, [256], options=lib.TDSE_OPT_STORE_CHECKPOINTS)) \
+        == lib.TDSE_E_INVALID                                                    # needs adjoint_k
+    bad = lib.make_params(-0.4, 0.05, 1.1, nt)
+    assert status_of(lambda: lib.Plan(bad, [256])) == lib.TDSE_E_INVALID
+    plan = lib.Plan(p, [256, 300])
+    E = torch.zeros(2, nt + 1, dtype=torch.float64, device=dev)
+    acc = torch.empty_like(E)
+    assert status_of(lambda: lib.tdse_propagate_batch(plan, E, None, None)) == lib.TDSE_E_INVALID
+    flat = torch.zeros(2 * (nt + 1) + 1, dtype=torch.float64, device=dev)
+    assert status_of(lambda: lib.tdse_propagate_batch(plan, E, None, flat[1:])) \
+        == lib.TDSE_E_INVALID                                                    # misaligned
+    assert status_of(lambda: lib.tdse_adjoint_batch(plan, E, None, acc, acc)) == lib.TDSE_E_INVALID
+    assert status_of(lambda: lib.tdse_adjoint_batch_stored(plan, 1, E, acc, acc)) \
+        == lib.TDSE_E_INVALID
+    lib.tdse_propagate_batch(plan, E, None, acc)      # still usable
+    torch.cuda.synchronize()
+    assert torch.isfinite(acc).all()
+    plan.close()
+
+
 def test_harmonic_yield_matches_oracle(lib, torch_dev):
     torch, dev = torch_dev
     rng = np.random.default_rng(4)
