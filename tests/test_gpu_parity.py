@@ -331,9 +331,33 @@ def test_stored_checkpoints_match_recomputing_adjoint(lib, torch_dev):
     stp.close()
 
 
+def test_table_placement_does_not_change_results(lib, torch_dev, monkeypatch):
+    """The per-point tables staged in LDS (both, or om alone) or read from
+    global memory hold the same values, so every placement gives bitwise
+    the same outputs (TDSE_PACK_LDS forces a placement at plan creation)."""
+    torch, dev = torch_dev
+    dx, dt = 0.2, 0.05
+    nt = 60
+    for ns, forced in (([600, 2048, 3000], "0"), ([9000, 12000], "0"), ([9000, 12000], "2")):
+        efield = ti.sin2_pulse(np.linspace(0.05, 0.08, len(ns)), 0.057, 1, dt, nt=nt)
+        monkeypatch.delenv("TDSE_PACK_LDS", raising=False)
+        plan_d, ref = _run_forward(lib, torch, dev, ns, efield, dx, dt, A_AR)
+        placement_d = [plan_d.launch_info(n).lds_tables for n in ns]
+        monkeypatch.setenv("TDSE_PACK_LDS", forced)
+        plan_f, out = _run_forward(lib, torch, dev, ns, efield, dx, dt, A_AR)
+        placement_f = [plan_f.launch_info(n).lds_tables for n in ns]
+        monkeypatch.delenv("TDSE_PACK_LDS")
+        print(f"placement ns={ns}: default {placement_d}, forced {placement_f}", flush=True)
+        assert placement_f == [int(forced)] * len(ns)
+        for key in ("accel", "xexp", "norm", "psi_final"):
+            assert np.array_equal(out[key], ref[key]), key
+        plan_d.close()
+        plan_f.close()
+
+
 def test_forward_uneven_wide_batch_sampled(lib, torch_dev):
-    """Uneven batch spanning N = 2048..16384 (many size classes, tables in LDS
-    and in global memory, 8 and 16 points per lane), first 400 steps of the
+    """Uneven batch spanning N = 2048..16384 (many size classes; tables in
+    LDS, om alone in LDS; 8 and 16 points per lane), first 400 steps of the
     1300 nm pulse; sampled systems against the oracle, all statuses clean."""
     torch, dev = torch_dev
     w = ti.cfg3_uneven(batch=96, wide=True)
