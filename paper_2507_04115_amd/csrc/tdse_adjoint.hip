@@ -149,6 +149,9 @@ __device__ __forceinline__ void add_source(cd (&kap)[C], cd& kgl, cd& kgr, const
 template <int C, bool LDSTAB>
 __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
 {
+    // the costate doubles the chunk state: pivot factors stay in registers
+    // only for 4 points per lane
+    constexpr bool kAdjQRegs = C <= 4;
     extern __shared__ double smem_raw[];
     const SizeClass sc = uniform_load(a.classes + a.cls);
     const int T = sc.T, W = T / kWave, np = C * T;
@@ -217,10 +220,10 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
         for (int k = 0; k < C; ++k) v[k] = (active && s + k < n) ? ld_psi(src, s + k) : czero();
         cd gl = (active && s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
         cd gr = (active && s + C < n) ? ld_psi(src, s + C) : czero();
-        LaneFactors<C> f;
+        LaneFactors<C, kAdjQRegs> f;
         {
             const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
-            f = load_factors<C>(sv.sc, sv.lc);
+            f = load_factors<C, kAdjQRegs>(sv.sc, sv.lc);
         }
         int flushed = 0;
         // forward pass length (uniform): none when the checkpoints are stored
@@ -301,7 +304,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 // psi^i is loaded first: its latency overlaps the costate step
                 load_state<C>(seg + np2 * (i - s0), T, loff, v, gl, gr);
-                phase_mask<C>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc, sv.lc);
+                phase_mask<C, !kAdjQRegs>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc, sv.lc);
                 cn_apply<C, true>(kap, kgl, kgr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
                 // + 2 abar_i dx (V' + E_i) conj(psi^i)
                 add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[i] * dx, e, sv.tb, T, sv.lc);

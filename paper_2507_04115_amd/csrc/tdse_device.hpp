@@ -363,30 +363,31 @@ struct QInRegs {
 // Per-lane factors: q at the C points of the chunk and at the point before
 // it (when held in registers), and the absorber flags (bit 0: a mask value of
 // the chunk differs from 1; bit 1: at s-1; bit 2: at s+C).
-template <int C>
+template <int C, bool QREG = QInRegs<C>::value>
 struct LaneFactors {
-    static constexpr int NQ = QInRegs<C>::value ? C : 1;
+    static constexpr bool kRegs = QREG;  // q held in registers
+    static constexpr int NQ = QREG ? C : 1;
     cd q_[NQ];
     cd ql_;
     int mflags;
     // q at point k of the chunk and at s-1 (zero for the first lane)
     __device__ __forceinline__ cd q(int k, const SizeClass& sc, const LaneCtx& lc) const
     {
-        if constexpr (QInRegs<C>::value) return q_[k];
+        if constexpr (QREG) return q_[k];
         else return ldg(sc.pt.q + lc.b0 + 64 * k);
     }
     __device__ __forceinline__ cd ql(const SizeClass& sc, const LaneCtx& lc) const
     {
-        if constexpr (QInRegs<C>::value) return ql_;
+        if constexpr (QREG) return ql_;
         else return lc.t > 0 ? ldg(sc.pt.q + lc.il()) : czero();
     }
 };
 
-template <int C>
-__device__ __forceinline__ LaneFactors<C> load_factors(const SizeClass& sc, const LaneCtx& lc)
+template <int C, bool QREG = QInRegs<C>::value>
+__device__ __forceinline__ LaneFactors<C, QREG> load_factors(const SizeClass& sc, const LaneCtx& lc)
 {
-    LaneFactors<C> f;
-    if constexpr (QInRegs<C>::value) {
+    LaneFactors<C, QREG> f;
+    if constexpr (QREG) {
 #pragma unroll
         for (int k = 0; k < C; ++k) f.q_[k] = ldg(sc.pt.q + lc.b0 + 64 * k);
         f.ql_ = lc.t > 0 ? ldg(sc.pt.q + lc.il()) : czero();
@@ -504,8 +505,8 @@ __device__ __forceinline__ cd gfac(double w, cd x)
 // only); backward recurrence from the exact carry.  The new neighbours follow
 // from the exact carries cf = z_{s-1} and cb = y_{s+C} without exchanging
 // data between lanes:  y_{s+C} = cb,  y_{s-1} = q_{s-1} cf + beta_{s-1} y_s.
-template <int C, bool RT, class TV>
-__device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneFactors<C>& f,
+template <int C, bool RT, class TV, class LF>
+__device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f,
                                          const TV& tb, const SizeClass& sc, const LaneCtx& lc,
                                          const RhsCoef rc, cd* lds_f, cd* lds_b)
 {
@@ -524,7 +525,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
         cd g_c = gfac<RT>(om_c, v[0]);
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            if (k == (QInRegs<C>::value ? C / 2 : C - 1)) {
+            if (k == (LF::kRegs ? C / 2 : C - 1)) {
                 if (sc.levels > 0) a0 = ld_lane(sc.lt.pa, off);
                 if (sc.levels > 1) a1 = ld_lane(sc.lt.pa + sc.T, off);
                 if (lc.lane < (1 << sc.levels)) aw = ld_lane(sc.lt.pw, off);
@@ -551,14 +552,14 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
         if (sc.levels > 1) b1c = ld_lane(sc.lt.qb + sc.T, off);
         if (lc.lane > kWave - 1 - (1 << sc.levels)) bw = ld_lane(sc.lt.qw, off);
     };
-    if constexpr (QInRegs<C>::value) load_bwd_windows();
+    if constexpr (LF::kRegs) load_bwd_windows();
     // B. forward recurrence from the exact carry, w = q z.  When q is read
     // from memory, each sweep hides the chunk base from the optimiser so
     // that it reloads q and om rather than keeping earlier sweeps' values
     // live (they would be spilled).
     {
         LaneCtx lcb = lc;
-        if constexpr (!QInRegs<C>::value) lcb.b0 = opaque(lc.b0);
+        if constexpr (!LF::kRegs) lcb.b0 = opaque(lc.b0);
         cd z = cf;
         double om_p = oml;
 #pragma unroll
@@ -573,7 +574,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
     cd yb = v[C - 1];
     {
         LaneCtx lcc = lc;
-        if constexpr (!QInRegs<C>::value) lcc.b0 = opaque(lc.b0);
+        if constexpr (!LF::kRegs) lcc.b0 = opaque(lc.b0);
         const int bc = lcc.b0;
 #pragma unroll
         for (int k = C - 2; k >= 0; --k) {
@@ -582,13 +583,13 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
             point_fence(yb);
         }
     }
-    if constexpr (!QInRegs<C>::value) load_bwd_windows();
+    if constexpr (!LF::kRegs) load_bwd_windows();
     const cd cb = scan_bwd(yb, b0c, b1c, bw, sc, lc, lds_b);
     // D. backward recurrence from the exact carry
     double om_0;
     {
         LaneCtx lcd = lc;
-        if constexpr (!QInRegs<C>::value) lcd.b0 = opaque(lc.b0);
+        if constexpr (!LF::kRegs) lcd.b0 = opaque(lc.b0);
         cd y = cb;
         double om_n = omr;
 #pragma unroll
@@ -608,7 +609,10 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LaneF
 // Field substep exp(-i dt E x_j) and absorber m_j on the chunk and its two
 // ghost points (x_{s-1} = xl).  The phase advances along the chunk by
 // multiplication with exp(-i dt E dx); each lane starts from its own sincos.
-template <int C>
+// BRANCHLESS: the absorber factor is applied to every point (1 away from
+// the edges); used where a branch would make the two paths' results meet in
+// different registers and cost spills of the chunk.
+template <int C, bool BRANCHLESS>
 __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e, double dt,
                                            double xl, double dx, int mflags,
                                            const SizeClass& sc, const LaneCtx& lc)
@@ -621,10 +625,7 @@ __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e,
     gl = cmul(ph, gl);
     if (mflags & 2) gl = cscale(ldg(sc.pt.m + lc.il()), gl);
     ph = cmul(ph, w1);
-    if (!QInRegs<C>::value) {
-        // long chunks: the absorber factor is applied to every point (1 away
-        // from the edges); a branch here would make the two paths' results
-        // meet in different registers, which costs spills of the chunk
+    if (BRANCHLESS) {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             v[k] = cscale(ldg(sc.pt.m + lc.b0 + 64 * k), cmul(ph, v[k]));
@@ -652,14 +653,14 @@ __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e,
 
 // One full step psi^(i) -> psi^(i+1) (CN right-hand side, partitioned solve,
 // ghost rebuild, field phase and absorber).
-template <int C, class TV>
-__device__ __forceinline__ void forward_step(cd (&v)[C], cd& gl, cd& gr, const LaneFactors<C>& f,
+template <int C, class TV, class LF>
+__device__ __forceinline__ void forward_step(cd (&v)[C], cd& gl, cd& gr, const LF& f,
                                              double e, double dt, double xl, const TV& tb,
                                              const SizeClass& sc, const LaneCtx& lc,
                                              const RhsCoef rc, cd* lds_f, cd* lds_b)
 {
     cn_apply<C, true, TV>(v, gl, gr, f, tb, sc, lc, rc, lds_f, lds_b);
-    phase_mask<C>(v, gl, gr, e, dt, xl, sc.dx, f.mflags, sc, lc);
+    phase_mask<C, !LF::kRegs>(v, gl, gr, e, dt, xl, sc.dx, f.mflags, sc, lc);
 }
 
 // Copies the om and dV/dx tables of a size class into LDS: 16 bytes per
