@@ -1126,7 +1126,6 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         fg.grid = std::min(fg.nbins, occ * num_cus());
         pl->fgroups.push_back(fg);
     }
-    const size_t plain0 = hbins.size();
     pl->plain_threads.assign(batch, 0);
     pl->plain_smem.assign(batch, 0);
     for (int b = 0; b < batch; ++b) {
@@ -1145,7 +1144,6 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     if (hipMemcpy(pl->d_bins, hbins.data(), sizeof(BinDesc) * hbins.size(), hipMemcpyHostToDevice) !=
         hipSuccess)
         return bail(fail(TDSE_E_DEVICE, "plan upload failed"));
-    (void)plain0;
 
     // adjoint launches, one per class, longest work first: classes by
     // (n_pad * count) descending
@@ -1561,7 +1559,7 @@ tdse_status tdse_soft_core_for_ip(double ip, int32_t n, double dx, double dtau, 
         // closest candidate and the new bracket
         double new_lo = lo, new_hi = hi;
         for (int c = 0; c < nc; ++c) {
-            if (std::fabs(e[c] + ip) < std::fabs(best_e + ip) || round == 0 && c == 0) {
+            if (std::fabs(e[c] + ip) < std::fabs(best_e + ip) || (round == 0 && c == 0)) {
                 best_a = cand[c];
                 best_e = e[c];
             }
