@@ -5,7 +5,9 @@ baseline leg of the benchmark may import this package.  The product path (the
 HIP library and its Python binding) never imports, loads or calls it, and the
 two share no code: the numerical core is the plain C file ``tdse_ref.c``
 (serial, fp64, Thomas algorithm, matrices rebuilt from their definitions),
-the harmonic-yield loss below is a direct discrete Fourier sum in numpy.
+the harmonic-yield loss below is a direct discrete Fourier sum in numpy, and
+the far-field diffraction integral is a direct sum over the medium in numpy
+(scipy's J0).
 
 Parity status: every function here is pinned by the CPU tests in
 ``tests/test_oracle_*.py`` against closed forms, dense textbook linear algebra
@@ -233,3 +235,76 @@ def harmonic_yield(accel, dt, omega0, h_lo, h_hi):
     loss = dw * np.sum(np.abs(amp) ** 2, axis=1)
     abar = 2.0 * dw * dt * w * np.real(np.conj(amp) @ ph)        # [P, ntp1]
     return loss, abar
+
+
+def band_amplitudes(accel, dt, omega0, h_lo, h_hi):
+    """(band bins k, A [P, K]) with A_k = dt sum_i w_i a_i exp(-i omega_k t_i),
+    the windowed spectrum of ``harmonic_yield`` on its band."""
+    accel = np.atleast_2d(np.asarray(accel, dtype=np.float64))
+    ntp1 = accel.shape[1]
+    i = np.arange(ntp1)
+    w = np.sin(np.pi * i / (ntp1 - 1)) ** 2
+    kb = band_bins(ntp1, dt, omega0, h_lo, h_hi)
+    ph = np.exp(-2j * np.pi * (np.outer(kb, i) % ntp1) / ntp1)
+    return kb, dt * (accel * w) @ ph.T
+
+
+def band_adjoint(amp_bar, ntp1, dt, kb):
+    """Gradient of a real loss with respect to the samples a_i, given
+    amp_bar_k = dl/dRe A_k + i dl/dIm A_k for the band amplitudes above:
+    dl/da_i = dt w_i sum_k Re(conj(amp_bar_k) exp(-i omega_k t_i))."""
+    amp_bar = np.atleast_2d(np.asarray(amp_bar, dtype=np.complex128))
+    i = np.arange(ntp1)
+    w = np.sin(np.pi * i / (ntp1 - 1)) ** 2
+    ph = np.exp(-2j * np.pi * (np.outer(kb, i) % ntp1) / ntp1)
+    return dt * w * np.real(np.conj(amp_bar) @ ph)
+
+
+# --------------------------------------------------------------------------
+# far field of the XUV emission (diffraction integral over the medium)
+# --------------------------------------------------------------------------
+
+def far_field_kernel(rho_src, z_src, weights, kw, rho_obs, z_obs):
+    """K[q, m, p]: the propagator of the homogeneous-medium diffraction
+    integral (section "XUV Propagation (Spectral Approach)", Eq. of the
+    far field in a homogeneous generating medium), with mu0 left to the
+    caller:
+
+      E(rho_m, z, omega_q) = -(exp(i k z) / (4 pi)) sum_{p=(i,j)} w_p
+            exp(-i k z'_j) exp(i k rho_m^2 / (2 d_j)) / d_j
+            exp(i k rho'_i^2 / (2 d_j)) J0(k rho_m rho'_i / d_j) S_p(omega_q),
+
+    k = kw[q], d_j = z - z'_j, p = i * n_z + j; w_p are the quadrature
+    weights of the rho' drho' dz' integral times the gas density."""
+    from scipy.special import j0
+
+    rho_src = np.asarray(rho_src, np.float64)
+    z_src = np.asarray(z_src, np.float64)
+    R = np.repeat(rho_src, len(z_src))            # rho'_i of p
+    Z = np.tile(z_src, len(rho_src))              # z'_j of p
+    W = np.asarray(weights, np.float64).ravel()
+    d = z_obs - Z
+    K = np.empty((len(kw), len(rho_obs), len(R)), np.complex128)
+    for q, k in enumerate(kw):
+        for m, r in enumerate(rho_obs):
+            phase = k * (R ** 2 + r ** 2) / (2.0 * d) - k * Z
+            K[q, m] = -np.exp(1j * k * z_obs) / (4.0 * np.pi) * W / d * np.exp(1j * phase) \
+                * j0(k * r * R / d)
+    return K
+
+
+def far_field(amp, rho_src, z_src, weights, kw, rho_obs, z_obs):
+    """Far field E [M, Q] of the source spectra amp [P, Q] (see
+    far_field_kernel)."""
+    K = far_field_kernel(rho_src, z_src, weights, kw, rho_obs, z_obs)
+    amp = np.asarray(amp, np.complex128)
+    return np.stack([K[q] @ amp[:, q] for q in range(len(kw))], axis=1)
+
+
+def far_field_adjoint(field_bar, rho_src, z_src, weights, kw, rho_obs, z_obs):
+    """amp_bar [P, Q] = sum_m conj(K[q, m, p]) field_bar[m, q]: the gradient
+    of a real loss with respect to the source spectra, given its gradient
+    with respect to the far field (same complex convention as band_adjoint)."""
+    K = far_field_kernel(rho_src, z_src, weights, kw, rho_obs, z_obs)
+    fb = np.asarray(field_bar, np.complex128)
+    return np.stack([np.conj(K[q]).T @ fb[:, q] for q in range(len(kw))], axis=1)
