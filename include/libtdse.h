@@ -250,6 +250,47 @@ tdse_status tdse_harmonic_yield(int32_t batch, int32_t nt, double dt, double ome
                                 double h_hi, const double* accel, const double* row_weight,
                                 double* work, double* yield, double* accel_bar, void* stream);
 
+/* The band spectrum alone: amp[b][k] = A_k of row b (as above) for the bins
+ * of tdse_harmonic_band, interleaved complex, dev [batch][nk].  And its
+ * adjoint: given amp_bar = dl/dRe A + i dl/dIm A of a real loss l (dev
+ * complex [batch][nk]), writes accel_bar[b][i] = dl/da_i
+ * = dt w_i sum_k Re(conj(amp_bar_k) exp(-i omega_k t_i)) (dev [batch][nt+1]).
+ * Asynchronous on `stream`. */
+tdse_status tdse_band_dft(int32_t batch, int32_t nt, double dt, double omega0, double h_lo,
+                          double h_hi, const double* accel, double* amp, void* stream);
+tdse_status tdse_band_dft_adjoint(int32_t batch, int32_t nt, double dt, double omega0, double h_lo,
+                                  double h_hi, const double* amp_bar, double* accel_bar, void* stream);
+
+/* ----------------------------------------------------------- far field */
+/* Far field of the emission of a cylindrically symmetric medium, the
+ * diffraction integral of a homogeneous generating medium (section "XUV
+ * Propagation (Spectral Approach)", Eq. of the far field in a homogeneous
+ * medium), evaluated as a direct sum over the n_rho x n_z source points
+ * (rho'_i, z'_j), source p = i * n_z + j:
+ *   field[m][q] = -(exp(i k z)/(4 pi)) sum_p weights[p] / d_j
+ *        exp(i (k (rho'_i^2 + rho_m^2) / (2 d_j) - k z'_j)) J0(k rho_m rho'_i / d_j) amp[p][q]
+ * with k = kwave[q], d_j = z_obs - z'_j and rho_m = rho_obs[m].  mu0 is left
+ * to the caller; weights[p] are the quadrature weights of rho' drho' dz'
+ * times the gas density.  Lengths in any one unit, kwave in its inverse.
+ * Every z'_j must lie before the observation plane (d_j > 0).
+ *   rho_src dev [n_rho], z_src dev [n_z], weights dev [n_rho n_z],
+ *   kwave dev [nk], rho_obs dev [n_obs]   (float64)
+ *   amp     dev complex [n_rho n_z][nk]   (e.g. tdse_band_dft of the systems
+ *           of an n_rho x n_z focus grid, times the density)
+ *   field   dev complex [n_obs][nk]
+ * tdse_far_field_adjoint takes field_bar = dl/dRe E + i dl/dIm E of a real
+ * loss and writes amp_bar = dl/dRe S + i dl/dIm S, the conjugate transpose
+ * of the same map.  Asynchronous on `stream`. */
+tdse_status tdse_far_field(int32_t n_rho, int32_t n_z, const double* rho_src, const double* z_src,
+                           const double* weights, int32_t nk, const double* kwave, const double* amp,
+                           int32_t n_obs, const double* rho_obs, double z_obs, double* field,
+                           void* stream);
+tdse_status tdse_far_field_adjoint(int32_t n_rho, int32_t n_z, const double* rho_src,
+                                   const double* z_src, const double* weights, int32_t nk,
+                                   const double* kwave, const double* field_bar, int32_t n_obs,
+                                   const double* rho_obs, double z_obs, double* amp_bar,
+                                   void* stream);
+
 #ifdef __cplusplus
 }
 #endif

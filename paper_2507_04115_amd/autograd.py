@@ -22,7 +22,8 @@ import torch
 
 from . import binding as L
 
-__all__ = ["TDSEFunction", "HarmonicYield", "TDSEBatch"]
+__all__ = ["TDSEFunction", "HarmonicYield", "TDSEBatch", "BandSpectrum", "FarFieldGeometry",
+           "FarField"]
 
 
 def _check_field(E: torch.Tensor, plan: "L.Plan"):
@@ -118,3 +119,73 @@ class TDSEBatch:
 
     def close(self):
         self.plan.close()
+
+
+class BandSpectrum(torch.autograd.Function):
+    """amp = BandSpectrum.apply(accel, dt, omega0, h_lo, h_hi): the windowed
+    band spectrum A_k of every row (tdse_band_dft), complex128 [P, nk].
+    backward: tdse_band_dft_adjoint."""
+
+    @staticmethod
+    def forward(ctx, accel: torch.Tensor, dt: float, omega0: float, h_lo: float, h_hi: float):
+        if accel.dtype != torch.float64 or not accel.is_cuda or accel.dim() != 2:
+            raise TypeError("accel must be a 2-D float64 tensor on the GPU")
+        accel = accel.contiguous()
+        batch, n1 = accel.shape
+        _, nk = L.tdse_harmonic_band(n1 - 1, dt, omega0, h_lo, h_hi)
+        amp = torch.empty(batch, max(nk, 1), dtype=torch.complex128, device=accel.device)
+        L.tdse_band_dft(batch, n1 - 1, dt, omega0, h_lo, h_hi, accel, amp)
+        ctx.args = (batch, n1, dt, omega0, h_lo, h_hi)
+        return amp[:, :nk]
+
+    @staticmethod
+    def backward(ctx, grad_amp: torch.Tensor):
+        batch, n1, dt, omega0, h_lo, h_hi = ctx.args
+        abar = torch.empty(batch, n1, dtype=torch.float64, device=grad_amp.device)
+        L.tdse_band_dft_adjoint(batch, n1 - 1, dt, omega0, h_lo, h_hi,
+                                grad_amp.to(torch.complex128).contiguous(), abar)
+        return abar, None, None, None, None
+
+
+class FarFieldGeometry:
+    """Source grid (rho'_i, z'_j; source p = i * n_z + j), quadrature weights
+    of rho' drho' dz' times the density, wave numbers of the band bins, and
+    the observation points (rho_m at distance z_obs), as float64 tensors on
+    the GPU."""
+
+    def __init__(self, rho_src, z_src, weights, kwave, rho_obs, z_obs: float, device="cuda:0"):
+        t = lambda x: torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
+        self.rho_src, self.z_src, self.weights = t(rho_src), t(z_src), t(weights).reshape(-1)
+        self.kwave, self.rho_obs = t(kwave), t(rho_obs)
+        self.z_obs = float(z_obs)
+        if self.weights.numel() != self.rho_src.numel() * self.z_src.numel():
+            raise ValueError("weights must have n_rho * n_z entries")
+
+
+class FarField(torch.autograd.Function):
+    """field = FarField.apply(amp, geometry): the far field [n_obs, nk]
+    (complex128) of the source spectra amp [n_rho n_z, nk] (tdse_far_field);
+    backward: tdse_far_field_adjoint."""
+
+    @staticmethod
+    def forward(ctx, amp: torch.Tensor, geom: FarFieldGeometry):
+        amp = amp.to(torch.complex128).contiguous()
+        nk = geom.kwave.numel()
+        if amp.shape != (geom.weights.numel(), nk):
+            raise ValueError(f"amp must have shape [{geom.weights.numel()}, {nk}]")
+        field = torch.empty(geom.rho_obs.numel(), nk, dtype=torch.complex128, device=amp.device)
+        L.tdse_far_field(geom.rho_src, geom.z_src, geom.weights, geom.kwave, amp, geom.rho_obs,
+                         geom.z_obs, field)
+        ctx.geom = geom
+        return field
+
+    @staticmethod
+    def backward(ctx, grad_field: torch.Tensor):
+        geom = ctx.geom
+        amp_bar = torch.empty(geom.weights.numel(), geom.kwave.numel(), dtype=torch.complex128,
+                              device=grad_field.device)
+        L.tdse_far_field(geom.rho_src, geom.z_src, geom.weights, geom.kwave,
+                         grad_field.to(torch.complex128).contiguous(), geom.rho_obs, geom.z_obs,
+                         amp_bar, adjoint=True)
+        return amp_bar, None
+

@@ -75,6 +75,11 @@ _PROTOS = {
     "tdse_adjoint_batch_stored": (_i32, [_vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp]),
     "tdse_harmonic_band": (_i32, [_i32, _d, _d, _d, _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "tdse_harmonic_yield": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tdse_band_dft": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
+    "tdse_band_dft_adjoint": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
+    "tdse_far_field": (_i32, [_i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _d, _vp, _vp]),
+    "tdse_far_field_adjoint": (_i32, [_i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _d, _vp,
+                                      _vp]),
 }
 
 
@@ -266,3 +271,26 @@ def tdse_harmonic_yield(batch: int, nt: int, dt: float, omega0: float, h_lo: flo
     _check(load().tdse_harmonic_yield(batch, nt, dt, omega0, h_lo, h_hi, _ptr(accel),
                                       _ptr(row_weight), _ptr(work), _ptr(yield_out),
                                       _ptr(accel_bar), _stream(stream)), "tdse_harmonic_yield")
+
+
+def tdse_band_dft(batch: int, nt: int, dt: float, omega0: float, h_lo: float, h_hi: float, accel,
+                  amp, stream=None):
+    _check(load().tdse_band_dft(batch, nt, dt, omega0, h_lo, h_hi, _ptr(accel), _ptr(amp),
+                                _stream(stream)), "tdse_band_dft")
+
+
+def tdse_band_dft_adjoint(batch: int, nt: int, dt: float, omega0: float, h_lo: float, h_hi: float,
+                          amp_bar, accel_bar, stream=None):
+    _check(load().tdse_band_dft_adjoint(batch, nt, dt, omega0, h_lo, h_hi, _ptr(amp_bar),
+                                        _ptr(accel_bar), _stream(stream)), "tdse_band_dft_adjoint")
+
+
+def tdse_far_field(rho_src, z_src, weights, kwave, amp, rho_obs, z_obs: float, field, stream=None,
+                   adjoint: bool = False):
+    """field = far field of amp (adjoint=False), or amp_bar from field_bar
+    (adjoint=True: `amp` is field_bar, `field` receives amp_bar)."""
+    fn = load().tdse_far_field_adjoint if adjoint else load().tdse_far_field
+    _check(fn(int(rho_src.numel()), int(z_src.numel()), _ptr(rho_src), _ptr(z_src), _ptr(weights),
+              int(kwave.numel()), _ptr(kwave), _ptr(amp), int(rho_obs.numel()), _ptr(rho_obs),
+              float(z_obs), _ptr(field), _stream(stream)),
+           "tdse_far_field_adjoint" if adjoint else "tdse_far_field")

@@ -1684,4 +1684,93 @@ tdse_status tdse_harmonic_yield(int32_t batch, int32_t nt, double dt, double ome
     return TDSE_OK;
 }
 
+tdse_status tdse_band_dft(int32_t batch, int32_t nt, double dt, double omega0, double h_lo,
+                          double h_hi, const double* accel, double* amp, void* stream)
+{
+    g_last_error.clear();
+    if (batch < 1 || nt < 1 || !(dt > 0.0) || !(omega0 > 0.0) || !(h_hi >= h_lo) || h_lo < 0.0)
+        return fail(TDSE_E_INVALID, "need batch >= 1, nt >= 1, dt > 0, omega0 > 0, 0 <= h_lo <= h_hi");
+    if (!accel || !amp) return fail(TDSE_E_INVALID, "accel and amp are required");
+    if (!aligned16(accel) || !aligned16(amp)) return fail(TDSE_E_INVALID, "device pointers must be 16-byte aligned");
+    YieldArgs a{};
+    band_of(nt, dt, omega0, h_lo, h_hi, &a.k_lo, &a.nk);
+    a.batch = batch;
+    a.nt = nt;
+    a.dt = dt;
+    a.accel = accel;
+    a.amp = amp;
+    HIP_TRY(launch_band_dft(a, reinterpret_cast<hipStream_t>(stream)));
+    return TDSE_OK;
+}
+
+tdse_status tdse_band_dft_adjoint(int32_t batch, int32_t nt, double dt, double omega0, double h_lo,
+                                  double h_hi, const double* amp_bar, double* accel_bar, void* stream)
+{
+    g_last_error.clear();
+    if (batch < 1 || nt < 1 || !(dt > 0.0) || !(omega0 > 0.0) || !(h_hi >= h_lo) || h_lo < 0.0)
+        return fail(TDSE_E_INVALID, "need batch >= 1, nt >= 1, dt > 0, omega0 > 0, 0 <= h_lo <= h_hi");
+    if (!amp_bar || !accel_bar) return fail(TDSE_E_INVALID, "amp_bar and accel_bar are required");
+    if (!aligned16(amp_bar) || !aligned16(accel_bar))
+        return fail(TDSE_E_INVALID, "device pointers must be 16-byte aligned");
+    BandAdjArgs a{};
+    band_of(nt, dt, omega0, h_lo, h_hi, &a.k_lo, &a.nk);
+    a.batch = batch;
+    a.nt = nt;
+    a.dt = dt;
+    a.amp_bar = amp_bar;
+    a.accel_bar = accel_bar;
+    HIP_TRY(launch_band_adjoint(a, reinterpret_cast<hipStream_t>(stream)));
+    return TDSE_OK;
+}
+
+static tdse_status far_field_common(int32_t n_rho, int32_t n_z, const double* rho_src,
+                                    const double* z_src, const double* weights, int32_t nk,
+                                    const double* kwave, const double* in, int32_t n_obs,
+                                    const double* rho_obs, double z_obs, double* out, bool adjoint,
+                                    void* stream)
+{
+    g_last_error.clear();
+    if (n_rho < 1 || n_z < 1 || nk < 1 || n_obs < 1 || (int64_t)n_rho * n_z > (1 << 26))
+        return fail(TDSE_E_INVALID, "need n_rho, n_z, nk, n_obs >= 1 and n_rho * n_z <= 2^26");
+    if (!std::isfinite(z_obs)) return fail(TDSE_E_INVALID, "z_obs must be finite");
+    const void* ptrs[] = {rho_src, z_src, weights, kwave, in, rho_obs, out};
+    for (const void* q : ptrs)
+        if (!q) return fail(TDSE_E_INVALID, "every array is required");
+    if (!aligned16(in) || !aligned16(out)) return fail(TDSE_E_INVALID, "complex arrays must be 16-byte aligned");
+    FarArgs a{};
+    a.n_rho = n_rho;
+    a.n_z = n_z;
+    a.n_obs = n_obs;
+    a.nk = nk;
+    a.rho_src = rho_src;
+    a.z_src = z_src;
+    a.weights = weights;
+    a.kwave = kwave;
+    a.rho_obs = rho_obs;
+    a.z_obs = z_obs;
+    a.in = in;
+    a.out = out;
+    HIP_TRY(launch_far_field(a, adjoint, reinterpret_cast<hipStream_t>(stream)));
+    return TDSE_OK;
+}
+
+tdse_status tdse_far_field(int32_t n_rho, int32_t n_z, const double* rho_src, const double* z_src,
+                           const double* weights, int32_t nk, const double* kwave, const double* amp,
+                           int32_t n_obs, const double* rho_obs, double z_obs, double* field,
+                           void* stream)
+{
+    return far_field_common(n_rho, n_z, rho_src, z_src, weights, nk, kwave, amp, n_obs, rho_obs,
+                            z_obs, field, false, stream);
+}
+
+tdse_status tdse_far_field_adjoint(int32_t n_rho, int32_t n_z, const double* rho_src,
+                                   const double* z_src, const double* weights, int32_t nk,
+                                   const double* kwave, const double* field_bar, int32_t n_obs,
+                                   const double* rho_obs, double z_obs, double* amp_bar,
+                                   void* stream)
+{
+    return far_field_common(n_rho, n_z, rho_src, z_src, weights, nk, kwave, field_bar, n_obs,
+                            rho_obs, z_obs, amp_bar, true, stream);
+}
+
 }  // extern "C"

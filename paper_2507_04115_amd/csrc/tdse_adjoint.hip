@@ -495,6 +495,13 @@ __global__ void __launch_bounds__(256) band_grad_kernel(YieldArgs a)
     a.abar[(size_t)b * M + i] = wgt * 2.0 * dw * a.dt * sw * sw * s;
 }
 
+hipError_t launch_band_dft(const YieldArgs& a, hipStream_t st)
+{
+    if (a.nk < 1) return hipSuccess;
+    hipLaunchKernelGGL(band_dft_kernel, dim3(a.nk, a.batch), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_yield(const YieldArgs& a, hipStream_t st)
 {
     if (a.nk > 0) {

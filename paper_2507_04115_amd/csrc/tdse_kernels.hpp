@@ -71,6 +71,28 @@ struct GsArgs {
     int32_t* iters;         // [ncand]; negative when not converged
 };
 
+// Far field of the medium (tdse_far_field) and its adjoint.
+struct FarArgs {
+    int32_t n_rho, n_z, n_obs, nk;
+    const double* rho_src;  // [n_rho]
+    const double* z_src;    // [n_z]
+    const double* weights;  // [n_rho * n_z], source p = i * n_z + j
+    const double* kwave;    // [nk]
+    const double* rho_obs;  // [n_obs]
+    double z_obs;
+    const double* in;       // forward: S [P][nk] complex; adjoint: E_bar [n_obs][nk]
+    double* out;            // forward: E [n_obs][nk] complex; adjoint: S_bar [P][nk]
+};
+
+// Adjoint of the band spectrum: accel_bar from amp_bar (tdse_band_dft_adjoint).
+struct BandAdjArgs {
+    int32_t batch, nt;
+    double dt;
+    int32_t k_lo, nk;
+    const double* amp_bar;  // [batch][nk] complex
+    double* accel_bar;      // [batch][nt+1]
+};
+
 struct YieldArgs {
     int32_t batch, nt;
     double dt, omega0, h_lo, h_hi;
@@ -81,6 +103,9 @@ struct YieldArgs {
     double* yield;
     double* abar;
 };
+
+hipError_t launch_far_field(const FarArgs& a, bool adjoint, hipStream_t st);
+hipError_t launch_band_adjoint(const BandAdjArgs& a, hipStream_t st);
 
 hipError_t launch_build_tables(const SizeClass* d_classes, const TableParams* d_params, int ncls,
                                double* d_metrics, cd* d_scratch, int max_t, hipStream_t st);
@@ -109,5 +134,6 @@ hipError_t launch_compact_rows(const double* abar, int nt, const int32_t* order_
                                int32_t* order_out, int32_t* counters, hipStream_t st);
 hipError_t launch_ground_state(int C, const GsArgs& a, int T, hipStream_t st);
 hipError_t launch_yield(const YieldArgs& a, hipStream_t st);
+hipError_t launch_band_dft(const YieldArgs& a, hipStream_t st);
 
 }  // namespace tdse
