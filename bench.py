@@ -93,6 +93,41 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def bench_far_field(torch, L, ti, dev, stream):
+    """Far field of the full-volume focus (64 r x 256 z sources) over the
+    H25-H35 band of its 1030 nm, 30-cycle pulse, at 64 observation radii,
+    from synthetic source spectra (the sum costs the same for any values)."""
+    w = ti.cfg5_volume(64, 256)
+    k_lo, nk = L.tdse_harmonic_band(w.nt, w.dt, w.omega, 25, 35)
+    omega_si = 2 * np.pi * (k_lo + np.arange(nk)) / ((w.nt + 1) * w.dt) / 2.4188843265857e-17
+    r = np.unique(w.meta["r_um"]) * 1e-6
+    z = np.unique(w.meta["z_um"]) * 1e-6
+    wts = np.outer(r * (r[1] - r[0]), np.full(len(z), z[1] - z[0])).ravel()
+    g = torch.Generator(device="cpu").manual_seed(7)
+    amp = torch.randn(len(r) * len(z), nk, dtype=torch.complex128, generator=g).to(dev)
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+    geo = (t(r), t(z), t(wts), t(omega_si / 299792458.0))
+    ro = t(np.linspace(0.0, 5e-3, 64))
+    field = torch.empty(64, nk, dtype=torch.complex128, device=dev)
+    amp_bar = torch.empty_like(amp)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for adj in (False, True):
+        src, dst = (field, amp_bar) if adj else (amp, field)
+        L.tdse_far_field(*geo, src, ro, 1.0, dst, adjoint=adj)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(5):
+            L.tdse_far_field(*geo, src, ro, 1.0, dst, adjoint=adj)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[adj] = e0.elapsed_time(e1) / 5
+    terms = float(len(r) * len(z) * nk * 64)
+    return {"geometry": f"{len(r)} r x {len(z)} z sources, {nk} bins (H25-H35), 64 observation radii",
+            "ms": res[False], "adjoint_ms": res[True], "terms": terms,
+            "terms_per_s": terms / (res[False] * 1e-3)}
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -115,6 +150,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-far-field", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default lane layouts instead of timing them at plan creation")
@@ -285,6 +321,12 @@ def main():
         log(f"adjoint: {ms[True] * 1e-3:.3f} s per gradient with stored checkpoints, "
             f"{ms[False] * 1e-3:.3f} s recomputing them ({wa.batch} systems)")
         plan_a.close()
+
+    # ------------------------------------------------------------ far field
+    if not args.no_far_field:
+        out["far_field"] = bench_far_field(torch, L, ti, dev, stream)
+        log(f"far field: {out['far_field']['ms']:.2f} ms, adjoint {out['far_field']['adjoint_ms']:.2f} ms "
+            f"({out['far_field']['terms']:.3g} source-observation-frequency terms)")
 
     # ------------------------------------------------------- CPU baseline
     if not args.no_cpu:
