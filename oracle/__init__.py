@@ -308,3 +308,36 @@ def far_field_adjoint(field_bar, rho_src, z_src, weights, kw, rho_obs, z_obs):
     K = far_field_kernel(rho_src, z_src, weights, kw, rho_obs, z_obs)
     fb = np.asarray(field_bar, np.complex128)
     return np.stack([np.conj(K[q]).T @ fb[:, q] for q in range(len(kw))], axis=1)
+
+
+# --------------------------------------------------------------------------
+# electron energy distribution (resolvent of the field-free Hamiltonian)
+# --------------------------------------------------------------------------
+
+def energy_spectrum(psi, energies, eps, dx, a, z=1.0):
+    """P(E) = (eps / pi) dx sum_j |phi_j|^2 with (E - i eps - H0) phi = psi
+    (section "Analysing the Time-Dependent Electron Energy Density": the
+    resolvent norm, the inverse taken in the solver's Numerov form).  With
+    H0 = M2^{-1}(-D2/2) + V the system is multiplied by M2:
+      ((E - i eps) M2 - A) phi = M2 psi,   A = -D2/2 + M2 diag(V),
+    a tridiagonal system solved here with scipy's banded solver.  The factor
+    1/(pi eps) makes int P dE equal dx sum |psi|^2."""
+    from scipy.linalg import solve_banded
+
+    psi = np.asarray(psi, np.complex128)
+    n = len(psi)
+    _, v, _ = grid(n, dx, a, z)
+    mpsi = 10.0 * psi
+    mpsi[1:] += psi[:-1]
+    mpsi[:-1] += psi[1:]
+    mpsi /= 12.0
+    out = np.empty(len(energies))
+    for q, e in enumerate(energies):
+        ec = e - 1j * eps
+        ab = np.zeros((3, n), np.complex128)
+        ab[1] = ec * 10.0 / 12.0 - (1.0 / dx ** 2 + 10.0 / 12.0 * v)     # T[j, j]
+        ab[0, 1:] = ec / 12.0 + 0.5 / dx ** 2 - v[1:] / 12.0           # T[j, j+1]
+        ab[2, :-1] = ec / 12.0 + 0.5 / dx ** 2 - v[:-1] / 12.0         # T[j+1, j]
+        phi = solve_banded((1, 1), ab, mpsi)
+        out[q] = eps / np.pi * dx * np.sum(np.abs(phi) ** 2)
+    return out

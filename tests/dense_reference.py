@@ -3,7 +3,8 @@
 Independent of the oracle's tridiagonal/Thomas formulation: here the
 Hamiltonian is assembled as the dense symmetric matrix
 H = M2^{-1}(-D2/2) + V (the operator whose Cayley transform the paper's
-Crank-Nicolson step is, see the design notes) and the propagators are built
+Crank-Nicolson step is: L^{-1} R = (I + i dt H / 2)^{-1} (I - i dt H / 2)
+after multiplying both matrices by M2^{-1}) and the propagators are built
 with numpy/scipy (solve, eigh, expm).
 """
 import numpy as np
