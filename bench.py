@@ -93,6 +93,36 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def bench_spectrum(torch, L, plan, w, dev, stream):
+    """Electron energy distribution of every system of the batch at 256
+    energies in [-0.7, 3] a.u. (resolution 0.01), from the plan's ground
+    states (the solve costs the same for any state)."""
+    n = w.n_per[0]
+    gs = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    plan.ground_state(n, gs)
+    if len(set(w.n_per)) != 1:
+        return None
+    psi = gs.repeat(w.batch).contiguous()
+    energies = torch.linspace(-0.7, 3.0, 256, dtype=torch.float64, device=dev)
+    spec = torch.empty(w.batch, 256, dtype=torch.float64, device=dev)
+    work = torch.empty(32 * n * 65536 // 8, dtype=torch.float64, device=dev)
+    L.tdse_plan_energy_spectrum(plan, psi, energies, 0.01, spec, work)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(3):
+        L.tdse_plan_energy_spectrum(plan, psi, energies, 0.01, spec, work)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    solves = float(w.batch * 256)
+    del work
+    return {"energies": 256, "eps": 0.01, "ms": ms, "solves": solves,
+            "grid_point_solves_per_s": solves * n / (ms * 1e-3),
+            "hbm_bytes_per_grid_point": 64, "note": "one lane per (system, energy): Thomas "
+            "elimination through a 32 B/point workspace (written, then read back)"}
+
+
 def bench_far_field(torch, L, ti, dev, stream):
     """Far field of the full-volume focus (64 r x 256 z sources) over the
     H25-H35 band of its 1030 nm, 30-cycle pulse, at 64 observation radii,
@@ -151,6 +181,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-far-field", action="store_true")
+    ap.add_argument("--no-spectrum", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default lane layouts instead of timing them at plan creation")
@@ -321,6 +352,12 @@ def main():
         log(f"adjoint: {ms[True] * 1e-3:.3f} s per gradient with stored checkpoints, "
             f"{ms[False] * 1e-3:.3f} s recomputing them ({wa.batch} systems)")
         plan_a.close()
+
+    # ------------------------------------------------- energy distribution
+    if not args.no_spectrum:
+        out["energy_spectrum"] = bench_spectrum(torch, L, plan, w, dev, stream)
+        log(f"energy spectrum: {out['energy_spectrum']['ms']:.2f} ms for "
+            f"{out['energy_spectrum']['solves']:.0f} (system, energy) solves")
 
     # ------------------------------------------------------------ far field
     if not args.no_far_field:

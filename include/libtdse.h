@@ -226,6 +226,28 @@ tdse_status tdse_adjoint_batch_stored(tdse_plan plan, uint64_t generation, const
                                       const double* accel_bar, double* grad_E, int32_t* sys_status,
                                       void* stream);
 
+/* ------------------------------------------------- energy distribution */
+/* Electron energy distribution of every system's wavefunction (section
+ * "Analysing the Time-Dependent Electron Energy Density"):
+ *   spectrum[b][e] = (eps/pi) dx sum_j |phi_j|^2,  (E_e - i eps - H0) phi = psi_b,
+ * H0 = M2^{-1}(-D2/2) + V the field-free Hamiltonian of the solver's Numerov
+ * scheme (the inverse taken in that form: ((E - i eps) M2 - A) phi = M2 psi).
+ * The factor 1/(pi eps) makes int P dE = dx sum |psi|^2, so the integral
+ * over E > 0 is the ionisation probability.  Applied to psi_final of a
+ * propagation (or to the states of a propagation split into segments) it
+ * gives the time-dependent distribution.
+ *   psi       dev ragged complex (tdse_plan_psi_offsets)
+ *   energies  dev [n_energy];  eps > 0 (the resolution)
+ *   spectrum  dev [batch][n_energy]
+ *   work      dev scratch of work_bytes bytes, at least 64 * 32 * n_max
+ *             (n_max = the plan's largest n); 32 n_max bytes hold one
+ *             (system, energy) solve in flight, and about 64k of them keep
+ *             the GPU busy.  Contents on return are undefined.
+ * Asynchronous on `stream`; allocates nothing. */
+tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t n_energy,
+                                      const double* energies, double eps, double* spectrum,
+                                      void* work, size_t work_bytes, void* stream);
+
 /* ------------------------------------------------------- harmonic yield */
 /* Windowed harmonic yield of each series and its gradient.  With
  * w_i = sin^2(pi i/nt), A_k = dt sum_i w_i a_i exp(-i omega_k t_i),

@@ -75,6 +75,7 @@ _PROTOS = {
     "tdse_adjoint_batch_stored": (_i32, [_vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp]),
     "tdse_harmonic_band": (_i32, [_i32, _d, _d, _d, _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "tdse_harmonic_yield": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tdse_plan_energy_spectrum": (_i32, [_vp, _vp, _i32, _vp, _d, _vp, _vp, ctypes.c_size_t, _vp]),
     "tdse_band_dft": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
     "tdse_band_dft_adjoint": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
     "tdse_far_field": (_i32, [_i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _d, _vp, _vp]),
@@ -294,3 +295,13 @@ def tdse_far_field(rho_src, z_src, weights, kwave, amp, rho_obs, z_obs: float, f
               int(kwave.numel()), _ptr(kwave), _ptr(amp), int(rho_obs.numel()), _ptr(rho_obs),
               float(z_obs), _ptr(field), _stream(stream)),
            "tdse_far_field_adjoint" if adjoint else "tdse_far_field")
+
+
+def tdse_plan_energy_spectrum(plan: Plan, psi, energies, eps: float, spectrum, work, stream=None):
+    """spectrum[b][e] = electron energy distribution of psi_b at energies[e]
+    (work: a device scratch tensor, its byte size is passed along)."""
+    _check(load().tdse_plan_energy_spectrum(plan.handle, _ptr(psi), int(energies.numel()),
+                                            _ptr(energies), float(eps), _ptr(spectrum), _ptr(work),
+                                            work.numel() * work.element_size(), _stream(stream)),
+           "tdse_plan_energy_spectrum")
+

@@ -1684,6 +1684,39 @@ tdse_status tdse_harmonic_yield(int32_t batch, int32_t nt, double dt, double ome
     return TDSE_OK;
 }
 
+tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t n_energy,
+                                      const double* energies, double eps, double* spectrum,
+                                      void* work, size_t work_bytes, void* stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
+    if (n_energy < 1 || !(eps > 0.0) || !std::isfinite(eps))
+        return fail(TDSE_E_INVALID, "need n_energy >= 1 and a finite eps > 0");
+    if (!psi || !energies || !spectrum || !work)
+        return fail(TDSE_E_INVALID, "psi, energies, spectrum and work are required");
+    if (!aligned16(psi) || !aligned16(work)) return fail(TDSE_E_INVALID, "psi and work must be 16-byte aligned");
+    const int n_max = *std::max_element(plan->n_per.begin(), plan->n_per.end());
+    const size_t per_lane = 32 * (size_t)n_max;
+    const int64_t items = (int64_t)plan->batch * n_energy;
+    int64_t lanes = (int64_t)std::min<size_t>(work_bytes / per_lane, (size_t)1 << 20);
+    if (lanes < kWave)
+        return fail(TDSE_E_INVALID, "work must hold at least %zu bytes (64 lanes of 32 n_max)", kWave * per_lane);
+    lanes = std::min<int64_t>(lanes, (items + kWave - 1) / kWave * kWave);
+    SpecArgs a{};
+    a.classes = plan->cls.d;
+    a.sys = plan->d_sys;
+    a.batch = plan->batch;
+    a.n_energy = n_energy;
+    a.psi = psi;
+    a.energies = energies;
+    a.eps = eps;
+    a.out = spectrum;
+    a.work = reinterpret_cast<cd*>(work);
+    a.lanes = lanes;
+    HIP_TRY(launch_energy_spectrum(a, reinterpret_cast<hipStream_t>(stream)));
+    return TDSE_OK;
+}
+
 tdse_status tdse_band_dft(int32_t batch, int32_t nt, double dt, double omega0, double h_lo,
                           double h_hi, const double* accel, double* amp, void* stream)
 {

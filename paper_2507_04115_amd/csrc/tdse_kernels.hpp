@@ -93,6 +93,19 @@ struct BandAdjArgs {
     double* accel_bar;      // [batch][nt+1]
 };
 
+// Electron energy distribution (tdse_plan_energy_spectrum).
+struct SpecArgs {
+    const SizeClass* classes;
+    const SysDesc* sys;
+    int32_t batch, n_energy;
+    const double* psi;       // ragged complex, plan offsets
+    const double* energies;  // [n_energy]
+    double eps;
+    double* out;             // [batch][n_energy]
+    cd* work;                // [n_max][lanes] pairs (c', d')
+    int64_t lanes;
+};
+
 struct YieldArgs {
     int32_t batch, nt;
     double dt, omega0, h_lo, h_hi;
@@ -105,6 +118,7 @@ struct YieldArgs {
 };
 
 hipError_t launch_far_field(const FarArgs& a, bool adjoint, hipStream_t st);
+hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st);
 hipError_t launch_band_adjoint(const BandAdjArgs& a, hipStream_t st);
 
 hipError_t launch_build_tables(const SizeClass* d_classes, const TableParams* d_params, int ncls,

@@ -1,0 +1,71 @@
+"""GPU parity of the electron energy distribution (tdse_plan_energy_spectrum)
+against the oracle: a ragged batch of random states, the Lorentzian of an
+eigenstate, and a workspace that holds only one wavefront of solves (each lane
+then takes many (system, energy) items)."""
+import numpy as np
+import pytest
+
+import oracle
+import tdse_inputs as ti
+
+pytestmark = pytest.mark.gpu
+
+A = 1.1891671
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0")
+
+
+def _c2d(psi):
+    return np.ascontiguousarray(np.asarray(psi, np.complex128)).view(np.float64)
+
+
+@pytest.mark.parametrize("lanes", [None, 64])
+def test_energy_spectrum_matches_oracle(lib, torch_dev, lanes):
+    torch, dev = torch_dev
+    ns = [100, 256, 300, 777]
+    dx, eps = 0.2, 0.02
+    p = lib.make_params(dx, 0.05, A, 10)
+    plan = lib.Plan(p, ns)
+    psis = [ti.random_state(n, 31 + i, width=min(8.0, n * dx / 8), k0=0.5, dx=dx)
+            for i, n in enumerate(ns)]
+    psi = torch.tensor(np.concatenate([_c2d(x) for x in psis]), device=dev)
+    energies = np.linspace(-0.7, 2.5, 41)
+    E = torch.tensor(energies, device=dev)
+    out = torch.empty(len(ns), len(energies), dtype=torch.float64, device=dev)
+    nbytes = 32 * max(ns) * (lanes or 65536)
+    work = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+    print(f"energy spectrum ns={ns} energies={len(energies)} work lanes={lanes}", flush=True)
+    lib.tdse_plan_energy_spectrum(plan, psi, E, eps, out, work)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for b, n in enumerate(ns):
+        ref = oracle.energy_spectrum(psis[b], energies, eps, dx, A)
+        err = np.max(np.abs(got[b] - ref)) / np.max(ref)
+        print(f"  n={n}: max err / max P = {err:.3e}", flush=True)
+        assert err < 1e-10
+    plan.close()
+
+
+def test_eigenstate_lorentzian_and_small_workspace(lib, torch_dev):
+    torch, dev = torch_dev
+    n, dx, eps = 512, 0.2, 1e-3
+    p = lib.make_params(dx, 0.05, A, 10)
+    plan = lib.Plan(p, [n])
+    psi = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    e_g = plan.ground_state(n, psi)
+    E = torch.tensor([e_g, e_g + eps, e_g + 3 * eps], device=dev)
+    out = torch.empty(1, 3, dtype=torch.float64, device=dev)
+    work = torch.empty(32 * n * 64 // 8, dtype=torch.float64, device=dev)
+    lib.tdse_plan_energy_spectrum(plan, psi, E, eps, out, work)
+    torch.cuda.synchronize()
+    lor = 1.0 / (np.pi * eps) / (1.0 + np.array([0.0, 1.0, 9.0]))
+    assert np.max(np.abs(out.cpu().numpy()[0] - lor) / lor) < 1e-6
+    with pytest.raises(lib.TDSEError):
+        lib.tdse_plan_energy_spectrum(plan, psi, E, eps, out, work[: 32 * n * 63 // 8])
+    plan.close()
