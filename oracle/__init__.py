@@ -341,3 +341,29 @@ def energy_spectrum(psi, energies, eps, dx, a, z=1.0):
         phi = solve_banded((1, 1), ab, mpsi)
         out[q] = eps / np.pi * dx * np.sum(np.abs(phi) ** 2)
     return out
+
+
+# --------------------------------------------------------------------------
+# driver-field resampling (Fourier zero-padding)
+# --------------------------------------------------------------------------
+
+def resample_field(e_coarse, dt_coarse, dt, nt):
+    """Fine samples E(i dt), i = 0..nt, of fields given at M coarse samples
+    (spacing dt_coarse, the first one taken as t = 0: the time-axis shift of
+    section "1D-TSDE Implementation (CTDSE)"), by Fourier zero-padding: the
+    trigonometric interpolant of period T = M dt_coarse,
+      E(t) = (1/M) [X_0 + sum_{0<k<M/2} 2 Re(X_k exp(2 pi i k t / T))
+                    + (M even) Re(X_{M/2}) cos(pi M t / T)],
+    with X the DFT of the coarse samples, evaluated directly.  T/dt must be
+    an integer (the padded length) no smaller than nt + 1."""
+    e = np.atleast_2d(np.asarray(e_coarse, np.float64))
+    M = e.shape[1]
+    T = M * dt_coarse
+    X = np.fft.rfft(e, axis=1)
+    t = dt * np.arange(nt + 1)
+    out = np.repeat(X[:, :1].real, nt + 1, axis=1)
+    for k in range(1, (M + 1) // 2):
+        out = out + 2.0 * np.real(X[:, k:k + 1] * np.exp(2j * np.pi * k * t / T)[None, :])
+    if M % 2 == 0:
+        out = out + X[:, M // 2:M // 2 + 1].real * np.cos(np.pi * M * t / T)[None, :]
+    return out / M
