@@ -367,3 +367,17 @@ def resample_field(e_coarse, dt_coarse, dt, nt):
     if M % 2 == 0:
         out = out + X[:, M // 2:M // 2 + 1].real * np.cos(np.pi * M * t / T)[None, :]
     return out / M
+
+
+def gabor(accel, dt, t_centres, omegas, sigma):
+    """Gabor transform of the source term: G[b, c, w] =
+    |dt sum_i a_b,i exp(-(t_i - t_c)^2 / (2 sigma^2)) exp(-i omega_w t_i)|^2,
+    t_i = i dt, summed over every sample."""
+    accel = np.atleast_2d(np.asarray(accel, np.float64))
+    t = dt * np.arange(accel.shape[1])
+    ph = np.exp(-1j * np.outer(omegas, t))                           # [W, nt+1]
+    out = np.empty((accel.shape[0], len(t_centres), len(omegas)))
+    for c, tc in enumerate(t_centres):
+        win = np.exp(-(t - tc) ** 2 / (2.0 * sigma ** 2))
+        out[:, c, :] = np.abs(dt * (accel * win) @ ph.T) ** 2
+    return out
