@@ -248,6 +248,19 @@ tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t
                                       const double* energies, double eps, double* spectrum,
                                       void* work, size_t work_bytes, void* stream);
 
+/* Gabor transform of the source term (section "Physical Examples &
+ * tutorials", the microscopic analysis: a joint time-frequency picture of
+ * the dipole acceleration):
+ *   out[b][c][w] = |dt sum_i accel[b][i] exp(-(t_i - t_c)^2 / (2 sigma^2)) exp(-i omega_w t_i)|^2
+ * with t_i = i dt, t_c = t_centres[c].  Samples farther than 9.5 sigma from
+ * t_c are skipped (window below 3e-20).
+ *   accel dev [batch][nt+1]; t_centres dev [n_tc] (n_tc <= 65535);
+ *   omegas dev [n_w] (n_w <= 1024); out dev [batch][n_tc][n_w]
+ * Asynchronous on `stream`. */
+tdse_status tdse_gabor(int32_t batch, int32_t nt, double dt, const double* accel, int32_t n_tc,
+                       const double* t_centres, int32_t n_w, const double* omegas, double sigma,
+                       double* out, void* stream);
+
 /* ------------------------------------------------------- harmonic yield */
 /* Windowed harmonic yield of each series and its gradient.  With
  * w_i = sin^2(pi i/nt), A_k = dt sum_i w_i a_i exp(-i omega_k t_i),

@@ -76,6 +76,7 @@ _PROTOS = {
     "tdse_harmonic_band": (_i32, [_i32, _d, _d, _d, _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "tdse_harmonic_yield": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tdse_plan_energy_spectrum": (_i32, [_vp, _vp, _i32, _vp, _d, _vp, _vp, ctypes.c_size_t, _vp]),
+    "tdse_gabor": (_i32, [_i32, _i32, _d, _vp, _i32, _vp, _i32, _vp, _d, _vp, _vp]),
     "tdse_band_dft": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
     "tdse_band_dft_adjoint": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
     "tdse_far_field": (_i32, [_i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _d, _vp, _vp]),
@@ -304,4 +305,12 @@ def tdse_plan_energy_spectrum(plan: Plan, psi, energies, eps: float, spectrum, w
                                             _ptr(energies), float(eps), _ptr(spectrum), _ptr(work),
                                             work.numel() * work.element_size(), _stream(stream)),
            "tdse_plan_energy_spectrum")
+
+
+def tdse_gabor(accel, dt: float, t_centres, omegas, sigma: float, out, stream=None):
+    """out[b][c][w] = Gabor transform of accel rows (see include/libtdse.h)."""
+    batch, n1 = accel.shape
+    _check(load().tdse_gabor(batch, n1 - 1, float(dt), _ptr(accel), int(t_centres.numel()),
+                             _ptr(t_centres), int(omegas.numel()), _ptr(omegas), float(sigma),
+                             _ptr(out), _stream(stream)), "tdse_gabor")
 

@@ -1717,6 +1717,31 @@ tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t
     return TDSE_OK;
 }
 
+tdse_status tdse_gabor(int32_t batch, int32_t nt, double dt, const double* accel, int32_t n_tc,
+                       const double* t_centres, int32_t n_w, const double* omegas, double sigma,
+                       double* out, void* stream)
+{
+    g_last_error.clear();
+    if (batch < 1 || nt < 1 || !(dt > 0.0) || n_tc < 1 || n_tc > 65535 || n_w < 1 ||
+        n_w > kGaborMaxFreqs || !(sigma > 0.0) || !std::isfinite(sigma))
+        return fail(TDSE_E_INVALID, "need batch, nt, dt > 0, 1 <= n_tc <= 65535, 1 <= n_w <= %d, sigma > 0",
+                    kGaborMaxFreqs);
+    if (!accel || !t_centres || !omegas || !out) return fail(TDSE_E_INVALID, "every array is required");
+    GaborArgs a{};
+    a.batch = batch;
+    a.nt = nt;
+    a.n_tc = n_tc;
+    a.n_w = n_w;
+    a.dt = dt;
+    a.sigma = sigma;
+    a.accel = accel;
+    a.t_centres = t_centres;
+    a.omegas = omegas;
+    a.out = out;
+    HIP_TRY(launch_gabor(a, reinterpret_cast<hipStream_t>(stream)));
+    return TDSE_OK;
+}
+
 tdse_status tdse_band_dft(int32_t batch, int32_t nt, double dt, double omega0, double h_lo,
                           double h_hi, const double* accel, double* amp, void* stream)
 {

@@ -106,6 +106,16 @@ struct SpecArgs {
     int64_t lanes;
 };
 
+// Gabor transform of the source term (tdse_gabor).
+struct GaborArgs {
+    int32_t batch, nt, n_tc, n_w;
+    double dt, sigma;
+    const double* accel;      // [batch][nt+1]
+    const double* t_centres;  // [n_tc]
+    const double* omegas;     // [n_w]
+    double* out;              // [batch][n_tc][n_w]
+};
+
 struct YieldArgs {
     int32_t batch, nt;
     double dt, omega0, h_lo, h_hi;
@@ -119,6 +129,8 @@ struct YieldArgs {
 
 hipError_t launch_far_field(const FarArgs& a, bool adjoint, hipStream_t st);
 hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st);
+hipError_t launch_gabor(const GaborArgs& a, hipStream_t st);
+constexpr int kGaborMaxFreqs = 1024;  // frequencies per call (4 per thread of 256)
 hipError_t launch_band_adjoint(const BandAdjArgs& a, hipStream_t st);
 
 hipError_t launch_build_tables(const SizeClass* d_classes, const TableParams* d_params, int ncls,

@@ -1,4 +1,5 @@
-// tdse_spectrum.hip -- electron energy distribution of a wavefunction.
+// tdse_spectrum.hip -- analysis of the microscopic response: electron energy
+// distribution of a wavefunction, Gabor transform of the source term.
 //
 // Section "Analysing the Time-Dependent Electron Energy Density": with the
 // field-free Hamiltonian H0 = M2^{-1}(-D2/2) + V of the solver's Numerov
@@ -74,6 +75,74 @@ __global__ void __launch_bounds__(256) energy_spectrum_kernel(SpecArgs a)
         }
         a.out[it] = eps / M_PI * dx * acc;
     }
+}
+
+// Gabor transform (section "Physical Examples & tutorials", microscopic
+// analysis): G[b][c][w] = |dt sum_i a_b,i exp(-(t_i - t_c)^2 / (2 sigma^2))
+// exp(-i omega_w t_i)|^2.  Samples farther than kGaborReach sigma from t_c
+// are skipped (their window is below 3e-20).  One workgroup per (t_c, row):
+// the windowed samples go through LDS in chunks, each thread accumulates up
+// to kGaborPerThread frequencies with a phase rotation started exactly at
+// every chunk.
+constexpr int kGaborChunk = 1024;
+constexpr int kGaborPerThread = 4;
+constexpr double kGaborReach = 9.5;
+
+__global__ void __launch_bounds__(256) gabor_kernel(GaborArgs a)
+{
+    __shared__ double buf[kGaborChunk];
+    const int c = blockIdx.x, b = blockIdx.y;
+    const double tc = a.t_centres[c];
+    const int64_t M = (int64_t)a.nt + 1;
+    const double reach = kGaborReach * a.sigma;
+    const int64_t i_lo = max((int64_t)0, (int64_t)floor((tc - reach) / a.dt));
+    const int64_t i_hi = min(M - 1, (int64_t)ceil((tc + reach) / a.dt));
+    const double* row = a.accel + (size_t)b * M;
+    const double inv2s2 = 1.0 / (2.0 * a.sigma * a.sigma);
+    double sre[kGaborPerThread], sim[kGaborPerThread], om[kGaborPerThread];
+#pragma unroll
+    for (int u = 0; u < kGaborPerThread; ++u) {
+        const int w = threadIdx.x + u * blockDim.x;
+        om[u] = w < a.n_w ? a.omegas[w] : 0.0;
+        sre[u] = sim[u] = 0.0;
+    }
+    for (int64_t i0 = i_lo; i0 <= i_hi; i0 += kGaborChunk) {
+        const int len = (int)min((int64_t)kGaborChunk, i_hi - i0 + 1);
+        __syncthreads();
+        for (int k = threadIdx.x; k < len; k += blockDim.x) {
+            const double t = a.dt * (double)(i0 + k) - tc;
+            buf[k] = row[i0 + k] * exp(-t * t * inv2s2);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kGaborPerThread; ++u) {
+            if (threadIdx.x + u * (int)blockDim.x >= a.n_w) continue;
+            double sp, cp, sr, cr;
+            sincos(-om[u] * a.dt * (double)i0, &sp, &cp);
+            sincos(-om[u] * a.dt, &sr, &cr);
+            cd ph = mkc(cp, sp);
+            const cd rot = mkc(cr, sr);
+            for (int k = 0; k < len; ++k) {
+                sre[u] = fma(buf[k], ph.re, sre[u]);
+                sim[u] = fma(buf[k], ph.im, sim[u]);
+                ph = cmul(ph, rot);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kGaborPerThread; ++u) {
+        const int w = threadIdx.x + u * blockDim.x;
+        if (w < a.n_w) {
+            const double re = a.dt * sre[u], im = a.dt * sim[u];
+            a.out[((size_t)b * a.n_tc + c) * a.n_w + w] = re * re + im * im;
+        }
+    }
+}
+
+hipError_t launch_gabor(const GaborArgs& a, hipStream_t st)
+{
+    hipLaunchKernelGGL(gabor_kernel, dim3(a.n_tc, a.batch), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st)

@@ -69,3 +69,22 @@ def test_eigenstate_lorentzian_and_small_workspace(lib, torch_dev):
     with pytest.raises(lib.TDSEError):
         lib.tdse_plan_energy_spectrum(plan, psi, E, eps, out, work[: 32 * n * 63 // 8])
     plan.close()
+
+
+def test_gabor_matches_oracle(lib, torch_dev):
+    """Gabor transform of random rows: centres at the edges and inside,
+    more frequencies than threads per workgroup."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(21)
+    dt, nt, sigma = 0.05, 6000, 8.0
+    a = rng.standard_normal((3, nt + 1))
+    tc = np.array([0.0, 40.0, 150.0, 299.0, nt * dt])
+    om = np.linspace(0.1, 6.0, 300)
+    out = torch.empty(3, len(tc), len(om), dtype=torch.float64, device=dev)
+    t = lambda x: torch.tensor(np.ascontiguousarray(x), device=dev)
+    lib.tdse_gabor(t(a), dt, t(tc), t(om), sigma, out)
+    torch.cuda.synchronize()
+    ref = oracle.gabor(a, dt, tc, om, sigma)
+    err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(ref)
+    print(f"gabor: max err / max G = {err:.3e}", flush=True)
+    assert err < 1e-10
