@@ -226,6 +226,17 @@ tdse_status tdse_adjoint_batch_stored(tdse_plan plan, uint64_t generation, const
                                       const double* accel_bar, double* grad_E, int32_t* sys_status,
                                       void* stream);
 
+/* The wavefunction of every system at step index * adjoint_k, as stored by
+ * the forward pass of generation `generation` on a plan created with
+ * TDSE_OPT_STORE_CHECKPOINTS (0 <= index <= nt / adjoint_k), copied into a
+ * ragged complex buffer (tdse_plan_psi_offsets).  With it the time-dependent
+ * analyses of the wavefunction (energy distribution, ground-state and
+ * volumetric populations) can be taken along a propagation.  Fails with
+ * TDSE_E_INVALID, before any launch, for a stale generation.  Asynchronous
+ * on `stream`. */
+tdse_status tdse_plan_stored_state(tdse_plan plan, uint64_t generation, int32_t index,
+                                   double* psi_out, void* stream);
+
 /* ------------------------------------------------- energy distribution */
 /* Electron energy distribution of every system's wavefunction (section
  * "Analysing the Time-Dependent Electron Energy Density"):

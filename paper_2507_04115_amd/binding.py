@@ -76,6 +76,7 @@ _PROTOS = {
     "tdse_harmonic_band": (_i32, [_i32, _d, _d, _d, _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "tdse_harmonic_yield": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tdse_plan_energy_spectrum": (_i32, [_vp, _vp, _i32, _vp, _d, _vp, _vp, ctypes.c_size_t, _vp]),
+    "tdse_plan_stored_state": (_i32, [_vp, ctypes.c_uint64, _i32, _vp, _vp]),
     "tdse_gabor": (_i32, [_i32, _i32, _d, _vp, _i32, _vp, _i32, _vp, _d, _vp, _vp]),
     "tdse_band_dft": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
     "tdse_band_dft_adjoint": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
@@ -313,4 +314,9 @@ def tdse_gabor(accel, dt: float, t_centres, omegas, sigma: float, out, stream=No
     _check(load().tdse_gabor(batch, n1 - 1, float(dt), _ptr(accel), int(t_centres.numel()),
                              _ptr(t_centres), int(omegas.numel()), _ptr(omegas), float(sigma),
                              _ptr(out), _stream(stream)), "tdse_gabor")
+
+
+def tdse_plan_stored_state(plan: Plan, generation: int, index: int, psi_out, stream=None):
+    _check(load().tdse_plan_stored_state(plan.handle, generation, index, _ptr(psi_out),
+                                         _stream(stream)), "tdse_plan_stored_state")
 

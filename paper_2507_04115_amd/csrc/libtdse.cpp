@@ -1684,6 +1684,24 @@ tdse_status tdse_harmonic_yield(int32_t batch, int32_t nt, double dt, double ome
     return TDSE_OK;
 }
 
+tdse_status tdse_plan_stored_state(tdse_plan plan, uint64_t generation, int32_t index,
+                                   double* psi_out, void* stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
+    if (!plan->d_store) return fail(TDSE_E_INVALID, "plan was created without TDSE_OPT_STORE_CHECKPOINTS");
+    if (generation == 0 || generation != plan->ckpt_gen)
+        return fail(TDSE_E_INVALID, "stored checkpoints are of generation %llu, not %llu",
+                    (unsigned long long)plan->ckpt_gen, (unsigned long long)generation);
+    const int nseg = plan->p.nt / plan->adjoint_k + 1;
+    if (index < 0 || index >= nseg) return fail(TDSE_E_INVALID, "index %d outside [0, %d)", index, nseg);
+    if (!psi_out || !aligned16(psi_out)) return fail(TDSE_E_INVALID, "psi_out must be a 16-byte aligned device pointer");
+    const int n_max = *std::max_element(plan->n_per.begin(), plan->n_per.end());
+    HIP_TRY(launch_stored_state(plan->cls.d, plan->d_sys, plan->batch, n_max, plan->d_store,
+                                plan->d_store_off, index, psi_out, reinterpret_cast<hipStream_t>(stream)));
+    return TDSE_OK;
+}
+
 tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t n_energy,
                                       const double* energies, double eps, double* spectrum,
                                       void* work, size_t work_bytes, void* stream)

@@ -327,6 +327,35 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
     }
 }
 
+// Copies checkpoint `index` (the state at step index * K) of every system out
+// of the per-system store into a ragged wavefunction buffer in natural point
+// order: point j = t C + k of the lane-chunked record [k][t].
+__global__ void __launch_bounds__(256) stored_state_kernel(const SizeClass* classes,
+                                                           const SysDesc* sys, const double* store,
+                                                           const int64_t* store_off, int index,
+                                                           double* psi_out)
+{
+    const int b = blockIdx.y;
+    const SysDesc d = sys[b];
+    const SizeClass& sc = classes[d.cls];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= sc.n) return;
+    const size_t np2 = 2 * (size_t)(sc.C + 2) * sc.T;
+    const double* rec = store + store_off[b] + np2 * (size_t)index;
+    const size_t at = 2 * ((size_t)(j % sc.C) * sc.T + (size_t)(j / sc.C));
+    psi_out[2 * (d.psi_off + j)] = rec[at];
+    psi_out[2 * (d.psi_off + j) + 1] = rec[at + 1];
+}
+
+hipError_t launch_stored_state(const SizeClass* classes, const SysDesc* sys, int batch, int n_max,
+                               const double* store, const int64_t* store_off, int index,
+                               double* psi_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(stored_state_kernel, dim3((n_max + 255) / 256, batch), dim3(256), 0, st,
+                       classes, sys, store, store_off, index, psi_out);
+    return hipGetLastError();
+}
+
 size_t adjoint_smem_bytes(int C, int T, int S, bool lds_tables)
 {
     return (lds_tables ? (size_t)kLdsTableBytes * C * T : 0) + S * sub_smem_bytes(T / kWave) +

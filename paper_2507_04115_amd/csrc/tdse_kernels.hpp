@@ -130,6 +130,9 @@ struct YieldArgs {
 hipError_t launch_far_field(const FarArgs& a, bool adjoint, hipStream_t st);
 hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st);
 hipError_t launch_gabor(const GaborArgs& a, hipStream_t st);
+hipError_t launch_stored_state(const SizeClass* classes, const SysDesc* sys, int batch, int n_max,
+                               const double* store, const int64_t* store_off, int index,
+                               double* psi_out, hipStream_t st);
 constexpr int kGaborMaxFreqs = 1024;  // frequencies per call (4 per thread of 256)
 hipError_t launch_band_adjoint(const BandAdjArgs& a, hipStream_t st);
 

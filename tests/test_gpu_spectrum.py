@@ -88,3 +88,45 @@ def test_gabor_matches_oracle(lib, torch_dev):
     err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(ref)
     print(f"gabor: max err / max G = {err:.3e}", flush=True)
     assert err < 1e-10
+
+
+def test_stored_states_along_a_propagation(lib, torch_dev):
+    """The states a storing forward pass keeps every K steps, copied out in
+    natural order, equal the oracle's state after the same number of steps;
+    from them the time-dependent ground-state population follows."""
+    torch, dev = torch_dev
+    ns = [256, 400]
+    dx, dt, om, nc, K = 0.4, 0.05, 0.25, 2, 37
+    nt = ti.n_steps(om, nc, dt)
+    efield = ti.sin2_pulse(np.array([0.1, 0.07]), om, nc, dt, nt=nt)
+    p = lib.make_params(dx, dt, 1.1, nt, mask_fraction=0.2)
+    plan = lib.Plan(p, ns, adjoint_k=K, options=lib.TDSE_OPT_STORE_CHECKPOINTS)
+    E = torch.tensor(efield, device=dev)
+    lib.tdse_propagate_batch(plan, E, None, torch.empty_like(E))
+    gen = plan.checkpoint_generation()
+    off = plan.psi_offsets()
+    psi = torch.empty(2 * sum(ns), dtype=torch.float64, device=dev)
+    for index in (0, 2, nt // K):
+        lib.tdse_plan_stored_state(plan, gen, index, psi)
+        torch.cuda.synchronize()
+        got = psi.cpu().numpy().view(np.complex128)
+        for b, n in enumerate(ns):
+            g0 = torch.empty(2 * n, dtype=torch.float64, device=dev)
+            plan.ground_state(n, g0)
+            psi0 = g0.cpu().numpy().view(np.complex128)
+            steps = index * K
+            if steps == 0:
+                ref = psi0
+            else:
+                ref = oracle.propagate(efield[b, :steps + 1], psi0, dx, dt, 1.1, mask_frac=0.2,
+                                       want_psi=True)["psi_final"]
+            r = float(np.linalg.norm(got[off[b]:off[b + 1]] - ref) / np.linalg.norm(ref))
+            pop = abs(dx * np.vdot(psi0, got[off[b]:off[b + 1]])) ** 2
+            print(f"  step {steps} n={n}: rel {r:.2e}, ground-state population {pop:.6f}", flush=True)
+            assert r < 1e-9
+    with pytest.raises(lib.TDSEError):
+        lib.tdse_plan_stored_state(plan, gen, nt // K + 1, psi)
+    lib.tdse_propagate_batch(plan, E, None, torch.empty_like(E))
+    with pytest.raises(lib.TDSEError):
+        lib.tdse_plan_stored_state(plan, gen, 0, psi)
+    plan.close()
