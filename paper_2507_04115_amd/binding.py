@@ -132,6 +132,24 @@ def _ptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
+def _f64(*ts):
+    """Raises unless every given tensor is float64 (complex128 for the
+    complex arrays is checked by the callers that take them)."""
+    import torch
+
+    for t in ts:
+        if t is not None and t.dtype != torch.float64:
+            raise TypeError(f"expected a float64 tensor, got {t.dtype}")
+
+
+def _c128(*ts):
+    import torch
+
+    for t in ts:
+        if t is not None and t.dtype not in (torch.complex128, torch.float64):
+            raise TypeError(f"expected a complex128 (or interleaved float64) tensor, got {t.dtype}")
+
+
 def _stream(stream) -> Optional[int]:
     import torch
 
@@ -241,8 +259,19 @@ class Plan:
         return e.value
 
 
+def _i32t(*ts):
+    import torch
+
+    for t in ts:
+        if t is not None and t.dtype != torch.int32:
+            raise TypeError(f"expected an int32 tensor, got {t.dtype}")
+
+
 def tdse_propagate_batch(plan: Plan, E, psi0, accel, xexp=None, norm=None, psi_final=None,
                          sys_status=None, stream=None):
+    _f64(E, accel, xexp, norm)
+    _c128(psi0, psi_final)
+    _i32t(sys_status)
     _check(load().tdse_propagate_batch(plan.handle, _ptr(E), _ptr(psi0), _ptr(accel), _ptr(xexp),
                                        _ptr(norm), _ptr(psi_final), _ptr(sys_status),
                                        _stream(stream)), "tdse_propagate_batch")
@@ -250,6 +279,9 @@ def tdse_propagate_batch(plan: Plan, E, psi0, accel, xexp=None, norm=None, psi_f
 
 def tdse_adjoint_batch(plan: Plan, E, psi0, accel_bar, grad_E, accel=None, sys_status=None,
                        stream=None):
+    _f64(E, accel_bar, grad_E, accel)
+    _c128(psi0)
+    _i32t(sys_status)
     _check(load().tdse_adjoint_batch(plan.handle, _ptr(E), _ptr(psi0), _ptr(accel_bar),
                                      _ptr(grad_E), _ptr(accel), _ptr(sys_status), _stream(stream)),
            "tdse_adjoint_batch")
@@ -257,6 +289,8 @@ def tdse_adjoint_batch(plan: Plan, E, psi0, accel_bar, grad_E, accel=None, sys_s
 
 def tdse_adjoint_batch_stored(plan: Plan, generation: int, E, accel_bar, grad_E, sys_status=None,
                               stream=None):
+    _f64(E, accel_bar, grad_E)
+    _i32t(sys_status)
     _check(load().tdse_adjoint_batch_stored(plan.handle, generation, _ptr(E), _ptr(accel_bar),
                                             _ptr(grad_E), _ptr(sys_status), _stream(stream)),
            "tdse_adjoint_batch_stored")
@@ -292,6 +326,8 @@ def tdse_far_field(rho_src, z_src, weights, kwave, amp, rho_obs, z_obs: float, f
                    adjoint: bool = False):
     """field = far field of amp (adjoint=False), or amp_bar from field_bar
     (adjoint=True: `amp` is field_bar, `field` receives amp_bar)."""
+    _f64(rho_src, z_src, weights, kwave, rho_obs)
+    _c128(amp, field)
     fn = load().tdse_far_field_adjoint if adjoint else load().tdse_far_field
     _check(fn(int(rho_src.numel()), int(z_src.numel()), _ptr(rho_src), _ptr(z_src), _ptr(weights),
               int(kwave.numel()), _ptr(kwave), _ptr(amp), int(rho_obs.numel()), _ptr(rho_obs),
@@ -302,6 +338,8 @@ def tdse_far_field(rho_src, z_src, weights, kwave, amp, rho_obs, z_obs: float, f
 def tdse_plan_energy_spectrum(plan: Plan, psi, energies, eps: float, spectrum, work, stream=None):
     """spectrum[b][e] = electron energy distribution of psi_b at energies[e]
     (work: a device scratch tensor, its byte size is passed along)."""
+    _f64(energies, spectrum)
+    _c128(psi)
     _check(load().tdse_plan_energy_spectrum(plan.handle, _ptr(psi), int(energies.numel()),
                                             _ptr(energies), float(eps), _ptr(spectrum), _ptr(work),
                                             work.numel() * work.element_size(), _stream(stream)),
@@ -310,6 +348,7 @@ def tdse_plan_energy_spectrum(plan: Plan, psi, energies, eps: float, spectrum, w
 
 def tdse_gabor(accel, dt: float, t_centres, omegas, sigma: float, out, stream=None):
     """out[b][c][w] = Gabor transform of accel rows (see include/libtdse.h)."""
+    _f64(accel, t_centres, omegas, out)
     batch, n1 = accel.shape
     _check(load().tdse_gabor(batch, n1 - 1, float(dt), _ptr(accel), int(t_centres.numel()),
                              _ptr(t_centres), int(omegas.numel()), _ptr(omegas), float(sigma),

@@ -59,7 +59,7 @@ def test_eigenstate_lorentzian_and_small_workspace(lib, torch_dev):
     plan = lib.Plan(p, [n])
     psi = torch.empty(2 * n, dtype=torch.float64, device=dev)
     e_g = plan.ground_state(n, psi)
-    E = torch.tensor([e_g, e_g + eps, e_g + 3 * eps], device=dev)
+    E = torch.tensor([e_g, e_g + eps, e_g + 3 * eps], dtype=torch.float64, device=dev)
     out = torch.empty(1, 3, dtype=torch.float64, device=dev)
     work = torch.empty(32 * n * 64 // 8, dtype=torch.float64, device=dev)
     lib.tdse_plan_energy_spectrum(plan, psi, E, eps, out, work)
