@@ -180,6 +180,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-far-field", action="store_true")
     ap.add_argument("--no-spectrum", action="store_true")
+    ap.add_argument("--adjoint-workload", default="adjoint", choices=["adjoint", "volume-axis"],
+                    help="256 systems x 4096 points (default) or the 256 on-axis systems of the "
+                         "full focal volume (8192 points, 213056 steps)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default lane layouts instead of timing them at plan creation")
@@ -303,7 +306,7 @@ def main():
 
     # ------------------------------------------------------------ adjoint
     if not args.no_adjoint:
-        wa = ti.cfg4_adjoint()
+        wa = ti.cfg4_adjoint() if args.adjoint_workload == "adjoint" else ti.cfg5_axis()
         pa = L.make_params(wa.dx, wa.dt, a_sc, wa.nt, mask_fraction=wa.mask_frac,
                            mask_power=wa.mask_pow)
         plan_a = L.Plan(pa, wa.n_per, adjoint_k=256,

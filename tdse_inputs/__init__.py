@@ -206,6 +206,18 @@ def cfg5_volume(nr: int = 64, nz: int = 256) -> Workload:
                     [8192] * (nr * nz), e0, ph, meta={"r_um": r, "z_um": z, "band": (25, 35)})
 
 
+def cfg5_axis(nz: int = 256) -> Workload:
+    """The on-axis (r = 0) points of the full focal volume: the systems whose
+    yields make up the volume's adjoint loss (the other rows get an all-zero
+    accel_bar and no reverse sweep)."""
+    w = cfg5_volume(64, nz)
+    keep = np.nonzero(w.meta["r_um"] == 0.0)[0]
+    return Workload(f"volume-axis-{len(keep)}-8192", w.dx, w.dt, w.omega, w.ncycles, w.nt,
+                    [w.n_per[i] for i in keep], w.e0[keep], w.phase[keep],
+                    meta={"r_um": w.meta["r_um"][keep], "z_um": w.meta["z_um"][keep],
+                          "band": (25, 35)})
+
+
 def probe_directions(shape, d: int, seed0: int = 250704117) -> np.ndarray:
     """Seeded N(0,1) direction number d for finite-difference checks."""
     return np.random.default_rng(seed0 + d).standard_normal(shape)
