@@ -307,7 +307,9 @@ def main():
     # ------------------------------------------------------------ adjoint
     if not args.no_adjoint:
         wa = ti.cfg4_adjoint() if args.adjoint_workload == "adjoint" else ti.cfg5_axis()
-        pa = L.make_params(wa.dx, wa.dt, a_sc, wa.nt, mask_fraction=wa.mask_frac,
+        a_adj = a_sc if wa.dx == w.dx else L.tdse_soft_core_for_ip(wa.ip, 2048, wa.dx, dtau=1.0,
+                                                                     tol=1e-13)[0]
+        pa = L.make_params(wa.dx, wa.dt, a_adj, wa.nt, mask_fraction=wa.mask_frac,
                            mask_power=wa.mask_pow)
         plan_a = L.Plan(pa, wa.n_per, adjoint_k=256,
                         options=L.TDSE_OPT_STORE_CHECKPOINTS |
