@@ -290,6 +290,48 @@ __device__ __forceinline__ double wave_sum(double x)
 }
 constexpr int kSumLane = kWave - 1;  // lane holding wave_sum's result
 
+// Halves of a and b exchanged (gfx950 v_permlane32_swap): returns
+// lo = [a lanes 0-31, b lanes 0-31] and hi = [a lanes 32-63, b lanes 32-63].
+__device__ __forceinline__ void swap_halves(double a, double b, double& lo, double& hi)
+{
+    const auto l = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    lo = __hiloint2double((int)h[0], (int)l[0]);
+    hi = __hiloint2double((int)h[1], (int)l[1]);
+}
+// Rows of 16 exchanged (v_permlane16_swap): even = [a r0, b r0, a r2, b r2],
+// odd = [a r1, b r1, a r3, b r3].
+__device__ __forceinline__ void swap_rows(double a, double b, double& even, double& odd)
+{
+    const auto l = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+    even = __hiloint2double((int)h[0], (int)l[0]);
+    odd = __hiloint2double((int)h[1], (int)l[1]);
+}
+
+// Three wavefront sums at once, as a reduce-scatter: the half and row
+// exchanges put the partial sums of a, c, b, c in rows 0, 1, 2, 3, then four
+// in-row DPP steps finish them.  Returns r with the total of a in lane 15,
+// of c in lane 31 (and 63) and of b in lane 47.  About a third of the
+// instructions of three wave_sum calls.
+constexpr int kSum3LaneA = 15, kSum3LaneB = 47, kSum3LaneC = 31;
+__device__ __forceinline__ double wave_sum3(double a, double b, double c)
+{
+    double lo, hi;
+    swap_halves(a, b, lo, hi);
+    const double p = lo + hi;  // lanes 0-31: a over lane pairs; 32-63: b
+    swap_halves(c, c, lo, hi);
+    const double q = lo + hi;  // c over lane pairs, twice
+    double even, odd;
+    swap_rows(p, q, even, odd);
+    double r = even + odd;     // rows: a, c, b, c, each over 4 lanes
+    r += dpp_d<0x111>(r);
+    r += dpp_d<0x112>(r);
+    r += dpp_d<0x114>(r);
+    r += dpp_d<0x118>(r);
+    return r;
+}
+
 // ------------------------------------------------------------ table views
 // om and dV/dx of a size class seen through LDS (staged once per workgroup,
 // shared by its systems) or directly in global memory.  The pivot factors q
@@ -779,7 +821,8 @@ __device__ __forceinline__ SubSmem carve_sub(char* base, int W)
 }
 
 // Per-lane partial sums of the observables of the current state, reduced over
-// the wavefront; lane 0 stores (sum V'|psi|^2, sum x|psi|^2, sum |psi|^2).
+// the wavefront; the lanes holding the totals store (sum V'|psi|^2,
+// sum x|psi|^2, sum |psi|^2).
 template <int C, class TV>
 __device__ __forceinline__ void observe(const cd (&v)[C], const TV& tb, int T,
                                         const LaneCtx& lc, double xs, double dx, double* slot)
@@ -793,15 +836,11 @@ __device__ __forceinline__ void observe(const cd (&v)[C], const TV& tb, int T,
         sv = fma(tb.dv(lc.b0 + 64 * k), p, sv);
         point_fence(sv, sn);
     }
-    double sx = fma(xs, sn, dx * sk);
-    sn = wave_sum(sn);
-    sx = wave_sum(sx);
-    sv = wave_sum(sv);
-    if (lc.lane == kSumLane) {
-        slot[lc.wave * 3 + 0] = sv;
-        slot[lc.wave * 3 + 1] = sx;
-        slot[lc.wave * 3 + 2] = sn;
-    }
+    const double sx = fma(xs, sn, dx * sk);
+    const double r = wave_sum3(sv, sx, sn);
+    if (lc.lane == kSum3LaneA) slot[lc.wave * 3 + 0] = r;
+    if (lc.lane == kSum3LaneB) slot[lc.wave * 3 + 1] = r;
+    if (lc.lane == kSum3LaneC) slot[lc.wave * 3 + 2] = r;
 }
 
 // Sums the per-wave partials of samples [a0, a1] in wave order and writes
