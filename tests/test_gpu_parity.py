@@ -184,6 +184,7 @@ def test_invalid_arguments_are_refused_before_any_launch(lib, torch_dev):
         assert str(ei.value)
         return ei.value.status
 
+    assert status_of(lambda: lib.Plan(p, [])) == lib.TDSE_E_INVALID               # empty batch
     assert status_of(lambda: lib.Plan(p, [8])) == lib.TDSE_E_INVALID              # n < 16
     assert status_of(lambda: lib.Plan(p, [20000])) == lib.TDSE_E_UNSUPPORTED      # n > 16384
     assert status_of(lambda: lib.Plan(p, [256], options=64)) == lib.TDSE_E_INVALID
@@ -379,6 +380,39 @@ def test_forward_uneven_wide_batch_sampled(lib, torch_dev):
         r = rel(out["accel"][b], ref["accel"])
         print(f"  system {b} n={ns[b]} layout={plan.layout(ns[b])}: accel rel-L2 {r:.3e}", flush=True)
         assert r < TOL_ACC
+    plan.close()
+
+
+def test_focus_batch_full_size_sampled(lib, torch_dev):
+    """The benchmark workload at its full size and in the benchmark's launch
+    configuration (1024 systems x 4096 points x 44093 steps, autotuned plan,
+    graph replay): two sampled systems (the hottest and one off-axis) against
+    the oracle over the whole pulse, every status clean, norms non-increasing."""
+    torch, dev = torch_dev
+    w = ti.cfg2_focus()
+    a_sc, _ = lib.tdse_soft_core_for_ip(w.ip, 2048, w.dx, dtau=1.0, tol=1e-13)
+    p = lib.make_params(w.dx, w.dt, a_sc, w.nt, mask_fraction=w.mask_frac, mask_power=w.mask_pow)
+    plan = lib.Plan(p, w.n_per, options=lib.TDSE_OPT_AUTOTUNE)
+    E = w.efield(xp={"device": dev}).contiguous()
+    acc = torch.empty_like(E)
+    nr = torch.empty_like(E)
+    st = torch.full((w.batch,), -1, dtype=torch.int32, device=dev)
+    print(f"focus full size: {w.batch} x {w.n_per[0]} x {w.nt}", flush=True)
+    lib.tdse_propagate_batch(plan, E, None, acc, None, nr, None, st)
+    torch.cuda.synchronize()
+    assert int((st != 0).sum()) == 0
+    assert bool((nr[:, 1:] <= nr[:, :-1] * (1 + 1e-12)).all())
+    psi0 = torch.empty(2 * w.n_per[0], dtype=torch.float64, device=dev)
+    plan.ground_state(w.n_per[0], psi0)
+    psi0 = psi0.cpu().numpy().view(np.complex128)
+    rows = [int(np.argmax(w.e0)), w.batch - 1]
+    ref = oracle.propagate_batch(E[rows].cpu().numpy(), [psi0, psi0], w.dx, w.dt, a_sc,
+                                 mask_frac=w.mask_frac, mask_pow=w.mask_pow, nthreads=2)
+    got = acc[rows].cpu().numpy()
+    for i, r in enumerate(rows):
+        e = rel(got[i], ref["accel"][i])
+        print(f"  system {r}: accel rel-L2 {e:.3e}", flush=True)
+        assert e < TOL_ACC
     plan.close()
 
 
