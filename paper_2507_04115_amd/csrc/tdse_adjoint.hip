@@ -144,14 +144,46 @@ __device__ __forceinline__ void add_source(cd (&kap)[C], cd& kgl, cd& kgr, const
     kgr = cadd(kgr, cscale(ci * (tb.dv(lc.ir()) + e), cconj(gr)));
 }
 
+// add_source and grad_partial in one pass that reads psi^i from its state
+// record one point at a time, for chunks too long to hold psi and the
+// costate in registers together.  Same operations in the same order, so the
+// results are those of the two calls above.
+template <int C, class TV>
+__device__ __forceinline__ void source_grad_streamed(cd (&kap)[C], cd& kgl, cd& kgr,
+                                                     const double* rec, int T, unsigned off,
+                                                     double ci, double e, const TV& tb,
+                                                     const LaneCtx& lc, bool want_grad, double xs,
+                                                     double dx, double* slot)
+{
+    const cd* b = reinterpret_cast<const cd*>(rec);
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const cd p = ld_lane(b + (size_t)k * T, off);
+        kap[k] = cadd(kap[k], cscale(ci * (tb.dv(lc.b0 + 64 * k) + e), cconj(p)));
+        const double im = fma(kap[k].re, p.im, kap[k].im * p.re);
+        s0 += im;
+        s1 = fma((double)k, im, s1);
+    }
+    const cd gl = ld_lane(b + (size_t)C * T, off), gr = ld_lane(b + (size_t)(C + 1) * T, off);
+    kgl = cadd(kgl, cscale(ci * (tb.dv(lc.il()) + e), cconj(gl)));
+    kgr = cadd(kgr, cscale(ci * (tb.dv(lc.ir()) + e), cconj(gr)));
+    if (want_grad) {
+        const double g = wave_sum(fma(xs, s0, dx * s1));
+        if (lc.lane == kSumLane) slot[lc.wave] = g;
+    }
+}
+
 }  // namespace
 
 template <int C, bool LDSTAB>
 __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
 {
     // the costate doubles the chunk state: pivot factors stay in registers
-    // only for 4 points per lane
+    // only for 4 points per lane; from 16 points the costate is parked in the
+    // slot while a segment is recomputed, and psi^i is read point by point
     constexpr bool kAdjQRegs = C <= 4;
+    constexpr bool kStream = C >= 16;
     extern __shared__ double smem_raw[];
     const SizeClass sc = uniform_load(a.classes + a.cls);
     const int T = sc.T, W = T / kWave, np = C * T;
@@ -202,6 +234,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
         double* ckpt = a.store ? a.store + uniform_load(a.store_off + p) : slot;
         double* n_row = ckpt + np2 * nseg;
         double* seg = a.store ? slot : n_row + ((nt + 2) & ~1);
+        double* kbuf = seg + np2 * (K + 1);  // parked costate (one record)
 
         // rows with an all-zero abar have a zero gradient and need no reverse sweep
         if (active && a.mode != kAdjForwardOnly)
@@ -277,6 +310,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
             const int s0 = sidx * K;
             const int s1 = min(s0 + K, nt);
             // recompute psi^{s0..s1} into the segment buffer
+            if constexpr (kStream) store_state<C>(kbuf, T, loff, kap, kgl, kgr);
             load_state<C>(ckpt + np2 * sidx, T, loff, v, gl, gr);
             store_state<C>(seg, T, loff, v, gl, gr);
             for (int i = s0; i < s1; ++i) {
@@ -285,12 +319,20 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
                                 sm.lds_f, sm.lds_b);
                 store_state<C>(seg + np2 * (i - s0 + 1), T, loff, v, gl, gr);
             }
+            if constexpr (kStream) load_state<C>(kbuf, T, loff, kap, kgl, kgr);
             if (!started) {
                 // kappa^nt = 2 abar_nt dx (V' + E_nt) conj(psi^nt); psi^nt = v
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
-                add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[nt] * dx, erow[nt], sv.tb, T,
-                              sv.lc);
-                if (nt > 0) grad_partial<C>(kap, v, sv.xs, dx, sv.lc, ring + ((nt - 1) % kRing) * W);
+                if constexpr (kStream) {
+                    source_grad_streamed<C>(kap, kgl, kgr, seg + np2 * (s1 - s0), T, loff,
+                                            2.0 * abar[nt] * dx, erow[nt], sv.tb, sv.lc, nt > 0,
+                                            sv.xs, dx, ring + ((nt > 0 ? nt - 1 : 0) % kRing) * W);
+                } else {
+                    add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[nt] * dx, erow[nt], sv.tb,
+                                  T, sv.lc);
+                    if (nt > 0)
+                        grad_partial<C>(kap, v, sv.xs, dx, sv.lc, ring + ((nt - 1) % kRing) * W);
+                }
                 started = true;
                 if (nt > 0 && (nt - 1) % kFlush == 0) {
                     __syncthreads();
@@ -303,14 +345,20 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
                 const double e = erow[i];
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 // psi^i is loaded first: its latency overlaps the costate step
-                load_state<C>(seg + np2 * (i - s0), T, loff, v, gl, gr);
+                if constexpr (!kStream) load_state<C>(seg + np2 * (i - s0), T, loff, v, gl, gr);
                 phase_mask<C, !kAdjQRegs>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc, sv.lc);
                 cn_apply<C, true>(kap, kgl, kgr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
-                // + 2 abar_i dx (V' + E_i) conj(psi^i)
-                add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[i] * dx, e, sv.tb, T, sv.lc);
+                // + 2 abar_i dx (V' + E_i) conj(psi^i), and the partial of
+                // grad_{i-1} from kappa^i and psi^i
+                if constexpr (kStream) {
+                    source_grad_streamed<C>(kap, kgl, kgr, seg + np2 * (i - s0), T, loff,
+                                            2.0 * abar[i] * dx, e, sv.tb, sv.lc, i > 0, sv.xs, dx,
+                                            ring + ((i > 0 ? i - 1 : 0) % kRing) * W);
+                } else {
+                    add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[i] * dx, e, sv.tb, T, sv.lc);
+                    if (i > 0) grad_partial<C>(kap, v, sv.xs, dx, sv.lc, ring + ((i - 1) % kRing) * W);
+                }
                 if (i > 0) {
-                    // partial of grad_{i-1} from kappa^i and psi^i
-                    grad_partial<C>(kap, v, sv.xs, dx, sv.lc, ring + ((i - 1) % kRing) * W);
                     if ((i - 1) % kFlush == 0) {
                         __syncthreads();
                         if (active && need_grad)

@@ -271,6 +271,47 @@ def test_adjoint_matches_oracle_and_fd(lib, torch_dev):
         plan.close()
 
 
+def test_adjoint_across_layouts(lib, torch_dev):
+    """The adjoint at 8 and 16 points per lane (N = 700, 9000 and the maximum
+    16384, where the 16-point kernel parks the costate while a segment is
+    recomputed and streams psi from the segment buffer), recomputing and from
+    stored checkpoints: bitwise equal to each other and within the bar of the
+    oracle's adjoint."""
+    torch, dev = torch_dev
+    ns = [700, 9000, 16384]
+    dx, dt, a, nt, k = 0.4, 0.05, 1.1, 240, 37
+    rng = np.random.default_rng(11)
+    efield = 0.05 * rng.standard_normal((len(ns), nt + 1))
+    abar = rng.standard_normal((len(ns), nt + 1))
+    p = lib.make_params(dx, dt, a, nt, mask_fraction=0.2)
+    E, AB = _to_dev(torch, dev, efield), _to_dev(torch, dev, abar)
+    print(f"adjoint layouts ns={ns} nt={nt} K={k}", flush=True)
+    ref = lib.Plan(p, ns, adjoint_k=k)
+    stp = lib.Plan(p, ns, adjoint_k=k, options=lib.TDSE_OPT_STORE_CHECKPOINTS)
+    assert [ref.layout(n).points_per_lane for n in ns] == [8, 16, 16]
+    g_full = torch.full_like(E, 7.0)
+    acc = torch.empty_like(E)
+    st = torch.full((len(ns),), -1, dtype=torch.int32, device=dev)
+    lib.tdse_adjoint_batch(ref, E, None, AB, g_full, acc, st)
+    lib.tdse_propagate_batch(stp, E, None, torch.empty_like(E))
+    g_st = torch.full_like(E, 7.0)
+    lib.tdse_adjoint_batch_stored(stp, stp.checkpoint_generation(), E, AB, g_st)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    g, acc_np = g_full.cpu().numpy(), acc.cpu().numpy()
+    assert np.array_equal(g_st.cpu().numpy(), g)
+    for b, n in enumerate(ns):
+        psi0 = torch.empty(2 * n, dtype=torch.float64, device=dev)
+        ref.ground_state(n, psi0)
+        g_ref, acc_ref = oracle.adjoint(efield[b], psi0.cpu().numpy().view(np.complex128),
+                                        abar[b], dx, dt, a, mask_frac=0.2, k=k)
+        r, ra = rel(g[b], g_ref), rel(acc_np[b], acc_ref)
+        print(f"  n={n}: grad rel-L2 {r:.3e}, accel rel-L2 {ra:.3e}", flush=True)
+        assert r < 1e-9 and ra < TOL_ACC
+    ref.close()
+    stp.close()
+
+
 def test_stored_checkpoints_match_recomputing_adjoint(lib, torch_dev):
     """A plan that stores the adjoint checkpoints in its forward pass gives
     the same forward outputs as a plain plan of the same layouts, its reverse
