@@ -237,6 +237,24 @@ tdse_status tdse_adjoint_batch_stored(tdse_plan plan, uint64_t generation, const
 tdse_status tdse_plan_stored_state(tdse_plan plan, uint64_t generation, int32_t index,
                                    double* psi_out, void* stream);
 
+/* Ground-state and volumetric populations along a propagation: the
+ * analyses of the wavefunction listed in section "Microscopic Response in
+ * XUV regime (TDSE)" and plotted against time in the interactive
+ * interface's example.  For every system b and stored state s (the state at
+ * step s * adjoint_k, 0 <= s <= nt / adjoint_k, of the forward pass of
+ * generation `generation` on a plan created with TDSE_OPT_STORE_CHECKPOINTS):
+ *   gs[b][s]  = |dx sum_j conj(phi_j) psi_j|^2
+ *   vol[b][s] = dx sum_{|x_j| <= radius} |psi_j|^2,  x_j = (j - (n-1)/2) dx
+ *   psi_ref   device, ragged complex (tdse_plan_psi_offsets): phi per system,
+ *             or NULL for the plan's ground state of the system's grid size
+ *   radius    half-width of the region around the nucleus (a.u.); finite
+ *   gs, vol   device float64 [batch][nt / adjoint_k + 1]; either may be NULL
+ * Fails with TDSE_E_INVALID, before any launch, for a plan without a store,
+ * a stale generation, both outputs NULL or a non-finite radius.
+ * Asynchronous on `stream`. */
+tdse_status tdse_plan_populations(tdse_plan plan, uint64_t generation, const double* psi_ref,
+                                  double radius, double* gs, double* vol, void* stream);
+
 /* ------------------------------------------------- energy distribution */
 /* Electron energy distribution of every system's wavefunction (section
  * "Analysing the Time-Dependent Electron Energy Density"):

@@ -381,3 +381,19 @@ def gabor(accel, dt, t_centres, omegas, sigma):
         win = np.exp(-(t - tc) ** 2 / (2.0 * sigma ** 2))
         out[:, c, :] = np.abs(dt * (accel * win) @ ph.T) ** 2
     return out
+
+
+def populations(psi, phi, dx, radius):
+    """Ground-state and volumetric populations of a wavefunction (section
+    "Microscopic Response in XUV regime (TDSE)", the analyses of psi listed
+    after the dipole acceleration): (|dx <phi, psi>|^2,
+    dx sum_{|x_j| <= radius} |psi_j|^2) on the centred grid
+    x_j = (j - (n-1)/2) dx."""
+    psi = np.asarray(psi, np.complex128)
+    phi = np.asarray(phi, np.complex128)
+    n = psi.shape[0]
+    x = (np.arange(n) - 0.5 * (n - 1)) * dx
+    gs = abs(dx * np.vdot(phi, psi)) ** 2
+    inside = np.abs(x) <= radius
+    vol = dx * float(np.sum(np.abs(psi[inside]) ** 2))
+    return gs, vol

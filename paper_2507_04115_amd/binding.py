@@ -77,6 +77,7 @@ _PROTOS = {
     "tdse_harmonic_yield": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tdse_plan_energy_spectrum": (_i32, [_vp, _vp, _i32, _vp, _d, _vp, _vp, ctypes.c_size_t, _vp]),
     "tdse_plan_stored_state": (_i32, [_vp, ctypes.c_uint64, _i32, _vp, _vp]),
+    "tdse_plan_populations": (_i32, [_vp, ctypes.c_uint64, _vp, _d, _vp, _vp, _vp]),
     "tdse_gabor": (_i32, [_i32, _i32, _d, _vp, _i32, _vp, _i32, _vp, _d, _vp, _vp]),
     "tdse_band_dft": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
     "tdse_band_dft_adjoint": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
@@ -356,6 +357,22 @@ def tdse_gabor(accel, dt: float, t_centres, omegas, sigma: float, out, stream=No
 
 
 def tdse_plan_stored_state(plan: Plan, generation: int, index: int, psi_out, stream=None):
+    _c128(psi_out)
     _check(load().tdse_plan_stored_state(plan.handle, generation, index, _ptr(psi_out),
                                          _stream(stream)), "tdse_plan_stored_state")
+
+
+def tdse_plan_populations(plan: Plan, generation: int, radius: float, gs=None, vol=None,
+                          psi_ref=None, stream=None):
+    """gs[b][s], vol[b][s]: ground-state and volumetric populations of every
+    stored state (s = 0 .. nt // adjoint_k); see include/libtdse.h."""
+    _f64(gs, vol)
+    _c128(psi_ref)
+    need = plan.batch * (plan.params.nt // max(plan.adjoint_k, 1) + 1)
+    for t in (gs, vol):
+        if t is not None and t.numel() < need:
+            raise ValueError(f"population outputs need {need} elements")
+    _check(load().tdse_plan_populations(plan.handle, generation, _ptr(psi_ref), float(radius),
+                                        _ptr(gs), _ptr(vol), _stream(stream)),
+           "tdse_plan_populations")
 

@@ -1703,6 +1703,35 @@ tdse_status tdse_plan_stored_state(tdse_plan plan, uint64_t generation, int32_t 
     return TDSE_OK;
 }
 
+tdse_status tdse_plan_populations(tdse_plan plan, uint64_t generation, const double* psi_ref,
+                                  double radius, double* gs, double* vol, void* stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
+    if (!plan->d_store) return fail(TDSE_E_INVALID, "plan was created without TDSE_OPT_STORE_CHECKPOINTS");
+    if (generation == 0 || generation != plan->ckpt_gen)
+        return fail(TDSE_E_INVALID, "stored checkpoints are of generation %llu, not %llu",
+                    (unsigned long long)plan->ckpt_gen, (unsigned long long)generation);
+    if (!gs && !vol) return fail(TDSE_E_INVALID, "gs and vol are both NULL");
+    if (!std::isfinite(radius)) return fail(TDSE_E_INVALID, "radius must be finite");
+    if (psi_ref && !aligned16(psi_ref)) return fail(TDSE_E_INVALID, "psi_ref must be 16-byte aligned");
+    PopArgs a{};
+    a.classes = plan->cls.d;
+    a.sys = plan->d_sys;
+    a.batch = plan->batch;
+    a.nrec = plan->p.nt / plan->adjoint_k + 1;
+    a.store = plan->d_store;
+    a.store_off = plan->d_store_off;
+    a.psi_ref = psi_ref;
+    a.gs = plan->d_gs;
+    a.gs_off = plan->d_gs_off;
+    a.radius = radius;
+    a.gs_out = gs;
+    a.vol_out = vol;
+    HIP_TRY(launch_populations(a, reinterpret_cast<hipStream_t>(stream)));
+    return TDSE_OK;
+}
+
 tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t n_energy,
                                       const double* energies, double eps, double* spectrum,
                                       void* work, size_t work_bytes, void* stream)

@@ -116,6 +116,21 @@ struct GaborArgs {
     double* out;              // [batch][n_tc][n_w]
 };
 
+// Ground-state and volumetric populations of stored records (tdse_plan_populations).
+struct PopArgs {
+    const SizeClass* classes;
+    const SysDesc* sys;
+    int32_t batch, nrec;
+    const double* store;       // per-system records
+    const int64_t* store_off;  // [batch]
+    const double* psi_ref;     // ragged complex, or null: the plan's ground states
+    const double* gs;          // plan ground states, per class
+    const int64_t* gs_off;
+    double radius;
+    double* gs_out;            // [batch][nrec], or null
+    double* vol_out;           // [batch][nrec], or null
+};
+
 struct YieldArgs {
     int32_t batch, nt;
     double dt, omega0, h_lo, h_hi;
@@ -130,6 +145,7 @@ struct YieldArgs {
 hipError_t launch_far_field(const FarArgs& a, bool adjoint, hipStream_t st);
 hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st);
 hipError_t launch_gabor(const GaborArgs& a, hipStream_t st);
+hipError_t launch_populations(const PopArgs& a, hipStream_t st);
 hipError_t launch_stored_state(const SizeClass* classes, const SysDesc* sys, int batch, int n_max,
                                const double* store, const int64_t* store_off, int index,
                                double* psi_out, hipStream_t st);

@@ -1,5 +1,6 @@
 // tdse_spectrum.hip -- analysis of the microscopic response: electron energy
-// distribution of a wavefunction, Gabor transform of the source term.
+// distribution of a wavefunction, Gabor transform of the source term,
+// ground-state and volumetric populations along a propagation.
 //
 // Section "Analysing the Time-Dependent Electron Energy Density": with the
 // field-free Hamiltonian H0 = M2^{-1}(-D2/2) + V of the solver's Numerov
@@ -137,6 +138,62 @@ __global__ void __launch_bounds__(256) gabor_kernel(GaborArgs a)
             a.out[((size_t)b * a.n_tc + c) * a.n_w + w] = re * re + im * im;
         }
     }
+}
+
+// Populations (section "Microscopic Response in XUV regime (TDSE)", the
+// analyses of psi it lists; the interface's example plots both against
+// time): for the state psi of a stored record and the reference phi,
+//   gs  = |dx sum_j conj(phi_j) psi_j|^2,
+//   vol = dx sum_{|x_j| <= radius} |psi_j|^2,   x_j = (j - (n-1)/2) dx.
+// One workgroup per (record, system).  The record is read in its own
+// [k][t] order (point j = t C + k), so the loads are coalesced; phi is a
+// gather from the plan's ground state (shared by all systems of a size, so
+// it stays in the L2) or the caller's reference.
+__global__ void __launch_bounds__(256) populations_kernel(PopArgs a)
+{
+    __shared__ double red[3][4];
+    const int s = blockIdx.x, b = blockIdx.y;
+    const SysDesc d = a.sys[b];
+    const SizeClass& sc = a.classes[d.cls];
+    const int C = sc.C, T = sc.T, n = sc.n;
+    const double dx = sc.dx, half = 0.5 * (double)(n - 1);
+    const size_t np2 = 2 * (size_t)(C + 2) * T;
+    const double* rec = a.store + a.store_off[b] + np2 * (size_t)s;
+    const double* ref = a.psi_ref ? a.psi_ref + 2 * d.psi_off : a.gs + 2 * a.gs_off[d.cls];
+    double ore = 0.0, oim = 0.0, vol = 0.0;
+    for (int idx = threadIdx.x; idx < C * T; idx += 256) {
+        const int k = idx / T, t = idx - k * T;
+        const int j = t * C + k;
+        if (j >= n) continue;
+        const double pr = rec[2 * (size_t)idx], pi = rec[2 * (size_t)idx + 1];
+        const double fr = ref[2 * (size_t)j], fi = ref[2 * (size_t)j + 1];
+        ore = fma(fr, pr, fma(fi, pi, ore));   // Re(conj(phi) psi)
+        oim = fma(fr, pi, fma(-fi, pr, oim));  // Im(conj(phi) psi)
+        if (fabs(((double)j - half) * dx) <= a.radius) vol = fma(pr, pr, fma(pi, pi, vol));
+    }
+    ore = wave_sum(ore);
+    oim = wave_sum(oim);
+    vol = wave_sum(vol);
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    if (lane == kSumLane) {
+        red[0][w] = ore;
+        red[1][w] = oim;
+        red[2][w] = vol;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double r = dx * (red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+        const double i = dx * (red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+        const size_t o = (size_t)b * a.nrec + s;
+        if (a.gs_out) a.gs_out[o] = fma(r, r, i * i);
+        if (a.vol_out) a.vol_out[o] = dx * (red[2][0] + red[2][1] + red[2][2] + red[2][3]);
+    }
+}
+
+hipError_t launch_populations(const PopArgs& a, hipStream_t st)
+{
+    hipLaunchKernelGGL(populations_kernel, dim3(a.nrec, a.batch), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_gabor(const GaborArgs& a, hipStream_t st)

@@ -130,3 +130,71 @@ def test_stored_states_along_a_propagation(lib, torch_dev):
     with pytest.raises(lib.TDSEError):
         lib.tdse_plan_stored_state(plan, gen, 0, psi)
     plan.close()
+
+
+def test_populations_along_a_propagation(lib, torch_dev):
+    """Ground-state and volumetric populations of every stored state against
+    the oracle's populations of the oracle's state after the same number of
+    steps, with the plan's ground state and with a caller's reference; a
+    field-free propagation without absorber keeps the ground state's
+    populations at 1."""
+    torch, dev = torch_dev
+    ns = [256, 400, 700]
+    dx, dt, om, nc, K, a = 0.4, 0.05, 0.25, 2, 37, 1.1
+    nt = ti.n_steps(om, nc, dt)
+    nrec = nt // K + 1
+    efield = ti.sin2_pulse(np.array([0.1, 0.07, 0.12]), om, nc, dt, nt=nt)
+    p = lib.make_params(dx, dt, a, nt, mask_fraction=0.2)
+    plan = lib.Plan(p, ns, adjoint_k=K, options=lib.TDSE_OPT_STORE_CHECKPOINTS)
+    E = torch.tensor(efield, device=dev)
+    lib.tdse_propagate_batch(plan, E, None, torch.empty_like(E))
+    gen = plan.checkpoint_generation()
+    off = plan.psi_offsets()
+    radius = 5.1
+    gs = torch.full((len(ns), nrec), -1.0, dtype=torch.float64, device=dev)
+    vol = torch.full_like(gs, -1.0)
+    lib.tdse_plan_populations(plan, gen, radius, gs, vol)
+    # a caller's reference: a normalised Gaussian wave packet per system
+    ref = np.concatenate([np.exp(-((np.arange(n) - 0.5 * (n - 1)) * dx) ** 2 / 8.0 + 0.3j * np.arange(n))
+                          for n in ns])
+    for b, n in enumerate(ns):
+        r = ref[off[b]:off[b + 1]]
+        ref[off[b]:off[b + 1]] = r / np.sqrt(dx * np.sum(np.abs(r) ** 2))
+    R = torch.tensor(ref.view(np.float64), device=dev)
+    gs_ref = torch.full_like(gs, -1.0)
+    lib.tdse_plan_populations(plan, gen, radius, gs_ref, None, psi_ref=R)
+    torch.cuda.synchronize()
+    g, v, gr = gs.cpu().numpy(), vol.cpu().numpy(), gs_ref.cpu().numpy()
+    for b, n in enumerate(ns):
+        g0 = torch.empty(2 * n, dtype=torch.float64, device=dev)
+        plan.ground_state(n, g0)
+        psi0 = g0.cpu().numpy().view(np.complex128)
+        for s in (0, 1, nrec // 2, nrec - 1):
+            steps = s * K
+            psi = psi0 if steps == 0 else oracle.propagate(
+                efield[b, :steps + 1], psi0, dx, dt, a, mask_frac=0.2, want_psi=True)["psi_final"]
+            e_gs, e_vol = oracle.populations(psi, psi0, dx, radius)
+            e_gr, _ = oracle.populations(psi, ref[off[b]:off[b + 1]], dx, radius)
+            print(f"  n={n} step {steps}: gs {g[b, s]:.12f} ({e_gs:.12f}), vol {v[b, s]:.12f}",
+                  flush=True)
+            assert abs(g[b, s] - e_gs) <= 1e-9 * max(e_gs, 1e-3)
+            assert abs(v[b, s] - e_vol) <= 1e-9 * e_vol
+            assert abs(gr[b, s] - e_gr) <= 1e-9 * max(e_gr, 1e-3)
+        assert abs(g[b, 0] - 1.0) < 1e-12
+    with pytest.raises(lib.TDSEError):
+        lib.tdse_plan_populations(plan, gen, radius, None, None)
+    with pytest.raises(lib.TDSEError):
+        lib.tdse_plan_populations(plan, gen + 1, radius, gs, vol)
+    plan.close()
+    # field-free, no absorber: the ground state only turns its phase
+    p0 = lib.make_params(dx, dt, a, 200, mask_fraction=0.0)
+    plan0 = lib.Plan(p0, [512, 300], adjoint_k=20, options=lib.TDSE_OPT_STORE_CHECKPOINTS)
+    E0 = torch.zeros((2, 201), dtype=torch.float64, device=dev)
+    lib.tdse_propagate_batch(plan0, E0, None, torch.empty_like(E0))
+    gs0 = torch.empty((2, 11), dtype=torch.float64, device=dev)
+    vol0 = torch.empty_like(gs0)
+    lib.tdse_plan_populations(plan0, plan0.checkpoint_generation(), 1e6, gs0, vol0)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(gs0.cpu().numpy() - 1.0)) < 1e-10
+    assert np.max(np.abs(vol0.cpu().numpy() - 1.0)) < 1e-10
+    plan0.close()
