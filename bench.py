@@ -36,6 +36,8 @@ sys.path.insert(0, ROOT)
 
 FLOPS_PER_POINT_STEP = 52.0        # algorithmic FP64 flops per grid-point-step
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
+HBM_PEAK_GBS = 8000.0              # HBM3E
+ADJ_FLOPS_PER_POINT_STEP = 158.0    # forward + recompute + costate step
 CSRC = os.path.join(ROOT, "paper_2507_04115_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -344,6 +346,15 @@ def main():
             ev1.record(stream)
             torch.cuda.synchronize()
             ms[stored] = ev0.elapsed_time(ev1)
+        # algorithmic work of one gradient with stored checkpoints: forward,
+        # segment recompute and costate step (52 + 52 + 54 flops per
+        # grid-point-step); HBM: each recomputed state written to the segment
+        # buffer and read back (32 B per grid-point-step) plus the checkpoints
+        # written and read once (32 B per grid point every K steps)
+        pts_a = float(sum(wa.n_per)) * wa.nt
+        t_a = ms[True] * 1e-3
+        fl_a = ADJ_FLOPS_PER_POINT_STEP * pts_a / t_a
+        by_a = (32.0 + 32.0 / 256) * pts_a / t_a
         out["adjoint"] = {"workload": wa.name, "systems": wa.batch, "nt": wa.nt, "checkpoint_k": 256,
                           "points_per_lane": lay_a.points_per_lane, "lanes": lay_a.lanes,
                           "time_per_gradient_s": ms[True] * 1e-3,
@@ -351,7 +362,13 @@ def main():
                           "forward_grid_point_steps": float(sum(wa.n_per)) * wa.nt,
                           "loss": f"sum of H{h_lo}-H{h_hi} Hann-windowed yields",
                           "checkpoints": "stored by the forward pass (time_per_gradient_s); "
-                                         "recomputed by the adjoint call (..._recompute_s)"}
+                                         "recomputed by the adjoint call (..._recompute_s)",
+                          "roofline": {"flops_per_grid_point_step": ADJ_FLOPS_PER_POINT_STEP,
+                                       "achieved_tflops": fl_a * 1e-12,
+                                       "frac_fp64": fl_a * 1e-12 / FP64_VECTOR_PEAK_TFLOPS,
+                                       "hbm_bytes_per_grid_point_step": 32.0 + 32.0 / 256,
+                                       "achieved_gbs": by_a * 1e-9,
+                                       "frac_hbm": by_a * 1e-9 / HBM_PEAK_GBS}}
         log(f"adjoint: {ms[True] * 1e-3:.3f} s per gradient with stored checkpoints, "
             f"{ms[False] * 1e-3:.3f} s recomputing them ({wa.batch} systems)")
         plan_a.close()
