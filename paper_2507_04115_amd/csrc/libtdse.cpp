@@ -748,7 +748,8 @@ tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int coun
     const int nt = kProbeSteps, K = 16;
     const int grid = std::min((P + S - 1) / S, occ * num_cus());
     const int64_t rec = 2 * (int64_t)(L.C + 2) * L.T;
-    const int64_t slot = rec * (nt / K + 1 + K + 2) + ((nt + 2) & ~int64_t(1));
+    const int64_t slot = rec * (nt / K + 2) + 2 * (int64_t)L.C * L.T * (K + 1) +
+                         ((nt + 2) & ~int64_t(1));
     ClassSet cs;
     tdse_status rc = build_classes(cs, {n}, {L}, {real_time_params(p)}, st);
     if (rc != TDSE_OK) {
@@ -1192,11 +1193,12 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
             L.alds = atab == kTabLds;
             L.agrid = std::min((L.count + L.aS - 1) / L.aS, aocc * num_cus());
             const int64_t rec = 2 * (int64_t)(L.C + 2) * L.T;   // one state record
+            const int64_t recs = 2 * (int64_t)L.C * L.T;        // one segment record
             const int64_t nseg = nt / adjoint_k + 1;
             const int64_t ck = rec * nseg + ((nt + 2) & ~int64_t(1));  // checkpoints + norm row
             // a slot holds the segment states and one parked costate record, and
             // the checkpoints unless they are stored per system
-            L.slot_doubles = rec * (adjoint_k + 2) + (store ? 0 : ck);
+            L.slot_doubles = recs * (adjoint_k + 1) + rec + (store ? 0 : ck);
             L.work_off = adj_total;
             adj_total += L.slot_doubles * (int64_t)L.agrid * L.aS;
             if (store)

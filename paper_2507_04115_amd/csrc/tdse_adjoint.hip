@@ -19,7 +19,8 @@
 //   dl/dE_i = abar_i n_i + dt sum_j x_j Im(kappa^{i+1}_j psi^{i+1}_j).
 // psi^i is recomputed segment by segment from checkpoints stored every K
 // steps during an initial forward pass; segment states live in a per-slot
-// HBM buffer in the lane-interleaved layout (coalesced 16 B per lane).
+// HBM buffer in the lane-interleaved layout (coalesced 16 B per lane), chunk
+// values only (the ghosts are read from the neighbouring lanes' entries).
 #include "tdse_device.hpp"
 #include "tdse_kernels.hpp"
 
@@ -59,6 +60,37 @@ __device__ __forceinline__ void load_state(const double* base, int T, unsigned o
     for (int k = 0; k < C; ++k) v[k] = ld_lane(b + (size_t)k * T, off);
     gl = ld_lane(b + (size_t)C * T, off);
     gr = ld_lane(b + (size_t)(C + 1) * T, off);
+}
+
+// Segment record: the chunk values only, [C][T] complex.  The ghosts are the
+// neighbouring lanes' end values, read back from the same record (the same
+// cache lines as the lane's own loads); outside the grid they are zero, as
+// in the forward step.  The offsets are clamped so that every load stays in
+// the record.
+template <int C>
+__device__ __forceinline__ void store_chunk(double* base, int T, unsigned off, const cd (&v)[C])
+{
+#pragma unroll
+    for (int k = 0; k < C; ++k) st_lane(base + 2 * (size_t)k * T, off, v[k]);
+}
+
+template <int C>
+__device__ __forceinline__ void chunk_ghosts(const cd* b, int T, int t, unsigned off, cd& gl, cd& gr)
+{
+    const cd l = ld_lane(b + (size_t)(C - 1) * T, t > 0 ? off - 16u : off);
+    const cd r = ld_lane(b, t + 1 < T ? off + 16u : off);
+    gl = t > 0 ? l : czero();
+    gr = t + 1 < T ? r : czero();
+}
+
+template <int C>
+__device__ __forceinline__ void load_chunk(const double* base, int T, int t, unsigned off,
+                                           cd (&v)[C], cd& gl, cd& gr)
+{
+    const cd* b = reinterpret_cast<const cd*>(base);
+#pragma unroll
+    for (int k = 0; k < C; ++k) v[k] = ld_lane(b + (size_t)k * T, off);
+    chunk_ghosts<C>(b, T, t, off, gl, gr);
 }
 
 // Outputs of the forward pass for samples [a0, a1]: the acceleration, <x> and
@@ -144,13 +176,13 @@ __device__ __forceinline__ void add_source(cd (&kap)[C], cd& kgl, cd& kgr, const
     kgr = cadd(kgr, cscale(ci * (tb.dv(lc.ir()) + e), cconj(gr)));
 }
 
-// add_source and grad_partial in one pass that reads psi^i from its state
+// add_source and grad_partial in one pass that reads psi^i from its segment
 // record one point at a time, for chunks too long to hold psi and the
 // costate in registers together.  Same operations in the same order, so the
-// results are those of the two calls above.
+// results are those of load_chunk followed by the two calls above.
 template <int C, class TV>
 __device__ __forceinline__ void source_grad_streamed(cd (&kap)[C], cd& kgl, cd& kgr,
-                                                     const double* rec, int T, unsigned off,
+                                                     const double* rec, int T, int t, unsigned off,
                                                      double ci, double e, const TV& tb,
                                                      const LaneCtx& lc, bool want_grad, double xs,
                                                      double dx, double* slot)
@@ -165,7 +197,8 @@ __device__ __forceinline__ void source_grad_streamed(cd (&kap)[C], cd& kgl, cd& 
         s0 += im;
         s1 = fma((double)k, im, s1);
     }
-    const cd gl = ld_lane(b + (size_t)C * T, off), gr = ld_lane(b + (size_t)(C + 1) * T, off);
+    cd gl, gr;
+    chunk_ghosts<C>(b, T, t, off, gl, gr);
     kgl = cadd(kgl, cscale(ci * (tb.dv(lc.il()) + e), cconj(gl)));
     kgr = cadd(kgr, cscale(ci * (tb.dv(lc.ir()) + e), cconj(gr)));
     if (want_grad) {
@@ -202,6 +235,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
     const int nt = a.nt, K = a.k_ckpt;
     const int nseg = nt / K + 1;
     const size_t np2 = 2 * (size_t)(C + 2) * T;  // doubles per state record
+    const size_t nps = 2 * (size_t)C * T;        // doubles per segment record
     double* const slot = a.work + ((size_t)blockIdx.x * S + sub) * (size_t)a.slot_doubles;
     double* ring = sm.ring;
     int* flag = sm.misc + 1;
@@ -234,7 +268,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
         double* ckpt = a.store ? a.store + uniform_load(a.store_off + p) : slot;
         double* n_row = ckpt + np2 * nseg;
         double* seg = a.store ? slot : n_row + ((nt + 2) & ~1);
-        double* kbuf = seg + np2 * (K + 1);  // parked costate (one record)
+        double* kbuf = seg + nps * (K + 1);  // parked costate (one state record)
 
         // rows with an all-zero abar have a zero gradient and need no reverse sweep
         if (active && a.mode != kAdjForwardOnly)
@@ -312,19 +346,19 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
             // recompute psi^{s0..s1} into the segment buffer
             if constexpr (kStream) store_state<C>(kbuf, T, loff, kap, kgl, kgr);
             load_state<C>(ckpt + np2 * sidx, T, loff, v, gl, gr);
-            store_state<C>(seg, T, loff, v, gl, gr);
+            store_chunk<C>(seg, T, loff, v);
             for (int i = s0; i < s1; ++i) {
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
                                 sm.lds_f, sm.lds_b);
-                store_state<C>(seg + np2 * (i - s0 + 1), T, loff, v, gl, gr);
+                store_chunk<C>(seg + nps * (i - s0 + 1), T, loff, v);
             }
             if constexpr (kStream) load_state<C>(kbuf, T, loff, kap, kgl, kgr);
             if (!started) {
                 // kappa^nt = 2 abar_nt dx (V' + E_nt) conj(psi^nt); psi^nt = v
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 if constexpr (kStream) {
-                    source_grad_streamed<C>(kap, kgl, kgr, seg + np2 * (s1 - s0), T, loff,
+                    source_grad_streamed<C>(kap, kgl, kgr, seg + nps * (s1 - s0), T, t, loff,
                                             2.0 * abar[nt] * dx, erow[nt], sv.tb, sv.lc, nt > 0,
                                             sv.xs, dx, ring + ((nt > 0 ? nt - 1 : 0) % kRing) * W);
                 } else {
@@ -345,13 +379,13 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
                 const double e = erow[i];
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 // psi^i is loaded first: its latency overlaps the costate step
-                if constexpr (!kStream) load_state<C>(seg + np2 * (i - s0), T, loff, v, gl, gr);
+                if constexpr (!kStream) load_chunk<C>(seg + nps * (i - s0), T, t, loff, v, gl, gr);
                 phase_mask<C, !kAdjQRegs>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc, sv.lc);
                 cn_apply<C, true>(kap, kgl, kgr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
                 // + 2 abar_i dx (V' + E_i) conj(psi^i), and the partial of
                 // grad_{i-1} from kappa^i and psi^i
                 if constexpr (kStream) {
-                    source_grad_streamed<C>(kap, kgl, kgr, seg + np2 * (i - s0), T, loff,
+                    source_grad_streamed<C>(kap, kgl, kgr, seg + nps * (i - s0), T, t, loff,
                                             2.0 * abar[i] * dx, e, sv.tb, sv.lc, i > 0, sv.xs, dx,
                                             ring + ((i > 0 ? i - 1 : 0) % kRing) * W);
                 } else {
