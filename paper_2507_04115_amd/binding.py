@@ -170,6 +170,7 @@ def tdse_version() -> str:
 
 def tdse_ground_state(p: tdse_params, n: int, dtau: float, max_iter: int, tol: float, psi_out,
                       stream=None) -> float:
+    _c128(psi_out)
     e = _d()
     _check(load().tdse_ground_state(ctypes.byref(p), n, dtau, max_iter, tol, _ptr(psi_out),
                                     ctypes.byref(e), _stream(stream)), "tdse_ground_state")
@@ -254,6 +255,7 @@ class Plan:
         return g.value
 
     def ground_state(self, n: int, psi_out) -> float:
+        _c128(psi_out)
         e = _d()
         _check(load().tdse_plan_ground_state(self.handle, n, _ptr(psi_out), ctypes.byref(e)),
                "tdse_plan_ground_state")
@@ -306,6 +308,7 @@ def tdse_harmonic_band(nt: int, dt: float, omega0: float, h_lo: float, h_hi: flo
 
 def tdse_harmonic_yield(batch: int, nt: int, dt: float, omega0: float, h_lo: float, h_hi: float,
                         accel, row_weight, work, yield_out, accel_bar=None, stream=None):
+    _f64(accel, row_weight, work, yield_out, accel_bar)
     _check(load().tdse_harmonic_yield(batch, nt, dt, omega0, h_lo, h_hi, _ptr(accel),
                                       _ptr(row_weight), _ptr(work), _ptr(yield_out),
                                       _ptr(accel_bar), _stream(stream)), "tdse_harmonic_yield")
@@ -313,12 +316,16 @@ def tdse_harmonic_yield(batch: int, nt: int, dt: float, omega0: float, h_lo: flo
 
 def tdse_band_dft(batch: int, nt: int, dt: float, omega0: float, h_lo: float, h_hi: float, accel,
                   amp, stream=None):
+    _f64(accel)
+    _c128(amp)
     _check(load().tdse_band_dft(batch, nt, dt, omega0, h_lo, h_hi, _ptr(accel), _ptr(amp),
                                 _stream(stream)), "tdse_band_dft")
 
 
 def tdse_band_dft_adjoint(batch: int, nt: int, dt: float, omega0: float, h_lo: float, h_hi: float,
                           amp_bar, accel_bar, stream=None):
+    _c128(amp_bar)
+    _f64(accel_bar)
     _check(load().tdse_band_dft_adjoint(batch, nt, dt, omega0, h_lo, h_hi, _ptr(amp_bar),
                                         _ptr(accel_bar), _stream(stream)), "tdse_band_dft_adjoint")
 

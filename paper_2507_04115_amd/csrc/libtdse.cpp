@@ -886,7 +886,7 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, hipSt
 }
 
 constexpr double kGsDtau = 0.5;
-constexpr double kGsTol = 1e-12;
+constexpr double kGsTol = 1e-13;
 constexpr int kGsMaxIter = 100000;
 
 // Ground states of every class of a plan (imaginary-time tables built on the

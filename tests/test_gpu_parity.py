@@ -1,10 +1,13 @@
 """GPU parity: the HIP path (through the C-ABI) against the CPU oracle on the
 same seeded inputs.  Bar: relative L2 <= 1e-9 on the dipole acceleration
-(and <norm>, <x>), <= 1e-5 on gradients."""
+(and <norm>, <x>), <= 1e-5 on gradients.  The oracle side computes its own
+ground states, soft-core fits and loss gradients (tests/oracle_side.py):
+no value from the HIP path is an oracle input."""
 import numpy as np
 import pytest
 
 import oracle
+import oracle_side
 import tdse_inputs as ti
 
 pytestmark = pytest.mark.gpu
@@ -34,6 +37,18 @@ def _c2d(psi):
     return np.ascontiguousarray(np.asarray(psi, np.complex128)).view(np.float64)
 
 
+def _gpu_abar(lib, torch, dev, acc, dt, om, h_lo, h_hi, weights):
+    """accel_bar of the weighted harmonic-yield loss, on the GPU."""
+    batch, n1 = acc.shape
+    k_lo, nk = lib.tdse_harmonic_band(n1 - 1, dt, om, h_lo, h_hi)
+    work = torch.empty(2 * batch * max(nk, 1), dtype=torch.float64, device=dev)
+    y = torch.empty(batch, dtype=torch.float64, device=dev)
+    ab = torch.empty_like(acc)
+    lib.tdse_harmonic_yield(batch, n1 - 1, dt, om, h_lo, h_hi, acc,
+                            _to_dev(torch, dev, np.asarray(weights, np.float64)), work, y, ab)
+    return ab
+
+
 def test_ground_state_matches_oracle(lib, torch_dev):
     torch, dev = torch_dev
     for n, dx, a in [(2048, 0.2, A_AR), (700, 0.3, 0.9)]:
@@ -51,8 +66,10 @@ def test_soft_core_fit_reaches_ip(lib, torch_dev):
     print("soft-core fit n=2048", flush=True)
     a, e = lib.tdse_soft_core_for_ip(ti.IP_ARGON, 2048, 0.2, dtau=1.0, tol=1e-13)
     assert abs(e + ti.IP_ARGON) < 1e-13
-    _, e_ref, _ = oracle.ground_state(2048, 0.2, a, dtau=1.0, tol=1e-13)
-    assert abs(e_ref + ti.IP_ARGON) < 1e-12
+    # the oracle's own bisection lands on the same parameter
+    a_ref = oracle_side.soft_core(ti.IP_ARGON, 0.2)
+    print(f"  a = {a:.15f}, oracle {a_ref:.15f}", flush=True)
+    assert abs(a - a_ref) < 1e-10
 
 
 def _run_forward(lib, torch, dev, ns, efield, dx, dt, a, psi0_list=None, mask=0.1, options=0,
@@ -109,10 +126,7 @@ def test_forward_single_2048_full_pulse(lib, torch_dev):
     efield = w.efield()
     print(f"forward single-2048 nt={w.nt}", flush=True)
     plan, out = _run_forward(lib, torch, dev, [2048], efield, w.dx, w.dt, A_AR)
-    psi0 = torch.empty(2 * 2048, dtype=torch.float64, device=dev)
-    plan.ground_state(2048, psi0)
-    ref = oracle.propagate(efield[0], psi0.cpu().numpy().view(np.complex128), w.dx, w.dt, A_AR,
-                           mask_frac=0.1)
+    ref = oracle_side.propagate(efield[0], 2048, w.dx, w.dt, A_AR, mask_frac=0.1)
     r = rel(out["accel"][0], ref["accel"])
     print(f"  accel rel-L2 {r:.3e}", flush=True)
     assert r < TOL_ACC
@@ -247,10 +261,8 @@ def test_adjoint_matches_oracle_and_fd(lib, torch_dev):
         E = _to_dev(torch, dev, efield)
         acc = torch.empty_like(E)
         lib.tdse_propagate_batch(plan, E, None, acc)
-        torch.cuda.synchronize()
-        _, abar = oracle.harmonic_yield(acc.cpu().numpy(), dt, om, 3, 9)
-        abar[1] = 0.0                      # an all-zero row is skipped
-        AB = _to_dev(torch, dev, abar)
+        # an all-zero row (weight 0) is skipped
+        AB = _gpu_abar(lib, torch, dev, acc, dt, om, 3, 9, [1.0, 0.0, 1.0])
         grad = torch.full_like(E, 7.0)
         acc2 = torch.empty_like(E)
         st = torch.full((3,), -1, dtype=torch.int32, device=dev)
@@ -261,10 +273,8 @@ def test_adjoint_matches_oracle_and_fd(lib, torch_dev):
         assert np.all(st.cpu().numpy() == 0)
         assert np.all(g[1] == 0.0)
         for b in (0, 2):
-            psi0 = torch.empty(2 * ns[b], dtype=torch.float64, device=dev)
-            plan.ground_state(ns[b], psi0)
-            g_ref, _ = oracle.adjoint(efield[b], psi0.cpu().numpy().view(np.complex128), abar[b],
-                                      dx, dt, a, mask_frac=0.2, k=k)
+            _, g_ref = oracle_side.yield_gradient(efield[b], ns[b], dx, dt, a, om, 3, 9,
+                                                  mask_frac=0.2, k=k)
             r = rel(g[b], g_ref)
             print(f"  grad rel-L2 system {b}: {r:.3e}", flush=True)
             assert r < 1e-9
@@ -301,10 +311,7 @@ def test_adjoint_across_layouts(lib, torch_dev):
     g, acc_np = g_full.cpu().numpy(), acc.cpu().numpy()
     assert np.array_equal(g_st.cpu().numpy(), g)
     for b, n in enumerate(ns):
-        psi0 = torch.empty(2 * n, dtype=torch.float64, device=dev)
-        ref.ground_state(n, psi0)
-        g_ref, acc_ref = oracle.adjoint(efield[b], psi0.cpu().numpy().view(np.complex128),
-                                        abar[b], dx, dt, a, mask_frac=0.2, k=k)
+        g_ref, acc_ref = oracle_side.adjoint(efield[b], abar[b], n, dx, dt, a, mask_frac=0.2, k=k)
         r, ra = rel(g[b], g_ref), rel(acc_np[b], acc_ref)
         print(f"  n={n}: grad rel-L2 {r:.3e}, accel rel-L2 {ra:.3e}", flush=True)
         assert r < 1e-9 and ra < TOL_ACC
@@ -342,9 +349,8 @@ def test_stored_checkpoints_match_recomputing_adjoint(lib, torch_dev):
     for x, y in zip(outs[0], outs[1]):
         assert np.array_equal(x, y)
     assert np.all(outs[1][4] == 0)
-    _, abar = oracle.harmonic_yield(outs[0][0], dt, om, 3, 9)
-    abar[1] = 0.0                          # an all-zero row is skipped here too
-    AB = _to_dev(torch, dev, abar)
+    # an all-zero row (weight 0) is skipped here too
+    AB = _gpu_abar(lib, torch, dev, _to_dev(torch, dev, outs[0][0]), dt, om, 3, 9, [1.0, 0.0, 1.0])
     g_full = torch.full_like(E, 7.0)
     lib.tdse_adjoint_batch(ref, E, None, AB, g_full)
     g_st = torch.full_like(E, 7.0)
@@ -354,10 +360,8 @@ def test_stored_checkpoints_match_recomputing_adjoint(lib, torch_dev):
     assert np.array_equal(g_st.cpu().numpy(), g_full.cpu().numpy())
     assert np.all(st.cpu().numpy() == 0)
     assert np.all(g_st.cpu().numpy()[1] == 0.0)
-    psi0 = torch.empty(2 * ns[2], dtype=torch.float64, device=dev)
-    stp.ground_state(ns[2], psi0)
-    g_ref, _ = oracle.adjoint(efield[2], psi0.cpu().numpy().view(np.complex128), abar[2], dx, dt, a,
-                              mask_frac=0.2, k=37)
+    _, g_ref = oracle_side.yield_gradient(efield[2], ns[2], dx, dt, a, om, 3, 9, mask_frac=0.2,
+                                          k=37)
     assert rel(g_st.cpu().numpy()[2], g_ref) < 1e-9
     # a later forward pass rewrites the store: the old generation is refused
     lib.tdse_propagate_batch(stp, E, None, torch.empty_like(E))
@@ -414,10 +418,7 @@ def test_forward_uneven_wide_batch_sampled(lib, torch_dev):
     plan, out = _run_forward(lib, torch, dev, ns, efield, w.dx, w.dt, A_AR, want=False)
     assert np.all(out["status"] == 0)
     for b in picks:
-        psi0 = torch.empty(2 * ns[b], dtype=torch.float64, device=dev)
-        plan.ground_state(ns[b], psi0)
-        ref = oracle.propagate(efield[b], psi0.cpu().numpy().view(np.complex128), w.dx, w.dt, A_AR,
-                               mask_frac=0.1)
+        ref = oracle_side.propagate(efield[b], ns[b], w.dx, w.dt, A_AR, mask_frac=0.1)
         r = rel(out["accel"][b], ref["accel"])
         print(f"  system {b} n={ns[b]} layout={plan.layout(ns[b])}: accel rel-L2 {r:.3e}", flush=True)
         assert r < TOL_ACC
@@ -443,17 +444,77 @@ def test_focus_batch_full_size_sampled(lib, torch_dev):
     torch.cuda.synchronize()
     assert int((st != 0).sum()) == 0
     assert bool((nr[:, 1:] <= nr[:, :-1] * (1 + 1e-12)).all())
-    psi0 = torch.empty(2 * w.n_per[0], dtype=torch.float64, device=dev)
-    plan.ground_state(w.n_per[0], psi0)
-    psi0 = psi0.cpu().numpy().view(np.complex128)
+    # the oracle's own soft-core fit and ground state
+    a_ref = oracle_side.soft_core(w.ip, w.dx)
+    psi0 = oracle_side.ground_state(w.n_per[0], w.dx, a_ref)
     rows = [int(np.argmax(w.e0)), w.batch - 1]
-    ref = oracle.propagate_batch(E[rows].cpu().numpy(), [psi0, psi0], w.dx, w.dt, a_sc,
+    ref = oracle.propagate_batch(w.efield(rows=rows), [psi0, psi0], w.dx, w.dt, a_ref,
                                  mask_frac=w.mask_frac, mask_pow=w.mask_pow, nthreads=2)
     got = acc[rows].cpu().numpy()
     for i, r in enumerate(rows):
         e = rel(got[i], ref["accel"][i])
         print(f"  system {r}: accel rel-L2 {e:.3e}", flush=True)
         assert e < TOL_ACC
+    plan.close()
+
+
+def test_adjoint_workload_full_size(lib, torch_dev):
+    """The adjoint workload at its full size in the benchmark's launch
+    configuration (256 systems x 4096 points x 22047 steps, autotuned plan,
+    checkpoints every 256 steps stored by the forward pass): the gradient of
+    the summed H21-H31 yields for two sampled systems against the oracle's
+    own forward, loss gradient and adjoint, and against central differences
+    of the GPU forward map along 16 seeded directions (h = 1e-6, bar 1e-5)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    torch, dev = torch_dev
+    w = ti.cfg4_adjoint()
+    h_lo, h_hi = w.meta["band"]
+    a_sc, _ = lib.tdse_soft_core_for_ip(w.ip, 2048, w.dx, dtau=1.0, tol=1e-13)
+    p = lib.make_params(w.dx, w.dt, a_sc, w.nt, mask_fraction=w.mask_frac, mask_power=w.mask_pow)
+    plan = lib.Plan(p, w.n_per, adjoint_k=256,
+                    options=lib.TDSE_OPT_STORE_CHECKPOINTS | lib.TDSE_OPT_AUTOTUNE)
+    E = w.efield(xp={"device": dev}).contiguous()
+    k_lo, nk = lib.tdse_harmonic_band(w.nt, w.dt, w.omega, h_lo, h_hi)
+    work = torch.empty(2 * w.batch * nk, dtype=torch.float64, device=dev)
+    y = torch.empty(w.batch, dtype=torch.float64, device=dev)
+    acc = torch.empty_like(E)
+    abar = torch.empty_like(E)
+
+    def loss(field):
+        lib.tdse_propagate_batch(plan, field, None, acc)
+        lib.tdse_harmonic_yield(w.batch, w.nt, w.dt, w.omega, h_lo, h_hi, acc, None, work, y, abar)
+        return float(y.sum())
+
+    print(f"adjoint workload full size: {w.batch} x {w.n_per[0]} x {w.nt}, "
+          f"layout {plan.layout(w.n_per[0])}", flush=True)
+    loss(E)
+    grad = torch.empty_like(E)
+    st = torch.full((w.batch,), -1, dtype=torch.int32, device=dev)
+    lib.tdse_adjoint_batch_stored(plan, plan.checkpoint_generation(), E, abar, grad, st)
+    torch.cuda.synchronize()
+    assert int((st != 0).sum()) == 0
+    g = grad.cpu().numpy()
+    # the oracle side: its own soft-core fit, ground state, forward and loss
+    a_ref = oracle_side.soft_core(w.ip, w.dx)
+    rows = [0, int(np.argmax(w.e0))]
+    e_rows = w.efield(rows=rows)
+    with ThreadPoolExecutor(len(rows)) as ex:
+        refs = list(ex.map(lambda i: oracle_side.yield_gradient(
+            e_rows[i], w.n_per[rows[i]], w.dx, w.dt, a_ref, w.omega, h_lo, h_hi,
+            mask_frac=w.mask_frac, mask_pow=w.mask_pow, k=256), range(len(rows))))
+    for i, r in enumerate(rows):
+        e = rel(g[r], refs[i][1])
+        print(f"  system {r}: grad rel-L2 vs oracle {e:.3e}", flush=True)
+        assert e < 1e-9
+    h = 1e-6
+    for d in range(16):
+        v = torch.tensor(ti.probe_directions(tuple(E.shape), d), dtype=torch.float64, device=dev)
+        fd = (loss(E + h * v) - loss(E - h * v)) / (2 * h)
+        ad = float((grad * v).sum())
+        print(f"  direction {d}: FD {fd:.10e} adjoint {ad:.10e} rel {abs(fd - ad) / abs(fd):.2e}",
+              flush=True)
+        assert abs(fd - ad) <= 1e-5 * abs(fd)
     plan.close()
 
 
@@ -481,10 +542,7 @@ def test_autotuned_plan_matches_oracle(lib, torch_dev):
         assert plan_d.launch_info(n).tuned_rate == 0.0
     assert np.all(out_t["status"] == 0)
     for b, n in enumerate(ns):
-        psi0 = torch.empty(2 * n, dtype=torch.float64, device=dev)
-        plan_t.ground_state(n, psi0)
-        ref = oracle.propagate(efield[b], psi0.cpu().numpy().view(np.complex128), dx, dt, A_AR,
-                               mask_frac=0.1)
+        ref = oracle_side.propagate(efield[b], n, dx, dt, A_AR, mask_frac=0.1)
         assert rel(out_t["accel"][b], ref["accel"]) < TOL_ACC
         assert rel(out_t["accel"][b], out_d["accel"][b]) < 1e-11
     plan_t.close()
@@ -509,9 +567,6 @@ def test_mixed_sizes_share_workgroups(lib, torch_dev):
     assert np.array_equal(out["accel"], out_p["accel"])
     assert np.array_equal(out["psi_final"], out_p["psi_final"])
     for b in (0, 5, 8, 10):
-        psi0 = torch.empty(2 * ns[b], dtype=torch.float64, device=dev)
-        plan.ground_state(ns[b], psi0)
-        ref = oracle.propagate(efield[b], psi0.cpu().numpy().view(np.complex128), dx, dt, A_AR,
-                               mask_frac=0.1)
+        ref = oracle_side.propagate(efield[b], ns[b], dx, dt, A_AR, mask_frac=0.1)
         assert rel(out["accel"][b], ref["accel"]) < TOL_ACC
     plan.close()

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle_side
 import tdse_inputs as ti
 
 pytestmark = pytest.mark.gpu
@@ -111,9 +112,7 @@ def test_stored_states_along_a_propagation(lib, torch_dev):
         torch.cuda.synchronize()
         got = psi.cpu().numpy().view(np.complex128)
         for b, n in enumerate(ns):
-            g0 = torch.empty(2 * n, dtype=torch.float64, device=dev)
-            plan.ground_state(n, g0)
-            psi0 = g0.cpu().numpy().view(np.complex128)
+            psi0 = oracle_side.ground_state(n, dx, 1.1)  # the oracle's own
             steps = index * K
             if steps == 0:
                 ref = psi0
@@ -166,9 +165,7 @@ def test_populations_along_a_propagation(lib, torch_dev):
     torch.cuda.synchronize()
     g, v, gr = gs.cpu().numpy(), vol.cpu().numpy(), gs_ref.cpu().numpy()
     for b, n in enumerate(ns):
-        g0 = torch.empty(2 * n, dtype=torch.float64, device=dev)
-        plan.ground_state(n, g0)
-        psi0 = g0.cpu().numpy().view(np.complex128)
+        psi0 = oracle_side.ground_state(n, dx, a)  # the oracle's own
         for s in (0, 1, nrec // 2, nrec - 1):
             steps = s * K
             psi = psi0 if steps == 0 else oracle.propagate(
