@@ -423,6 +423,23 @@ struct LaneFactors {
         if constexpr (QREG) return ql_;
         else return lc.t > 0 ? ldg(sc.pt.q + lc.il()) : czero();
     }
+    // Elimination factors at point k of the chunk: alpha_k (k >= 1) from
+    // om_{k-1} = om_p and q_{k-1}, beta_k from om_{k+1} = om_n and q_k;
+    // read from the tables where q is not in registers.
+    template <bool RT>
+    __device__ __forceinline__ cd alpha(int k, double om_p, const SizeClass& sc,
+                                        const LaneCtx& lc) const
+    {
+        if constexpr (QREG) return elim<RT>(om_p, q_[k - 1]);
+        else return ldg(sc.pt.alpha + lc.b0 + 64 * k);
+    }
+    template <bool RT>
+    __device__ __forceinline__ cd beta(int k, double om_n, const SizeClass& sc,
+                                       const LaneCtx& lc) const
+    {
+        if constexpr (QREG) return elim<RT>(om_n, q_[k]);
+        else return ldg(sc.pt.beta + lc.b0 + 64 * k);
+    }
 };
 
 template <int C, bool QREG = QInRegs<C>::value>
@@ -577,7 +594,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
             const cd gh = gfac<RT>(om_c + rc.dofs10, v[k]);
             const cd r = mkc(fma(10.0, gh.re, g_p.re + g_n.re), fma(10.0, gh.im, g_p.im + g_n.im));
             v[k] = r;
-            ze = (k == 0) ? r : cmad(elim<RT>(om_p, f.q(k - 1, sc, lc)), ze, r);
+            ze = (k == 0) ? r : cmad(f.template alpha<RT>(k, om_p, sc, lc), ze, r);
             g_p = g_c;
             g_c = g_n;
             om_p = om_c;
@@ -620,8 +637,8 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         const int bc = lcc.b0;
 #pragma unroll
         for (int k = C - 2; k >= 0; --k) {
-            const double om_n = tb.om(bc + 64 * (k + 1));
-            yb = cmad(elim<RT>(om_n, f.q(k, sc, lcc)), yb, v[k]);
+            const double om_n = LF::kRegs ? tb.om(bc + 64 * (k + 1)) : 0.0;
+            yb = cmad(f.template beta<RT>(k, om_n, sc, lcc), yb, v[k]);
             point_fence(yb);
         }
     }
@@ -636,7 +653,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         double om_n = omr;
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
-            y = cmad(elim<RT>(om_n, f.q(k, sc, lcd)), y, v[k]);
+            y = cmad(f.template beta<RT>(k, om_n, sc, lcd), y, v[k]);
             v[k] = y;
             om_n = tb.om(lcd.b0 + 64 * k);
             point_fence(y);

@@ -50,9 +50,10 @@ __host__ __device__ inline int pidx(int t, int k, int C) { return pbase(t, C) + 
 //   q_j   = 1 / (12 p_j)
 //   alpha_j = -(1 + h' om_{j-1}) q_{j-1}    forward  z_j = r_j + alpha_j z_{j-1}
 //   beta_j  = -(1 + h' om_{j+1}) q_j        backward y_j = q_j z_j + beta_j y_{j+1}
-// alpha and beta are kept only to build the lane carry products; the
-// kernels recompute them from om and q (two FMAs each), with q held in
-// registers and om read from LDS.
+// alpha and beta build the lane carry products.  Where q is held in
+// registers the kernels recompute them from om and q (two FMAs each, om read
+// from LDS); where q would be read from memory they read alpha and beta
+// instead, which costs the same 16 bytes and saves the FMAs.
 // Padding points (j >= n) have q = 0, V = 0, dV = 0, m = 0, so they stay 0.
 struct PointTables {
     double* v;      // V_j

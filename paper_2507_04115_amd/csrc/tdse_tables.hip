@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(256) build_tables_kernel(const SizeClass* clas
         cd q_prev = czero(), u_prev = czero(), l_prev = czero();
         for (int j = 0; j < np; ++j) {
             const int idx = pidx(j / C, j % C, C);
-            cd alpha = czero(), q = czero(), beta = czero();
+            cd q = czero();
             if (j < n) {
                 const double vj = sc.pt.v[idx];
                 // diagonal of L: 10/12 + h (1/dx^2 + 10/12 V_j)
@@ -83,7 +83,6 @@ __global__ void __launch_bounds__(256) build_tables_kernel(const SizeClass* clas
                     const cd ell = cmul(l_prev, q_prev);          // l_{j-1} / p_{j-1}
                     d = mkc(d.re - (ell.re * u_prev.re - ell.im * u_prev.im),
                             d.im - (ell.re * u_prev.im + ell.im * u_prev.re));
-                    alpha = mkc(-ell.re, -ell.im);
                 }
                 q = cinv(d);
                 if (j + 1 < n) {
@@ -95,15 +94,33 @@ __global__ void __launch_bounds__(256) build_tables_kernel(const SizeClass* clas
                     // subdiagonal (j+1, j): 1/12 + h (-1/(2dx^2) + V_j/12)
                     const double al = -0.5 * inv_dx2 + m2o * vj;
                     l_prev = mkc(m2o + P.h.re * al, P.h.im * al);
-                    const cd uq = cmul(u_prev, q);
-                    beta = mkc(-uq.re, -uq.im);
                 }
                 q_prev = q;
             }
-            sc.pt.alpha[idx] = alpha;
-            sc.pt.beta[idx] = beta;
             sc.pt.q[idx] = cscale(1.0 / 12.0, q);
         }
+    }
+    __syncthreads();
+
+    // 2b. elimination factors from the stored om and q, by the kernels' own
+    // formula (so a kernel that loads them gets the values it would compute):
+    //   alpha_j = -(1 + h' om_{j-1}) q_{j-1},  beta_j = -(1 + h' om_{j+1}) q_j
+    const bool rt = P.h.im != 0.0;
+    for (int j = threadIdx.x; j < np; j += blockDim.x) {
+        const int idx = pidx(j / C, j % C, C);
+        cd alpha = czero(), beta = czero();
+        if (j < n) {
+            if (j > 0) {
+                const int ip = pidx((j - 1) / C, (j - 1) % C, C);
+                alpha = rt ? elim<true>(sc.pt.om[ip], sc.pt.q[ip]) : elim<false>(sc.pt.om[ip], sc.pt.q[ip]);
+            }
+            if (j + 1 < n) {
+                const int in = pidx((j + 1) / C, (j + 1) % C, C);
+                beta = rt ? elim<true>(sc.pt.om[in], sc.pt.q[idx]) : elim<false>(sc.pt.om[in], sc.pt.q[idx]);
+            }
+        }
+        sc.pt.alpha[idx] = alpha;
+        sc.pt.beta[idx] = beta;
     }
     __syncthreads();
 
