@@ -412,6 +412,9 @@ struct tdse_plan_s {
     std::vector<size_t> plain_smem;
     int ncls_real = 0;                     // classes [0, ncls_real) are real, the rest padding
     int ctr_plain = 0, ctr_fwd = 0;        // offsets into d_counters
+    // elimination factors from their tables in the forward / adjoint
+    // launches of layouts without q in registers (FwdArgs::ab)
+    bool fwd_ab = true, adj_ab = true;
 };
 
 namespace {
@@ -700,6 +703,7 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, i
             break;
         }
         FwdArgs a{};
+        a.ab = 1;  // one size: its tables fit the L2
         a.classes = cs.d;
         a.sys = sys;
         a.bins = bins;
@@ -795,6 +799,7 @@ tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int coun
             break;
         }
         FwdArgs a{};
+        a.ab = 1;  // one size: its tables fit the L2
         a.classes = cs.d;
         a.sys = sys;
         a.order = ord;
@@ -884,6 +889,11 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, hipSt
     *out = best;
     return TDSE_OK;
 }
+
+// L2 bytes that the elimination-factor tables of a plan's layouts without q
+// in registers may take before the plan forms the factors from q instead
+// (half of one XCD's 4 MiB L2).
+constexpr int64_t kAbL2Budget = int64_t(2) << 20;
 
 constexpr double kGsDtau = 0.5;
 constexpr double kGsTol = 1e-13;
@@ -1019,6 +1029,22 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         }
         if (lay[c].T > 1024 || !layout_supported(lay[c].C))
             return bail(fail(TDSE_E_UNSUPPORTED, "no lane layout for n=%d", ns[c]));
+    }
+    // Layouts without q in registers read either q (forming alpha and beta
+    // with two FMAs each) or alpha and beta themselves: no FMAs, but three
+    // tables per point instead of one to keep in every XCD's L2, which pays
+    // only while the tables of all such classes fit in part of it.
+    {
+        int64_t fb = 0, ab = 0;
+        for (int c = 0; c < ncls; ++c) {
+            const int64_t bytes = 3 * (int64_t)sizeof(cd) * lay[c].C * lay[c].T;
+            if (lay[c].C > 8) fb += bytes;   // forward: q in registers up to 8 points
+            if (lay[c].C > 4) ab += bytes;   // adjoint: up to 4
+        }
+        // TDSE_AB_L2_KIB: experiment override of the budget
+        const int64_t budget = (int64_t)env_int("TDSE_AB_L2_KIB", (int)(kAbL2Budget >> 10)) << 10;
+        pl->fwd_ab = fb <= budget;
+        pl->adj_ab = ab <= budget;
     }
     // systems of each class
     pl->ncls_real = ncls;
@@ -1340,6 +1366,7 @@ static tdse_status enqueue_forward(tdse_plan pl, const FwdArgs& base, hipStream_
         a.nbins = G.nbins;
         a.item_off = (int32_t)(G.smem - 16);
         a.queue = ctr + g;
+        a.ab = pl->fwd_ab ? 1 : 0;
         if (launch_forward(G.C, G.tab, a, G.threads, G.smem, G.grid, s) != hipSuccess)
             return fail(TDSE_E_DEVICE, "forward launch failed: %s", hipGetErrorString(hipGetLastError()));
         return TDSE_OK;
@@ -1396,6 +1423,7 @@ static tdse_status enqueue_adjoint(tdse_plan plan, const FwdArgs& base, const do
         a.sub_bytes = (int64_t)sub_smem_bytes(L.T / kWave);
         a.work = plan->d_adj + L.work_off;
         a.slot_doubles = L.slot_doubles;
+        a.ab = plan->adj_ab ? 1 : 0;
         if (launch_adjoint(L.C, L.alds, a, L.T, L.aS, L.agrid, st) != hipSuccess)
             return fail(TDSE_E_DEVICE, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
@@ -1438,6 +1466,7 @@ tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* 
             a.nbins = 1;
             a.item_off = (int32_t)(plan->plain_smem[b] - 16);
             a.queue = ctr + b;
+            a.ab = plan->fwd_ab ? 1 : 0;
             if (launch_forward(L.C, L.tab, a, plan->plain_threads[b], plan->plain_smem[b], 1, st) !=
                 hipSuccess)
                 return fail(TDSE_E_DEVICE, "forward launch failed");

@@ -209,7 +209,7 @@ __device__ __forceinline__ void source_grad_streamed(cd (&kap)[C], cd& kgl, cd& 
 
 }  // namespace
 
-template <int C, bool LDSTAB>
+template <int C, bool LDSTAB, bool AB = false>
 __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
 {
     // the costate doubles the chunk state: pivot factors stay in registers
@@ -287,10 +287,10 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
         for (int k = 0; k < C; ++k) v[k] = (active && s + k < n) ? ld_psi(src, s + k) : czero();
         cd gl = (active && s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
         cd gr = (active && s + C < n) ? ld_psi(src, s + C) : czero();
-        LaneFactors<C, kAdjQRegs> f;
+        LaneFactors<C, kAdjQRegs, AB> f;
         {
             const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
-            f = load_factors<C, kAdjQRegs>(sv.sc, sv.lc);
+            f = load_factors<C, kAdjQRegs, AB>(sv.sc, sv.lc);
         }
         int flushed = 0;
         // forward pass length (uniform): none when the checkpoints are stored
@@ -481,13 +481,19 @@ hipError_t launch_adjoint(int C, bool lds_tables, const FwdArgs& a, int T, int S
 {
     const size_t sh = adjoint_smem_bytes(C, T, S, lds_tables);
     const dim3 b(T * S);
-    switch (C * 2 + (lds_tables ? 1 : 0)) {
-        case 8: hipLaunchKernelGGL((adjoint_kernel<4, false>), dim3(grid), b, sh, st, a); break;
-        case 9: hipLaunchKernelGGL((adjoint_kernel<4, true>), dim3(grid), b, sh, st, a); break;
-        case 16: hipLaunchKernelGGL((adjoint_kernel<8, false>), dim3(grid), b, sh, st, a); break;
-        case 17: hipLaunchKernelGGL((adjoint_kernel<8, true>), dim3(grid), b, sh, st, a); break;
-        case 32: hipLaunchKernelGGL((adjoint_kernel<16, false>), dim3(grid), b, sh, st, a); break;
-        case 33: hipLaunchKernelGGL((adjoint_kernel<16, true>), dim3(grid), b, sh, st, a); break;
+    // above 4 points per lane: elimination factors from their tables (a.ab)
+    // or formed from q and om
+    switch (C * 4 + (lds_tables ? 2 : 0) + (a.ab && C > 4 ? 1 : 0)) {
+        case 16: hipLaunchKernelGGL((adjoint_kernel<4, false>), dim3(grid), b, sh, st, a); break;
+        case 18: hipLaunchKernelGGL((adjoint_kernel<4, true>), dim3(grid), b, sh, st, a); break;
+        case 32: hipLaunchKernelGGL((adjoint_kernel<8, false>), dim3(grid), b, sh, st, a); break;
+        case 33: hipLaunchKernelGGL((adjoint_kernel<8, false, true>), dim3(grid), b, sh, st, a); break;
+        case 34: hipLaunchKernelGGL((adjoint_kernel<8, true>), dim3(grid), b, sh, st, a); break;
+        case 35: hipLaunchKernelGGL((adjoint_kernel<8, true, true>), dim3(grid), b, sh, st, a); break;
+        case 64: hipLaunchKernelGGL((adjoint_kernel<16, false>), dim3(grid), b, sh, st, a); break;
+        case 65: hipLaunchKernelGGL((adjoint_kernel<16, false, true>), dim3(grid), b, sh, st, a); break;
+        case 66: hipLaunchKernelGGL((adjoint_kernel<16, true>), dim3(grid), b, sh, st, a); break;
+        case 67: hipLaunchKernelGGL((adjoint_kernel<16, true, true>), dim3(grid), b, sh, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -290,48 +290,6 @@ __device__ __forceinline__ double wave_sum(double x)
 }
 constexpr int kSumLane = kWave - 1;  // lane holding wave_sum's result
 
-// Halves of a and b exchanged (gfx950 v_permlane32_swap): returns
-// lo = [a lanes 0-31, b lanes 0-31] and hi = [a lanes 32-63, b lanes 32-63].
-__device__ __forceinline__ void swap_halves(double a, double b, double& lo, double& hi)
-{
-    const auto l = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
-    const auto h = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
-    lo = __hiloint2double((int)h[0], (int)l[0]);
-    hi = __hiloint2double((int)h[1], (int)l[1]);
-}
-// Rows of 16 exchanged (v_permlane16_swap): even = [a r0, b r0, a r2, b r2],
-// odd = [a r1, b r1, a r3, b r3].
-__device__ __forceinline__ void swap_rows(double a, double b, double& even, double& odd)
-{
-    const auto l = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
-    const auto h = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
-    even = __hiloint2double((int)h[0], (int)l[0]);
-    odd = __hiloint2double((int)h[1], (int)l[1]);
-}
-
-// Three wavefront sums at once, as a reduce-scatter: the half and row
-// exchanges put the partial sums of a, c, b, c in rows 0, 1, 2, 3, then four
-// in-row DPP steps finish them.  Returns r with the total of a in lane 15,
-// of c in lane 31 (and 63) and of b in lane 47.  About a third of the
-// instructions of three wave_sum calls.
-constexpr int kSum3LaneA = 15, kSum3LaneB = 47, kSum3LaneC = 31;
-__device__ __forceinline__ double wave_sum3(double a, double b, double c)
-{
-    double lo, hi;
-    swap_halves(a, b, lo, hi);
-    const double p = lo + hi;  // lanes 0-31: a over lane pairs; 32-63: b
-    swap_halves(c, c, lo, hi);
-    const double q = lo + hi;  // c over lane pairs, twice
-    double even, odd;
-    swap_rows(p, q, even, odd);
-    double r = even + odd;     // rows: a, c, b, c, each over 4 lanes
-    r += dpp_d<0x111>(r);
-    r += dpp_d<0x112>(r);
-    r += dpp_d<0x114>(r);
-    r += dpp_d<0x118>(r);
-    return r;
-}
-
 // ------------------------------------------------------------ table views
 // om and dV/dx of a size class seen through LDS (staged once per workgroup,
 // shared by its systems) or directly in global memory.  The pivot factors q
@@ -404,10 +362,15 @@ struct QInRegs {
 
 // Per-lane factors: q at the C points of the chunk and at the point before
 // it (when held in registers), and the absorber flags (bit 0: a mask value of
-// the chunk differs from 1; bit 1: at s-1; bit 2: at s+C).
-template <int C, bool QREG = QInRegs<C>::value>
+// the chunk differs from 1; bit 1: at s-1; bit 2: at s+C).  Where q is not
+// in registers, AB selects where the elimination factors come from: the
+// alpha and beta tables (no arithmetic, but three tables to keep in the L2
+// instead of one) or q and om (two FMAs each).
+template <int C, bool QREG = QInRegs<C>::value, bool AB = true>
 struct LaneFactors {
     static constexpr bool kRegs = QREG;  // q held in registers
+    static constexpr bool kTabAB = !QREG && AB;  // alpha, beta read from their tables
+    static constexpr bool kOm = !kTabAB;         // om needed to form them
     static constexpr int NQ = QREG ? C : 1;
     cd q_[NQ];
     cd ql_;
@@ -423,29 +386,30 @@ struct LaneFactors {
         if constexpr (QREG) return ql_;
         else return lc.t > 0 ? ldg(sc.pt.q + lc.il()) : czero();
     }
-    // Elimination factors at point k of the chunk: alpha_k (k >= 1) from
-    // om_{k-1} = om_p and q_{k-1}, beta_k from om_{k+1} = om_n and q_k;
-    // read from the tables where q is not in registers.
+    // Elimination factors at point k of the chunk: alpha_k from
+    // om_{k-1} = om_p and q_{k-1} (the previous lane's last q for k = 0),
+    // beta_k from om_{k+1} = om_n and q_k.
     template <bool RT>
     __device__ __forceinline__ cd alpha(int k, double om_p, const SizeClass& sc,
                                         const LaneCtx& lc) const
     {
-        if constexpr (QREG) return elim<RT>(om_p, q_[k - 1]);
-        else return ldg(sc.pt.alpha + lc.b0 + 64 * k);
+        if constexpr (kTabAB) return ldg(sc.pt.alpha + lc.b0 + 64 * k);
+        else return elim<RT>(om_p, k == 0 ? ql(sc, lc) : q(k - 1, sc, lc));
     }
     template <bool RT>
     __device__ __forceinline__ cd beta(int k, double om_n, const SizeClass& sc,
                                        const LaneCtx& lc) const
     {
-        if constexpr (QREG) return elim<RT>(om_n, q_[k]);
-        else return ldg(sc.pt.beta + lc.b0 + 64 * k);
+        if constexpr (kTabAB) return ldg(sc.pt.beta + lc.b0 + 64 * k);
+        else return elim<RT>(om_n, q(k, sc, lc));
     }
 };
 
-template <int C, bool QREG = QInRegs<C>::value>
-__device__ __forceinline__ LaneFactors<C, QREG> load_factors(const SizeClass& sc, const LaneCtx& lc)
+template <int C, bool QREG = QInRegs<C>::value, bool AB = true>
+__device__ __forceinline__ LaneFactors<C, QREG, AB> load_factors(const SizeClass& sc,
+                                                                 const LaneCtx& lc)
 {
-    LaneFactors<C, QREG> f;
+    LaneFactors<C, QREG, AB> f;
     if constexpr (QREG) {
 #pragma unroll
         for (int k = 0; k < C; ++k) f.q_[k] = ldg(sc.pt.q + lc.b0 + 64 * k);
@@ -614,7 +578,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
     if constexpr (LF::kRegs) load_bwd_windows();
     // B. forward recurrence from the exact carry, w = q z.  When q is read
     // from memory, each sweep hides the chunk base from the optimiser so
-    // that it reloads q and om rather than keeping earlier sweeps' values
+    // that it reloads its factors rather than keeping earlier sweeps' values
     // live (they would be spilled).
     {
         LaneCtx lcb = lc;
@@ -623,7 +587,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         double om_p = oml;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            z = cmad(elim<RT>(om_p, k == 0 ? f.ql(sc, lc) : f.q(k - 1, sc, lcb)), z, v[k]);
+            z = cmad(f.template alpha<RT>(k, om_p, sc, lcb), z, v[k]);
             v[k] = cmul(f.q(k, sc, lcb), z);
             if (k + 1 < C) om_p = tb.om(lcb.b0 + 64 * k);
             point_fence(v[k]);
@@ -637,7 +601,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         const int bc = lcc.b0;
 #pragma unroll
         for (int k = C - 2; k >= 0; --k) {
-            const double om_n = LF::kRegs ? tb.om(bc + 64 * (k + 1)) : 0.0;
+            const double om_n = LF::kOm ? tb.om(bc + 64 * (k + 1)) : 0.0;
             yb = cmad(f.template beta<RT>(k, om_n, sc, lcc), yb, v[k]);
             point_fence(yb);
         }
@@ -838,7 +802,7 @@ __device__ __forceinline__ SubSmem carve_sub(char* base, int W)
 }
 
 // Per-lane partial sums of the observables of the current state, reduced over
-// the wavefront; the lanes holding the totals store (sum V'|psi|^2,
+// the wavefront; the lane holding the totals stores (sum V'|psi|^2,
 // sum x|psi|^2, sum |psi|^2).
 template <int C, class TV>
 __device__ __forceinline__ void observe(const cd (&v)[C], const TV& tb, int T,
@@ -853,11 +817,18 @@ __device__ __forceinline__ void observe(const cd (&v)[C], const TV& tb, int T,
         sv = fma(tb.dv(lc.b0 + 64 * k), p, sv);
         point_fence(sv, sn);
     }
-    const double sx = fma(xs, sn, dx * sk);
-    const double r = wave_sum3(sv, sx, sn);
-    if (lc.lane == kSum3LaneA) slot[lc.wave * 3 + 0] = r;
-    if (lc.lane == kSum3LaneB) slot[lc.wave * 3 + 1] = r;
-    if (lc.lane == kSum3LaneC) slot[lc.wave * 3 + 2] = r;
+    double sx = fma(xs, sn, dx * sk);
+    // three independent DPP reductions: a one-pass reduce-scatter of the
+    // three sums over permlane swaps issues fewer instructions but measured
+    // 3-10 % slower (one serial chain instead of three interleaved ones)
+    sn = wave_sum(sn);
+    sx = wave_sum(sx);
+    sv = wave_sum(sv);
+    if (lc.lane == kSumLane) {
+        slot[lc.wave * 3 + 0] = sv;
+        slot[lc.wave * 3 + 1] = sx;
+        slot[lc.wave * 3 + 2] = sn;
+    }
 }
 
 // Sums the per-wave partials of samples [a0, a1] in wave order and writes

@@ -34,7 +34,7 @@ size_t sub_smem_bytes(int W)
 // systems of one lane layout that together fill the workgroup's lanes (plus a
 // padding system where they do not); every subgroup runs the whole time loop
 // of its system with the same barrier sequence as the others.
-template <int C, int TAB>
+template <int C, int TAB, bool AB = false>
 __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
 {
     extern __shared__ double smem_raw[];
@@ -88,10 +88,10 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
         cd gl = (active && s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
         cd gr = (active && s + C < n) ? ld_psi(src, s + C) : czero();
 
-        LaneFactors<C> f;
+        LaneFactors<C, QInRegs<C>::value, AB> f;
         {
             const StepView<TAB> sv = step_view<TAB>(clsp, wsys, tab);
-            f = load_factors<C>(sv.sc, sv.lc);
+            f = load_factors<C, QInRegs<C>::value, AB>(sv.sc, sv.lc);
             observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, sm.ring);
         }
         __syncthreads();
@@ -293,6 +293,17 @@ hipError_t launch_forward(int C, int tab, const FwdArgs& a, int threads, size_t 
         (size_t)a.item_off + 16 > smem)
         return hipErrorInvalidValue;
     const dim3 b(threads);
+    // 16 points per lane: elimination factors from their tables (a.ab) or
+    // formed from q and om
+    if (C == 16 && a.ab) {
+        switch (tab) {
+            case kTabGlobal: hipLaunchKernelGGL((forward_kernel<16, kTabGlobal, true>), dim3(grid), b, smem, st, a); break;
+            case kTabLds: hipLaunchKernelGGL((forward_kernel<16, kTabLds, true>), dim3(grid), b, smem, st, a); break;
+            case kTabOmLds: hipLaunchKernelGGL((forward_kernel<16, kTabOmLds, true>), dim3(grid), b, smem, st, a); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (C * 4 + tab) {
         case 16: hipLaunchKernelGGL((forward_kernel<4, kTabGlobal>), dim3(grid), b, smem, st, a); break;
         case 17: hipLaunchKernelGGL((forward_kernel<4, kTabLds>), dim3(grid), b, smem, st, a); break;

@@ -45,6 +45,9 @@ struct FwdArgs {
     int64_t slot_doubles;   // doubles per slot
     int32_t k_ckpt;
     int32_t mode;           // kAdjFull, kAdjForwardOnly or kAdjReverseOnly
+    // layouts without q in registers: read the elimination factors from
+    // their tables (1) or form them from q and om (0)
+    int32_t ab;
     // per-system checkpoints and norm rows (stored mode), or NULL: then they
     // live in the slot
     double* store;
