@@ -380,7 +380,8 @@ struct tdse_plan_s {
     std::vector<Launch> launches;       // one per class, longest work first
     std::vector<int> launch_of_cls;
     int32_t* d_order_all = nullptr;     // 2*batch: forward order, adjoint order
-    int32_t* d_counters = nullptr;      // launches + batch (plain mode) + 2*launches (compaction)
+    int32_t* d_counters = nullptr;      // adjoint: launches + 2*launches (compaction); then one
+                                        // kQueueInts queue per system (plain) and per forward group
     int32_t* d_ident = nullptr;
     // graph replay
     hipStream_t cap = nullptr;
@@ -702,6 +703,13 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, i
             rc = fail(TDSE_E_DEVICE, "autotune probe setup failed");
             break;
         }
+        // one queue: every bin in the first run
+        int32_t qb[kQueueInts] = {};
+        for (int x = 1; x <= kXcds; ++x) qb[kXcds + x] = nb;
+        if (hipMemcpy(ctr, qb, sizeof(qb), hipMemcpyHostToDevice) != hipSuccess) {
+            rc = fail(TDSE_E_DEVICE, "autotune probe setup failed");
+            break;
+        }
         FwdArgs a{};
         a.ab = 1;  // one size: its tables fit the L2
         a.classes = cs.d;
@@ -719,7 +727,7 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, i
         float best_ms = 0.0f;
         for (int rep = 0; rep < 3 && rc == TDSE_OK; ++rep) {  // warm-up, then best of two
             float ms = 0.0f;
-            if (launch_reset_counters(ctr, 1, st) != hipSuccess ||
+            if (launch_reset_queues(ctr, 1, st) != hipSuccess ||
                 hipEventRecord(e0, st) != hipSuccess ||
                 launch_forward(L.C, tab, a, S * L.T, smem, grid, st) != hipSuccess ||
                 hipEventRecord(e1, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess ||
@@ -890,11 +898,6 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, hipSt
     return TDSE_OK;
 }
 
-// L2 bytes that the elimination-factor tables of a plan's layouts without q
-// in registers may take before the plan forms the factors from q instead
-// (half of one XCD's 4 MiB L2).
-constexpr int64_t kAbL2Budget = int64_t(2) << 20;
-
 constexpr double kGsDtau = 0.5;
 constexpr double kGsTol = 1e-13;
 constexpr int kGsMaxIter = 100000;
@@ -1030,22 +1033,6 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         if (lay[c].T > 1024 || !layout_supported(lay[c].C))
             return bail(fail(TDSE_E_UNSUPPORTED, "no lane layout for n=%d", ns[c]));
     }
-    // Layouts without q in registers read either q (forming alpha and beta
-    // with two FMAs each) or alpha and beta themselves: no FMAs, but three
-    // tables per point instead of one to keep in every XCD's L2, which pays
-    // only while the tables of all such classes fit in part of it.
-    {
-        int64_t fb = 0, ab = 0;
-        for (int c = 0; c < ncls; ++c) {
-            const int64_t bytes = 3 * (int64_t)sizeof(cd) * lay[c].C * lay[c].T;
-            if (lay[c].C > 8) fb += bytes;   // forward: q in registers up to 8 points
-            if (lay[c].C > 4) ab += bytes;   // adjoint: up to 4
-        }
-        // TDSE_AB_L2_KIB: experiment override of the budget
-        const int64_t budget = (int64_t)env_int("TDSE_AB_L2_KIB", (int)(kAbL2Budget >> 10)) << 10;
-        pl->fwd_ab = fb <= budget;
-        pl->adj_ab = ab <= budget;
-    }
     // systems of each class
     pl->ncls_real = ncls;
     pl->cls_of.resize(batch);
@@ -1171,6 +1158,25 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     if (hipMemcpy(pl->d_bins, hbins.data(), sizeof(BinDesc) * hbins.size(), hipMemcpyHostToDevice) !=
         hipSuccess)
         return bail(fail(TDSE_E_DEVICE, "plan upload failed"));
+    // Per-XCD queues: each group's bins (ordered by lane count, so the
+    // systems of one grid size are contiguous) are cut into kXcds contiguous
+    // runs, one per XCD; a workgroup takes bins from the run of the XCD it
+    // runs on first, so in a group of several sizes each L2 holds the tables
+    // of about 1/kXcds of them.  Every bin of a group fills the same
+    // workgroup (padding included), so the runs hold equal numbers of bins.
+    std::vector<int32_t> xq;  // per group: kXcds + 1 run bounds
+    for (size_t g = 0; g < pl->fgroups.size(); ++g) {
+        const int64_t nb = pl->fgroups[g].nbins;
+        for (int x = 0; x <= kXcds; ++x) xq.push_back((int32_t)(nb * x / kXcds));
+    }
+    {
+        // Layouts without q in registers read alpha and beta from their
+        // tables (no FMAs; three tables per point in the L2 instead of one).
+        // Measured faster than forming them from q and om for every
+        // workload here, the 57-size uneven batch included once its bins are
+        // spread by XCD; TDSE_AB_TABLES=0 forms them from q (experiments).
+        pl->fwd_ab = pl->adj_ab = env_int("TDSE_AB_TABLES", 1) != 0;
+    }
 
     // adjoint launches, one per class, longest work first: classes by
     // (n_pad * count) descending
@@ -1184,12 +1190,25 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     const int nl = ncls;
     const int ng = (int)pl->fgroups.size();
     pl->ctr_plain = 3 * nl;
-    pl->ctr_fwd = 3 * nl + batch;
+    pl->ctr_fwd = 3 * nl + kQueueInts * batch;
     if (hipMalloc(&pl->d_sys, sizeof(SysDesc) * batch) != hipSuccess ||
         hipMalloc(&pl->d_order_all, sizeof(int32_t) * 2 * batch) != hipSuccess ||
-        hipMalloc(&pl->d_counters, sizeof(int32_t) * (3 * nl + batch + ng)) != hipSuccess ||
+        hipMalloc(&pl->d_counters, sizeof(int32_t) * (3 * nl + kQueueInts * (batch + ng))) != hipSuccess ||
         hipMalloc(&pl->d_ident, sizeof(int32_t) * batch) != hipSuccess)
         return bail(fail(TDSE_E_NOMEM, "plan allocation failed"));
+    {
+        // run bounds of the queues (the counters are reset by every launch):
+        // a plain launch's one bin sits in the first run
+        std::vector<int32_t> qs((size_t)kQueueInts * (batch + ng), 0);
+        for (int b = 0; b < batch; ++b)
+            for (int x = 1; x <= kXcds; ++x) qs[(size_t)kQueueInts * b + kXcds + x] = 1;
+        for (int g = 0; g < ng; ++g)
+            for (int x = 0; x <= kXcds; ++x)
+                qs[(size_t)kQueueInts * (batch + g) + kXcds + x] = xq[(size_t)(kXcds + 1) * g + x];
+        if (hipMemcpy(pl->d_counters + pl->ctr_plain, qs.data(), sizeof(int32_t) * qs.size(),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(TDSE_E_DEVICE, "plan upload failed"));
+    }
     std::vector<int32_t> order_all;
     pl->launch_of_cls.assign(ncls, -1);
     const int64_t nt = p->nt;
@@ -1357,7 +1376,7 @@ static tdse_status enqueue_forward(tdse_plan pl, const FwdArgs& base, hipStream_
 {
     const int ng = (int)pl->fgroups.size();
     int32_t* ctr = pl->d_counters + pl->ctr_fwd;
-    if (launch_reset_counters(ctr, ng, st) != hipSuccess)
+    if (launch_reset_queues(ctr, ng, st) != hipSuccess)
         return fail(TDSE_E_DEVICE, "counter reset launch failed");
     auto one = [&](int g, hipStream_t s) -> tdse_status {
         const tdse_plan_s::FwdGroup& G = pl->fgroups[g];
@@ -1365,7 +1384,7 @@ static tdse_status enqueue_forward(tdse_plan pl, const FwdArgs& base, hipStream_
         a.bins = G.d_bins;
         a.nbins = G.nbins;
         a.item_off = (int32_t)(G.smem - 16);
-        a.queue = ctr + g;
+        a.queue = ctr + kQueueInts * g;
         a.ab = pl->fwd_ab ? 1 : 0;
         if (launch_forward(G.C, G.tab, a, G.threads, G.smem, G.grid, s) != hipSuccess)
             return fail(TDSE_E_DEVICE, "forward launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -1454,7 +1473,7 @@ tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* 
     if (plan->options & TDSE_OPT_PLAIN) {
         // one system per launch, serially on the caller's stream
         int32_t* ctr = plan->d_counters + plan->ctr_plain;
-        if (launch_reset_counters(ctr, plan->batch, st) != hipSuccess)
+        if (launch_reset_queues(ctr, plan->batch, st) != hipSuccess)
             return fail(TDSE_E_DEVICE, "counter reset launch failed");
         const BinDesc* pb = plan->d_bins;
         size_t off = 0;
@@ -1465,7 +1484,7 @@ tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* 
             a.bins = pb + off + b;
             a.nbins = 1;
             a.item_off = (int32_t)(plan->plain_smem[b] - 16);
-            a.queue = ctr + b;
+            a.queue = ctr + kQueueInts * b;
             a.ab = plan->fwd_ab ? 1 : 0;
             if (launch_forward(L.C, L.tab, a, plan->plain_threads[b], plan->plain_smem[b], 1, st) !=
                 hipSuccess)

@@ -22,6 +22,10 @@
 
 namespace tdse {
 
+// s_getreg operand of the XCC_ID hardware register (id 20), bits 3:0: the
+// accelerator complex die a wave runs on (size - 1 = 3 goes in bits 15:11).
+constexpr int kHwRegXccId = 20;
+
 size_t sub_smem_bytes(int W)
 {
     size_t b = sizeof(cd) * 2 * kMaxWaves + sizeof(double) * 2 * kMaxWaves +
@@ -45,7 +49,25 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
     const int nt = a.nt;
 
     for (;;) {
-        if (tid == 0) wg_item[0] = atomicAdd(a.queue, 1);
+        if (tid == 0) {
+            // the run of the XCD this workgroup runs on first (its tables
+            // stay in that XCD's L2), then what is left in the other runs;
+            // everything is read here so that nothing stays live in the loop
+            const int home = __builtin_amdgcn_s_getreg((3 << 11) | kHwRegXccId) & (kXcds - 1);
+            const int32_t* bound = a.queue + kXcds;
+            int item = a.nbins;
+            for (int k = 0; k < kXcds; ++k) {
+                const int x = (home + k) & (kXcds - 1);
+                const int lo = bound[x], hi = bound[x + 1];
+                if (lo >= hi) continue;
+                const int i = atomicAdd(a.queue + x, 1);
+                if (lo + i < hi) {
+                    item = lo + i;
+                    break;
+                }
+            }
+            wg_item[0] = item;
+        }
         __syncthreads();
         const int b = uniform(wg_item[0]);
         if (b >= a.nbins) break;
@@ -235,6 +257,19 @@ __global__ void reset_counters_kernel(int32_t* c, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) c[i] = 0;
+}
+
+__global__ void reset_queues_kernel(int32_t* q, int nq)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nq * kXcds) q[(i / kXcds) * kQueueInts + i % kXcds] = 0;
+}
+
+hipError_t launch_reset_queues(int32_t* queues, int nq, hipStream_t st)
+{
+    if (nq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reset_queues_kernel, dim3((nq * kXcds + 63) / 64), dim3(64), 0, st, queues, nq);
+    return hipGetLastError();
 }
 
 hipError_t launch_reset_counters(int32_t* counters, int n, hipStream_t st)

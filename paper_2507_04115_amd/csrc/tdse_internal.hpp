@@ -109,6 +109,9 @@ struct BinSub {
     int32_t pad_[2];
 };
 
+constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
+constexpr int kQueueInts = 2 * kXcds + 1;  // a forward work queue: counters, run bounds
+
 struct BinDesc {
     int32_t nsub;
     int32_t pad_[3];

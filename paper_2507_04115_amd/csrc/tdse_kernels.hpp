@@ -25,7 +25,10 @@ struct FwdArgs {
     const int32_t* order;   // systems of this launch, in queue order
     int32_t count;          // number of entries in `order`
     int32_t cls;            // size class of every system of this launch
-    int32_t* queue;         // work counter, reset to 0 before the launch
+    // adjoint: one work counter, reset to 0 before the launch.  forward:
+    // kQueueInts ints, queue[x] the counter of XCD x (reset to 0 before the
+    // launch) and queue[kXcds + x] .. queue[kXcds + x + 1] the bins of its run
+    int32_t* queue;
     int32_t nt;
     int64_t sub_bytes;      // LDS bytes per subgroup
     double dt;
@@ -158,6 +161,8 @@ hipError_t launch_band_adjoint(const BandAdjArgs& a, hipStream_t st);
 hipError_t launch_build_tables(const SizeClass* d_classes, const TableParams* d_params, int ncls,
                                double* d_metrics, cd* d_scratch, int max_t, hipStream_t st);
 hipError_t launch_reset_counters(int32_t* counters, int n, hipStream_t st);
+// Zeroes the kXcds counters of `nq` consecutive forward queues.
+hipError_t launch_reset_queues(int32_t* queues, int nq, hipStream_t st);
 bool layout_supported(int C);
 size_t sub_smem_bytes(int W);
 

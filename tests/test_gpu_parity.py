@@ -403,9 +403,10 @@ def test_table_placement_does_not_change_results(lib, torch_dev, monkeypatch):
 
 def test_elimination_factor_source_does_not_change_results(lib, torch_dev, monkeypatch):
     """Layouts without q in registers (16 points per lane forward, 8 and 16
-    in the adjoint) read alpha and beta from their tables when the plan's
-    tables fit the L2 budget, else form them from q and om: both give the
-    same forward outputs and gradients to rounding, and the oracle's."""
+    in the adjoint) read alpha and beta from their tables, or form them from
+    q and om (TDSE_AB_TABLES=0): the tables hold the kernels' own values, so
+    both give bitwise the same forward outputs and gradients, and the
+    oracle's."""
     torch, dev = torch_dev
     ns = [3000, 9000, 12000]
     dx, dt, a, nt, k = 0.2, 0.05, A_AR, 150, 40
@@ -417,24 +418,24 @@ def test_elimination_factor_source_does_not_change_results(lib, torch_dev, monke
     res = {}
     for budget in (None, "0"):
         if budget is None:
-            monkeypatch.delenv("TDSE_AB_L2_KIB", raising=False)
+            monkeypatch.delenv("TDSE_AB_TABLES", raising=False)
         else:
-            monkeypatch.setenv("TDSE_AB_L2_KIB", budget)
+            monkeypatch.setenv("TDSE_AB_TABLES", budget)
         plan = lib.Plan(p, ns, adjoint_k=k)
-        monkeypatch.delenv("TDSE_AB_L2_KIB", raising=False)
+        monkeypatch.delenv("TDSE_AB_TABLES", raising=False)
         acc = torch.empty_like(E)
         g = torch.empty_like(E)
         lib.tdse_propagate_batch(plan, E, None, acc)
         lib.tdse_adjoint_batch(plan, E, None, AB, g)
         torch.cuda.synchronize()
         res[budget] = (acc.cpu().numpy(), g.cpu().numpy())
-        print(f"  budget {budget}: layouts {[plan.layout(n).points_per_lane for n in ns]}", flush=True)
+        print(f"  TDSE_AB_TABLES={budget}: layouts {[plan.layout(n).points_per_lane for n in ns]}", flush=True)
         plan.close()
     for b, n in enumerate(ns):
         r_acc = rel(res[None][0][b], res["0"][0][b])
         r_g = rel(res[None][1][b], res["0"][1][b])
         print(f"  n={n}: tables vs formed: accel {r_acc:.2e}, grad {r_g:.2e}", flush=True)
-        assert r_acc < 1e-12 and r_g < 1e-12
+        assert r_acc == 0.0 and r_g == 0.0
     for b in (1, 2):
         g_ref, acc_ref = oracle_side.adjoint(efield[b], abar[b], ns[b], dx, dt, a, mask_frac=0.1,
                                              k=k)
