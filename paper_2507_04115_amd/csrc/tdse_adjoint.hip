@@ -481,15 +481,15 @@ hipError_t launch_adjoint(int C, bool lds_tables, const FwdArgs& a, int T, int S
 {
     const size_t sh = adjoint_smem_bytes(C, T, S, lds_tables);
     const dim3 b(T * S);
-    // above 4 points per lane: elimination factors from their tables (a.ab)
-    // or formed from q and om
-    switch (C * 4 + (lds_tables ? 2 : 0) + (a.ab && C > 4 ? 1 : 0)) {
+    // 16 points per lane: elimination factors from their tables (a.ab) or
+    // formed from q and om.  At 8 points the tables measured 26 % slower on
+    // the 256 on-axis systems of the full focal volume (N = 8192), so that
+    // layout always forms them.
+    switch (C * 4 + (lds_tables ? 2 : 0) + (a.ab && C > 8 ? 1 : 0)) {
         case 16: hipLaunchKernelGGL((adjoint_kernel<4, false>), dim3(grid), b, sh, st, a); break;
         case 18: hipLaunchKernelGGL((adjoint_kernel<4, true>), dim3(grid), b, sh, st, a); break;
         case 32: hipLaunchKernelGGL((adjoint_kernel<8, false>), dim3(grid), b, sh, st, a); break;
-        case 33: hipLaunchKernelGGL((adjoint_kernel<8, false, true>), dim3(grid), b, sh, st, a); break;
         case 34: hipLaunchKernelGGL((adjoint_kernel<8, true>), dim3(grid), b, sh, st, a); break;
-        case 35: hipLaunchKernelGGL((adjoint_kernel<8, true, true>), dim3(grid), b, sh, st, a); break;
         case 64: hipLaunchKernelGGL((adjoint_kernel<16, false>), dim3(grid), b, sh, st, a); break;
         case 65: hipLaunchKernelGGL((adjoint_kernel<16, false, true>), dim3(grid), b, sh, st, a); break;
         case 66: hipLaunchKernelGGL((adjoint_kernel<16, true>), dim3(grid), b, sh, st, a); break;
