@@ -222,6 +222,51 @@ def test_invalid_arguments_are_refused_before_any_launch(lib, torch_dev):
     plan.close()
 
 
+@pytest.mark.parametrize("nt", [0, 1, 5])
+def test_degenerate_lengths_and_layout_boundaries(lib, torch_dev, nt):
+    """Propagations of 0, 1 and 5 steps (checkpoint interval longer than the
+    run, and one checkpoint per step) on the smallest grid and on both sides
+    of every layout boundary (4 | 8 points per lane at 512, 8 | 16 at 8192):
+    outputs, final states and gradients, recomputed and from stored
+    checkpoints, against the oracle."""
+    torch, dev = torch_dev
+    ns = [16, 17, 511, 512, 513, 8192, 8193]
+    dx, dt, a = 0.4, 0.05, 1.1
+    rng = np.random.default_rng(100 + nt)
+    efield = 0.05 * rng.standard_normal((len(ns), nt + 1))
+    abar = rng.standard_normal((len(ns), nt + 1))
+    E, AB = _to_dev(torch, dev, efield), _to_dev(torch, dev, abar)
+    p = lib.make_params(dx, dt, a, nt, mask_fraction=0.2)
+    for k in (256, 1):
+        print(f"degenerate ns={ns} nt={nt} K={k}", flush=True)
+        plan = lib.Plan(p, ns, adjoint_k=k, options=lib.TDSE_OPT_STORE_CHECKPOINTS)
+        acc, xe, nr = (torch.empty_like(E) for _ in range(3))
+        pf = torch.empty(2 * sum(ns), dtype=torch.float64, device=dev)
+        st = torch.full((len(ns),), -1, dtype=torch.int32, device=dev)
+        lib.tdse_propagate_batch(plan, E, None, acc, xe, nr, pf, st)
+        g_st = torch.full_like(E, 7.0)
+        lib.tdse_adjoint_batch_stored(plan, plan.checkpoint_generation(), E, AB, g_st)
+        g = torch.full_like(E, 7.0)
+        lib.tdse_adjoint_batch(plan, E, None, AB, g)
+        torch.cuda.synchronize()
+        assert np.all(st.cpu().numpy() == 0)
+        assert np.array_equal(g.cpu().numpy(), g_st.cpu().numpy())
+        off = plan.psi_offsets()
+        got = {key: t.cpu().numpy() for key, t in (("accel", acc), ("xexp", xe), ("norm", nr))}
+        pfin = pf.cpu().numpy().view(np.complex128)
+        gg = g.cpu().numpy()
+        for b, n in enumerate(ns):
+            ref = oracle_side.propagate(efield[b], n, dx, dt, a, mask_frac=0.2, want_psi=True)
+            g_ref, _ = oracle_side.adjoint(efield[b], abar[b], n, dx, dt, a, mask_frac=0.2, k=k)
+            for key in ("accel", "norm"):
+                assert rel(got[key][b], ref[key]) < TOL_ACC, (n, key)
+            # <x> is zero by symmetry at t = 0: compare on the scale of the grid
+            assert np.max(np.abs(got["xexp"][b] - ref["xexp"])) < TOL_ACC * n * dx
+            assert rel(pfin[off[b]:off[b + 1]], ref["psi_final"]) < TOL_ACC
+            assert rel(gg[b], g_ref) < 1e-9, (n, k)
+        plan.close()
+
+
 def test_harmonic_yield_matches_oracle(lib, torch_dev):
     torch, dev = torch_dev
     rng = np.random.default_rng(4)
