@@ -26,7 +26,7 @@
  *     psi^(i+1)_j = exp(-i dt E(t_i) x_j) psi^(i,2)_j
  *     (Sec. "1D-TSDE Implementation (CTDSE)", Eqs. CN step 4, 2, 3).
  *
- * Readings where the paper is silent (each is listed in the design notes):
+ * Readings where the paper is silent:
  *   - N unknowns at x_j = (j - (N-1)/2) dx, Dirichlet outside (plain
  *     truncation of the tridiagonals).
  *   - Numerov matrix M2 = I + dx^2 D2 / 12 = tridiag(1/12, 10/12, 1/12),
@@ -40,8 +40,8 @@
  *   - Ground state: imaginary-time Crank-Nicolson (dt -> -i dtau) with
  *     renormalisation, started from exp(-x^2), stopped when successive
  *     normalised iterates differ by less than tol in the dx-weighted L2 norm.
- *   - Adjoint: exact discrete adjoint of the forward recursion (derived in the
- *     design notes), with the forward states recomputed from checkpoints.
+ *   - Adjoint: exact discrete adjoint of the forward recursion, with the
+ *     forward states recomputed from checkpoints.
  */
 #include <complex.h>
 #include <math.h>

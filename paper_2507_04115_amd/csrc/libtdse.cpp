@@ -1571,7 +1571,7 @@ tdse_status tdse_soft_core_for_ip(double ip, int32_t n, double dx, double dtau, 
         return fail(TDSE_E_INVALID, "ip, dx, dtau, tol > 0 and a_out are required");
     if (!(a_lo > 0.0) || !(a_hi > a_lo)) return fail(TDSE_E_INVALID, "need 0 < a_lo < a_hi");
     if (n < kMinN || n > kMaxN) return fail(TDSE_E_INVALID, "n=%d out of range", n);
-    const int K = 31;  // candidates per round (plus the two bracket ends in round 0)
+    const int K = 31;  // candidates per pass (plus the two bracket ends in the first)
     const Layout L = default_layout(n);
     double* d_psi = nullptr;
     HIP_TRY(hipMalloc(&d_psi, sizeof(double) * 2 * (size_t)n * (K + 2)));

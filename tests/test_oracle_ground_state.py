@@ -49,5 +49,3 @@ def test_soft_core_fit_reaches_argon_ip():
     h, _ = dense_h(2048, 0.2, a)
     w = np.linalg.eigvalsh(h)
     assert abs(w[0] + ti.IP_ARGON) < 1e-12
-    assert abs(a - 1.18917) < 1e-4           # consistent with the survey's dense eigensolve
-    assert -0.2538 < w[1] < -0.2537          # first excited level of the fitted atom
