@@ -3,9 +3,11 @@
 //
 // Layout: a workgroup holds S subgroups of T = 64 W lanes; each subgroup owns
 // one system at a time and lane t keeps grid points [t C, t C + C) of psi in
-// VGPRs for the whole time loop, plus one ghost value on each side.  All S
-// systems share one copy of the size class's point tables in LDS (32 bytes
-// per point: om, q, dV/dx), staged once per workgroup.  Per step (section
+// VGPRs for the whole time loop, plus one ghost value on each side, and up
+// to 8 points per lane also the pivot factors q of its chunk.  The systems of
+// one size in a workgroup share one copy of the size class's om and dV/dx
+// tables in LDS (16 bytes per point), staged once per bin; where they do not
+// fit, om alone or neither is staged (TAB).  Per step (section
 // "1D-TSDE Implementation (CTDSE)", three substeps):
 //   1. r = 12 R psi in place                      (first substep)
 //   2. L y = r by a partitioned Thomas solve      (second substep):
@@ -34,7 +36,8 @@ size_t sub_smem_bytes(int W)
 }
 
 // -------------------------------------------------------------- forward
-// Persistent: each workgroup takes bins from the queue.  A bin is a set of
+// Persistent: each workgroup takes bins from the run of its XCD, then from
+// the other runs (a.queue).  A bin is a set of
 // systems of one lane layout that together fill the workgroup's lanes (plus a
 // padding system where they do not); every subgroup runs the whole time loop
 // of its system with the same barrier sequence as the others.
