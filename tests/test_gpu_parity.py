@@ -546,6 +546,43 @@ def test_focus_batch_full_size_sampled(lib, torch_dev):
     plan.close()
 
 
+def test_uneven_workload_full_size_sampled(lib, torch_dev):
+    """The uneven workload at its full size in the benchmark's launch
+    configuration (4096 systems, six grid sizes 2048-3328 sharing
+    workgroups, 85 924 steps, autotuned plan, graph replay): the systems with
+    the smallest and the largest grid against the oracle over the whole
+    pulse, every status clean."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    torch, dev = torch_dev
+    w = ti.cfg3_uneven()
+    a_sc, _ = lib.tdse_soft_core_for_ip(w.ip, 2048, w.dx, dtau=1.0, tol=1e-13)
+    p = lib.make_params(w.dx, w.dt, a_sc, w.nt, mask_fraction=w.mask_frac, mask_power=w.mask_pow)
+    plan = lib.Plan(p, w.n_per, options=lib.TDSE_OPT_AUTOTUNE)
+    E = w.efield(xp={"device": dev}).contiguous()
+    acc = torch.empty_like(E)
+    st = torch.full((w.batch,), -1, dtype=torch.int32, device=dev)
+    print(f"uneven full size: {w.batch} systems, n {min(w.n_per)}-{max(w.n_per)}, nt={w.nt}",
+          flush=True)
+    lib.tdse_propagate_batch(plan, E, None, acc, None, None, None, st)
+    torch.cuda.synchronize()
+    assert int((st != 0).sum()) == 0
+    order = np.argsort(w.n_per, kind="stable")
+    rows = [int(order[0]), int(order[-1])]
+    a_ref = oracle_side.soft_core(w.ip, w.dx)
+    e_rows = w.efield(rows=rows)
+    with ThreadPoolExecutor(len(rows)) as ex:
+        refs = list(ex.map(lambda i: oracle_side.propagate(
+            e_rows[i], w.n_per[rows[i]], w.dx, w.dt, a_ref, mask_frac=w.mask_frac,
+            mask_pow=w.mask_pow)["accel"], range(len(rows))))
+    got = acc[rows].cpu().numpy()
+    for i, r in enumerate(rows):
+        e = rel(got[i], refs[i])
+        print(f"  system {r} (n={w.n_per[r]}): accel rel-L2 {e:.3e}", flush=True)
+        assert e < TOL_ACC
+    plan.close()
+
+
 def test_adjoint_workload_full_size(lib, torch_dev):
     """The adjoint workload at its full size in the benchmark's launch
     configuration (256 systems x 4096 points x 22047 steps, autotuned plan,
