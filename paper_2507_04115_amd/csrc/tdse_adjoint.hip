@@ -344,7 +344,13 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
             const int s0 = sidx * K;
             const int s1 = min(s0 + K, nt);
             // recompute psi^{s0..s1} into the segment buffer
-            if constexpr (kStream) store_state<C>(kbuf, T, loff, kap, kgl, kgr);
+            if constexpr (kStream) {
+                // the streamed reads of the previous segment's states (after
+                // the last costate step's barriers) are done in every wave
+                // before its first state is overwritten
+                __syncthreads();
+                store_state<C>(kbuf, T, loff, kap, kgl, kgr);
+            }
             load_state<C>(ckpt + np2 * sidx, T, loff, v, gl, gr);
             store_chunk<C>(seg, T, loff, v);
             for (int i = s0; i < s1; ++i) {
@@ -358,6 +364,8 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
                 // kappa^nt = 2 abar_nt dx (V' + E_nt) conj(psi^nt); psi^nt = v
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 if constexpr (kStream) {
+                    // psi^nt was just stored; its ghosts are other waves' entries
+                    __syncthreads();
                     source_grad_streamed<C>(kap, kgl, kgr, seg + nps * (s1 - s0), T, t, loff,
                                             2.0 * abar[nt] * dx, erow[nt], sv.tb, sv.lc, nt > 0,
                                             sv.xs, dx, ring + ((nt > 0 ? nt - 1 : 0) % kRing) * W);
