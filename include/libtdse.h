@@ -268,14 +268,23 @@ tdse_status tdse_plan_populations(tdse_plan plan, uint64_t generation, const dou
  *   psi       dev ragged complex (tdse_plan_psi_offsets)
  *   energies  dev [n_energy];  eps > 0 (the resolution)
  *   spectrum  dev [batch][n_energy]
- *   work      dev scratch of work_bytes bytes, at least 64 * 32 * n_max
- *             (n_max = the plan's largest n); 32 n_max bytes hold one
- *             (system, energy) solve in flight, and about 64k of them keep
- *             the GPU busy.  Contents on return are undefined.
+ *   work      dev scratch of work_bytes bytes, 16-byte aligned: first the
+ *             elimination factors shared by the systems of one size (32 n_max
+ *             bytes per grid size and energy, n_max = the plan's largest n),
+ *             then 16 n_max bytes per (system, energy) solve in flight, at
+ *             least 64 of them; about 64k keep the GPU busy.
+ *             tdse_plan_energy_spectrum_work gives the size for a number of
+ *             solves in flight.  Contents on return are undefined.
+ * Fails with TDSE_E_INVALID, before any launch, when work is too small.
  * Asynchronous on `stream`; allocates nothing. */
 tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t n_energy,
                                       const double* energies, double eps, double* spectrum,
                                       void* work, size_t work_bytes, void* stream);
+
+/* Bytes of work tdse_plan_energy_spectrum needs for n_energy energies with
+ * `lanes` (>= 64) solves in flight (host output). */
+tdse_status tdse_plan_energy_spectrum_work(tdse_plan plan, int32_t n_energy, int64_t lanes,
+                                           size_t* bytes);
 
 /* Gabor transform of the source term (section "Physical Examples &
  * tutorials", the microscopic analysis: a joint time-frequency picture of

@@ -76,6 +76,7 @@ _PROTOS = {
     "tdse_harmonic_band": (_i32, [_i32, _d, _d, _d, _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "tdse_harmonic_yield": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tdse_plan_energy_spectrum": (_i32, [_vp, _vp, _i32, _vp, _d, _vp, _vp, ctypes.c_size_t, _vp]),
+    "tdse_plan_energy_spectrum_work": (_i32, [_vp, _i32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "tdse_plan_stored_state": (_i32, [_vp, ctypes.c_uint64, _i32, _vp, _vp]),
     "tdse_plan_populations": (_i32, [_vp, ctypes.c_uint64, _vp, _d, _vp, _vp, _vp]),
     "tdse_gabor": (_i32, [_i32, _i32, _d, _vp, _i32, _vp, _i32, _vp, _d, _vp, _vp]),
@@ -352,6 +353,14 @@ def tdse_plan_energy_spectrum(plan: Plan, psi, energies, eps: float, spectrum, w
                                             _ptr(energies), float(eps), _ptr(spectrum), _ptr(work),
                                             work.numel() * work.element_size(), _stream(stream)),
            "tdse_plan_energy_spectrum")
+
+
+def tdse_plan_energy_spectrum_work(plan: Plan, n_energy: int, lanes: int = 65536) -> int:
+    """Bytes of work tdse_plan_energy_spectrum needs with `lanes` solves in flight."""
+    b = ctypes.c_size_t()
+    _check(load().tdse_plan_energy_spectrum_work(plan.handle, int(n_energy), int(lanes),
+                                                 ctypes.byref(b)), "tdse_plan_energy_spectrum_work")
+    return b.value
 
 
 def tdse_gabor(accel, dt: float, t_centres, omegas, sigma: float, out, stream=None):

@@ -1803,13 +1803,21 @@ tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t
         return fail(TDSE_E_INVALID, "psi, energies, spectrum and work are required");
     if (!aligned16(psi) || !aligned16(work)) return fail(TDSE_E_INVALID, "psi and work must be 16-byte aligned");
     const int n_max = *std::max_element(plan->n_per.begin(), plan->n_per.end());
-    const size_t per_lane = 32 * (size_t)n_max;
+    const int64_t pairs = (int64_t)plan->ncls_real * n_energy;
+    if (pairs > std::numeric_limits<int32_t>::max())
+        return fail(TDSE_E_INVALID, "too many (size, energy) pairs");
+    const size_t fac = spectrum_factor_bytes(n_max, pairs);
+    const size_t per_lane = 16 * (size_t)n_max;
     const int64_t items = (int64_t)plan->batch * n_energy;
-    int64_t lanes = (int64_t)std::min<size_t>(work_bytes / per_lane, (size_t)1 << 20);
-    if (lanes < kWave)
-        return fail(TDSE_E_INVALID, "work must hold at least %zu bytes (64 lanes of 32 n_max)", kWave * per_lane);
+    if (work_bytes < fac + kWave * per_lane)
+        return fail(TDSE_E_INVALID,
+                    "work must hold at least %zu bytes: %zu of elimination factors and 64 lanes of %zu",
+                    fac + kWave * per_lane, fac, per_lane);
+    int64_t lanes = (int64_t)std::min<size_t>((work_bytes - fac) / per_lane, (size_t)1 << 20);
     lanes = std::min<int64_t>(lanes, (items + kWave - 1) / kWave * kWave);
     SpecArgs a{};
+    a.fac = reinterpret_cast<cd*>(work);
+    a.pairs = (int32_t)pairs;
     a.classes = plan->cls.d;
     a.sys = plan->d_sys;
     a.batch = plan->batch;
@@ -1818,9 +1826,21 @@ tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t
     a.energies = energies;
     a.eps = eps;
     a.out = spectrum;
-    a.work = reinterpret_cast<cd*>(work);
+    a.work = reinterpret_cast<cd*>(static_cast<char*>(work) + fac);
     a.lanes = lanes;
     HIP_TRY(launch_energy_spectrum(a, reinterpret_cast<hipStream_t>(stream)));
+    return TDSE_OK;
+}
+
+tdse_status tdse_plan_energy_spectrum_work(tdse_plan plan, int32_t n_energy, int64_t lanes,
+                                           size_t* bytes)
+{
+    g_last_error.clear();
+    if (!plan || !bytes) return fail(TDSE_E_INVALID, "plan and bytes are required");
+    if (n_energy < 1 || lanes < kWave) return fail(TDSE_E_INVALID, "need n_energy >= 1 and lanes >= 64");
+    const int n_max = *std::max_element(plan->n_per.begin(), plan->n_per.end());
+    *bytes = spectrum_factor_bytes(n_max, (int64_t)plan->ncls_real * n_energy) +
+             (size_t)lanes * 16 * (size_t)n_max;
     return TDSE_OK;
 }
 

@@ -108,7 +108,9 @@ struct SpecArgs {
     const double* energies;  // [n_energy]
     double eps;
     double* out;             // [batch][n_energy]
-    cd* work;                // [n_max][lanes] pairs (c', d')
+    cd* fac;                 // [n_max][pairs] (c', 1/pivot), pair = class * n_energy + energy
+    int32_t pairs;           // real classes * n_energy
+    cd* work;                // [n_max][lanes] d'
     int64_t lanes;
 };
 
@@ -150,6 +152,8 @@ struct YieldArgs {
 
 hipError_t launch_far_field(const FarArgs& a, bool adjoint, hipStream_t st);
 hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st);
+// Bytes of the shared elimination factors of tdse_plan_energy_spectrum.
+size_t spectrum_factor_bytes(int n_max, int64_t pairs);
 hipError_t launch_gabor(const GaborArgs& a, hipStream_t st);
 hipError_t launch_populations(const PopArgs& a, hipStream_t st);
 hipError_t launch_stored_state(const SizeClass* classes, const SysDesc* sys, int batch, int n_max,

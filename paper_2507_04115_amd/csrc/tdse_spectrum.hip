@@ -12,21 +12,67 @@
 //   diagonal   (E - i eps) 10/12 - 1/dx^2 - 10/12 V_j
 //   T[j, j-1]  (E - i eps) /12 + 1/(2 dx^2) - V_{j-1}/12   (and T[j, j+1] with V_{j+1}).
 // Its imaginary part -eps M2 is negative definite, so elimination without
-// pivoting meets no zero pivot.  One lane per (system, energy): forward
-// elimination storing (c'_j, d'_j) in the caller's workspace (interleaved by
-// lane, so the stores are coalesced), then back substitution accumulating
-// |phi_j|^2.  Lanes of a wavefront mostly share the system, so psi and V
-// are broadcast loads.
+// pivoting meets no zero pivot.  The elimination factors (c'_j, 1/p_j) of
+// each (size class, energy) pair go to the head of the caller's workspace;
+// then one lane per (system, energy) runs the forward elimination of d'_j
+// into its own part of the workspace (interleaved by lane, so the stores are
+// coalesced) and the back substitution accumulating |phi_j|^2.  Lanes of a
+// wavefront mostly share the system, so psi and V are broadcast loads and
+// the factors of neighbouring energies are adjacent.
 #include "tdse_device.hpp"
 #include "tdse_kernels.hpp"
 
 namespace tdse {
+
+// The coefficients of the system depend on the size class and the energy
+// only, so the elimination factors c'_j = up_j / p_j and 1/p_j (p_j the
+// pivot) are formed once per (class, energy) pair, one lane per pair, and
+// shared by every system of that size; each (system, energy) lane then only
+// carries d'_j = (rhs_j - low_j d'_{j-1}) / p_j through its own workspace.
+__device__ __forceinline__ void spec_coefs(const SpecArgs& a, double E, double dx, double& off_re,
+                                           double& off_im, double& dia_re, double& dia_im)
+{
+    const double k2 = 1.0 / (dx * dx);
+    off_re = E / 12.0 + 0.5 * k2;
+    off_im = -a.eps / 12.0;
+    dia_re = E * (10.0 / 12.0) - k2;
+    dia_im = -a.eps * (10.0 / 12.0);
+}
+
+__global__ void __launch_bounds__(256) spectrum_factor_kernel(SpecArgs a)
+{
+    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pair >= a.pairs) return;
+    const int c = pair / a.n_energy, e = pair - c * a.n_energy;
+    const SizeClass& sc = a.classes[c];
+    const int n = sc.n, C = sc.C;
+    const double* v = sc.pt.v;
+    double off_re, off_im, dia_re, dia_im;
+    spec_coefs(a, a.energies[e], sc.dx, off_re, off_im, dia_re, dia_im);
+    const int64_t P = a.pairs;
+    cd cp = czero();
+    double vm = 0.0, v0 = v[pidx(0, 0, C)];
+    for (int j = 0; j < n; ++j) {
+        const bool last = j + 1 == n;
+        const double vp = last ? 0.0 : v[pidx((j + 1) / C, (j + 1) % C, C)];
+        const cd dia = mkc(dia_re - (10.0 / 12.0) * v0, dia_im);
+        const cd low = j > 0 ? mkc(off_re - vm / 12.0, off_im) : czero();
+        const cd up = last ? czero() : mkc(off_re - vp / 12.0, off_im);
+        const cd inv = cinv(cadd(dia, cscale(-1.0, cmul(low, cp))));
+        cp = cmul(up, inv);
+        a.fac[2 * ((int64_t)j * P + pair)] = cp;
+        a.fac[2 * ((int64_t)j * P + pair) + 1] = inv;
+        vm = v0;
+        v0 = vp;
+    }
+}
 
 __global__ void __launch_bounds__(256) energy_spectrum_kernel(SpecArgs a)
 {
     const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (lane >= a.lanes) return;
     const int64_t items = (int64_t)a.batch * a.n_energy;
+    const int64_t P = a.pairs;
     for (int64_t it = lane; it < items; it += a.lanes) {
         const int b = (int)(it / a.n_energy);
         const int e = (int)(it - (int64_t)b * a.n_energy);
@@ -36,30 +82,27 @@ __global__ void __launch_bounds__(256) energy_spectrum_kernel(SpecArgs a)
         const double dx = sc.dx;
         const double* v = sc.pt.v;
         const double* psi = a.psi + 2 * d.psi_off;
-        const double E = a.energies[e], eps = a.eps;
-        const double k2 = 1.0 / (dx * dx);
-        const double off_re = E / 12.0 + 0.5 * k2, off_im = -eps / 12.0;
-        const double dia_re = E * (10.0 / 12.0) - k2, dia_im = -eps * (10.0 / 12.0);
+        const int64_t pair = (int64_t)d.cls * a.n_energy + e;
+        double off_re, off_im, dia_re, dia_im;
+        spec_coefs(a, a.energies[e], dx, off_re, off_im, dia_re, dia_im);
         cd* w = a.work;
         const int64_t L = a.lanes;
 
-        // forward elimination
-        cd cp = czero(), dp = czero();
+        // forward elimination: d' only (c' and 1/p from the shared factors,
+        // loads of several points issued ahead of their use)
+        cd dp = czero();
         cd pm = czero(), p0 = ld_psi(psi, 0);
         double vm = 0.0, v0 = v[pidx(0, 0, C)];
+#pragma unroll 8
         for (int j = 0; j < n; ++j) {
             const bool last = j + 1 == n;
             const cd pp = last ? czero() : ld_psi(psi, j + 1);
             const double vp = last ? 0.0 : v[pidx((j + 1) / C, (j + 1) % C, C)];
-            const cd dia = mkc(dia_re - (10.0 / 12.0) * v0, dia_im);
             const cd low = j > 0 ? mkc(off_re - vm / 12.0, off_im) : czero();
-            const cd up = last ? czero() : mkc(off_re - vp / 12.0, off_im);
             const cd rhs = mkc((pm.re + 10.0 * p0.re + pp.re) / 12.0, (pm.im + 10.0 * p0.im + pp.im) / 12.0);
-            const cd inv = cinv(cadd(dia, cscale(-1.0, cmul(low, cp))));
-            cp = cmul(up, inv);
+            const cd inv = a.fac[2 * ((int64_t)j * P + pair) + 1];
             dp = cmul(cadd(rhs, cscale(-1.0, cmul(low, dp))), inv);
-            w[2 * ((int64_t)j * L + lane)] = cp;
-            w[2 * ((int64_t)j * L + lane) + 1] = dp;
+            w[(int64_t)j * L + lane] = dp;
             pm = p0;
             p0 = pp;
             vm = v0;
@@ -68,14 +111,20 @@ __global__ void __launch_bounds__(256) energy_spectrum_kernel(SpecArgs a)
         // back substitution with |phi|^2 accumulated
         cd phi = dp;
         double acc = cabs2(phi);
+#pragma unroll 8
         for (int j = n - 2; j >= 0; --j) {
-            const cd c = w[2 * ((int64_t)j * L + lane)];
-            const cd dd = w[2 * ((int64_t)j * L + lane) + 1];
+            const cd c = a.fac[2 * ((int64_t)j * P + pair)];
+            const cd dd = w[(int64_t)j * L + lane];
             phi = cadd(dd, cscale(-1.0, cmul(c, phi)));
             acc += cabs2(phi);
         }
-        a.out[it] = eps / M_PI * dx * acc;
+        a.out[it] = a.eps / M_PI * dx * acc;
     }
+}
+
+size_t spectrum_factor_bytes(int n_max, int64_t pairs)
+{
+    return ((size_t)n_max * (size_t)pairs * 2 * sizeof(cd) + 255) & ~size_t(255);
 }
 
 // Gabor transform (section "Physical Examples & tutorials", microscopic
@@ -204,6 +253,7 @@ hipError_t launch_gabor(const GaborArgs& a, hipStream_t st)
 
 hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st)
 {
+    hipLaunchKernelGGL(spectrum_factor_kernel, dim3((a.pairs + 255) / 256), dim3(256), 0, st, a);
     const unsigned blocks = (unsigned)((a.lanes + 255) / 256);
     hipLaunchKernelGGL(energy_spectrum_kernel, dim3(blocks), dim3(256), 0, st, a);
     return hipGetLastError();

@@ -39,7 +39,7 @@ def test_energy_spectrum_matches_oracle(lib, torch_dev, lanes):
     energies = np.linspace(-0.7, 2.5, 41)
     E = torch.tensor(energies, device=dev)
     out = torch.empty(len(ns), len(energies), dtype=torch.float64, device=dev)
-    nbytes = 32 * max(ns) * (lanes or 65536)
+    nbytes = lib.tdse_plan_energy_spectrum_work(plan, len(energies), lanes or 65536)
     work = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
     print(f"energy spectrum ns={ns} energies={len(energies)} work lanes={lanes}", flush=True)
     lib.tdse_plan_energy_spectrum(plan, psi, E, eps, out, work)
@@ -62,13 +62,14 @@ def test_eigenstate_lorentzian_and_small_workspace(lib, torch_dev):
     e_g = plan.ground_state(n, psi)
     E = torch.tensor([e_g, e_g + eps, e_g + 3 * eps], dtype=torch.float64, device=dev)
     out = torch.empty(1, 3, dtype=torch.float64, device=dev)
-    work = torch.empty(32 * n * 64 // 8, dtype=torch.float64, device=dev)
+    nbytes = lib.tdse_plan_energy_spectrum_work(plan, 3, 64)
+    work = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
     lib.tdse_plan_energy_spectrum(plan, psi, E, eps, out, work)
     torch.cuda.synchronize()
     lor = 1.0 / (np.pi * eps) / (1.0 + np.array([0.0, 1.0, 9.0]))
     assert np.max(np.abs(out.cpu().numpy()[0] - lor) / lor) < 1e-6
     with pytest.raises(lib.TDSEError):
-        lib.tdse_plan_energy_spectrum(plan, psi, E, eps, out, work[: 32 * n * 63 // 8])
+        lib.tdse_plan_energy_spectrum(plan, psi, E, eps, out, work[: (nbytes - 16 * n) // 8])
     plan.close()
 
 
