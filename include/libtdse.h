@@ -152,7 +152,8 @@ tdse_status tdse_plan_layout(tdse_plan plan, int32_t n, int32_t* points_per_lane
  * the probe rate in grid-point-steps/s measured by the autotuner (0 when
  * the plan was not created with TDSE_OPT_AUTOTUNE).  The autotuner times,
  * for each distinct n, every lane layout that fits (points per lane C in
- * {4, 8, 16}, i.e. the length of the lane-local Thomas chunks against the
+ * {4, 8, 12, 16}, 12 only for plans without the adjoint, i.e. the length of
+ * the lane-local Thomas chunks against the
  * width of the cross-lane scan; systems per workgroup; table placement) on
  * a probe batch that fills the GPU once, and keeps the fastest.  Results are
  * cached per process. */

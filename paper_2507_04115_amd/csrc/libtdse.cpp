@@ -96,7 +96,7 @@ Layout default_layout(int n)
     // beats 16 points (register spills) and 4 (per-lane overheads)
     int C = n > 8192 ? 16 : (n > 512 ? 8 : 4);
     const int fc = env_int("TDSE_LAYOUT_C", 0);  // experiment override
-    if (fc == 4 || fc == 8 || fc == 16) C = fc;
+    if (fc == 4 || fc == 8 || fc == 12 || fc == 16) C = fc;  // 12: forward-only plans
     int T = ((n + C - 1) / C + kWave - 1) / kWave * kWave;
     if (T < kWave) T = kWave;
     return {C, T};
@@ -861,9 +861,10 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, hipSt
     }
     TuneChoice best;
     double best_cost = 0.0;  // seconds per grid-point-step (forward [+ adjoint])
-    for (int C : {4, 8, 16}) {
+    for (int C : {4, 8, 12, 16}) {
         const Layout L = layout_for(n, C);
         if (L.T > 1024 || !layout_supported(C)) continue;
+        if (adjoint && C == 12) continue;  // the adjoint kernel has no 12-point layout
         double adj_cost = 0.0;
         if (adjoint) {
             double ra = 0.0;

@@ -282,7 +282,7 @@ hipError_t launch_reset_counters(int32_t* counters, int n, hipStream_t st)
     return hipGetLastError();
 }
 
-bool layout_supported(int C) { return C == 4 || C == 8 || C == 16; }
+bool layout_supported(int C) { return C == 4 || C == 8 || C == 12 || C == 16; }
 
 template <int C, int TAB>
 static int occ_fwd(int threads, size_t sh)
@@ -300,13 +300,14 @@ static int occ_fwd(int threads, size_t sh)
     return nb;
 }
 
-// Instantiated layouts: C in {4, 8, 16} with tables in global memory or in
-// LDS; om alone in LDS only for 16 points per lane (the grids whose full
-// tables do not fit).
+// Instantiated layouts: C in {4, 8, 12, 16} with tables in global memory or
+// in LDS; om alone in LDS only for 12 and 16 points per lane (the grids whose
+// full tables do not fit).  12 points per lane (forward only) fill 1024-lane
+// workgroups at N = 12288, where 16 points leave a quarter of them idle.
 bool forward_tab_supported(int C, int tab)
 {
     if (!layout_supported(C)) return false;
-    return tab == kTabGlobal || tab == kTabLds || (tab == kTabOmLds && C == 16);
+    return tab == kTabGlobal || tab == kTabLds || (tab == kTabOmLds && C >= 12);
 }
 
 int forward_occupancy(int C, int threads, size_t smem, int tab)
@@ -317,6 +318,9 @@ int forward_occupancy(int C, int threads, size_t smem, int tab)
         case 17: return occ_fwd<4, kTabLds>(threads, smem);
         case 32: return occ_fwd<8, kTabGlobal>(threads, smem);
         case 33: return occ_fwd<8, kTabLds>(threads, smem);
+        case 48: return occ_fwd<12, kTabGlobal>(threads, smem);
+        case 49: return occ_fwd<12, kTabLds>(threads, smem);
+        case 50: return occ_fwd<12, kTabOmLds>(threads, smem);
         case 64: return occ_fwd<16, kTabGlobal>(threads, smem);
         case 65: return occ_fwd<16, kTabLds>(threads, smem);
         case 66: return occ_fwd<16, kTabOmLds>(threads, smem);
@@ -331,13 +335,16 @@ hipError_t launch_forward(int C, int tab, const FwdArgs& a, int threads, size_t 
         (size_t)a.item_off + 16 > smem)
         return hipErrorInvalidValue;
     const dim3 b(threads);
-    // 16 points per lane: elimination factors from their tables (a.ab) or
-    // formed from q and om
-    if (C == 16 && a.ab) {
-        switch (tab) {
-            case kTabGlobal: hipLaunchKernelGGL((forward_kernel<16, kTabGlobal, true>), dim3(grid), b, smem, st, a); break;
-            case kTabLds: hipLaunchKernelGGL((forward_kernel<16, kTabLds, true>), dim3(grid), b, smem, st, a); break;
-            case kTabOmLds: hipLaunchKernelGGL((forward_kernel<16, kTabOmLds, true>), dim3(grid), b, smem, st, a); break;
+    // 12 and 16 points per lane: elimination factors from their tables
+    // (a.ab) or formed from q and om
+    if (C >= 12 && a.ab) {
+        switch (C * 4 + tab) {
+            case 48: hipLaunchKernelGGL((forward_kernel<12, kTabGlobal, true>), dim3(grid), b, smem, st, a); break;
+            case 49: hipLaunchKernelGGL((forward_kernel<12, kTabLds, true>), dim3(grid), b, smem, st, a); break;
+            case 50: hipLaunchKernelGGL((forward_kernel<12, kTabOmLds, true>), dim3(grid), b, smem, st, a); break;
+            case 64: hipLaunchKernelGGL((forward_kernel<16, kTabGlobal, true>), dim3(grid), b, smem, st, a); break;
+            case 65: hipLaunchKernelGGL((forward_kernel<16, kTabLds, true>), dim3(grid), b, smem, st, a); break;
+            case 66: hipLaunchKernelGGL((forward_kernel<16, kTabOmLds, true>), dim3(grid), b, smem, st, a); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -347,6 +354,9 @@ hipError_t launch_forward(int C, int tab, const FwdArgs& a, int threads, size_t 
         case 17: hipLaunchKernelGGL((forward_kernel<4, kTabLds>), dim3(grid), b, smem, st, a); break;
         case 32: hipLaunchKernelGGL((forward_kernel<8, kTabGlobal>), dim3(grid), b, smem, st, a); break;
         case 33: hipLaunchKernelGGL((forward_kernel<8, kTabLds>), dim3(grid), b, smem, st, a); break;
+        case 48: hipLaunchKernelGGL((forward_kernel<12, kTabGlobal>), dim3(grid), b, smem, st, a); break;
+        case 49: hipLaunchKernelGGL((forward_kernel<12, kTabLds>), dim3(grid), b, smem, st, a); break;
+        case 50: hipLaunchKernelGGL((forward_kernel<12, kTabOmLds>), dim3(grid), b, smem, st, a); break;
         case 64: hipLaunchKernelGGL((forward_kernel<16, kTabGlobal>), dim3(grid), b, smem, st, a); break;
         case 65: hipLaunchKernelGGL((forward_kernel<16, kTabLds>), dim3(grid), b, smem, st, a); break;
         case 66: hipLaunchKernelGGL((forward_kernel<16, kTabOmLds>), dim3(grid), b, smem, st, a); break;
@@ -361,6 +371,7 @@ hipError_t launch_ground_state(int C, const GsArgs& a, int T, hipStream_t st)
     switch (C) {
         case 4: hipLaunchKernelGGL(gs_kernel<4>, dim3(a.ncand), dim3(T), sh, st, a); break;
         case 8: hipLaunchKernelGGL(gs_kernel<8>, dim3(a.ncand), dim3(T), sh, st, a); break;
+        case 12: hipLaunchKernelGGL(gs_kernel<12>, dim3(a.ncand), dim3(T), sh, st, a); break;
         case 16: hipLaunchKernelGGL(gs_kernel<16>, dim3(a.ncand), dim3(T), sh, st, a); break;
         default: return hipErrorInvalidValue;
     }

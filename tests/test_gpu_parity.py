@@ -489,6 +489,31 @@ def test_elimination_factor_source_does_not_change_results(lib, torch_dev, monke
             assert rel(res[key][1][b], g_ref) < 1e-9
 
 
+def test_twelve_points_per_lane(lib, torch_dev, monkeypatch):
+    """The 12-point layout (forward only; chosen by the autotuner where it
+    fills workgroups better than 16 points, e.g. N = 12288 = 12 x 1024),
+    forced here for every size: outputs against the oracle, statuses clean."""
+    torch, dev = torch_dev
+    ns = [3000, 9000, 12288]
+    dx, dt, nt = 0.2, 0.05, 300
+    efield = 0.06 * np.random.default_rng(41).standard_normal((len(ns), nt + 1))
+    monkeypatch.setenv("TDSE_LAYOUT_C", "12")
+    plan, out = _run_forward(lib, torch, dev, ns, efield, dx, dt, A_AR)
+    monkeypatch.delenv("TDSE_LAYOUT_C")
+    assert [plan.layout(n).points_per_lane for n in ns] == [12, 12, 12]
+    assert np.all(out["status"] == 0)
+    off = plan.psi_offsets()
+    pf = out["psi_final"].view(np.complex128)
+    for b, n in enumerate(ns):
+        ref = oracle_side.propagate(efield[b], n, dx, dt, A_AR, mask_frac=0.1, want_psi=True)
+        r = rel(out["accel"][b], ref["accel"])
+        print(f"  n={n} lanes={plan.layout(n).lanes}: accel rel-L2 {r:.3e}", flush=True)
+        assert r < TOL_ACC
+        assert rel(out["norm"][b], ref["norm"]) < TOL_ACC
+        assert rel(pf[off[b]:off[b + 1]], ref["psi_final"]) < TOL_ACC
+    plan.close()
+
+
 def test_forward_uneven_wide_batch_sampled(lib, torch_dev):
     """Uneven batch spanning N = 2048..16384 (many size classes; tables in
     LDS, om alone in LDS; 8 and 16 points per lane), first 400 steps of the
