@@ -59,11 +59,14 @@ const char* tdse_last_error(void);
  *  a, charge_z     soft-core potential V(x) = -charge_z / sqrt(x^2 + a^2)
  *                  (section "Microscopic Response in XUV regime (TDSE)",
  *                  Eq. SC potential); charge_z = 0 gives a free particle
- *  mask_fraction   absorber on the outer fraction of each side (0 disables);
+ *  mask_fraction   absorber on this fraction of the whole grid at each side,
+ *                  in [0, 0.5) (0 disables; 0.1: the outer tenth of the grid
+ *                  at each side, |x| > 0.8 x_max);
  *                  m(x) = cos(pi/2 (|x|-x_a)/(x_max-x_a))^mask_power for
- *                  x_a < |x| < x_max, x_a = (1-mask_fraction) x_max, 1 inside
- *                  and 0 at the two outermost points.  The paper's solver has
- *                  no absorber; this one is applied after the field substep.
+ *                  x_a < |x| < x_max, x_a = (1 - 2 mask_fraction) x_max,
+ *                  x_max = (n-1) dx / 2, 1 inside and 0 at the two outermost
+ *                  points.  The paper's solver has no absorber; this one is
+ *                  applied after the field substep.
  *  mask_power      exponent of the absorber (e.g. 0.125)
  *  nt              number of time steps; every series has nt+1 samples
  *  flags           reserved, must be 0 */

@@ -34,7 +34,8 @@
  *   - "M2 V_C" is the matrix product M2 * diag(V).
  *   - Absorber (not in the paper): after the field substep every point is
  *     multiplied by a real mask m_j, 1 in the interior, cos(...)^power on the
- *     outer fraction of each side and exactly 0 at the two outermost points.
+ *     outer fraction of the grid at each side (a tenth of the grid each side:
+ *     |x| > 0.8 x_max) and exactly 0 at the two outermost points.
  *   - Acceleration sample i uses psi^(i) and E(t_i):
  *     a_i = dx sum_j |psi_j|^2 (dV/dx)_j + E_i n_i,  n_i = dx sum_j |psi_j|^2.
  *   - Ground state: imaginary-time Crank-Nicolson (dt -> -i dtau) with
@@ -78,14 +79,17 @@ int ref_grid(int n, double dx, double a, double z, double* x, double* v, double*
     return REF_OK;
 }
 
-/* Absorbing mask: 1 for |x| <= x_a, cos(pi/2 (|x|-x_a)/(x_max-x_a))^power
- * between x_a = (1-frac) x_max and x_max, and 0 at |x| >= x_max (the two
- * outermost points).  frac <= 0 disables the mask (all ones). */
+/* Absorbing mask on the outer fraction `frac` of the grid at each side:
+ * the grid spans 2 x_max, so the absorber starts at x_a = x_max - 2 frac x_max
+ * (frac = 0.1: x_a = 0.8 x_max).  m = 1 for |x| <= x_a,
+ * cos(pi/2 (|x|-x_a)/(x_max-x_a))^power between x_a and x_max, and 0 at
+ * |x| >= x_max (the two outermost points).  frac <= 0 disables the mask (all
+ * ones); frac must stay below 1/2. */
 int ref_mask(int n, double dx, double frac, double power, double* m)
 {
-    if (n < 3 || !(dx > 0.0)) return REF_EINVAL;
+    if (n < 3 || !(dx > 0.0) || !(frac < 0.5)) return REF_EINVAL;
     double xmax = 0.5 * (double)(n - 1) * dx;
-    double xa = (1.0 - frac) * xmax;
+    double xa = xmax - 2.0 * frac * xmax;
     for (int j = 0; j < n; ++j) {
         double ax = fabs(((double)j - 0.5 * (double)(n - 1)) * dx);
         if (frac <= 0.0 || ax <= xa) {

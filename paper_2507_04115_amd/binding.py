@@ -152,6 +152,30 @@ def _c128(*ts):
             raise TypeError(f"expected a complex128 (or interleaved float64) tensor, got {t.dtype}")
 
 
+def _cplx_len(t) -> int:
+    """Complex elements held by a complex128 tensor or an interleaved float64 one."""
+    import torch
+
+    return t.numel() if t.dtype == torch.complex128 else t.numel() // 2
+
+
+def _need(t, n: int, name: str, complex_: bool = False):
+    """Raises ValueError unless tensor t (if given) holds at least n elements
+    (complex elements for complex_ buffers) and lives on the current device:
+    a short buffer would make the kernels read or write past its end."""
+    if t is None:
+        return
+    import torch
+
+    if isinstance(t, torch.Tensor) and t.is_cuda and t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{name} lives on {t.device}, the current device is "
+                         f"cuda:{torch.cuda.current_device()}")
+    have = _cplx_len(t) if complex_ else t.numel()
+    if have < n:
+        kind = "complex elements" if complex_ else "elements"
+        raise ValueError(f"{name} holds {have} {kind}, needs {n}")
+
+
 def _stream(stream) -> Optional[int]:
     import torch
 
@@ -172,6 +196,7 @@ def tdse_version() -> str:
 def tdse_ground_state(p: tdse_params, n: int, dtau: float, max_iter: int, tol: float, psi_out,
                       stream=None) -> float:
     _c128(psi_out)
+    _need(psi_out, n, "psi_out", True)
     e = _d()
     _check(load().tdse_ground_state(ctypes.byref(p), n, dtau, max_iter, tol, _ptr(psi_out),
                                     ctypes.byref(e), _stream(stream)), "tdse_ground_state")
@@ -216,6 +241,21 @@ class Plan:
         self.handle = h
         self.options = options
         self.adjoint_k = adjoint_k
+        self._offsets = None
+
+    @property
+    def nt(self) -> int:
+        return int(self.params.nt)
+
+    @property
+    def series_len(self) -> int:
+        """Elements of a [batch][nt+1] series buffer."""
+        return self.batch * (self.nt + 1)
+
+    @property
+    def psi_len(self) -> int:
+        """Complex elements of a ragged wavefunction buffer."""
+        return self.psi_offsets()[-1]
 
     def close(self):
         if getattr(self, "handle", None):
@@ -229,9 +269,11 @@ class Plan:
             pass
 
     def psi_offsets(self):
-        off = (ctypes.c_int64 * (self.batch + 1))()
-        _check(load().tdse_plan_psi_offsets(self.handle, off), "tdse_plan_psi_offsets")
-        return list(off)
+        if self._offsets is None:
+            off = (ctypes.c_int64 * (self.batch + 1))()
+            _check(load().tdse_plan_psi_offsets(self.handle, off), "tdse_plan_psi_offsets")
+            self._offsets = list(off)
+        return list(self._offsets)
 
     def layout(self, n: int) -> Layout:
         c, t, l = _i32(), _i32(), _i32()
@@ -257,6 +299,7 @@ class Plan:
 
     def ground_state(self, n: int, psi_out) -> float:
         _c128(psi_out)
+        _need(psi_out, n, "psi_out", True)
         e = _d()
         _check(load().tdse_plan_ground_state(self.handle, n, _ptr(psi_out), ctypes.byref(e)),
                "tdse_plan_ground_state")
@@ -276,6 +319,13 @@ def tdse_propagate_batch(plan: Plan, E, psi0, accel, xexp=None, norm=None, psi_f
     _f64(E, accel, xexp, norm)
     _c128(psi0, psi_final)
     _i32t(sys_status)
+    if accel is None:
+        raise ValueError("accel is required")
+    for t, nm in ((E, "E"), (accel, "accel"), (xexp, "xexp"), (norm, "norm")):
+        _need(t, plan.series_len, nm)
+    _need(psi0, plan.psi_len, "psi0", True)
+    _need(psi_final, plan.psi_len, "psi_final", True)
+    _need(sys_status, plan.batch, "sys_status")
     _check(load().tdse_propagate_batch(plan.handle, _ptr(E), _ptr(psi0), _ptr(accel), _ptr(xexp),
                                        _ptr(norm), _ptr(psi_final), _ptr(sys_status),
                                        _stream(stream)), "tdse_propagate_batch")
@@ -286,6 +336,10 @@ def tdse_adjoint_batch(plan: Plan, E, psi0, accel_bar, grad_E, accel=None, sys_s
     _f64(E, accel_bar, grad_E, accel)
     _c128(psi0)
     _i32t(sys_status)
+    for t, nm in ((E, "E"), (accel_bar, "accel_bar"), (grad_E, "grad_E"), (accel, "accel")):
+        _need(t, plan.series_len, nm)
+    _need(psi0, plan.psi_len, "psi0", True)
+    _need(sys_status, plan.batch, "sys_status")
     _check(load().tdse_adjoint_batch(plan.handle, _ptr(E), _ptr(psi0), _ptr(accel_bar),
                                      _ptr(grad_E), _ptr(accel), _ptr(sys_status), _stream(stream)),
            "tdse_adjoint_batch")
@@ -295,6 +349,9 @@ def tdse_adjoint_batch_stored(plan: Plan, generation: int, E, accel_bar, grad_E,
                               stream=None):
     _f64(E, accel_bar, grad_E)
     _i32t(sys_status)
+    for t, nm in ((E, "E"), (accel_bar, "accel_bar"), (grad_E, "grad_E")):
+        _need(t, plan.series_len, nm)
+    _need(sys_status, plan.batch, "sys_status")
     _check(load().tdse_adjoint_batch_stored(plan.handle, generation, _ptr(E), _ptr(accel_bar),
                                             _ptr(grad_E), _ptr(sys_status), _stream(stream)),
            "tdse_adjoint_batch_stored")
@@ -310,6 +367,12 @@ def tdse_harmonic_band(nt: int, dt: float, omega0: float, h_lo: float, h_hi: flo
 def tdse_harmonic_yield(batch: int, nt: int, dt: float, omega0: float, h_lo: float, h_hi: float,
                         accel, row_weight, work, yield_out, accel_bar=None, stream=None):
     _f64(accel, row_weight, work, yield_out, accel_bar)
+    _, nk = tdse_harmonic_band(nt, dt, omega0, h_lo, h_hi)
+    _need(accel, batch * (nt + 1), "accel")
+    _need(accel_bar, batch * (nt + 1), "accel_bar")
+    _need(row_weight, batch, "row_weight")
+    _need(yield_out, batch, "yield_out")
+    _need(work, 2 * batch * max(nk, 1), "work")
     _check(load().tdse_harmonic_yield(batch, nt, dt, omega0, h_lo, h_hi, _ptr(accel),
                                       _ptr(row_weight), _ptr(work), _ptr(yield_out),
                                       _ptr(accel_bar), _stream(stream)), "tdse_harmonic_yield")
@@ -319,6 +382,9 @@ def tdse_band_dft(batch: int, nt: int, dt: float, omega0: float, h_lo: float, h_
                   amp, stream=None):
     _f64(accel)
     _c128(amp)
+    _, nk = tdse_harmonic_band(nt, dt, omega0, h_lo, h_hi)
+    _need(accel, batch * (nt + 1), "accel")
+    _need(amp, batch * nk, "amp", True)
     _check(load().tdse_band_dft(batch, nt, dt, omega0, h_lo, h_hi, _ptr(accel), _ptr(amp),
                                 _stream(stream)), "tdse_band_dft")
 
@@ -327,6 +393,9 @@ def tdse_band_dft_adjoint(batch: int, nt: int, dt: float, omega0: float, h_lo: f
                           amp_bar, accel_bar, stream=None):
     _c128(amp_bar)
     _f64(accel_bar)
+    _, nk = tdse_harmonic_band(nt, dt, omega0, h_lo, h_hi)
+    _need(amp_bar, batch * nk, "amp_bar", True)
+    _need(accel_bar, batch * (nt + 1), "accel_bar")
     _check(load().tdse_band_dft_adjoint(batch, nt, dt, omega0, h_lo, h_hi, _ptr(amp_bar),
                                         _ptr(accel_bar), _stream(stream)), "tdse_band_dft_adjoint")
 
@@ -337,6 +406,10 @@ def tdse_far_field(rho_src, z_src, weights, kwave, amp, rho_obs, z_obs: float, f
     (adjoint=True: `amp` is field_bar, `field` receives amp_bar)."""
     _f64(rho_src, z_src, weights, kwave, rho_obs)
     _c128(amp, field)
+    nsrc, nk, nobs = int(rho_src.numel()) * int(z_src.numel()), int(kwave.numel()), int(rho_obs.numel())
+    _need(weights, nsrc, "weights")
+    _need(amp, (nobs if adjoint else nsrc) * nk, "field_bar" if adjoint else "amp", True)
+    _need(field, (nsrc if adjoint else nobs) * nk, "amp_bar" if adjoint else "field", True)
     fn = load().tdse_far_field_adjoint if adjoint else load().tdse_far_field
     _check(fn(int(rho_src.numel()), int(z_src.numel()), _ptr(rho_src), _ptr(z_src), _ptr(weights),
               int(kwave.numel()), _ptr(kwave), _ptr(amp), int(rho_obs.numel()), _ptr(rho_obs),
@@ -349,6 +422,8 @@ def tdse_plan_energy_spectrum(plan: Plan, psi, energies, eps: float, spectrum, w
     (work: a device scratch tensor, its byte size is passed along)."""
     _f64(energies, spectrum)
     _c128(psi)
+    _need(psi, plan.psi_len, "psi", True)
+    _need(spectrum, plan.batch * int(energies.numel()), "spectrum")
     _check(load().tdse_plan_energy_spectrum(plan.handle, _ptr(psi), int(energies.numel()),
                                             _ptr(energies), float(eps), _ptr(spectrum), _ptr(work),
                                             work.numel() * work.element_size(), _stream(stream)),
@@ -367,6 +442,7 @@ def tdse_gabor(accel, dt: float, t_centres, omegas, sigma: float, out, stream=No
     """out[b][c][w] = Gabor transform of accel rows (see include/libtdse.h)."""
     _f64(accel, t_centres, omegas, out)
     batch, n1 = accel.shape
+    _need(out, batch * int(t_centres.numel()) * int(omegas.numel()), "out")
     _check(load().tdse_gabor(batch, n1 - 1, float(dt), _ptr(accel), int(t_centres.numel()),
                              _ptr(t_centres), int(omegas.numel()), _ptr(omegas), float(sigma),
                              _ptr(out), _stream(stream)), "tdse_gabor")
@@ -374,6 +450,7 @@ def tdse_gabor(accel, dt: float, t_centres, omegas, sigma: float, out, stream=No
 
 def tdse_plan_stored_state(plan: Plan, generation: int, index: int, psi_out, stream=None):
     _c128(psi_out)
+    _need(psi_out, plan.psi_len, "psi_out", True)
     _check(load().tdse_plan_stored_state(plan.handle, generation, index, _ptr(psi_out),
                                          _stream(stream)), "tdse_plan_stored_state")
 

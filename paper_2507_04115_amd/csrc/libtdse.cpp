@@ -333,8 +333,8 @@ tdse_status check_params(const tdse_params* p, bool need_time)
     if (!std::isfinite(p->a) || (p->charge_z != 0.0 && !(p->a > 0.0)))
         return fail(TDSE_E_INVALID, "soft-core a must be > 0");
     if (!std::isfinite(p->charge_z)) return fail(TDSE_E_INVALID, "charge_z must be finite");
-    if (need_time && (!(p->mask_fraction >= 0.0) || p->mask_fraction >= 1.0))
-        return fail(TDSE_E_INVALID, "mask_fraction must be in [0, 1)");
+    if (need_time && (!(p->mask_fraction >= 0.0) || p->mask_fraction >= 0.5))
+        return fail(TDSE_E_INVALID, "mask_fraction must be in [0, 0.5)");
     if (need_time && p->mask_fraction > 0.0 && !(p->mask_power > 0.0))
         return fail(TDSE_E_INVALID, "mask_power must be > 0");
     if (need_time && p->nt < 0) return fail(TDSE_E_INVALID, "nt must be >= 0");
@@ -1031,6 +1031,10 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     std::vector<int> ccount(ncls, 0);
     for (int b = 0; b < batch; ++b) ++ccount[pl->cls_of_n[pl->n_per[b]]];
     const bool tune = (options & TDSE_OPT_AUTOTUNE) && !(options & TDSE_OPT_PLAIN);
+    if (adjoint_k > 0 && !tune && env_int("TDSE_LAYOUT_C", 0) == 12)
+        return bail(fail(TDSE_E_UNSUPPORTED,
+                         "TDSE_LAYOUT_C=12 is a forward-only layout: the adjoint kernel has "
+                         "4, 8 and 16 points per lane (create the plan with adjoint_k = 0)"));
     std::vector<TuneChoice> tuned(ncls);
     for (int c = 0; c < ncls; ++c) {
         if (tune) {

@@ -20,11 +20,13 @@ __device__ __forceinline__ double soft_core_slope(double x, double a, double z)
     const double s = fma(x, x, a * a);
     return z * x / (s * sqrt(s));
 }
-// Absorber: 1 for |x| <= x_a, cos(pi/2 (|x|-x_a)/(x_max-x_a))^power up to
-// x_max, and 0 at |x| >= x_max.
+// Absorber on the outer fraction `frac` of the grid at each side: the grid
+// spans 2 x_max, so it starts at x_a = x_max - 2 frac x_max.  1 for
+// |x| <= x_a, cos(pi/2 (|x|-x_a)/(x_max-x_a))^power up to x_max, and 0 at
+// |x| >= x_max.
 __device__ __forceinline__ double absorber(double ax, double xmax, double frac, double power)
 {
-    const double xa = (1.0 - frac) * xmax;
+    const double xa = xmax - 2.0 * frac * xmax;
     if (frac <= 0.0 || ax <= xa) return 1.0;
     if (ax >= xmax) return 0.0;
     return pow(cos(0.5 * M_PI * (ax - xa) / (xmax - xa)), power);

@@ -11,6 +11,22 @@ from paper_2507_04115_amd import binding as L
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
+def _ensure_built():
+    """A clean checkout has no libtdse.so: build it (hipcc cross-compiles for
+    gfx950 without a GPU), or skip the module when no HIP compiler is here."""
+    if os.path.exists(L.LIB_PATH):
+        return
+    from paper_2507_04115_amd import build as hip_build
+
+    if not os.path.exists(hip_build.HIPCC):
+        pytest.skip(f"libtdse.so is not built and {hip_build.HIPCC} is missing",
+                    allow_module_level=True)
+    hip_build.build()
+
+
+_ensure_built()
+
+
 def _declared():
     txt = open(os.path.join(ROOT, "include", "libtdse.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
@@ -44,7 +60,8 @@ def _create(p, ns, out=True):
 
 @pytest.mark.parametrize("field,value,msg", [
     ("dx", 0.0, "dx"), ("dt", -1.0, "dt"), ("a", -1.0, "soft-core"),
-    ("mask_fraction", 1.5, "mask_fraction"), ("nt", -3, "nt"), ("flags", 1, "flags"),
+    ("mask_fraction", 1.5, "mask_fraction"), ("mask_fraction", 0.5, "mask_fraction"),
+    ("nt", -3, "nt"), ("flags", 1, "flags"),
 ])
 def test_plan_create_rejects_bad_params_before_touching_the_device(field, value, msg):
     p = L.make_params(0.2, 0.05, 1.2, 100)

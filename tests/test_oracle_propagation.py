@@ -149,15 +149,20 @@ def test_split_step_orders_against_expm():
 
 
 def test_absorber_profile_and_absorption():
-    """Mask: 1 inside, strictly decreasing on the outer 10 %, 0 at the two
-    outermost points; a packet sent into it is absorbed, not reflected."""
+    """Mask with fraction 0.1: 1 for |x| <= 0.8 x_max (a tenth of the whole
+    grid absorbs at each side), below 1 and strictly decreasing beyond it,
+    0 at the two outermost points; a packet sent into it is absorbed, not
+    reflected."""
     n, dx = 601, 0.2
     m = oracle.mask(n, dx, 0.1, 0.125)
     x = grid_x(n, dx)
     xmax = x[-1]
-    assert np.all(m[np.abs(x) <= 0.9 * xmax] == 1.0)
+    inner = np.abs(x) <= 0.8 * xmax
+    assert np.all(m[inner] == 1.0)
+    assert np.all(m[~inner] < 1.0)
+    assert np.sum(~inner) == 2 * 60          # 10 % of the 600 intervals at each side
     assert m[0] == 0.0 and m[-1] == 0.0
-    right = m[np.abs(x) > 0.9 * xmax][-(np.sum(np.abs(x) > 0.9 * xmax) // 2):]
+    right = m[x > 0.8 * xmax]
     assert np.all(np.diff(right) < 0)
     psi0 = np.exp(-(x - 30.0) ** 2 / 8.0 + 2.0j * x)
     psi0 /= np.sqrt(dx * np.sum(np.abs(psi0) ** 2))
@@ -166,3 +171,69 @@ def test_absorber_profile_and_absorption():
     assert out["norm"][-1] < 0.05
     assert np.all(np.diff(out["norm"]) <= 4e-15)          # the mask only removes norm
     assert dx * np.sum(np.abs(out["psi_final"][x < 0]) ** 2) < 0.01
+
+
+@pytest.mark.parametrize("power", [0.125, 0.5, 1.0])
+@pytest.mark.parametrize("frac", [0.1, 0.25])
+def test_absorber_exponent_at_exact_cosine_points(frac, power):
+    """Values of the cos^p profile where the cosine is exact: with
+    u = (|x| - x_a)/(x_max - x_a), u = 1/3, 1/2, 2/3 give cos = sqrt(3)/2,
+    2^-1/2, 1/2, so m = (sqrt(3)/2)^p, 2^(-p/2), 2^-p (for p = 1/8:
+    2^(-1/16) at u = 1/2 and 2^(-1/8) at u = 2/3).  The grid has 2M
+    intervals with M a multiple of 30, so these u fall on grid points; a
+    wrong exponent, a wrong x_a or a wrong fraction fails here."""
+    big_m = 60
+    n, dx = 2 * big_m + 1, 0.3
+    m = oracle.mask(n, dx, frac, power)
+    # x_j = (j - M) dx, x_max = M dx, x_a = (1 - 2 frac) M dx: u = 1/3 at
+    # |j - M| = M (1 - 2 frac + 2 frac / 3), and so on
+    for u, ref in [(1.0 / 3.0, (np.sqrt(3.0) / 2.0) ** power), (0.5, 2.0 ** (-0.5 * power)),
+                   (2.0 / 3.0, 2.0 ** (-power))]:
+        d = big_m * (1.0 - 2.0 * frac + 2.0 * frac * u)
+        assert abs(d - round(d)) < 1e-9
+        for j in (big_m + int(round(d)), big_m - int(round(d))):
+            assert abs(m[j] - ref) < 4e-15, (u, j, m[j], ref)
+    # the first point past x_a is the first one below 1
+    k_a = big_m * (1.0 - 2.0 * frac)
+    assert m[big_m + int(round(k_a))] == 1.0 and m[big_m + int(round(k_a)) + 1] < 1.0
+
+
+def test_propagate_batch_equals_single_propagations():
+    """The threaded batch oracle gives, bitwise, what one ragged system at a
+    time gives: rows of different sizes and fields, their initial states
+    read at non-contiguous offsets of one buffer (gaps between them), four
+    host threads."""
+    import ctypes
+
+    rng = np.random.default_rng(11)
+    ns = [64, 97, 33, 128, 64]
+    nt, dx, dt, a = 40, 0.3, 0.05, 1.1
+    efield = rng.uniform(-0.1, 0.1, size=(len(ns), nt + 1))
+    psis = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for n in ns]
+    off = np.zeros(len(ns) + 1, np.int64)
+    gap = 5
+    for b, n in enumerate(ns):
+        off[b + 1] = off[b] + n + gap
+    buf = np.full(int(off[-1]), np.nan + 1j * np.nan)
+    for b, n in enumerate(ns):
+        buf[off[b]:off[b] + n] = psis[b]
+    acc = np.empty((len(ns), nt + 1))
+    xe = np.empty_like(acc)
+    nr = np.empty_like(acc)
+    lib = oracle._load()
+    n_per = np.array(ns, np.int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = lib.ref_propagate_batch(len(ns), n_per.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                 off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), dx, dt, a,
+                                 1.0, 0.1, 0.125, nt, efield.ctypes.data_as(dp),
+                                 buf.ctypes.data_as(dp), acc.ctypes.data_as(dp),
+                                 xe.ctypes.data_as(dp), nr.ctypes.data_as(dp), 4)
+    assert st == 0
+    for b in range(len(ns)):
+        ref = oracle.propagate(efield[b], psis[b], dx, dt, a, mask_frac=0.1)
+        assert np.array_equal(acc[b], ref["accel"])
+        assert np.array_equal(xe[b], ref["xexp"])
+        assert np.array_equal(nr[b], ref["norm"])
+    # the wrapper with its contiguous offsets gives the same rows
+    out = oracle.propagate_batch(efield, psis, dx, dt, a, mask_frac=0.1, nthreads=3)
+    assert np.array_equal(out["accel"], acc)
