@@ -1,25 +1,33 @@
 """Benchmark of the batched 1D-TDSE microscopic step on one MI355X.
 
-Workload (default): the 32 r x 32 z Gaussian-beam focus -- 1024 independent
-systems, N = 4096 points (dx = 0.2), dt = 0.05, 20-cycle 800 nm sin^2 pulse,
-peak 2e14 W/cm^2 at w0 = 50 um, soft-core argon (Ip = 0.5792), cos^(1/8)
-absorber.  Inputs are synthetic and generated on the device.
+Workload (default): the full focal volume -- 16 384 independent systems on a
+64 r x 256 z Gaussian-beam grid (w0 = 80 um, 1030 nm, 2.5e14 W/cm^2,
+30-cycle sin^2), N = 8192 points (dx = 0.15), dt = 0.02, 213 056 steps,
+soft-core argon (Ip = 0.5792), cos^(1/8) absorber on the outer tenth of the
+grid at each side.  Inputs are synthetic and generated on the device before
+the timed region.
 
-One timed step = one batched forward solve of the whole batch through
-tdse_propagate_batch (graph replay of the persistent kernel): every system
-propagated over all Nt steps with the dipole acceleration, <x> and norm
-recorded at every sample.  The plan (soft-core fit, tables, ground states)
-is built once before the timed region.
+The time loop of that solve is split into as many segments as there are
+timed steps; one timed step propagates every system through one segment
+(tdse_propagate_batch, graph replay of the persistent kernel, starting from
+the previous segment's psi_final), so the K timed steps are exactly one full
+solve of the volume.  The dipole acceleration, <x> and the norm are recorded
+at every sample.  The warm-up steps run the first segments of the same solve.
+The plans (soft-core fit, tables, ground states, autotuned layout) are built
+once before the timed region.  --workload focus (or any other) times whole
+solves instead (one step = one solve).
 
 Besides the headline `value` (grid-point-steps/s = sum_p N_p Nt / time), the
 JSON line carries
-  plain       the same kernel launched once per system, serially (subset)
-  adjoint     time per gradient of the H21-H31 yield of the 256-system
-              adjoint batch (forward + checkpointed reverse sweep)
-  roofline    achieved FP64 rate of the forward kernel (52 algorithmic flops
-              per grid-point-step) against the 78.6 TFLOP/s vector peak
+  roofline      achieved FP64 rate of the forward kernel (52 algorithmic flops
+                per grid-point-step) against the 78.6 TFLOP/s vector peak,
+                its LDS traffic against the LDS peak, and its occupancy
+  plain         the same kernel launched once per system, serially (subset)
+  focus         the 1024-system focus batch (N = 4096, 44 093 steps)
+  adjoint       time per gradient of the H21-H31 yield of the 256-system
+                adjoint batch (forward + checkpointed reverse sweep)
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
-  parity      rel-L2 of the sampled GPU accelerations against that oracle run
+  parity        rel-L2 of the sampled GPU accelerations against that oracle run
 """
 from __future__ import annotations
 
@@ -37,6 +45,8 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_POINT_STEP = 52.0        # algorithmic FP64 flops per grid-point-step
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 HBM_PEAK_GBS = 8000.0              # HBM3E
+# LDS read bandwidth: 256 CUs x 128 B/clk x 2.4 GHz
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
 ADJ_FLOPS_PER_POINT_STEP = 158.0    # forward + recompute + costate step
 CSRC = os.path.join(ROOT, "paper_2507_04115_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
@@ -161,26 +171,151 @@ def bench_far_field(torch, L, ti, dev, stream):
             "terms_per_s": terms / (res[False] * 1e-3)}
 
 
-def cpu_model() -> str:
+def cpu_model() -> dict:
+    """Host CPU model and sizes (lscpu's model name, sockets, cores, threads)."""
+    info = {"model": "unknown"}
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
-    except OSError:
+        import subprocess
+
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        info["model"] = kv.get("Model name", "unknown")
+        for key, name in (("Socket(s)", "sockets"), ("Core(s) per socket", "cores_per_socket"),
+                          ("Thread(s) per core", "threads_per_core"), ("CPU(s)", "cpus")):
+            if key in kv:
+                info[name] = int(kv[key])
+    except Exception:
         pass
-    return "unknown"
+    try:
+        info["threads_available"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        info["threads_available"] = os.cpu_count() or 1
+    return info
+
+
+def seg_lengths(nt: int, nseg: int):
+    """Lengths of nseg consecutive time segments covering nt steps."""
+    nseg = max(1, min(nseg, nt)) if nt > 0 else 1
+    base, extra = divmod(nt, nseg)
+    return [base + 1] * extra + [base] * (nseg - extra)
+
+
+class SegmentedSolve:
+    """One solve of a workload split into time segments: segment c propagates
+    every system over steps [start_c, start_c + len_c], continuing from the
+    previous segment's final states (psi_final -> psi0).  One plan per
+    distinct segment length (at most two)."""
+
+    def __init__(self, torch, L, w, a_sc, nseg, options, dev):
+        self.torch, self.L, self.w, self.dev = torch, L, w, dev
+        self.lens = seg_lengths(w.nt, nseg)
+        self.starts = [0]
+        for n in self.lens[:-1]:
+            self.starts.append(self.starts[-1] + n)
+        self.plans = {}
+        for n in sorted(set(self.lens), reverse=True):
+            p = L.make_params(w.dx, w.dt, a_sc, n, mask_fraction=w.mask_frac, mask_power=w.mask_pow)
+            self.plans[n] = L.Plan(p, w.n_per, options=options)
+        self.E, self.acc, self.xe, self.nr, self.st = [], [], [], [], []
+        for i0, n in zip(self.starts, self.lens):
+            e = w.efield(xp={"device": dev}, i0=i0, nt=n).contiguous()
+            self.E.append(e)
+            self.acc.append(torch.empty_like(e))
+            self.xe.append(torch.empty_like(e))
+            self.nr.append(torch.empty_like(e))
+            self.st.append(torch.full((w.batch,), -1, dtype=torch.int32, device=dev))
+        npsi = 2 * int(sum(w.n_per))
+        self.psi = [torch.empty(npsi, dtype=torch.float64, device=dev) if len(self.lens) > 1 else None
+                    for _ in range(2)]
+        self.work = [float(sum(w.n_per)) * n for n in self.lens]
+
+    @property
+    def nseg(self):
+        return len(self.lens)
+
+    def plan(self, c=0):
+        return self.plans[self.lens[c]]
+
+    def run(self, c):
+        """Segment c (from the plan's ground states for c = 0)."""
+        psi_in = None if c == 0 else self.psi[(c - 1) % 2]
+        psi_out = self.psi[c % 2] if c + 1 < self.nseg else None
+        self.L.tdse_propagate_batch(self.plans[self.lens[c]], self.E[c], psi_in, self.acc[c],
+                                    self.xe[c], self.nr[c], psi_out, self.st[c])
+
+    def series(self, rows, nseg=None):
+        """Accelerations of `rows` over segments [0, nseg), as one series
+        (each segment's last sample is the next one's first)."""
+        nseg = self.nseg if nseg is None else nseg
+        idx = self.torch.as_tensor(rows, device=self.dev)
+        parts = [self.acc[c][idx][:, :-1] for c in range(nseg - 1)] + [self.acc[nseg - 1][idx]]
+        return self.torch.cat(parts, dim=1).cpu().numpy()
+
+    def statuses_clean(self, nseg=None):
+        nseg = self.nseg if nseg is None else nseg
+        return all(int((self.st[c] != 0).sum()) == 0 for c in range(nseg))
+
+    def close(self):
+        for p in self.plans.values():
+            p.close()
+
+
+def timed_steps(torch, solve, steps, warmup, stream):
+    """Warm-up, then `steps` timed bench steps (step j runs segment j mod
+    nseg); HIP events on the launch stream around every step.  Returns
+    (total ms, per-step ms list, grid-point-steps done)."""
+    for j in range(warmup):
+        solve.run(j % solve.nseg)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for j in range(steps):
+        solve.run(j % solve.nseg)
+        ev[j + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[j].elapsed_time(ev[j + 1]) for j in range(steps)]
+    work = sum(solve.work[j % solve.nseg] for j in range(steps))
+    return ev[0].elapsed_time(ev[steps]), per, work
+
+
+def kernel_shape(plan, n):
+    ki = plan.kernel_info(n)
+    lay, info = plan.layout(n), plan.launch_info(n)
+    return {"points_per_lane": lay.points_per_lane, "lanes": lay.lanes,
+            "scan_levels": lay.scan_levels, "systems_per_workgroup": info.systems_per_workgroup,
+            "lds_tables": info.lds_tables, "workgroup_lanes": ki.workgroup_lanes,
+            "grid": ki.grid, "workgroups_per_cu": ki.workgroups_per_cu,
+            "waves_per_simd": ki.waves_per_simd, "max_waves_per_simd": 8,
+            "lds_bytes_per_workgroup": ki.lds_bytes, "vgprs": ki.vgprs}
+
+
+def lds_bytes_per_point_step(shape):
+    """LDS bytes the forward kernel reads per grid-point-step: om is read by
+    each of the four sweeps and dV/dx once by the observables (8 B each)
+    when both tables are staged in LDS; om alone is staged for the largest
+    grids; nothing otherwise."""
+    return {1: 40.0, 2: 32.0}.get(shape["lds_tables"], 0.0)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="focus",
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="volume",
                     choices=["focus", "single", "uneven", "uneven-wide", "volume", "sweep"])
+    ap.add_argument("--segments", type=int, default=0,
+                    help="time segments of one solve (default: --steps for the volume, so the "
+                         "timed steps make up one full solve; 1 otherwise)")
     ap.add_argument("--sweep-n", type=int, default=8192, help="grid size of the sweep workload")
     ap.add_argument("--plain-systems", type=int, default=8)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-focus", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-far-field", action="store_true")
@@ -213,53 +348,44 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     L.load()
+    stream = torch.cuda.current_stream()
+    opts = 0 if args.no_autotune else L.TDSE_OPT_AUTOTUNE
 
     w = {"focus": ti.cfg2_focus, "single": ti.cfg1_single, "uneven": ti.cfg3_uneven,
          "uneven-wide": lambda: ti.cfg3_uneven(wide=True),
          "volume": ti.cfg5_volume,
          "sweep": lambda: ti.size_sweep(args.sweep_n)}[args.workload]()
+    nseg = args.segments or (args.steps if args.workload == "volume" else 1)
     a_sc, e_g = L.tdse_soft_core_for_ip(w.ip, 2048, w.dx, dtau=1.0, tol=1e-13)
-    log(f"workload {w.name}: P={w.batch} nt={w.nt} soft-core a={a_sc:.10f} (E_g={e_g:.13f})")
-    p = L.make_params(w.dx, w.dt, a_sc, w.nt, mask_fraction=w.mask_frac, mask_power=w.mask_pow)
+    log(f"workload {w.name}: P={w.batch} nt={w.nt} in {nseg} segment(s); soft-core "
+        f"a={a_sc:.10f} (E_g={e_g:.13f})")
     t0 = time.time()
-    plan = L.Plan(p, w.n_per, options=0 if args.no_autotune else L.TDSE_OPT_AUTOTUNE)
-    layouts = {}
-    for n in sorted(set(w.n_per)):
-        lay, info = plan.layout(n), plan.launch_info(n)
-        layouts[n] = {"points_per_lane": lay.points_per_lane, "lanes": lay.lanes,
-                      "scan_levels": lay.scan_levels,
-                      "systems_per_workgroup": info.systems_per_workgroup,
-                      "lds_tables": info.lds_tables}
-    log(f"plan built in {time.time() - t0:.2f} s ({'default layouts' if args.no_autotune else 'autotuned'}); "
-        f"{len(layouts)} sizes, first {next(iter(layouts.items()))}")
-    E = w.efield(xp={"device": dev}).contiguous()
-    acc = torch.empty_like(E)
-    xe = torch.empty_like(E)
-    nr = torch.empty_like(E)
-    status = torch.empty(w.batch, dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
-    point_steps = float(sum(w.n_per)) * w.nt
+    solve = SegmentedSolve(torch, L, w, a_sc, nseg, opts, dev)
+    shapes = {n: kernel_shape(solve.plan(), n) for n in sorted(set(w.n_per))}
+    log(f"plans built in {time.time() - t0:.2f} s "
+        f"({'default layouts' if args.no_autotune else 'autotuned'}), segments of "
+        f"{sorted(set(solve.lens))} steps; {len(shapes)} sizes, first {next(iter(shapes.items()))}")
 
-    for _ in range(args.warmup):
-        L.tdse_propagate_batch(plan, E, None, acc, xe, nr, None, status)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t_wall = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        L.tdse_propagate_batch(plan, E, None, acc, xe, nr, None, status)
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    ms_total, per_ms, work = timed_steps(torch, solve, args.steps, args.warmup, stream)
     t_wall = time.perf_counter() - t_wall
-    ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
-    value = point_steps / (ms_step * 1e-3)
-    st = status.cpu().numpy()
-    log(f"batched: {ms_step:.1f} ms/step, {value:.4e} grid-point-steps/s (wall {t_wall:.2f} s); "
-        f"status nonzero: {int(np.count_nonzero(st))}")
-    achieved = FLOPS_PER_POINT_STEP * value / 1e12
+    value = work / (ms_total * 1e-3)
+    clean = solve.statuses_clean(min(args.steps, solve.nseg))
+    log(f"batched: {ms_step:.1f} ms/step, {value:.4e} grid-point-steps/s (wall {t_wall:.2f} s "
+        f"incl. warm-up); statuses clean: {clean}")
+    # the dominant kernel: one forward launch per step (graph replay with a
+    # counter reset of a few microseconds)
+    avg_launch_s = float(np.mean(per_ms)) * 1e-3
+    avg_work = work / args.steps
+    achieved = FLOPS_PER_POINT_STEP * avg_work / avg_launch_s / 1e12
+    shape0 = next(iter(shapes.values()))
+    lds_b = lds_bytes_per_point_step(shape0) if len(shapes) == 1 else None
+    lds = None
+    if lds_b:
+        lds_rate = lds_b * avg_work / avg_launch_s / 1e12
+        lds = {"bytes_per_grid_point_step": lds_b, "achieved_tbs": lds_rate,
+               "peak_tbs": LDS_PEAK_TBS, "frac": lds_rate / LDS_PEAK_TBS}
 
     out = {
         "metric": "TDSE grid-point-steps/s FP64, batched vs plain; adjoint grad time at 1e-9 err",
@@ -274,40 +400,78 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "systems": w.batch, "grid_points": int(w.n_per[0]) if len(set(w.n_per)) == 1 else "ragged",
-                   "nt": w.nt, "dx": w.dx, "dt": w.dt, "grid_point_steps": point_steps,
+        "config": {"workload": w.name, "systems": w.batch,
+                   "grid_points": int(w.n_per[0]) if len(shapes) == 1 else "ragged",
+                   "nt": w.nt, "dx": w.dx, "dt": w.dt,
+                   "grid_point_steps": float(sum(w.n_per)) * w.nt,
+                   "segments": solve.nseg, "segment_steps": sorted(set(solve.lens)),
+                   "timed_grid_point_steps": work,
+                   "step": ("one time segment of the solve for every system (psi carried from "
+                            "segment to segment); the timed steps make up one full solve"
+                            if solve.nseg == args.steps and solve.nseg > 1 else
+                            "one full solve of the batch" if solve.nseg == 1 else
+                            f"one of {solve.nseg} time segments of the solve"),
                    "parallelism": "single-gpu", "autotune": not args.no_autotune,
-                   "layout": next(iter(layouts.values())) if len(layouts) == 1 else
-                   f"{len(layouts)} sizes"},
+                   "layout": shape0 if len(shapes) == 1 else f"{len(shapes)} sizes"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": read_traffic(w.name),
                      "kernel": "forward_kernel (graph replay incl. counter reset)",
-                     "flops_per_grid_point_step": FLOPS_PER_POINT_STEP},
+                     "flops_per_grid_point_step": FLOPS_PER_POINT_STEP,
+                     "grid_point_steps_per_launch": avg_work,
+                     "avg_launch_ms": avg_launch_s * 1e3,
+                     "lds": lds,
+                     "occupancy": {k: shape0[k] for k in ("waves_per_simd", "max_waves_per_simd",
+                                                          "workgroups_per_cu", "workgroup_lanes",
+                                                          "vgprs", "lds_bytes_per_workgroup")}},
+        "statuses_clean": clean,
     }
 
     # ---------------------------------------------------------- plain form
     if not args.no_plain:
         m = min(args.plain_systems, w.batch)
         rows = list(range(m))
-        pp = L.Plan(p, [w.n_per[r] for r in rows], options=L.TDSE_OPT_PLAIN)
-        Ep = E[:m].contiguous()
+        n0 = solve.lens[0]
+        pp_params = L.make_params(w.dx, w.dt, a_sc, n0, mask_fraction=w.mask_frac,
+                                  mask_power=w.mask_pow)
+        pp = L.Plan(pp_params, [w.n_per[r] for r in rows], options=L.TDSE_OPT_PLAIN)
+        Ep = solve.E[0][:m].contiguous()
         ap_ = torch.empty_like(Ep)
         L.tdse_propagate_batch(pp, Ep, None, ap_)
         torch.cuda.synchronize()
-        ev0.record(stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         L.tdse_propagate_batch(pp, Ep, None, ap_)
-        ev1.record(stream)
+        e1.record(stream)
         torch.cuda.synchronize()
-        ms_plain = ev0.elapsed_time(ev1)
-        ps_plain = float(sum(w.n_per[r] for r in rows)) * w.nt
+        ms_plain = e0.elapsed_time(e1)
+        ps_plain = float(sum(w.n_per[r] for r in rows)) * n0
         v_plain = ps_plain / (ms_plain * 1e-3)
-        same = bool(torch.equal(ap_, acc[:m]))
+        same = bool(torch.equal(ap_, solve.acc[0][:m]))
         out["plain"] = {"value": v_plain, "unit": "grid-point-steps/s", "systems_timed": m,
-                        "ms": ms_plain, "batched_over_plain": value / v_plain,
+                        "steps": n0, "ms": ms_plain, "batched_over_plain": value / v_plain,
                         "bitwise_equal_to_batched": same}
-        log(f"plain: {v_plain:.4e} grid-point-steps/s on {m} systems; batched/plain = {value / v_plain:.1f}")
+        log(f"plain: {v_plain:.4e} grid-point-steps/s on {m} systems x {n0} steps; "
+            f"batched/plain = {value / v_plain:.1f}")
         pp.close()
+
+    # ------------------------------------------------------------- focus
+    focus = None
+    if not args.no_focus and args.workload != "focus":
+        wf = ti.cfg2_focus()
+        a_f = a_sc if wf.dx == w.dx else L.tdse_soft_core_for_ip(wf.ip, 2048, wf.dx, dtau=1.0,
+                                                                   tol=1e-13)[0]
+        focus = SegmentedSolve(torch, L, wf, a_f, 1, opts, dev)
+        ms_f, per_f, work_f = timed_steps(torch, focus, 3, 1, stream)
+        v_f = work_f / (ms_f * 1e-3)
+        fl_f = FLOPS_PER_POINT_STEP * (work_f / 3) / (np.mean(per_f) * 1e-3) / 1e12
+        out["focus"] = {"workload": wf.name, "systems": wf.batch, "nt": wf.nt,
+                        "value": v_f, "unit": "grid-point-steps/s", "ms_per_solve": ms_f / 3,
+                        "frac": fl_f / FP64_VECTOR_PEAK_TFLOPS,
+                        "traffic": read_traffic(wf.name),
+                        "layout": kernel_shape(focus.plan(), wf.n_per[0]),
+                        "statuses_clean": focus.statuses_clean()}
+        log(f"focus: {ms_f / 3:.1f} ms per solve, {v_f:.4e} grid-point-steps/s")
 
     # ------------------------------------------------------------ adjoint
     if not args.no_adjoint:
@@ -316,15 +480,13 @@ def main():
                                                                      tol=1e-13)[0]
         pa = L.make_params(wa.dx, wa.dt, a_adj, wa.nt, mask_fraction=wa.mask_frac,
                            mask_power=wa.mask_pow)
-        plan_a = L.Plan(pa, wa.n_per, adjoint_k=256,
-                        options=L.TDSE_OPT_STORE_CHECKPOINTS |
-                        (0 if args.no_autotune else L.TDSE_OPT_AUTOTUNE))
+        plan_a = L.Plan(pa, wa.n_per, adjoint_k=256, options=L.TDSE_OPT_STORE_CHECKPOINTS | opts)
         lay_a = plan_a.layout(wa.n_per[0])
         Ea = wa.efield(xp={"device": dev}).contiguous()
         acc_a = torch.empty_like(Ea)
         h_lo, h_hi = wa.meta["band"]
         k_lo, nk = L.tdse_harmonic_band(wa.nt, wa.dt, wa.omega, h_lo, h_hi)
-        work = torch.empty(2 * wa.batch * max(nk, 1), dtype=torch.float64, device=dev)
+        work_y = torch.empty(2 * wa.batch * max(nk, 1), dtype=torch.float64, device=dev)
         yld = torch.empty(wa.batch, dtype=torch.float64, device=dev)
         abar = torch.empty_like(Ea)
         grad = torch.empty_like(Ea)
@@ -333,7 +495,7 @@ def main():
             # forward (stores the checkpoints), loss gradient, reverse sweep; or
             # the adjoint call that runs its own forward pass again
             L.tdse_propagate_batch(plan_a, Ea, None, acc_a)
-            L.tdse_harmonic_yield(wa.batch, wa.nt, wa.dt, wa.omega, h_lo, h_hi, acc_a, None, work,
+            L.tdse_harmonic_yield(wa.batch, wa.nt, wa.dt, wa.omega, h_lo, h_hi, acc_a, None, work_y,
                                   yld, abar)
             if stored:
                 L.tdse_adjoint_batch_stored(plan_a, plan_a.checkpoint_generation(), Ea, abar, grad)
@@ -341,14 +503,15 @@ def main():
                 L.tdse_adjoint_batch(plan_a, Ea, None, abar, grad)
 
         ms = {}
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         for stored in (True, False):
             gradient(stored)
             torch.cuda.synchronize()
-            ev0.record(stream)
+            e0.record(stream)
             gradient(stored)
-            ev1.record(stream)
+            e1.record(stream)
             torch.cuda.synchronize()
-            ms[stored] = ev0.elapsed_time(ev1)
+            ms[stored] = e0.elapsed_time(e1)
         # algorithmic work of one gradient with stored checkpoints: forward,
         # segment recompute and costate step (52 + 52 + 54 flops per
         # grid-point-step); HBM: each recomputed state written to the segment
@@ -362,7 +525,7 @@ def main():
                           "points_per_lane": lay_a.points_per_lane, "lanes": lay_a.lanes,
                           "time_per_gradient_s": ms[True] * 1e-3,
                           "time_per_gradient_recompute_s": ms[False] * 1e-3,
-                          "forward_grid_point_steps": float(sum(wa.n_per)) * wa.nt,
+                          "forward_grid_point_steps": pts_a,
                           "loss": f"sum of H{h_lo}-H{h_hi} Hann-windowed yields",
                           "checkpoints": "stored by the forward pass (time_per_gradient_s); "
                                          "recomputed by the adjoint call (..._recompute_s)",
@@ -377,10 +540,14 @@ def main():
         plan_a.close()
 
     # ------------------------------------------------- energy distribution
-    if not args.no_spectrum and len(set(w.n_per)) == 1:
-        out["energy_spectrum"] = bench_spectrum(torch, L, plan, w, dev, stream)
-        log(f"energy spectrum: {out['energy_spectrum']['ms']:.2f} ms for "
-            f"{out['energy_spectrum']['solves']:.0f} (system, energy) solves")
+    if not args.no_spectrum:
+        host = focus if focus is not None else (solve if args.workload == "focus" else None)
+        if host is not None:
+            out["energy_spectrum"] = bench_spectrum(torch, L, host.plan(), host.w, dev, stream)
+            log(f"energy spectrum: {out['energy_spectrum']['ms']:.2f} ms for "
+                f"{out['energy_spectrum']['solves']:.0f} (system, energy) solves")
+    if focus is not None:
+        focus.close()
 
     # ------------------------------------------------------------ far field
     if not args.no_far_field:
@@ -392,12 +559,25 @@ def main():
     if not args.no_cpu:
         import oracle
 
-        nth = args.cpu_threads or min(16, os.cpu_count() or 1)
-        # a stratified sample: rows spread over the batch (two per thread),
-        # plus the smallest and the largest grid
+        cpu = cpu_model()
+        # the GPU machine allots 16 host threads to a one-GPU job
+        nth = args.cpu_threads or max(1, min(16, cpu["threads_available"]))
+        # a stratified sample: the hottest system, the smallest and the
+        # largest grid, and rows spread over the batch; one per thread
         by_n = np.argsort(np.asarray(w.n_per), kind="stable")
-        rows = np.array(sorted(set(np.linspace(0, w.batch - 1, 2 * nth).round().astype(int).tolist())
-                               | {int(by_n[0]), int(by_n[-1])}))
+        picks = {int(np.argmax(w.e0)), int(by_n[0]), int(by_n[-1])}
+        picks |= set(np.linspace(0, w.batch - 1, nth).round().astype(int).tolist())
+        rows = np.array(sorted(picks))[:max(nth, 3)]
+        # over a bounded number of segments: about ten seconds per system on
+        # one core at the oracle's rate of a few 1e7 grid-point-steps/s
+        n_max = max(w.n_per[r] for r in rows)
+        budget = 4.0e8 / n_max
+        cseg, steps_cpu = 0, 0
+        while cseg < solve.nseg and (cseg == 0 or steps_cpu + solve.lens[cseg] <= budget):
+            steps_cpu += solve.lens[cseg]
+            cseg += 1
+        cseg = min(cseg, args.steps)
+        steps_cpu = sum(solve.lens[:cseg])
         # the oracle's own soft-core fit and ground states (outside the timing)
         a_ref = oracle.soft_core_for_ip(w.ip, 2048, w.dx, dtau=1.0)[0]
         gs = {}
@@ -407,34 +587,39 @@ def main():
             if n not in gs:
                 gs[n] = oracle.ground_state(n, w.dx, a_ref, dtau=1.0, tol=1e-14)[0]
             psi_list.append(gs[n])
-        e_rows = np.ascontiguousarray(w.efield(rows=rows))
+        e_rows = np.ascontiguousarray(w.efield(rows=rows, nt=steps_cpu))
         t0 = time.perf_counter()
         ref = oracle.propagate_batch(e_rows, psi_list, w.dx, w.dt, a_ref, mask_frac=w.mask_frac,
                                      mask_pow=w.mask_pow, nthreads=nth)
         t_cpu = time.perf_counter() - t0
-        ps_cpu = float(sum(w.n_per[r] for r in rows)) * w.nt
-        # one core: the first sampled system alone
+        ps_cpu = float(sum(w.n_per[r] for r in rows)) * steps_cpu
+        # one core: the first sampled system alone over a tenth of the window
+        st1 = max(1, steps_cpu // 10)
         t1 = time.perf_counter()
-        oracle.propagate_batch(e_rows[:1], psi_list[:1], w.dx, w.dt, a_ref, mask_frac=w.mask_frac,
-                               mask_pow=w.mask_pow, nthreads=1)
+        oracle.propagate_batch(e_rows[:1, :st1 + 1], psi_list[:1], w.dx, w.dt, a_ref,
+                               mask_frac=w.mask_frac, mask_pow=w.mask_pow, nthreads=1)
         t1 = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": ps_cpu / t_cpu, "unit": "grid-point-steps/s", "cores": nth,
                                "kind": "oracle",
-                               "sample": f"{len(rows)} systems of the same batch (rows spread over it, "
-                                         f"smallest and largest grid included), full {w.nt} steps, "
-                                         f"one system per thread at a time on {nth} threads, {t_cpu:.1f} s",
-                               "single_core_value": float(w.n_per[rows[0]]) * w.nt / t1,
-                               "cpu_model": cpu_model()}
-        got = acc[torch.as_tensor(rows, device=dev)].cpu().numpy()
+                               "sample": f"{len(rows)} systems of the same batch (the hottest, the "
+                                         f"smallest and largest grid, the rest spread over it), "
+                                         f"first {steps_cpu} of {w.nt} steps "
+                                         f"({cseg} of {solve.nseg} segments), one system per "
+                                         f"thread on {nth} threads, {t_cpu:.1f} s",
+                               "single_core_value": float(w.n_per[rows[0]]) * st1 / t1,
+                               "cpu": cpu,
+                               "full_workload_estimate_s": float(sum(w.n_per)) * w.nt / (ps_cpu / t_cpu)}
+        got = solve.series(rows.tolist(), cseg)
         errs = [float(np.linalg.norm(got[i] - ref["accel"][i]) / np.linalg.norm(ref["accel"][i]))
                 for i in range(len(rows))]
         out["parity"] = {"accel_rel_l2_max": max(errs), "systems_checked": len(rows),
-                         "tolerance": 1e-9}
+                         "samples_checked": steps_cpu + 1, "tolerance": 1e-9,
+                         "oracle_side": "own soft-core fit and ground state"}
         log(f"cpu oracle: {ps_cpu / t_cpu:.3e} grid-point-steps/s on {nth} threads "
-            f"({out['cpu_baseline']['single_core_value']:.3e} on one core, {cpu_model()}); "
-            f"parity max rel-L2 {max(errs):.2e} over {len(rows)} systems")
+            f"({out['cpu_baseline']['single_core_value']:.3e} on one core, {cpu['model']}); "
+            f"parity max rel-L2 {max(errs):.2e} over {len(rows)} systems x {steps_cpu} steps")
 
-    plan.close()
+    solve.close()
     print(json.dumps(out), flush=True)
 
 

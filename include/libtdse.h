@@ -97,6 +97,7 @@ typedef struct {
 tdse_status tdse_ground_state(const tdse_params* p, int32_t n, double dtau, int32_t max_iter,
                               double tol, double* psi_out, double* energy_out, void* stream);
 
+
 /* Soft-core parameter a in [a_lo, a_hi] whose ground-state energy on the
  * n-point grid of spacing dx equals -ip (E_g increases with a).  Multisection:
  * each round evaluates a batch of candidates on the device.
@@ -162,6 +163,18 @@ tdse_status tdse_plan_layout(tdse_plan plan, int32_t n, int32_t* points_per_lane
  * cached per process. */
 tdse_status tdse_plan_launch_info(tdse_plan plan, int32_t n, int32_t* systems_per_workgroup,
                                   int32_t* lds_tables, double* tuned_rate);
+
+/* Launch shape of the persistent forward kernel that propagates the systems
+ * of size n (section "1D-TSDE Implementation (CTDSE)" is run by one such
+ * launch per lane layout): lanes per workgroup, workgroups launched,
+ * workgroups resident per CU, LDS bytes per workgroup and vector registers
+ * per lane.  Resident wavefronts per SIMD = workgroups_per_cu *
+ * workgroup_lanes / 64 / 4.  Any output pointer may be NULL.  Fails with
+ * TDSE_E_INVALID on a plan created with TDSE_OPT_PLAIN or an n the plan does
+ * not hold. */
+tdse_status tdse_plan_kernel_info(tdse_plan plan, int32_t n, int32_t* workgroup_lanes,
+                                  int32_t* grid, int32_t* workgroups_per_cu, int32_t* lds_bytes,
+                                  int32_t* vgprs);
 
 /* Device copy of the plan's ground state for size n (dev, 2n doubles) and its
  * energy (host, may be NULL).  Synchronous. */
@@ -367,6 +380,33 @@ tdse_status tdse_far_field_adjoint(int32_t n_rho, int32_t n_z, const double* rho
                                    const double* kwave, const double* field_bar, int32_t n_obs,
                                    const double* rho_obs, double z_obs, double* amp_bar,
                                    void* stream);
+
+/* ----------------------------------------------------- field resampling */
+/* The input interface of the solver (section "1D-TSDE Implementation
+ * (CTDSE)": the driving field's time axis is shifted to start at 0 and the
+ * samples are interpolated to the propagation step dt in the Fourier
+ * domain).  Row b of e_coarse holds M samples of one field at spacing
+ * dt_coarse, the first taken as t = 0.  With X_k their DFT and
+ * M' = M dt_coarse / dt, the zero-padded inverse transform of length M'
+ * (the Nyquist bin of an even M split between +M/2 and -M/2) gives
+ *   e_fine[b][i] = (1/M) [X_0 + 2 sum_{0<k<M/2} Re(X_k exp(2 pi i k i/M'))
+ *                         + (M even) Re(X_{M/2}) cos(pi M i / M')],
+ * i = 0..nt, which reproduces the coarse samples at i = j M'/M.  Both
+ * transforms are direct sums on the device (O(M^2/2) and O(M (nt+1)/2)
+ * per row): meant for coarse records of up to about 10^4 samples.
+ *   batch      1 .. 65535 rows;  m: 2 .. 2^20 coarse samples per row
+ *   dt_coarse, dt  > 0, with M dt_coarse / dt an integer M' (to 1e-9
+ *              relative) and M' >= max(m, nt + 1)
+ *   e_coarse   dev [batch][m], 8-byte aligned
+ *   work       dev scratch of at least 16 batch (m/2 + 1) bytes, 16-byte
+ *              aligned (the DFT of every row); contents on return undefined
+ *   e_fine     dev [batch][nt+1], 8-byte aligned: ready for
+ *              tdse_propagate_batch
+ * Fails with TDSE_E_INVALID before any launch.  Asynchronous on `stream`;
+ * allocates nothing. */
+tdse_status tdse_resample_field(int32_t batch, int32_t m, double dt_coarse, double dt, int32_t nt,
+                                const double* e_coarse, double* work, size_t work_bytes,
+                                double* e_fine, void* stream);
 
 #ifdef __cplusplus
 }

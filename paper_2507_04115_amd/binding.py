@@ -69,6 +69,9 @@ _PROTOS = {
     "tdse_plan_launch_info": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                      ctypes.POINTER(_d)]),
     "tdse_plan_ground_state": (_i32, [_vp, _i32, _vp, ctypes.POINTER(_d)]),
+    "tdse_plan_kernel_info": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                     ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                     ctypes.POINTER(_i32)]),
     "tdse_propagate_batch": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tdse_adjoint_batch": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tdse_plan_checkpoint_generation": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint64)]),
@@ -80,6 +83,7 @@ _PROTOS = {
     "tdse_plan_stored_state": (_i32, [_vp, ctypes.c_uint64, _i32, _vp, _vp]),
     "tdse_plan_populations": (_i32, [_vp, ctypes.c_uint64, _vp, _d, _vp, _vp, _vp]),
     "tdse_gabor": (_i32, [_i32, _i32, _d, _vp, _i32, _vp, _i32, _vp, _d, _vp, _vp]),
+    "tdse_resample_field": (_i32, [_i32, _i32, _d, _d, _i32, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "tdse_band_dft": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
     "tdse_band_dft_adjoint": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
     "tdse_far_field": (_i32, [_i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _d, _vp, _vp]),
@@ -220,6 +224,19 @@ class Layout:
 
 
 @dataclass
+class KernelInfo:
+    workgroup_lanes: int
+    grid: int
+    workgroups_per_cu: int
+    lds_bytes: int
+    vgprs: int
+
+    @property
+    def waves_per_simd(self) -> float:
+        return self.workgroups_per_cu * self.workgroup_lanes / 64 / 4
+
+
+@dataclass
 class LaunchInfo:
     systems_per_workgroup: int
     lds_tables: int        # 0 global, 1 om and dV/dx in LDS, 2 om in LDS
@@ -287,6 +304,12 @@ class Plan:
                                             ctypes.byref(r_)), "tdse_plan_launch_info")
         return LaunchInfo(s_.value, int(l_.value), r_.value)
 
+    def kernel_info(self, n: int) -> KernelInfo:
+        v = [_i32() for _ in range(5)]
+        _check(load().tdse_plan_kernel_info(self.handle, n, *[ctypes.byref(x) for x in v]),
+               "tdse_plan_kernel_info")
+        return KernelInfo(*[x.value for x in v])
+
     @property
     def stores_checkpoints(self) -> bool:
         return bool(self.options & TDSE_OPT_STORE_CHECKPOINTS)
@@ -319,8 +342,6 @@ def tdse_propagate_batch(plan: Plan, E, psi0, accel, xexp=None, norm=None, psi_f
     _f64(E, accel, xexp, norm)
     _c128(psi0, psi_final)
     _i32t(sys_status)
-    if accel is None:
-        raise ValueError("accel is required")
     for t, nm in ((E, "E"), (accel, "accel"), (xexp, "xexp"), (norm, "norm")):
         _need(t, plan.series_len, nm)
     _need(psi0, plan.psi_len, "psi0", True)
@@ -469,3 +490,26 @@ def tdse_plan_populations(plan: Plan, generation: int, radius: float, gs=None, v
                                         _ptr(gs), _ptr(vol), _stream(stream)),
            "tdse_plan_populations")
 
+
+def tdse_resample_field(e_coarse, dt_coarse: float, dt: float, nt: int, e_fine=None, work=None,
+                        stream=None):
+    """e_fine [P, nt+1] = the coarse rows e_coarse [P, M] interpolated to dt by
+    Fourier zero-padding (see include/libtdse.h).  e_fine and work are
+    allocated when not given."""
+    import torch
+
+    _f64(e_coarse, e_fine, work)
+    if e_coarse.dim() == 1:
+        e_coarse = e_coarse[None, :]
+    batch, m = e_coarse.shape
+    if e_fine is None:
+        e_fine = torch.empty(batch, nt + 1, dtype=torch.float64, device=e_coarse.device)
+    if work is None:
+        work = torch.empty(2 * batch * (m // 2 + 1), dtype=torch.float64, device=e_coarse.device)
+    _need(e_coarse, batch * m, "e_coarse")
+    _need(e_fine, batch * (nt + 1), "e_fine")
+    _need(work, 2 * batch * (m // 2 + 1), "work")
+    _check(load().tdse_resample_field(batch, m, float(dt_coarse), float(dt), int(nt), _ptr(e_coarse),
+                                      _ptr(work), work.numel() * work.element_size(), _ptr(e_fine),
+                                      _stream(stream)), "tdse_resample_field")
+    return e_fine

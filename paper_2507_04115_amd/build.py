@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libtdse.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["tdse_tables.hip", "tdse_forward.hip", "tdse_adjoint.hip", "tdse_farfield.hip", "tdse_spectrum.hip",
-           "libtdse.cpp"]
+           "tdse_resample.hip", "libtdse.cpp"]
 FLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-mcode-object-version=5", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

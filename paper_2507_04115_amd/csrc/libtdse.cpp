@@ -132,16 +132,41 @@ void carve_class(Arena& ar, SizeClass& sc)
     sc.lt.hasmask = ar.take<int32_t>(T);
 }
 
+// Device memory of the set-up helpers: from hipMalloc (base == nullptr), or
+// carved from a fixed region that the caller owns (the allocation-free
+// ground state's static workspace), 256-byte aligned.
+struct DevMem {
+    char* base = nullptr;
+    size_t size = 0, used = 0;
+    bool heap() const { return base == nullptr; }
+    hipError_t take(void** p, size_t bytes)
+    {
+        if (heap()) return hipMalloc(p, bytes);
+        const size_t b = (bytes + 255) & ~size_t(255);
+        if (used + b > size) return hipErrorOutOfMemory;
+        *p = base + used;
+        used += b;
+        return hipSuccess;
+    }
+    void give(void* p)
+    {
+        if (heap() && p) (void)hipFree(p);
+    }
+};
+
 // A set of size classes with their device tables.
 struct ClassSet {
     std::vector<SizeClass> h;
     SizeClass* d = nullptr;
     char* mem = nullptr;
+    bool owned = true;  // d and mem came from hipMalloc
 
     void release()
     {
-        if (d) (void)hipFree(d);
-        if (mem) (void)hipFree(mem);
+        if (owned) {
+            if (d) (void)hipFree(d);
+            if (mem) (void)hipFree(mem);
+        }
         d = nullptr;
         mem = nullptr;
         h.clear();
@@ -152,8 +177,11 @@ struct ClassSet {
 // depth of each class from the measured decay of the carry products.
 tdse_status build_classes(ClassSet& cs, const std::vector<int>& ns,
                           const std::vector<Layout>& layouts, const std::vector<TableParams>& params,
-                          hipStream_t st)
+                          hipStream_t st, DevMem* dm = nullptr)
 {
+    DevMem heap;
+    DevMem& m = dm ? *dm : heap;
+    cs.owned = m.heap();
     const int ncls = (int)ns.size();
     cs.h.assign(ncls, SizeClass{});
     size_t total = 0;
@@ -165,7 +193,7 @@ tdse_status build_classes(ClassSet& cs, const std::vector<int>& ns,
     const size_t scratch_bytes = (size_t)ncls * 2 * max_t * sizeof(cd);
     const size_t metric_bytes = (size_t)ncls * 2 * (kMaxLevels + 1) * sizeof(double);
     const size_t param_bytes = (size_t)ncls * sizeof(TableParams);
-    HIP_TRY(hipMalloc(&cs.mem, total + 3 * 256));
+    HIP_TRY(m.take(reinterpret_cast<void**>(&cs.mem), total + 3 * 256));
     Arena ar{cs.mem, total, 0};
     for (int c = 0; c < ncls; ++c) {
         SizeClass& sc = cs.h[c];
@@ -180,9 +208,9 @@ tdse_status build_classes(ClassSet& cs, const std::vector<int>& ns,
         sc.dofs10 = 7.2 * habs / (params[c].dx * params[c].dx);
         carve_class(ar, sc);
     }
-    HIP_TRY(hipMalloc(&cs.d, sizeof(SizeClass) * ncls));
+    HIP_TRY(m.take(reinterpret_cast<void**>(&cs.d), sizeof(SizeClass) * ncls));
     char* tmp = nullptr;
-    HIP_TRY(hipMalloc(&tmp, scratch_bytes + metric_bytes + param_bytes + 3 * 256));
+    HIP_TRY(m.take(reinterpret_cast<void**>(&tmp), scratch_bytes + metric_bytes + param_bytes + 3 * 256));
     cd* d_scratch = reinterpret_cast<cd*>(tmp);
     double* d_metrics = reinterpret_cast<double*>(tmp + ((scratch_bytes + 255) & ~size_t(255)));
     TableParams* d_params = reinterpret_cast<TableParams*>(
@@ -237,7 +265,7 @@ tdse_status build_classes(ClassSet& cs, const std::vector<int>& ns,
             hipStreamSynchronize(st) != hipSuccess)
             rc = fail(TDSE_E_DEVICE, "copy of size classes failed");
     } while (0);
-    (void)hipFree(tmp);
+    m.give(tmp);
     return rc;
 }
 
@@ -268,14 +296,17 @@ TableParams imag_time_params(double dx, double a, double z, double dtau)
 // Runs the ground-state kernel for candidates that all share one layout.
 tdse_status run_ground_states(const ClassSet& cs, const std::vector<int>& cls_of, double dtau,
                               int max_iter, double tol, double* d_psi, const int64_t* h_psi_off,
-                              std::vector<double>& energy, std::vector<int>& iters, hipStream_t st)
+                              std::vector<double>& energy, std::vector<int>& iters, hipStream_t st,
+                              DevMem* dm = nullptr)
 {
+    DevMem heap;
+    DevMem& m = dm ? *dm : heap;
     const int nc = (int)cls_of.size();
     char* tmp = nullptr;
     const size_t b_cls = ((sizeof(int32_t) * nc + 255) & ~size_t(255));
     const size_t b_off = ((sizeof(int64_t) * nc + 255) & ~size_t(255));
     const size_t b_e = ((sizeof(double) * nc + 255) & ~size_t(255));
-    HIP_TRY(hipMalloc(&tmp, b_cls + b_off + b_e + sizeof(int32_t) * nc));
+    HIP_TRY(m.take(reinterpret_cast<void**>(&tmp), b_cls + b_off + b_e + sizeof(int32_t) * nc));
     int32_t* d_cls = reinterpret_cast<int32_t*>(tmp);
     int64_t* d_off = reinterpret_cast<int64_t*>(tmp + b_cls);
     double* d_e = reinterpret_cast<double*>(tmp + b_cls + b_off);
@@ -320,8 +351,20 @@ tdse_status run_ground_states(const ClassSet& cs, const std::vector<int>& cls_of
         }
         for (int i = 0; i < nc; ++i) iters[i] = it32[i];
     } while (0);
-    (void)hipFree(tmp);
+    m.give(tmp);
     return rc;
+}
+
+// Device bytes build_classes and run_ground_states take for one ground state
+// of layout L (each piece rounded to 256 bytes as DevMem::take does).
+size_t ground_state_device_bytes(const Layout& L)
+{
+    auto r = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t scratch_bytes = 2 * (size_t)L.T * sizeof(cd);
+    const size_t metric_bytes = 2 * (kMaxLevels + 1) * sizeof(double);
+    return r(class_bytes(L) + 3 * 256) + r(sizeof(SizeClass)) +
+           r(scratch_bytes + metric_bytes + sizeof(TableParams) + 3 * 256) +
+           r(3 * 256 + sizeof(int32_t));
 }
 
 tdse_status check_params(const tdse_params* p, bool need_time)
@@ -1354,6 +1397,26 @@ tdse_status tdse_plan_launch_info(tdse_plan plan, int32_t n, int32_t* systems_pe
     return TDSE_OK;
 }
 
+tdse_status tdse_plan_kernel_info(tdse_plan plan, int32_t n, int32_t* workgroup_lanes,
+                                  int32_t* grid, int32_t* workgroups_per_cu, int32_t* lds_bytes,
+                                  int32_t* vgprs)
+{
+    if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
+    auto it = plan->cls_of_n.find(n);
+    if (it == plan->cls_of_n.end()) return fail(TDSE_E_INVALID, "n=%d is not in the plan", n);
+    const int gi = plan->fgroup_of_cls[it->second];
+    if (gi < 0 || gi >= (int)plan->fgroups.size())
+        return fail(TDSE_E_INVALID, "n=%d has no forward launch (plain plan)", n);
+    const tdse_plan_s::FwdGroup& g = plan->fgroups[gi];
+    const bool ab = g.C >= 12 && plan->fwd_ab;
+    if (workgroup_lanes) *workgroup_lanes = g.threads;
+    if (grid) *grid = g.grid;
+    if (workgroups_per_cu) *workgroups_per_cu = forward_occupancy(g.C, g.threads, g.smem, g.tab);
+    if (lds_bytes) *lds_bytes = (int32_t)g.smem;
+    if (vgprs) *vgprs = forward_vgprs(g.C, g.tab, ab);
+    return TDSE_OK;
+}
+
 tdse_status tdse_plan_ground_state(tdse_plan plan, int32_t n, double* psi_out, double* energy_out)
 {
     if (!plan || !psi_out) return fail(TDSE_E_INVALID, "NULL argument");
@@ -1566,6 +1629,41 @@ tdse_status tdse_ground_state(const tdse_params* p, int32_t n, double dtau, int3
     }
     cs.release();
     return st;
+}
+
+tdse_status tdse_resample_field(int32_t batch, int32_t m, double dt_coarse, double dt, int32_t nt,
+                                const double* e_coarse, double* work, size_t work_bytes,
+                                double* e_fine, void* stream)
+{
+    g_last_error.clear();
+    if (batch < 1 || batch > 65535) return fail(TDSE_E_INVALID, "batch must be in [1, 65535]");
+    if (m < 2 || m > (1 << 20)) return fail(TDSE_E_INVALID, "m must be in [2, 2^20]");
+    if (nt < 0) return fail(TDSE_E_INVALID, "nt must be >= 0");
+    if (!(dt_coarse > 0.0) || !(dt > 0.0)) return fail(TDSE_E_INVALID, "dt_coarse and dt must be > 0");
+    const double ratio = (double)m * dt_coarse / dt;
+    const double mp = std::round(ratio);
+    if (!(std::fabs(ratio - mp) <= 1e-9 * ratio) || mp > 2147483647.0)
+        return fail(TDSE_E_INVALID, "m dt_coarse / dt = %.12g is not an integer (the padded length)", ratio);
+    if (mp < (double)m || mp < (double)nt + 1.0)
+        return fail(TDSE_E_INVALID, "the padded length %.0f is below max(m, nt+1) = %d", mp,
+                    std::max(m, nt + 1));
+    if (!e_coarse || !work || !e_fine) return fail(TDSE_E_INVALID, "e_coarse, work and e_fine are required");
+    if (!aligned16(work) || (reinterpret_cast<uintptr_t>(e_coarse) & 7u) ||
+        (reinterpret_cast<uintptr_t>(e_fine) & 7u))
+        return fail(TDSE_E_INVALID, "work must be 16-byte aligned, e_coarse and e_fine 8-byte aligned");
+    const size_t need = (size_t)16 * (size_t)batch * (size_t)(m / 2 + 1);
+    if (work_bytes < need) return fail(TDSE_E_INVALID, "work holds %zu bytes, needs %zu", work_bytes, need);
+    ResampleArgs a{};
+    a.batch = batch;
+    a.m = m;
+    a.nt = nt;
+    a.mp = (int64_t)mp;
+    a.coarse = e_coarse;
+    a.spec = work;
+    a.fine = e_fine;
+    if (launch_resample(a, reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(TDSE_E_DEVICE, "resampling launch failed: %s", hipGetErrorString(hipGetLastError()));
+    return TDSE_OK;
 }
 
 tdse_status tdse_soft_core_for_ip(double ip, int32_t n, double dx, double dtau, double tol,

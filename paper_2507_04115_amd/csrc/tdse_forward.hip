@@ -328,6 +328,43 @@ int forward_occupancy(int C, int threads, size_t smem, int tab)
     }
 }
 
+template <int C, int TAB, bool AB>
+static int regs_fwd()
+{
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(forward_kernel<C, TAB, AB>)) != hipSuccess)
+        return 0;
+    return fa.numRegs;
+}
+
+int forward_vgprs(int C, int tab, bool ab)
+{
+    if (C >= 12 && ab) {
+        switch (C * 4 + tab) {
+            case 48: return regs_fwd<12, kTabGlobal, true>();
+            case 49: return regs_fwd<12, kTabLds, true>();
+            case 50: return regs_fwd<12, kTabOmLds, true>();
+            case 64: return regs_fwd<16, kTabGlobal, true>();
+            case 65: return regs_fwd<16, kTabLds, true>();
+            case 66: return regs_fwd<16, kTabOmLds, true>();
+            default: return 0;
+        }
+    }
+    switch (C * 4 + tab) {
+        case 16: return regs_fwd<4, kTabGlobal, false>();
+        case 17: return regs_fwd<4, kTabLds, false>();
+        case 32: return regs_fwd<8, kTabGlobal, false>();
+        case 33: return regs_fwd<8, kTabLds, false>();
+        case 48: return regs_fwd<12, kTabGlobal, false>();
+        case 49: return regs_fwd<12, kTabLds, false>();
+        case 50: return regs_fwd<12, kTabOmLds, false>();
+        case 64: return regs_fwd<16, kTabGlobal, false>();
+        case 65: return regs_fwd<16, kTabLds, false>();
+        case 66: return regs_fwd<16, kTabOmLds, false>();
+        default: return 0;
+    }
+}
+
 hipError_t launch_forward(int C, int tab, const FwdArgs& a, int threads, size_t smem, int grid,
                           hipStream_t st)
 {

@@ -150,6 +150,16 @@ struct YieldArgs {
     double* abar;
 };
 
+// Field resampling by Fourier zero-padding (tdse_resample_field).
+struct ResampleArgs {
+    int32_t batch, m, nt;
+    int64_t mp;             // padded length M' = M dt_coarse / dt
+    const double* coarse;   // [batch][m]
+    double* spec;           // [batch][m/2+1] complex: the DFT of each row
+    double* fine;           // [batch][nt+1]
+};
+
+hipError_t launch_resample(const ResampleArgs& a, hipStream_t st);
 hipError_t launch_far_field(const FarArgs& a, bool adjoint, hipStream_t st);
 hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st);
 // Bytes of the shared elimination factors of tdse_plan_energy_spectrum.
@@ -177,6 +187,8 @@ size_t sub_smem_bytes(int W);
 // when it does not fit or the combination is not instantiated).
 bool forward_tab_supported(int C, int tab);
 int forward_occupancy(int C, int threads, size_t smem, int tab);
+// Vector registers per lane of the forward kernel instance (0 if not instantiated).
+int forward_vgprs(int C, int tab, bool ab);
 hipError_t launch_forward(int C, int tab, const FwdArgs& a, int threads, size_t smem, int grid,
                           hipStream_t st);
 

@@ -75,23 +75,11 @@ def resample_field(e_coarse: torch.Tensor, dt_coarse: float, dt: float, nt: int)
     spectrum (section "1D-TSDE Implementation (CTDSE)": the input interface
     shifts the time axis to start at 0 and interpolates to dt in the Fourier
     domain).  The interpolant has period M dt_coarse, which must be an integer
-    multiple M' >= nt + 1 of dt; for even M the Nyquist bin is split between
-    +M/2 and -M/2.  Runs on the tensor's device (rocFFT through torch.fft);
-    the result is a contiguous [P, nt+1] float64 tensor ready for
-    tdse_propagate_batch."""
-    e = torch.atleast_2d(e_coarse).to(torch.float64)
-    M = e.shape[1]
-    ratio = M * dt_coarse / dt
-    Mp = int(round(ratio))
-    if abs(ratio - Mp) > 1e-9 * ratio or Mp < max(M, nt + 1):
-        raise ValueError("M dt_coarse / dt must be an integer >= max(M, nt + 1)")
-    X = torch.fft.rfft(e, dim=1)
-    Y = torch.zeros(e.shape[0], Mp // 2 + 1, dtype=X.dtype, device=e.device)
-    keep = (M + 1) // 2                      # bins 0 .. ceil(M/2)-1
-    Y[:, :keep] = X[:, :keep]
-    if M % 2 == 0:
-        # the Nyquist bin X_{M/2} (real) counts once at +M/2 and once at -M/2
-        Y[:, M // 2] = X[:, M // 2] * (1.0 if Mp == M else 0.5)
-    fine = torch.fft.irfft(Y, n=Mp, dim=1) * (Mp / M)
-    return fine[:, :nt + 1].contiguous()
+    multiple M' >= max(M, nt + 1) of dt; for even M the Nyquist bin is split
+    between +M/2 and -M/2.  Runs in the library (tdse_resample_field) on the
+    tensor's device; the result is a contiguous [P, nt+1] float64 tensor
+    ready for tdse_propagate_batch."""
+    from . import binding as L
 
+    e = torch.atleast_2d(e_coarse).to(torch.float64).contiguous()
+    return L.tdse_resample_field(e, dt_coarse, dt, nt)

@@ -52,16 +52,17 @@ def n_steps(omega: float, ncycles: float, dt: float) -> int:
 
 
 def sin2_pulse(e0, omega: float, ncycles: float, dt: float, phase=0.0,
-               nt: Optional[int] = None, xp=np):
+               nt: Optional[int] = None, xp=np, i0: int = 0):
     """Samples E_i = e0 sin^2(pi t_i/T) sin(omega t_i + phase), t_i = i dt,
-    i = 0..nt, and 0 for t_i > T.  ``e0`` and ``phase`` may be arrays of
+    i = i0..i0+nt, and 0 for t_i > T.  ``e0`` and ``phase`` may be arrays of
     shape [P] (one row per macroscopic point); the result is [P, nt+1] or
-    [nt+1].  ``xp`` is numpy or torch (for generation on the device)."""
+    [nt+1].  ``xp`` is numpy or torch (for generation on the device).  A
+    window starting at i0 holds bitwise the samples of the full series."""
     T = pulse_duration(omega, ncycles)
     if nt is None:
-        nt = n_steps(omega, ncycles, dt)
+        nt = n_steps(omega, ncycles, dt) - i0
     if xp is np:
-        t = np.arange(nt + 1, dtype=np.float64) * dt
+        t = np.arange(i0, i0 + nt + 1, dtype=np.float64) * dt
         e0a = np.asarray(e0, dtype=np.float64)
         pha = np.asarray(phase, dtype=np.float64)
         env = np.where(t <= T, np.sin(np.pi * t / T) ** 2, 0.0)
@@ -73,7 +74,7 @@ def sin2_pulse(e0, omega: float, ncycles: float, dt: float, phase=0.0,
     import torch  # generation on a device; plumbing only
 
     dev = xp["device"] if isinstance(xp, dict) else "cpu"
-    t = torch.arange(nt + 1, dtype=torch.float64, device=dev) * dt
+    t = torch.arange(i0, i0 + nt + 1, dtype=torch.float64, device=dev) * dt
     env = torch.where(t <= T, torch.sin(math.pi * t / T) ** 2, torch.zeros_like(t))
     e0t = torch.as_tensor(e0, dtype=torch.float64, device=dev).reshape(-1, 1)
     pht = torch.as_tensor(phase, dtype=torch.float64, device=dev).reshape(-1, 1)
@@ -131,13 +132,25 @@ class Workload:
     def point_steps(self) -> int:
         return int(sum(self.n_per)) * self.nt
 
-    def efield(self, rows=None, xp=np):
+    def subset(self, rows, name: Optional[str] = None) -> "Workload":
+        """The systems `rows` of this batch, in that order, as a batch of their own."""
+        rows = [int(r) for r in rows]
+        meta = {k: (v[rows] if isinstance(v, np.ndarray) and v.shape[:1] == (self.batch,) else v)
+                for k, v in self.meta.items()}
+        return Workload(name or f"{self.name}-sub{len(rows)}", self.dx, self.dt, self.omega,
+                        self.ncycles, self.nt, [self.n_per[r] for r in rows], self.e0[rows],
+                        self.phase[rows], self.ip, self.mask_frac, self.mask_pow, meta)
+
+    def efield(self, rows=None, xp=np, i0: int = 0, nt: Optional[int] = None):
         """Field samples [P, nt+1] (numpy, or torch on a device when xp is
-        {"device": dev})."""
+        {"device": dev}); with i0/nt the window of samples i0..i0+nt of the
+        full series (nt defaults to the rest of the pulse)."""
         e0, ph = self.e0, self.phase
         if rows is not None:
             e0, ph = e0[rows], ph[rows]
-        return sin2_pulse(e0, self.omega, self.ncycles, self.dt, ph, nt=self.nt, xp=xp)
+        if nt is None:
+            nt = self.nt - i0
+        return sin2_pulse(e0, self.omega, self.ncycles, self.dt, ph, nt=nt, xp=xp, i0=i0)
 
 
 def cfg1_single() -> Workload:

@@ -94,3 +94,23 @@ def test_harmonic_band_matches_definition():
     k = np.arange(22048 // 2 + 1)
     sel = k[(k * dw >= 21 * 0.057) & (k * dw <= 31 * 0.057)]
     assert (k_lo, nk) == (sel[0], len(sel))
+
+
+def test_resample_validation_before_any_launch():
+    """tdse_resample_field refuses bad sizes on the host (no device needed):
+    a padded length M dt_coarse / dt that is not an integer or is below
+    max(M, nt+1), a short workspace, an empty batch, misalignment."""
+    lib = L.load()
+    f = lib.tdse_resample_field
+    bad = [
+        (4, 64, 0.3, 0.07, 100, 16, 16, 16 * 4 * 33, 16, None),    # 64 * 0.3 / 0.07 not an integer
+        (4, 64, 0.3, 0.1, 192, 16, 16, 16 * 4 * 33, 16, None),     # M' = 192 < nt + 1
+        (4, 64, 0.3, 0.1, 100, 16, 16, 16 * 4 * 33 - 1, 16, None), # work too small
+        (0, 64, 0.3, 0.1, 100, 16, 16, 16 * 4 * 33, 16, None),     # empty batch
+        (4, 1, 0.3, 0.1, 100, 16, 16, 16 * 4 * 33, 16, None),      # one sample
+        (4, 64, 0.3, 0.1, 100, 16, 24, 16 * 4 * 33, 16, None),     # work not 16-byte aligned
+        (4, 64, 0.3, 0.1, 100, None, 16, 16 * 4 * 33, 16, None),   # no input
+    ]
+    for args in bad:
+        assert f(*args) == L.TDSE_E_INVALID, args
+        assert lib.tdse_last_error().decode()

@@ -29,3 +29,14 @@ def test_traffic_only_for_matching_sources(tmp_path, monkeypatch):
     assert bench.read_traffic("w") == 1024.0 * (2 * 1000 + 3000)
     assert bench.read_traffic("x") is None
     assert bench.read_traffic("missing") is None
+
+
+def test_segments_cover_the_time_loop_once():
+    """The headline run splits one solve into time segments: the lengths add
+    up to the pulse's steps, differ by at most one, and each segment starts
+    where the previous one ended."""
+    for nt, k in [(213056, 20), (213056, 64), (44093, 1), (7, 20), (100, 3)]:
+        lens = bench.seg_lengths(nt, k)
+        assert sum(lens) == nt
+        assert max(lens) - min(lens) <= 1
+        assert len(lens) == min(k, nt)

@@ -62,22 +62,3 @@ def test_gradient_matches_central_differences(field):
             fd = float((loss(c + h * v) - loss(c - h * v)) / (2 * h))
         ad = float((c.grad * v).sum())
         assert abs(fd - ad) <= 1e-7 * abs(fd)
-
-
-@pytest.mark.parametrize("M,r", [(64, 4), (75, 3), (90, 1)])
-def test_resample_matches_oracle(M, r):
-    import oracle
-    from paper_2507_04115_amd.driver import resample_field
-
-    x = np.random.default_rng(M + r).standard_normal((4, M))
-    nt = M * r - 1
-    got = resample_field(torch.tensor(x), 0.3, 0.3 / r, nt).numpy()
-    ref = oracle.resample_field(x, 0.3, 0.3 / r, nt)
-    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
-
-
-def test_resample_rejects_a_non_integer_period():
-    from paper_2507_04115_amd.driver import resample_field
-
-    with pytest.raises(ValueError):
-        resample_field(torch.zeros(1, 10), 0.3, 0.07, 20)

@@ -31,7 +31,6 @@ def test_short_buffers_raise_before_any_launch(lib):
         dict(E=good, psi0=psi_short_f, accel=acc),
         dict(E=good, psi0=None, accel=acc, psi_final=psi_short),
         dict(E=good, psi0=None, accel=acc, sys_status=st_short),
-        dict(E=good, psi0=None, accel=None),
     ]
     for kw in cases:
         with pytest.raises(ValueError):

@@ -58,3 +58,28 @@ def test_uneven_sizes_and_seeds():
 def test_adjoint_workload_amplitudes():
     w = ti.cfg4_adjoint()
     assert w.batch == 256 and np.all((w.e0 >= 0.05) & (w.e0 <= 0.075))
+
+
+def test_time_windows_hold_the_full_series_samples():
+    """A window i0..i0+nt of the field is bitwise the same samples as the
+    full series (the benchmark chains time segments of one pulse)."""
+    w = ti.cfg5_volume(2, 4)
+    full = w.efield()
+    for i0, nt in [(0, 100), (10653, 10653), (w.nt - 37, 37)]:
+        win = w.efield(i0=i0, nt=nt)
+        assert win.shape == (w.batch, nt + 1)
+        assert np.array_equal(win, full[:, i0:i0 + nt + 1])
+    rest = w.efield(i0=w.nt - 5)
+    assert np.array_equal(rest, full[:, -6:])
+    # past the end of the pulse the field is zero
+    assert np.all(w.efield(i0=w.nt, nt=50)[:, 1:] == 0.0)
+
+
+def test_subset_keeps_rows_and_fields():
+    w = ti.cfg5_volume(4, 8)
+    rows = [5, 0, 31]
+    sub = w.subset(rows)
+    assert sub.batch == 3 and sub.nt == w.nt and sub.dx == w.dx
+    assert np.array_equal(sub.efield(nt=50), w.efield(rows=rows, nt=50))
+    assert np.array_equal(sub.meta["r_um"], w.meta["r_um"][rows])
+    assert sub.meta["band"] == w.meta["band"]
