@@ -115,7 +115,7 @@ def bench_spectrum(torch, L, plan, w, dev, stream):
     psi = gs.repeat(w.batch).contiguous()
     energies = torch.linspace(-0.7, 3.0, 256, dtype=torch.float64, device=dev)
     spec = torch.empty(w.batch, 256, dtype=torch.float64, device=dev)
-    # every (system, energy) solve in flight at once (16 B per point each)
+    # every (system, energy) solve in flight at once (2 B per point each)
     work = torch.empty(L.tdse_plan_energy_spectrum_work(plan, 256, w.batch * 256) // 8,
                        dtype=torch.float64, device=dev)
     L.tdse_plan_energy_spectrum(plan, psi, energies, 0.01, spec, work)
@@ -129,11 +129,20 @@ def bench_spectrum(torch, L, plan, w, dev, stream):
     ms = e0.elapsed_time(e1) / 3
     solves = float(w.batch * 256)
     del work
+    # algorithmic HBM bytes: psi in (16 B per point and system), the shared
+    # factors (48 B per point and energy), the spectrum out; plus the d'
+    # group starts the kernel keeps (2 B per point and solve, written and
+    # read back)
+    algo = 16.0 * n * w.batch + 48.0 * n * 256 + 8.0 * solves
+    ckpt = 2.0 * 2.0 * n * solves
     return {"energies": 256, "eps": 0.01, "ms": ms, "solves": solves,
             "grid_point_solves_per_s": solves * n / (ms * 1e-3),
-            "hbm_bytes_per_grid_point": 32, "note": "elimination factors per (grid size, energy) "
-            "shared by the systems; one lane per (system, energy) carries d' through a "
-            "16 B/point workspace (written, then read back)"}
+            "algorithmic_hbm_bytes": algo, "group_start_bytes": ckpt,
+            "hbm_gbs_incl_group_starts": (algo + ckpt) / (ms * 1e-3) / 1e9,
+            "note": "elimination factors per (grid size, energy) shared by the systems; "
+                    "one lane per (system, energy), tiles of 8 systems x 8 energies per "
+                    "wavefront; d' kept in registers in groups of 8 points, recomputed from "
+                    "each group's start value in the backward sweep"}
 
 
 def bench_far_field(torch, L, ti, dev, stream):

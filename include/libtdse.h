@@ -160,9 +160,28 @@ tdse_status tdse_plan_layout(tdse_plan plan, int32_t n, int32_t* points_per_lane
  * the lane-local Thomas chunks against the
  * width of the cross-lane scan; systems per workgroup; table placement) on
  * a probe batch that fills the GPU once, and keeps the fastest.  Results are
- * cached per process. */
+ * cached per process, and on disk when a cache file is set
+ * (tdse_set_tune_cache, or the TDSE_TUNE_CACHE environment variable). */
 tdse_status tdse_plan_launch_info(tdse_plan plan, int32_t n, int32_t* systems_per_workgroup,
                                   int32_t* lds_tables, double* tuned_rate);
+
+/* Sets the file where the autotuner keeps its choices across processes (path
+ * NULL or "": none; until this is called, the TDSE_TUNE_CACHE environment
+ * variable names it) and clears the per-process cache.  Choices are keyed by
+ * device architecture, n, batch count, dx, dt, a, charge and absorber; a
+ * line that is unreadable, fails its checksum or names a layout that does
+ * not fit is ignored, the size is timed again and the file rewritten (whole,
+ * then renamed into place).  A file that cannot be written only costs the
+ * next process its probes.  Thread-safe. */
+tdse_status tdse_set_tune_cache(const char* path);
+
+/* How the plan's forward calls run: 0 no call yet, 1 replay of a captured
+ * hipGraph, 2 direct launches because graph capture failed (or was
+ * switched off with the TDSE_FORCE_CAPTURE_FAILURE environment variable,
+ * a failure-injection hook); direct launches run the same kernels with the
+ * same arguments.  Plans with TDSE_OPT_NO_GRAPH, TDSE_OPT_PLAIN or stored
+ * checkpoints never capture (state 0). */
+tdse_status tdse_plan_graph_state(tdse_plan plan, int32_t* state);
 
 /* Launch shape of the persistent forward kernel that propagates the systems
  * of size n (section "1D-TSDE Implementation (CTDSE)" is run by one such
@@ -201,6 +220,29 @@ tdse_status tdse_plan_ground_state(tdse_plan plan, int32_t n, double* psi_out,
 tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* psi0,
                                  double* accel, double* xexp, double* norm, double* psi_final,
                                  int32_t* sys_status, void* stream);
+
+/* tdse_propagate_batch that also records, at every sample i = 0..nt, the
+ * ground-state population and the volumetric population near the nucleus
+ * (section "Microscopic Response in XUV regime (TDSE)", the analyses of psi
+ * listed after the dipole acceleration, shown over time in the microscopic
+ * insights of the physical examples):
+ *   gs_pop[b][i]  = |dx sum_j conj(phi_j) psi^(i)_j|^2
+ *   vol_pop[b][i] = dx sum_{|x_j| <= radius} |psi^(i)_j|^2,
+ *                   x_j = (j - (n-1)/2) dx
+ * reduced in the time loop with the other observables.
+ *   psi_ref   dev ragged complex reference states phi (plan offsets), or
+ *             NULL = the plan's ground state of each system's grid
+ *   radius    >= 0 (a.u.)
+ *   gs_pop, vol_pop  dev [batch][nt+1]; at least one of them
+ * The other arguments and outputs are those of tdse_propagate_batch (same
+ * values).  Launched directly (no graph replay).  TDSE_E_UNSUPPORTED on a
+ * plan created with TDSE_OPT_STORE_CHECKPOINTS (its stored states have
+ * tdse_plan_populations).  Asynchronous on `stream`. */
+tdse_status tdse_propagate_batch_populations(tdse_plan plan, const double* E, const double* psi0,
+                                             double* accel, double* xexp, double* norm,
+                                             double* psi_final, int32_t* sys_status,
+                                             const double* psi_ref, double radius,
+                                             double* gs_pop, double* vol_pop, void* stream);
 
 /* --------------------------------------------------------------- adjoint */
 /* Gradient of a loss l(accel) with respect to every field sample.  Given
@@ -286,10 +328,13 @@ tdse_status tdse_plan_populations(tdse_plan plan, uint64_t generation, const dou
  *   energies  dev [n_energy];  eps > 0 (the resolution)
  *   spectrum  dev [batch][n_energy]
  *   work      dev scratch of work_bytes bytes, 16-byte aligned: first the
- *             elimination factors shared by the systems of one size (32 n_max
+ *             elimination factors shared by the systems of one size (48 n_max
  *             bytes per grid size and energy, n_max = the plan's largest n),
- *             then 16 n_max bytes per (system, energy) solve in flight, at
- *             least 64 of them; about 64k keep the GPU busy.
+ *             then M2 psi of every system (16 bytes per point), then
+ *             2 n_max bytes per (system, energy) solve in flight (the start
+ *             of every 8-point group of the forward sweep, recomputed from
+ *             in the backward sweep), at least 64 of them; 256k keep the GPU
+ *             busy.
  *             tdse_plan_energy_spectrum_work gives the size for a number of
  *             solves in flight.  Contents on return are undefined.
  * Fails with TDSE_E_INVALID, before any launch, when work is too small.

@@ -69,10 +69,14 @@ _PROTOS = {
     "tdse_plan_launch_info": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                      ctypes.POINTER(_d)]),
     "tdse_plan_ground_state": (_i32, [_vp, _i32, _vp, ctypes.POINTER(_d)]),
+    "tdse_set_tune_cache": (_i32, [ctypes.c_char_p]),
+    "tdse_plan_graph_state": (_i32, [_vp, ctypes.POINTER(_i32)]),
     "tdse_plan_kernel_info": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                      ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                      ctypes.POINTER(_i32)]),
     "tdse_propagate_batch": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tdse_propagate_batch_populations": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d,
+                                                _vp, _vp, _vp]),
     "tdse_adjoint_batch": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tdse_plan_checkpoint_generation": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint64)]),
     "tdse_adjoint_batch_stored": (_i32, [_vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp]),
@@ -193,6 +197,11 @@ def make_params(dx: float, dt: float, a: float, nt: int, charge_z: float = 1.0,
     return tdse_params(dx, dt, a, charge_z, mask_fraction, mask_power, int(nt), 0)
 
 
+def tdse_set_tune_cache(path: Optional[str]):
+    """File of the autotuner's choices across processes (None: none)."""
+    _check(load().tdse_set_tune_cache(path.encode() if path else None), "tdse_set_tune_cache")
+
+
 def tdse_version() -> str:
     return load().tdse_version().decode()
 
@@ -304,6 +313,12 @@ class Plan:
                                             ctypes.byref(r_)), "tdse_plan_launch_info")
         return LaunchInfo(s_.value, int(l_.value), r_.value)
 
+    def graph_state(self) -> int:
+        """0 no forward call yet, 1 graph replay, 2 direct launches (capture failed)."""
+        v = _i32()
+        _check(load().tdse_plan_graph_state(self.handle, ctypes.byref(v)), "tdse_plan_graph_state")
+        return v.value
+
     def kernel_info(self, n: int) -> KernelInfo:
         v = [_i32() for _ in range(5)]
         _check(load().tdse_plan_kernel_info(self.handle, n, *[ctypes.byref(x) for x in v]),
@@ -350,6 +365,26 @@ def tdse_propagate_batch(plan: Plan, E, psi0, accel, xexp=None, norm=None, psi_f
     _check(load().tdse_propagate_batch(plan.handle, _ptr(E), _ptr(psi0), _ptr(accel), _ptr(xexp),
                                        _ptr(norm), _ptr(psi_final), _ptr(sys_status),
                                        _stream(stream)), "tdse_propagate_batch")
+
+
+def tdse_propagate_batch_populations(plan: Plan, E, psi0, accel, radius: float, gs_pop=None,
+                                     vol_pop=None, xexp=None, norm=None, psi_final=None,
+                                     sys_status=None, psi_ref=None, stream=None):
+    """tdse_propagate_batch plus the ground-state (gs_pop) and volumetric
+    (vol_pop, |x| <= radius) populations at every sample."""
+    _f64(E, accel, xexp, norm, gs_pop, vol_pop)
+    _c128(psi0, psi_final, psi_ref)
+    _i32t(sys_status)
+    for t, nm in ((E, "E"), (accel, "accel"), (xexp, "xexp"), (norm, "norm"), (gs_pop, "gs_pop"),
+                  (vol_pop, "vol_pop")):
+        _need(t, plan.series_len, nm)
+    for t, nm in ((psi0, "psi0"), (psi_final, "psi_final"), (psi_ref, "psi_ref")):
+        _need(t, plan.psi_len, nm, True)
+    _need(sys_status, plan.batch, "sys_status")
+    _check(load().tdse_propagate_batch_populations(
+        plan.handle, _ptr(E), _ptr(psi0), _ptr(accel), _ptr(xexp), _ptr(norm), _ptr(psi_final),
+        _ptr(sys_status), _ptr(psi_ref), float(radius), _ptr(gs_pop), _ptr(vol_pop),
+        _stream(stream)), "tdse_propagate_batch_populations")
 
 
 def tdse_adjoint_batch(plan: Plan, E, psi0, accel_bar, grad_E, accel=None, sys_status=None,

@@ -17,6 +17,8 @@
 #include <string>
 #include <vector>
 
+#include <unistd.h>
+
 #include "libtdse.h"
 #include "tdse_internal.hpp"
 #include "tdse_kernels.hpp"
@@ -88,6 +90,12 @@ int env_int(const char* name, int dflt)
 {
     const char* v = std::getenv(name);
     return (v && *v) ? std::atoi(v) : dflt;
+}
+
+double env_double(const char* name, double dflt)
+{
+    const char* v = std::getenv(name);
+    return (v && *v) ? std::strtod(v, nullptr) : dflt;
 }
 
 Layout default_layout(int n)
@@ -426,7 +434,9 @@ struct tdse_plan_s {
     int32_t* d_counters = nullptr;      // adjoint: launches + 2*launches (compaction); then one
                                         // kQueueInts queue per system (plain) and per forward group
     int32_t* d_ident = nullptr;
-    // graph replay
+    // graph replay; graph_state: 0 not captured yet, 1 replaying a graph,
+    // 2 capture failed (or was switched off) and calls launch directly
+    int graph_state = 0;
     hipStream_t cap = nullptr;
     std::vector<hipStream_t> branch;
     std::vector<hipEvent_t> ev;
@@ -669,12 +679,152 @@ struct TuneChoice {
 using TuneKey = std::tuple<int, int, double, double, double, double, double, double>;
 std::map<TuneKey, TuneChoice> g_tune_cache;
 std::mutex g_tune_mutex;
+std::string g_tune_file;        // on-disk cache (tdse_set_tune_cache), "" = none
+bool g_tune_file_set = false;   // false: TDSE_TUNE_CACHE names the file
 
 Layout layout_for(int n, int C)
 {
     int T = ((n + C - 1) / C + kWave - 1) / kWave * kWave;
     if (T < kWave) T = kWave;
     return {C, T};
+}
+
+// ---- on-disk autotune cache -------------------------------------------
+// One text line per choice:
+//   tdse-tune 1 <arch> <n> <count> <dx> <dt> <a> <z> <mask_frac> <mask_pow> : <C> <T> <S> <tab> <rate> # <fnv>
+// with the doubles as hexadecimal floats (exact) and <fnv> the FNV-1a hash
+// of everything before " # ".  A line that does not parse, fails its hash,
+// belongs to another device architecture or names a layout that does not
+// fit is ignored: the size is probed again and the file rewritten.
+
+uint64_t fnv1a(const std::string& t)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char c : t) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+std::string tune_file()
+{
+    if (g_tune_file_set) return g_tune_file;
+    const char* v = std::getenv("TDSE_TUNE_CACHE");
+    return (v && *v) ? std::string(v) : std::string();
+}
+
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string a = prop.gcnArchName;
+    for (char& c : a)
+        if (c == ' ' || c == '#' || c == ':') c = '_';
+    return a;
+}
+
+std::string tune_key_text(const std::string& arch, const TuneKey& k)
+{
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "tdse-tune 1 %s %d %d %a %a %a %a %a %a", arch.c_str(),
+                  std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+                  std::get<5>(k), std::get<6>(k), std::get<7>(k));
+    return buf;
+}
+
+int fwd_occupancy(int C, int T, int S, int tab);
+
+// A cached choice is used only if it is a layout the plan could have picked.
+bool choice_fits(int n, bool adjoint, const TuneChoice& c)
+{
+    if (!layout_supported(c.C) || (adjoint && c.C == 12)) return false;
+    const Layout L = layout_for(n, c.C);
+    if (L.T != c.T || L.T > 1024 || c.S < 1 || c.S * c.T > 1024) return false;
+    if (!forward_tab_supported(c.C, c.tab)) return false;
+    if (!(c.rate > 0.0) || !std::isfinite(c.rate)) return false;
+    return fwd_occupancy(c.C, c.T, c.S, c.tab) >= 1;
+}
+
+// Reads the file's lines: valid ones into `lines` (key text -> full line),
+// returns the number of lines that were not valid.
+int read_tune_file(const std::string& path, std::map<std::string, std::string>& lines)
+{
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return 0;
+    int bad = 0;
+    char buf[1024];
+    while (std::fgets(buf, sizeof(buf), f)) {
+        std::string line(buf);
+        while (!line.empty() && (line.back() == '\n' || line.back() == '\r')) line.pop_back();
+        if (line.empty()) continue;
+        const size_t h = line.rfind(" # ");
+        const size_t c = line.find(" : ");
+        unsigned long long fnv = 0;
+        if (h == std::string::npos || c == std::string::npos || c > h ||
+            std::sscanf(line.c_str() + h + 3, "%llx", &fnv) != 1 ||
+            fnv1a(line.substr(0, h)) != (uint64_t)fnv) {
+            ++bad;
+            continue;
+        }
+        lines[line.substr(0, c)] = line;
+    }
+    std::fclose(f);
+    return bad;
+}
+
+bool parse_choice(const std::string& line, TuneChoice* out)
+{
+    const size_t c = line.find(" : ");
+    if (c == std::string::npos) return false;
+    TuneChoice t;
+    char tail[8] = {0};
+    if (std::sscanf(line.c_str() + c + 3, "%d %d %d %d %la %1s", &t.C, &t.T, &t.S, &t.tab, &t.rate,
+                    tail) != 6 || tail[0] != '#')
+        return false;
+    *out = t;
+    return true;
+}
+
+// The cached choice for `key`, if the file holds a valid one.
+bool tune_file_lookup(const TuneKey& key, int n, bool adjoint, TuneChoice* out)
+{
+    const std::string path = tune_file();
+    if (path.empty()) return false;
+    std::map<std::string, std::string> lines;
+    read_tune_file(path, lines);
+    auto it = lines.find(tune_key_text(device_arch(), key));
+    if (it == lines.end()) return false;
+    TuneChoice c;
+    if (!parse_choice(it->second, &c) || !choice_fits(n, adjoint, c)) return false;
+    *out = c;
+    return true;
+}
+
+// Adds (or replaces) the choice for `key`, dropping invalid lines; the file
+// is written whole and renamed into place, so readers never see half of it.
+void tune_file_store(const TuneKey& key, const TuneChoice& c)
+{
+    const std::string path = tune_file();
+    if (path.empty()) return;
+    std::map<std::string, std::string> lines;
+    read_tune_file(path, lines);
+    const std::string k = tune_key_text(device_arch(), key);
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), " : %d %d %d %d %a", c.C, c.T, c.S, c.tab, c.rate);
+    const std::string body = k + buf;
+    char h[32];
+    std::snprintf(h, sizeof(h), " # %016llx", (unsigned long long)fnv1a(body));
+    lines[k] = body + h;
+    const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;  // a cache that cannot be written only costs the next probe
+    bool ok = true;
+    for (const auto& kv : lines) ok = ok && std::fprintf(f, "%s\n", kv.second.c_str()) > 0;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
 }
 
 constexpr int kProbeSteps = 128;
@@ -792,8 +942,11 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, i
 // Rate of the adjoint kernel (forward pass, checkpointed recompute and
 // reverse sweep over kProbeSteps steps, checkpoints every 16 steps) for one
 // layout, with its default packing; 0 when it does not fit.
-tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int count, hipStream_t st,
-                          double* rate)
+// stored: time the reverse sweep alone from per-system checkpoints (the
+// path of plans that store them; the forward kernel writes the
+// checkpoints), else the adjoint call that recomputes them.
+tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int count, bool stored,
+                          hipStream_t st, double* rate)
 {
     *rate = 0.0;
     int S = 1, occ = 0, tab = kTabGlobal;
@@ -803,8 +956,10 @@ tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int coun
     const int nt = kProbeSteps, K = 16;
     const int grid = std::min((P + S - 1) / S, occ * num_cus());
     const int64_t rec = 2 * (int64_t)(L.C + 2) * L.T;
-    const int64_t slot = rec * (nt / K + 2) + 2 * (int64_t)L.C * L.T * (K + 1) +
-                         ((nt + 2) & ~int64_t(1));
+    const int64_t ck = rec * (nt / K + 1) + ((nt + 2) & ~int64_t(1));  // checkpoints + norm row
+    const int64_t slot = (stored ? rec : rec + ck) + 2 * (int64_t)L.C * L.T * (K + 1);
+    const size_t b_store = stored ? sizeof(double) * (size_t)ck * P : 0;
+    const size_t b_soff = stored ? ((sizeof(int64_t) * (size_t)P + 255) & ~size_t(255)) : 0;
     ClassSet cs;
     tdse_status rc = build_classes(cs, {n}, {L}, {real_time_params(p)}, st);
     if (rc != TDSE_OK) {
@@ -819,7 +974,8 @@ tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int coun
     char* mem = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     do {
-        if (hipMalloc(&mem, 3 * b_e + b_psi + b_sys + b_ord + 256 + b_work) != hipSuccess) {
+        if (hipMalloc(&mem, 3 * b_e + b_psi + b_sys + b_ord + 256 + b_work + b_soff + b_store) !=
+            hipSuccess) {
             rc = fail(TDSE_E_NOMEM, "autotune probe allocation failed");
             break;
         }
@@ -867,6 +1023,22 @@ tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int coun
         a.work = work;
         a.slot_doubles = slot;
         a.k_ckpt = K;
+        if (stored) {
+            // zero checkpoints: the kernel's work does not depend on the values
+            int64_t* soff = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(work) + b_work);
+            double* store = reinterpret_cast<double*>(reinterpret_cast<char*>(soff) + b_soff);
+            std::vector<int64_t> ho_off(P);
+            for (int i = 0; i < P; ++i) ho_off[i] = (int64_t)i * ck;
+            if (hipMemcpyAsync(soff, ho_off.data(), sizeof(int64_t) * P, hipMemcpyHostToDevice, st) !=
+                    hipSuccess ||
+                hipMemsetAsync(store, 0, b_store, st) != hipSuccess) {
+                rc = fail(TDSE_E_DEVICE, "autotune probe setup failed");
+                break;
+            }
+            a.store = store;
+            a.store_off = soff;
+            a.mode = kAdjReverseOnly;
+        }
         float ms = 0.0f;
         for (int rep = 0; rep < 2 && rc == TDSE_OK; ++rep) {  // warm-up, then timed
             if (launch_reset_counters(ctr, 1, st) != hipSuccess ||
@@ -889,16 +1061,23 @@ tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int coun
 
 // For plans with the adjoint the score is the time of one forward and one
 // adjoint pass per grid-point-step, with the adjoint's own default packing.
-tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, hipStream_t st,
-                     TuneChoice* out)
+tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, bool stored,
+                     hipStream_t st, TuneChoice* out)
 {
-    const TuneKey key{n, adjoint ? -count : count, p->dx, p->dt, p->a, p->charge_z,
-                      p->mask_fraction, p->mask_power};
+    // the count field of the key also says which adjoint path the plan takes
+    const int kc = adjoint ? (stored ? -(count + (1 << 29)) : -count) : count;
+    const TuneKey key{n, kc, p->dx, p->dt, p->a, p->charge_z, p->mask_fraction, p->mask_power};
     {
         std::lock_guard<std::mutex> g(g_tune_mutex);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             *out = it->second;
+            return TDSE_OK;
+        }
+        TuneChoice c;
+        if (tune_file_lookup(key, n, adjoint, &c)) {
+            g_tune_cache[key] = c;
+            *out = c;
             return TDSE_OK;
         }
     }
@@ -911,8 +1090,12 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, hipSt
         double adj_cost = 0.0;
         if (adjoint) {
             double ra = 0.0;
-            tdse_status rc = probe_adjoint(p, n, L, count, st, &ra);
+            tdse_status rc = probe_adjoint(p, n, L, count, stored, st, &ra);
             if (rc != TDSE_OK) return rc;
+            if (env_int("TDSE_TUNE_LOG", 0))
+                std::fprintf(stderr, "[tdse autotune] n=%d C=%d T=%d adjoint (%s): %.4e grid-point-steps/s\n",
+                             n, C, L.T, stored ? "reverse from stored checkpoints" : "recomputing",
+                             ra);
             if (ra <= 0.0) continue;
             adj_cost = 1.0 / ra;
         }
@@ -947,6 +1130,7 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, hipSt
     if (best_cost <= 0.0) return fail(TDSE_E_UNSUPPORTED, "no lane layout fits n=%d", n);
     std::lock_guard<std::mutex> g(g_tune_mutex);
     g_tune_cache[key] = best;
+    tune_file_store(key, best);
     *out = best;
     return TDSE_OK;
 }
@@ -998,7 +1182,17 @@ tdse_status plan_ground_states(tdse_plan pl, hipStream_t st)
 
 extern "C" {
 
-const char* tdse_version(void) { return "libtdse 0.2.0 (gfx950, fp64)"; }
+const char* tdse_version(void) { return "libtdse 0.3.0 (gfx950, fp64)"; }
+
+tdse_status tdse_set_tune_cache(const char* path)
+{
+    g_last_error.clear();
+    std::lock_guard<std::mutex> g(g_tune_mutex);
+    g_tune_cache.clear();
+    g_tune_file_set = true;
+    g_tune_file = path ? std::string(path) : std::string();
+    return TDSE_OK;
+}
 
 const char* tdse_status_string(tdse_status s)
 {
@@ -1081,7 +1275,8 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     std::vector<TuneChoice> tuned(ncls);
     for (int c = 0; c < ncls; ++c) {
         if (tune) {
-            st = autotune(p, ns[c], ccount[c], adjoint_k > 0, s0, &tuned[c]);
+            st = autotune(p, ns[c], ccount[c], adjoint_k > 0,
+                          (options & TDSE_OPT_STORE_CHECKPOINTS) != 0, s0, &tuned[c]);
             if (st != TDSE_OK) return bail(st);
             lay[c] = {tuned[c].C, tuned[c].T};
         } else {
@@ -1338,6 +1533,14 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
 
     if (adjoint_k > 0) {
         pl->adj_bytes = sizeof(double) * (size_t)adj_total;
+        // an optional cap on the adjoint workspace and checkpoint store
+        // (TDSE_MAX_WORKSPACE_BYTES): exceeding it fails like an allocation
+        // the device cannot satisfy, before anything is allocated
+        const double cap = env_double("TDSE_MAX_WORKSPACE_BYTES", 0.0);
+        const double want = (double)pl->adj_bytes + (store ? sizeof(double) * (double)store_total : 0.0);
+        if (cap > 0.0 && want > cap)
+            return bail(fail(TDSE_E_NOMEM, "adjoint workspace and checkpoint store of %.0f bytes "
+                                           "exceed TDSE_MAX_WORKSPACE_BYTES = %.0f", want, cap));
         if (hipMalloc(&pl->d_adj, pl->adj_bytes) != hipSuccess)
             return bail(fail(TDSE_E_NOMEM, "adjoint workspace of %.1f GB not available",
                              pl->adj_bytes / 1e9));
@@ -1526,6 +1729,58 @@ static tdse_status enqueue_adjoint(tdse_plan plan, const FwdArgs& base, const do
     return TDSE_OK;
 }
 
+// One system per launch, serially on the caller's stream (TDSE_OPT_PLAIN).
+static tdse_status enqueue_plain(tdse_plan plan, const FwdArgs& base, hipStream_t st)
+{
+    int32_t* ctr = plan->d_counters + plan->ctr_plain;
+    if (launch_reset_queues(ctr, plan->batch, st) != hipSuccess)
+        return fail(TDSE_E_DEVICE, "counter reset launch failed");
+    const BinDesc* pb = plan->d_bins;
+    size_t off = 0;
+    for (const auto& G : plan->fgroups) off += G.nbins;
+    for (int b = 0; b < plan->batch; ++b) {
+        const Launch& L = plan->launches[plan->launch_of_cls[plan->cls_of[b]]];
+        FwdArgs a = base;
+        a.bins = pb + off + b;
+        a.nbins = 1;
+        a.item_off = (int32_t)(plan->plain_smem[b] - 16);
+        a.queue = ctr + kQueueInts * b;
+        a.ab = plan->fwd_ab ? 1 : 0;
+        if (launch_forward(L.C, L.tab, a, plan->plain_threads[b], plan->plain_smem[b], 1, st) !=
+            hipSuccess)
+            return fail(TDSE_E_DEVICE, "forward launch failed");
+    }
+    return TDSE_OK;
+}
+
+tdse_status tdse_propagate_batch_populations(tdse_plan plan, const double* E, const double* psi0,
+                                             double* accel, double* xexp, double* norm,
+                                             double* psi_final, int32_t* sys_status,
+                                             const double* psi_ref, double radius,
+                                             double* gs_pop, double* vol_pop, void* stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(TDSE_E_INVALID, "plan is NULL");
+    if (!E || !accel) return fail(TDSE_E_INVALID, "E and accel are required");
+    if (!gs_pop && !vol_pop) return fail(TDSE_E_INVALID, "gs_pop or vol_pop is required");
+    if (!(radius >= 0.0)) return fail(TDSE_E_INVALID, "radius must be >= 0");
+    const void* ptrs[] = {E, psi0, accel, xexp, norm, psi_final, sys_status, psi_ref, gs_pop, vol_pop};
+    for (const void* q : ptrs)
+        if (q && !aligned16(q)) return fail(TDSE_E_INVALID, "device pointers must be 16-byte aligned");
+    if (plan->d_store)
+        return fail(TDSE_E_UNSUPPORTED, "a plan that stores checkpoints samples populations at its "
+                                        "stored states (tdse_plan_populations)");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    FwdArgs base;
+    fill_fwd_args(plan, base, E, psi0, accel, xexp, norm, psi_final, sys_status);
+    base.pop_ref = psi_ref;
+    base.gs_pop = gs_pop;
+    base.vol_pop = vol_pop;
+    base.pop_radius = radius;
+    if (plan->options & TDSE_OPT_PLAIN) return enqueue_plain(plan, base, st);
+    return enqueue_forward(plan, base, st, false);
+}
+
 tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* psi0,
                                  double* accel, double* xexp, double* norm, double* psi_final,
                                  int32_t* sys_status, void* stream)
@@ -1541,35 +1796,16 @@ tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* 
     fill_fwd_args(plan, base, E, psi0, accel, xexp, norm, psi_final, sys_status);
 
     if (plan->d_store) {
-        // the adjoint kernel's forward pass: the same outputs, plus the
-        // checkpoints and norm rows a later tdse_adjoint_batch_stored uses
-        tdse_status rc = enqueue_adjoint(plan, base, nullptr, kAdjForwardOnly, st);
-        if (rc == TDSE_OK) ++plan->ckpt_gen;
-        return rc;
+        // the forward kernel also writes the checkpoints and norm rows that a
+        // later tdse_adjoint_batch_stored reads, in the adjoint's lane layout
+        base.store = plan->d_store;
+        base.store_off = plan->d_store_off;
+        base.k_ckpt = plan->adjoint_k;
+        ++plan->ckpt_gen;
     }
-    if (plan->options & TDSE_OPT_PLAIN) {
-        // one system per launch, serially on the caller's stream
-        int32_t* ctr = plan->d_counters + plan->ctr_plain;
-        if (launch_reset_queues(ctr, plan->batch, st) != hipSuccess)
-            return fail(TDSE_E_DEVICE, "counter reset launch failed");
-        const BinDesc* pb = plan->d_bins;
-        size_t off = 0;
-        for (const auto& G : plan->fgroups) off += G.nbins;
-        for (int b = 0; b < plan->batch; ++b) {
-            const Launch& L = plan->launches[plan->launch_of_cls[plan->cls_of[b]]];
-            FwdArgs a = base;
-            a.bins = pb + off + b;
-            a.nbins = 1;
-            a.item_off = (int32_t)(plan->plain_smem[b] - 16);
-            a.queue = ctr + kQueueInts * b;
-            a.ab = plan->fwd_ab ? 1 : 0;
-            if (launch_forward(L.C, L.tab, a, plan->plain_threads[b], plan->plain_smem[b], 1, st) !=
-                hipSuccess)
-                return fail(TDSE_E_DEVICE, "forward launch failed");
-        }
-        return TDSE_OK;
-    }
-    if (plan->options & TDSE_OPT_NO_GRAPH) return enqueue_forward(plan, base, st, false);
+    if (plan->options & TDSE_OPT_PLAIN) return enqueue_plain(plan, base, st);
+    if ((plan->options & TDSE_OPT_NO_GRAPH) || plan->graph_state == 2)
+        return enqueue_forward(plan, base, st, false);
 
     std::vector<const void*> key{E, psi0, accel, xexp, norm, psi_final, sys_status};
     if (!plan->gexec || key != plan->gkey) {
@@ -1577,24 +1813,42 @@ tdse_status tdse_propagate_batch(tdse_plan plan, const double* E, const double* 
             (void)hipGraphExecDestroy(plan->gexec);
             plan->gexec = nullptr;
         }
+        // a capture that fails (or is switched off with
+        // TDSE_FORCE_CAPTURE_FAILURE) leaves the plan on direct launches,
+        // which run the same kernels with the same arguments
+        const bool forced = env_int("TDSE_FORCE_CAPTURE_FAILURE", 0) != 0;
         hipGraph_t graph = nullptr;
-        HIP_TRY(hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal));
-        tdse_status rc = enqueue_forward(plan, base, plan->cap, true);
-        hipError_t ec = hipStreamEndCapture(plan->cap, &graph);
-        if (rc != TDSE_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return rc;
+        hipError_t ec = forced ? hipErrorNotSupported
+                               : hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal);
+        if (ec == hipSuccess) {
+            tdse_status rc = enqueue_forward(plan, base, plan->cap, true);
+            ec = hipStreamEndCapture(plan->cap, &graph);
+            if (rc != TDSE_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (ec == hipSuccess) {
+                ec = hipGraphInstantiate(&plan->gexec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ec != hipSuccess) plan->gexec = nullptr;
+            }
         }
-        if (ec != hipSuccess) return fail(TDSE_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
-        ec = hipGraphInstantiate(&plan->gexec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
         if (ec != hipSuccess) {
-            plan->gexec = nullptr;
-            return fail(TDSE_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ec));
+            (void)hipGetLastError();  // the failed capture's error is not the caller's
+            plan->graph_state = 2;
+            return enqueue_forward(plan, base, st, false);
         }
+        plan->graph_state = 1;
         plan->gkey = key;
     }
     HIP_TRY(hipGraphLaunch(plan->gexec, st));
+    return TDSE_OK;
+}
+
+tdse_status tdse_plan_graph_state(tdse_plan plan, int32_t* state)
+{
+    if (!plan || !state) return fail(TDSE_E_INVALID, "NULL argument");
+    *state = plan->graph_state;
     return TDSE_OK;
 }
 
@@ -1910,27 +2164,34 @@ tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t
     if (pairs > std::numeric_limits<int32_t>::max())
         return fail(TDSE_E_INVALID, "too many (size, energy) pairs");
     const size_t fac = spectrum_factor_bytes(n_max, pairs);
-    const size_t per_lane = 16 * (size_t)n_max;
-    const int64_t items = (int64_t)plan->batch * n_energy;
-    if (work_bytes < fac + kWave * per_lane)
+    const size_t rhs = ((size_t)plan->psi_off[plan->batch] * sizeof(cd) + 255) & ~size_t(255);
+    const size_t per_lane = spectrum_slot_bytes(n_max);
+    // tiles of 8 systems x 8 energies, one wavefront each
+    const int64_t tiles = (int64_t)((plan->batch + 7) / 8) * ((n_energy + 7) / 8);
+    if (work_bytes < fac + rhs + kWave * per_lane)
         return fail(TDSE_E_INVALID,
-                    "work must hold at least %zu bytes: %zu of elimination factors and 64 lanes of %zu",
-                    fac + kWave * per_lane, fac, per_lane);
-    int64_t lanes = (int64_t)std::min<size_t>((work_bytes - fac) / per_lane, (size_t)1 << 20);
-    lanes = std::min<int64_t>(lanes, (items + kWave - 1) / kWave * kWave);
+                    "work must hold at least %zu bytes: %zu of elimination factors, %zu of right-hand "
+                    "sides and 64 solves of %zu",
+                    fac + rhs + kWave * per_lane, fac, rhs, per_lane);
+    int64_t waves = (int64_t)std::min<size_t>((work_bytes - fac - rhs) / (kWave * per_lane),
+                                              (size_t)1 << 16);
+    waves = std::max<int64_t>(1, std::min<int64_t>(waves, tiles));
     SpecArgs a{};
     a.fac = reinterpret_cast<cd*>(work);
     a.pairs = (int32_t)pairs;
     a.classes = plan->cls.d;
     a.sys = plan->d_sys;
+    a.order = plan->d_order_all;
     a.batch = plan->batch;
     a.n_energy = n_energy;
+    a.n_max = n_max;
     a.psi = psi;
     a.energies = energies;
     a.eps = eps;
     a.out = spectrum;
-    a.work = reinterpret_cast<cd*>(static_cast<char*>(work) + fac);
-    a.lanes = lanes;
+    a.rhs = reinterpret_cast<cd*>(static_cast<char*>(work) + fac);
+    a.work = reinterpret_cast<cd*>(static_cast<char*>(work) + fac + rhs);
+    a.lanes = waves * kWave;
     HIP_TRY(launch_energy_spectrum(a, reinterpret_cast<hipStream_t>(stream)));
     return TDSE_OK;
 }
@@ -1943,7 +2204,8 @@ tdse_status tdse_plan_energy_spectrum_work(tdse_plan plan, int32_t n_energy, int
     if (n_energy < 1 || lanes < kWave) return fail(TDSE_E_INVALID, "need n_energy >= 1 and lanes >= 64");
     const int n_max = *std::max_element(plan->n_per.begin(), plan->n_per.end());
     *bytes = spectrum_factor_bytes(n_max, (int64_t)plan->ncls_real * n_energy) +
-             (size_t)lanes * 16 * (size_t)n_max;
+             (((size_t)plan->psi_off[plan->batch] * sizeof(cd) + 255) & ~size_t(255)) +
+             (size_t)((lanes + kWave - 1) / kWave * kWave) * spectrum_slot_bytes(n_max);
     return TDSE_OK;
 }
 

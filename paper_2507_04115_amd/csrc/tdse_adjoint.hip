@@ -28,29 +28,6 @@ namespace tdse {
 
 namespace {
 
-// State record: chunk values and the two ghosts, [C+2][T] complex.  The
-// record base is wave-uniform (scalar registers); each access adds the
-// lane's byte offset 16 t, so the loads and stores take one VGPR offset.
-__device__ __forceinline__ void st_lane(double* base, unsigned off_bytes, cd x)
-{
-    typedef double dvec2 __attribute__((ext_vector_type(2)));
-    typedef __attribute__((address_space(1))) dvec2* gptr;
-    dvec2 w;
-    w.x = x.re;
-    w.y = x.im;
-    *(gptr)(reinterpret_cast<char*>(base) + off_bytes) = w;
-}
-
-template <int C>
-__device__ __forceinline__ void store_state(double* base, int T, unsigned off, const cd (&v)[C],
-                                            cd gl, cd gr)
-{
-#pragma unroll
-    for (int k = 0; k < C; ++k) st_lane(base + 2 * (size_t)k * T, off, v[k]);
-    st_lane(base + 2 * (size_t)C * T, off, gl);
-    st_lane(base + 2 * (size_t)(C + 1) * T, off, gr);
-}
-
 template <int C>
 __device__ __forceinline__ void load_state(const double* base, int T, unsigned off, cd (&v)[C],
                                            cd& gl, cd& gr)
@@ -209,14 +186,19 @@ __device__ __forceinline__ void source_grad_streamed(cd (&kap)[C], cd& kgl, cd& 
 
 }  // namespace
 
-template <int C, bool LDSTAB, bool AB = false>
+// REV: the reverse sweep alone (tdse_adjoint_batch_stored: the checkpoints
+// were stored by the forward kernel).  Without the forward pass in the same
+// kernel, the costate is parked in the slot while a segment is recomputed
+// and psi^i is read point by point at every chunk length, which leaves room
+// for the pivot factors in registers up to 8 points per lane.
+template <int C, bool LDSTAB, bool AB = false, bool REV = false>
 __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
 {
     // the costate doubles the chunk state: pivot factors stay in registers
     // only for 4 points per lane; from 16 points the costate is parked in the
     // slot while a segment is recomputed, and psi^i is read point by point
-    constexpr bool kAdjQRegs = C <= 4;
-    constexpr bool kStream = C >= 16;
+    constexpr bool kAdjQRegs = REV ? C <= 8 : C <= 4;
+    constexpr bool kStream = REV || C >= 16;
     extern __shared__ double smem_raw[];
     const SizeClass sc = uniform_load(a.classes + a.cls);
     const int T = sc.T, W = T / kWave, np = C * T;
@@ -263,7 +245,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
         double* acc_row = (active && a.accel) ? a.accel + row : nullptr;
         double* x_row = (active && a.xexp) ? a.xexp + row : nullptr;
         double* nu_row = (active && a.norm) ? a.norm + row : nullptr;
-        const double* src = a.psi0 ? a.psi0 + 2 * d.psi_off : a.gs + 2 * a.gs_off[a.cls];
+        const double* src = REV ? nullptr : (a.psi0 ? a.psi0 + 2 * d.psi_off : a.gs + 2 * a.gs_off[a.cls]);
         // checkpoints and norm row: the system's own (stored) or the slot's
         double* ckpt = a.store ? a.store + uniform_load(a.store_off + p) : slot;
         double* n_row = ckpt + np2 * nseg;
@@ -283,15 +265,19 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
 
         // ---------------- forward pass: outputs, norms, checkpoints
         cd v[C];
+        cd gl = czero(), gr = czero();
+        if constexpr (!REV) {
 #pragma unroll
-        for (int k = 0; k < C; ++k) v[k] = (active && s + k < n) ? ld_psi(src, s + k) : czero();
-        cd gl = (active && s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
-        cd gr = (active && s + C < n) ? ld_psi(src, s + C) : czero();
+            for (int k = 0; k < C; ++k) v[k] = (active && s + k < n) ? ld_psi(src, s + k) : czero();
+            gl = (active && s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
+            gr = (active && s + C < n) ? ld_psi(src, s + C) : czero();
+        }
         LaneFactors<C, kAdjQRegs, AB> f;
         {
             const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
             f = load_factors<C, kAdjQRegs, AB>(sv.sc, sv.lc);
         }
+        if constexpr (!REV) {
         int flushed = 0;
         // forward pass length (uniform): none when the checkpoints are stored
         const int nfwd = a.mode == kAdjReverseOnly ? -1
@@ -331,6 +317,7 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
             }
         }
         __syncthreads();
+        }  // forward pass
 
         // ---------------- reverse sweep (every subgroup runs it, so barriers
         // stay uniform; subgroups without a gradient write nothing)
@@ -370,6 +357,12 @@ __global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
                                             2.0 * abar[nt] * dx, erow[nt], sv.tb, sv.lc, nt > 0,
                                             sv.xs, dx, ring + ((nt > 0 ? nt - 1 : 0) % kRing) * W);
                 } else {
+                    // the ghosts of psi^nt as every later step reads them: the
+                    // neighbouring lanes' entries of the stored state (the
+                    // streamed form and the reverse-only kernel do the same)
+                    __syncthreads();
+                    chunk_ghosts<C>(reinterpret_cast<const cd*>(seg + nps * (s1 - s0)), T, t, loff,
+                                    gl, gr);
                     add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[nt] * dx, erow[nt], sv.tb,
                                   T, sv.lc);
                     if (nt > 0)
@@ -484,8 +477,9 @@ int adjoint_occupancy(int C, int T, int S, bool lds_tables)
     }
 }
 
-hipError_t launch_adjoint(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
-                          hipStream_t st)
+template <bool REV>
+static hipError_t launch_adjoint_t(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
+                                   hipStream_t st)
 {
     const size_t sh = adjoint_smem_bytes(C, T, S, lds_tables);
     const dim3 b(T * S);
@@ -494,17 +488,24 @@ hipError_t launch_adjoint(int C, bool lds_tables, const FwdArgs& a, int T, int S
     // the 256 on-axis systems of the full focal volume (N = 8192), so that
     // layout always forms them.
     switch (C * 4 + (lds_tables ? 2 : 0) + (a.ab && C > 8 ? 1 : 0)) {
-        case 16: hipLaunchKernelGGL((adjoint_kernel<4, false>), dim3(grid), b, sh, st, a); break;
-        case 18: hipLaunchKernelGGL((adjoint_kernel<4, true>), dim3(grid), b, sh, st, a); break;
-        case 32: hipLaunchKernelGGL((adjoint_kernel<8, false>), dim3(grid), b, sh, st, a); break;
-        case 34: hipLaunchKernelGGL((adjoint_kernel<8, true>), dim3(grid), b, sh, st, a); break;
-        case 64: hipLaunchKernelGGL((adjoint_kernel<16, false>), dim3(grid), b, sh, st, a); break;
-        case 65: hipLaunchKernelGGL((adjoint_kernel<16, false, true>), dim3(grid), b, sh, st, a); break;
-        case 66: hipLaunchKernelGGL((adjoint_kernel<16, true>), dim3(grid), b, sh, st, a); break;
-        case 67: hipLaunchKernelGGL((adjoint_kernel<16, true, true>), dim3(grid), b, sh, st, a); break;
+        case 16: hipLaunchKernelGGL((adjoint_kernel<4, false, false, REV>), dim3(grid), b, sh, st, a); break;
+        case 18: hipLaunchKernelGGL((adjoint_kernel<4, true, false, REV>), dim3(grid), b, sh, st, a); break;
+        case 32: hipLaunchKernelGGL((adjoint_kernel<8, false, false, REV>), dim3(grid), b, sh, st, a); break;
+        case 34: hipLaunchKernelGGL((adjoint_kernel<8, true, false, REV>), dim3(grid), b, sh, st, a); break;
+        case 64: hipLaunchKernelGGL((adjoint_kernel<16, false, false, REV>), dim3(grid), b, sh, st, a); break;
+        case 65: hipLaunchKernelGGL((adjoint_kernel<16, false, true, REV>), dim3(grid), b, sh, st, a); break;
+        case 66: hipLaunchKernelGGL((adjoint_kernel<16, true, false, REV>), dim3(grid), b, sh, st, a); break;
+        case 67: hipLaunchKernelGGL((adjoint_kernel<16, true, true, REV>), dim3(grid), b, sh, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_adjoint(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
+                          hipStream_t st)
+{
+    if (a.mode == kAdjReverseOnly) return launch_adjoint_t<true>(C, lds_tables, a, T, S, grid, st);
+    return launch_adjoint_t<false>(C, lds_tables, a, T, S, grid, st);
 }
 
 // Reorders the systems of one launch so that rows with a non-zero abar come

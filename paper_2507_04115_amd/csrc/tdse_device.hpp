@@ -429,6 +429,30 @@ __device__ __forceinline__ cd ld_lane(const cd* base, unsigned off_bytes)
     return ldg(reinterpret_cast<const cd*>(reinterpret_cast<const char*>(base) + off_bytes));
 }
 
+// State record of the adjoint's checkpoints: chunk values and the two
+// ghosts, [C+2][T] complex.  The record base is wave-uniform (scalar
+// registers); each access adds the lane's byte offset 16 t, so the loads
+// and stores take one VGPR offset.
+__device__ __forceinline__ void st_lane(double* base, unsigned off_bytes, cd x)
+{
+    typedef double dvec2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) dvec2* gptr;
+    dvec2 w;
+    w.x = x.re;
+    w.y = x.im;
+    *(gptr)(reinterpret_cast<char*>(base) + off_bytes) = w;
+}
+
+template <int C>
+__device__ __forceinline__ void store_state(double* base, int T, unsigned off, const cd (&v)[C],
+                                            cd gl, cd gr)
+{
+#pragma unroll
+    for (int k = 0; k < C; ++k) st_lane(base + 2 * (size_t)k * T, off, v[k]);
+    st_lane(base + 2 * (size_t)C * T, off, gl);
+    st_lane(base + 2 * (size_t)(C + 1) * T, off, gr);
+}
+
 // ------------------------------------------------------------ carry scans
 // Forward carries of z_j = r_j + alpha_j z_{j-1}.  Input: the lane's chunk-end
 // value computed with a zero carry-in.  Output: the true z at the point just
@@ -831,26 +855,92 @@ __device__ __forceinline__ void observe(const cd (&v)[C], const TV& tb, int T,
     }
 }
 
+// The same sums plus the two population observables of the current state
+// (ring values 3..5 of the wavefront): the overlap sum_j conj(phi_j) psi_j
+// with the reference state phi (natural point order, interleaved complex,
+// n points; padding points read phi_{n-1} against psi = 0) and
+// sum_{|x_j| <= radius} |psi_j|^2 with x_j = (j - (n-1)/2) dx.
+template <int C, class TV>
+__device__ __forceinline__ void observe_pop(const cd (&v)[C], const TV& tb, int T,
+                                            const LaneCtx& lc, double xs, double dx, int n,
+                                            const double* phi, double radius, double* slot)
+{
+    double sn = 0.0, sk = 0.0, sv = 0.0, orr = 0.0, oi = 0.0, sr = 0.0;
+    const cd* ph = reinterpret_cast<const cd*>(phi);
+    const double c = 0.5 * (double)(n - 1);
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const double p = cabs2(v[k]);
+        sn += p;
+        sk = fma((double)k, p, sk);
+        sv = fma(tb.dv(lc.b0 + 64 * k), p, sv);
+        const int j = lc.s + k;
+        const cd f = ldg(ph + min(j, n - 1));
+        orr = fma(f.re, v[k].re, fma(f.im, v[k].im, orr));
+        oi = fma(f.re, v[k].im, fma(-f.im, v[k].re, oi));
+        const double xj = ((double)j - c) * dx;
+        sr += (fabs(xj) <= radius) ? p : 0.0;
+    }
+    double sx = fma(xs, sn, dx * sk);
+    sn = wave_sum(sn);
+    sx = wave_sum(sx);
+    sv = wave_sum(sv);
+    orr = wave_sum(orr);
+    oi = wave_sum(oi);
+    sr = wave_sum(sr);
+    if (lc.lane == kSumLane) {
+        double* o = slot + lc.wave * 6;
+        o[0] = sv;
+        o[1] = sx;
+        o[2] = sn;
+        o[3] = orr;
+        o[4] = oi;
+        o[5] = sr;
+    }
+}
+
 // Sums the per-wave partials of samples [a0, a1] in wave order and writes
 //   accel = dx (sum V'|psi|^2 + E sum |psi|^2), xexp = dx sum x|psi|^2,
 //   norm = dx sum |psi|^2.
+// With POP the ring holds six values per wavefront and sample in a ring of
+// kRing / 2 samples (the same LDS bytes), and the populations are written:
+//   gs_row  = |dx sum conj(phi) psi|^2,   vol_row = dx sum_{|x| <= r} |psi|^2.
+// n2_row, when set, receives the norm as well (the checkpoint store's row).
+template <bool POP = false>
 __device__ __forceinline__ void flush(int a0, int a1, int t, int T, const double* ring, int W,
                                       double dx, const double* erow, double* acc_row,
-                                      double* x_row, double* n_row, double n0, int* flag)
+                                      double* x_row, double* n_row, double n0, int* flag,
+                                      double* gs_row = nullptr, double* vol_row = nullptr,
+                                      double* n2_row = nullptr)
 {
+    constexpr int NV = POP ? 6 : 3;
+    constexpr int RING = POP ? kRing / 2 : kRing;
     for (int smp = a0 + t; smp <= a1; smp += T) {
-        const double* r = ring + (smp % kRing) * W * 3;
+        const double* r = ring + (smp % RING) * W * NV;
         double sv = 0.0, sx = 0.0, sn = 0.0;
         for (int w = 0; w < W; ++w) {
-            sv += r[w * 3 + 0];
-            sx += r[w * 3 + 1];
-            sn += r[w * 3 + 2];
+            sv += r[w * NV + 0];
+            sx += r[w * NV + 1];
+            sn += r[w * NV + 2];
+        }
+        if constexpr (POP) {
+            double orr = 0.0, oi = 0.0, sr = 0.0;
+            for (int w = 0; w < W; ++w) {
+                orr += r[w * NV + 3];
+                oi += r[w * NV + 4];
+                sr += r[w * NV + 5];
+            }
+            orr *= dx;
+            oi *= dx;
+            if (gs_row) gs_row[smp] = fma(orr, orr, oi * oi);
+            if (vol_row) vol_row[smp] = dx * sr;
         }
         const double nn = dx * sn;
         const double acc = dx * fma(erow[smp], sn, sv);
         acc_row[smp] = acc;
         if (x_row) x_row[smp] = dx * sx;
         if (n_row) n_row[smp] = nn;
+        if (n2_row) n2_row[smp] = nn;
         int f = 0;
         if (!isfinite(acc) || !isfinite(nn) || !isfinite(sx)) f |= 1;
         if (nn > n0 * (1.0 + 1e-8)) f |= 2;

@@ -41,9 +41,24 @@ size_t sub_smem_bytes(int W)
 // systems of one lane layout that together fill the workgroup's lanes (plus a
 // padding system where they do not); every subgroup runs the whole time loop
 // of its system with the same barrier sequence as the others.
-template <int C, int TAB, bool AB = false>
+// X selects what the time loop records besides the outputs: kFwdPlain
+// nothing; kFwdPop the ground-state and volumetric populations at every
+// sample (six ring values per wavefront and sample, flushed every
+// kFlush / 2); kFwdStore the adjoint's checkpoints, the state record (chunk
+// and ghosts) of every K-th step and the norm row, in each system's part of
+// the checkpoint store.
+constexpr int kFwdPlain = 0;
+constexpr int kFwdPop = 1;
+constexpr int kFwdStore = 2;
+
+template <int C, int TAB, bool AB = false, int X = kFwdPlain>
 __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
 {
+    constexpr bool POP = X == kFwdPop;
+    constexpr bool STORE = X == kFwdStore;
+    constexpr int NV = POP ? 6 : 3;                   // ring values per wavefront and sample
+    constexpr int RING = POP ? kRing / 2 : kRing;     // samples in the ring (same LDS bytes)
+    constexpr int FLUSH = POP ? kFlush / 2 : kFlush;  // samples per output flush
     extern __shared__ double smem_raw[];
     char* const smem = reinterpret_cast<char*>(smem_raw);
     const int tid = threadIdx.x;
@@ -106,6 +121,22 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
         double* acc_row = a.accel + row;
         double* x_row = a.xexp ? a.xexp + row : nullptr;
         double* n_row = a.norm ? a.norm + row : nullptr;
+        double* gs_row = (POP && a.gs_pop) ? a.gs_pop + row : nullptr;
+        double* vol_row = (POP && a.vol_pop) ? a.vol_pop + row : nullptr;
+        // checkpoint store of the system: records of (C+2) T complex values
+        // at steps 0, K, 2K, ..., then the norm row
+        const int K = STORE ? a.k_ckpt : 1;
+        const size_t np2 = 2 * (size_t)(C + 2) * T;
+        double* st_norm = nullptr;
+        if (STORE && active) st_norm = a.store + uniform_load(a.store_off + p) + np2 * (size_t)(nt / K + 1);
+        // reference state of the ground-state population (inactive subgroups
+        // read one valid element)
+        const double* phi = a.gs;
+        int n_pop = 1;
+        if (POP && active) {
+            phi = a.pop_ref ? a.pop_ref + 2 * d.psi_off : a.gs + 2 * a.gs_off[bs.cls];
+            n_pop = n;
+        }
 
         cd v[C];
 #pragma unroll
@@ -117,31 +148,49 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
         {
             const StepView<TAB> sv = step_view<TAB>(clsp, wsys, tab);
             f = load_factors<C, QInRegs<C>::value, AB>(sv.sc, sv.lc);
-            observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, sm.ring);
+            if constexpr (POP)
+                observe_pop<C>(v, sv.tb, T, sv.lc, sv.xs, dx, n_pop, phi, a.pop_radius, sm.ring);
+            else
+                observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, sm.ring);
         }
         __syncthreads();
         double n0 = 0.0;
-        for (int w = 0; w < W; ++w) n0 += sm.ring[w * 3 + 2];
+        for (int w = 0; w < W; ++w) n0 += sm.ring[w * NV + 2];
         n0 *= dx;
 
         int flushed = 0;
         for (int i = 0; i < nt; ++i) {
             const StepView<TAB> sv = step_view<TAB>(clsp, wsys, tab);
+            if constexpr (STORE) {
+                if (active && i % K == 0)
+                    store_state<C>(a.store + uniform_load(a.store_off + p) + np2 * (size_t)(i / K),
+                                   sv.sc.T, 16u * (unsigned)sv.lc.t, v, gl, gr);
+            }
             forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
                             sm.lds_f, sm.lds_b);
-            if ((i + 1) % kFlush == 0) {
+            if ((i + 1) % FLUSH == 0) {
                 __syncthreads();
                 if (active)
-                    flush(i + 1 - kFlush, i, t, T, sm.ring, W, dx, erow, acc_row, x_row, n_row, n0,
-                          sm.misc + 1);
+                    flush<POP>(i + 1 - FLUSH, i, t, T, sm.ring, W, dx, erow, acc_row, x_row, n_row,
+                               n0, sm.misc + 1, gs_row, vol_row, STORE ? st_norm : nullptr);
                 flushed = i + 1;
             }
-            observe<C>(v, sv.tb, sv.sc.T, sv.lc, sv.xs, sv.sc.dx,
-                       sm.ring + ((i + 1) % kRing) * W * 3);
+            double* slot = sm.ring + ((i + 1) % RING) * W * NV;
+            if constexpr (POP)
+                observe_pop<C>(v, sv.tb, sv.sc.T, sv.lc, sv.xs, sv.sc.dx, n_pop, phi, a.pop_radius,
+                               slot);
+            else
+                observe<C>(v, sv.tb, sv.sc.T, sv.lc, sv.xs, sv.sc.dx, slot);
         }
         __syncthreads();
+        if constexpr (STORE) {
+            if (active && nt % K == 0)
+                store_state<C>(a.store + uniform_load(a.store_off + p) + np2 * (size_t)(nt / K), T,
+                               16u * (unsigned)t, v, gl, gr);
+        }
         if (active) {
-            flush(flushed, nt, t, T, sm.ring, W, dx, erow, acc_row, x_row, n_row, n0, sm.misc + 1);
+            flush<POP>(flushed, nt, t, T, sm.ring, W, dx, erow, acc_row, x_row, n_row, n0,
+                       sm.misc + 1, gs_row, vol_row, STORE ? st_norm : nullptr);
             if (a.psi_final) {
                 double* dst = a.psi_final + 2 * d.psi_off;
 #pragma unroll
@@ -365,41 +414,53 @@ int forward_vgprs(int C, int tab, bool ab)
     }
 }
 
+template <int X>
+static hipError_t launch_forward_t(int C, int tab, const FwdArgs& a, int threads, size_t smem,
+                                   int grid, hipStream_t st)
+{
+    const dim3 b(threads);
+    // 12 and 16 points per lane: elimination factors from their tables
+    // (a.ab) or formed from q and om
+    if (C >= 12 && a.ab) {
+        switch (C * 4 + tab) {
+            case 48: if constexpr (X != kFwdStore) { hipLaunchKernelGGL((forward_kernel<12, kTabGlobal, true, X>), dim3(grid), b, smem, st, a); } break;
+            case 49: if constexpr (X != kFwdStore) { hipLaunchKernelGGL((forward_kernel<12, kTabLds, true, X>), dim3(grid), b, smem, st, a); } break;
+            case 50: if constexpr (X != kFwdStore) { hipLaunchKernelGGL((forward_kernel<12, kTabOmLds, true, X>), dim3(grid), b, smem, st, a); } break;
+            case 64: hipLaunchKernelGGL((forward_kernel<16, kTabGlobal, true, X>), dim3(grid), b, smem, st, a); break;
+            case 65: hipLaunchKernelGGL((forward_kernel<16, kTabLds, true, X>), dim3(grid), b, smem, st, a); break;
+            case 66: hipLaunchKernelGGL((forward_kernel<16, kTabOmLds, true, X>), dim3(grid), b, smem, st, a); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    switch (C * 4 + tab) {
+        case 16: hipLaunchKernelGGL((forward_kernel<4, kTabGlobal, false, X>), dim3(grid), b, smem, st, a); break;
+        case 17: hipLaunchKernelGGL((forward_kernel<4, kTabLds, false, X>), dim3(grid), b, smem, st, a); break;
+        case 32: hipLaunchKernelGGL((forward_kernel<8, kTabGlobal, false, X>), dim3(grid), b, smem, st, a); break;
+        case 33: hipLaunchKernelGGL((forward_kernel<8, kTabLds, false, X>), dim3(grid), b, smem, st, a); break;
+        case 48: if constexpr (X != kFwdStore) { hipLaunchKernelGGL((forward_kernel<12, kTabGlobal, false, X>), dim3(grid), b, smem, st, a); } break;
+        case 49: if constexpr (X != kFwdStore) { hipLaunchKernelGGL((forward_kernel<12, kTabLds, false, X>), dim3(grid), b, smem, st, a); } break;
+        case 50: if constexpr (X != kFwdStore) { hipLaunchKernelGGL((forward_kernel<12, kTabOmLds, false, X>), dim3(grid), b, smem, st, a); } break;
+        case 64: hipLaunchKernelGGL((forward_kernel<16, kTabGlobal, false, X>), dim3(grid), b, smem, st, a); break;
+        case 65: hipLaunchKernelGGL((forward_kernel<16, kTabLds, false, X>), dim3(grid), b, smem, st, a); break;
+        case 66: hipLaunchKernelGGL((forward_kernel<16, kTabOmLds, false, X>), dim3(grid), b, smem, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_forward(int C, int tab, const FwdArgs& a, int threads, size_t smem, int grid,
                           hipStream_t st)
 {
     if (smem > (size_t)kMaxLds || threads < kWave || threads > 1024 || threads % kWave ||
         (size_t)a.item_off + 16 > smem)
         return hipErrorInvalidValue;
-    const dim3 b(threads);
-    // 12 and 16 points per lane: elimination factors from their tables
-    // (a.ab) or formed from q and om
-    if (C >= 12 && a.ab) {
-        switch (C * 4 + tab) {
-            case 48: hipLaunchKernelGGL((forward_kernel<12, kTabGlobal, true>), dim3(grid), b, smem, st, a); break;
-            case 49: hipLaunchKernelGGL((forward_kernel<12, kTabLds, true>), dim3(grid), b, smem, st, a); break;
-            case 50: hipLaunchKernelGGL((forward_kernel<12, kTabOmLds, true>), dim3(grid), b, smem, st, a); break;
-            case 64: hipLaunchKernelGGL((forward_kernel<16, kTabGlobal, true>), dim3(grid), b, smem, st, a); break;
-            case 65: hipLaunchKernelGGL((forward_kernel<16, kTabLds, true>), dim3(grid), b, smem, st, a); break;
-            case 66: hipLaunchKernelGGL((forward_kernel<16, kTabOmLds, true>), dim3(grid), b, smem, st, a); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
+    if (a.store) {
+        if (a.gs_pop || a.vol_pop || C == 12 || a.k_ckpt < 1) return hipErrorInvalidValue;
+        return launch_forward_t<kFwdStore>(C, tab, a, threads, smem, grid, st);
     }
-    switch (C * 4 + tab) {
-        case 16: hipLaunchKernelGGL((forward_kernel<4, kTabGlobal>), dim3(grid), b, smem, st, a); break;
-        case 17: hipLaunchKernelGGL((forward_kernel<4, kTabLds>), dim3(grid), b, smem, st, a); break;
-        case 32: hipLaunchKernelGGL((forward_kernel<8, kTabGlobal>), dim3(grid), b, smem, st, a); break;
-        case 33: hipLaunchKernelGGL((forward_kernel<8, kTabLds>), dim3(grid), b, smem, st, a); break;
-        case 48: hipLaunchKernelGGL((forward_kernel<12, kTabGlobal>), dim3(grid), b, smem, st, a); break;
-        case 49: hipLaunchKernelGGL((forward_kernel<12, kTabLds>), dim3(grid), b, smem, st, a); break;
-        case 50: hipLaunchKernelGGL((forward_kernel<12, kTabOmLds>), dim3(grid), b, smem, st, a); break;
-        case 64: hipLaunchKernelGGL((forward_kernel<16, kTabGlobal>), dim3(grid), b, smem, st, a); break;
-        case 65: hipLaunchKernelGGL((forward_kernel<16, kTabLds>), dim3(grid), b, smem, st, a); break;
-        case 66: hipLaunchKernelGGL((forward_kernel<16, kTabOmLds>), dim3(grid), b, smem, st, a); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (a.gs_pop || a.vol_pop) return launch_forward_t<kFwdPop>(C, tab, a, threads, smem, grid, st);
+    return launch_forward_t<kFwdPlain>(C, tab, a, threads, smem, grid, st);
 }
 
 hipError_t launch_ground_state(int C, const GsArgs& a, int T, hipStream_t st)

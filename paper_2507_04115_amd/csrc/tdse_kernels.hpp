@@ -55,6 +55,13 @@ struct FwdArgs {
     // live in the slot
     double* store;
     const int64_t* store_off;  // [batch] doubles into store
+    // forward only: per-step populations (tdse_propagate_batch_populations),
+    // written when either row pointer is set
+    const double* pop_ref;     // ragged complex reference states, or NULL: the
+                               // plan's ground states
+    double* gs_pop;            // [batch][nt+1] or NULL
+    double* vol_pop;           // [batch][nt+1] or NULL
+    double pop_radius;
 };
 
 // Adjoint kernel modes: forward pass then reverse sweep; forward pass only
@@ -103,15 +110,17 @@ struct BandAdjArgs {
 struct SpecArgs {
     const SizeClass* classes;
     const SysDesc* sys;
-    int32_t batch, n_energy;
+    const int32_t* order;    // systems grouped by size class
+    int32_t batch, n_energy, n_max;
     const double* psi;       // ragged complex, plan offsets
     const double* energies;  // [n_energy]
     double eps;
     double* out;             // [batch][n_energy]
-    cd* fac;                 // [n_max][pairs] (c', 1/pivot), pair = class * n_energy + energy
+    cd* fac;                 // [n_max][pairs][3] (1/p, -low/p, -c'), pair = class * n_energy + energy
     int32_t pairs;           // real classes * n_energy
-    cd* work;                // [n_max][lanes] d'
-    int64_t lanes;
+    cd* rhs;                 // ragged M2 psi
+    cd* work;                // [groups - 1][lanes] start values of the d' groups
+    int64_t lanes;           // solves in flight (a multiple of 64)
 };
 
 // Gabor transform of the source term (tdse_gabor).
@@ -162,8 +171,10 @@ struct ResampleArgs {
 hipError_t launch_resample(const ResampleArgs& a, hipStream_t st);
 hipError_t launch_far_field(const FarArgs& a, bool adjoint, hipStream_t st);
 hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st);
-// Bytes of the shared elimination factors of tdse_plan_energy_spectrum.
+// Bytes of the shared elimination factors of tdse_plan_energy_spectrum, and
+// of one solve's slot of d' group starts.
 size_t spectrum_factor_bytes(int n_max, int64_t pairs);
+size_t spectrum_slot_bytes(int n_max);
 hipError_t launch_gabor(const GaborArgs& a, hipStream_t st);
 hipError_t launch_populations(const PopArgs& a, hipStream_t st);
 hipError_t launch_stored_state(const SizeClass* classes, const SysDesc* sys, int batch, int n_max,

@@ -8,37 +8,51 @@
 //   P(E) = (eps / pi) dx sum_j |phi_j|^2,   (E - i eps - H0) phi = psi,
 // the normalisation 1/(pi eps) making int P dE = dx sum |psi|^2.  Multiplied
 // by M2 the system is tridiagonal,
-//   ((E - i eps) M2 - A) phi = M2 psi,   A = -D2/2 + M2 diag(V):
+//   ((E - i eps) M2 - A) phi = b = M2 psi,   A = -D2/2 + M2 diag(V):
 //   diagonal   (E - i eps) 10/12 - 1/dx^2 - 10/12 V_j
 //   T[j, j-1]  (E - i eps) /12 + 1/(2 dx^2) - V_{j-1}/12   (and T[j, j+1] with V_{j+1}).
 // Its imaginary part -eps M2 is negative definite, so elimination without
-// pivoting meets no zero pivot.  The elimination factors (c'_j, 1/p_j) of
-// each (size class, energy) pair go to the head of the caller's workspace;
-// then one lane per (system, energy) runs the forward elimination of d'_j
-// into its own part of the workspace (interleaved by lane, so the stores are
-// coalesced) and the back substitution accumulating |phi_j|^2.  Lanes of a
-// wavefront mostly share the system, so psi and V are broadcast loads and
-// the factors of neighbouring energies are adjacent.
+// pivoting meets no zero pivot.
+//
+// The matrix depends on the grid size and the energy only: its elimination
+// factors are formed once per (size, energy) pair and shared by every
+// system.  With pivots p_j, 1/p_j = inv_j, m_j = -T[j, j-1] inv_j and
+// c'_j = T[j, j+1] inv_j,
+//   forward   d'_j  = b_j inv_j + m_j d'_{j-1}
+//   backward  phi_j = d'_j - c'_j phi_{j+1},
+// the norm accumulated in the backward sweep.  The backward sweep needs d'
+// in reverse order: the forward sweep keeps only every kSpecGroup-th value
+// (16 / kSpecGroup bytes per point and solve, in the caller's workspace),
+// and the backward sweep recomputes each group of kSpecGroup values from
+// its start value into registers before walking it backwards.  A wavefront
+// works on a tile of 8 systems x 8 energies (systems ordered by size), so a
+// factor load serves 8 lanes and a right-hand-side load 8 lanes.
 #include "tdse_device.hpp"
 #include "tdse_kernels.hpp"
 
 namespace tdse {
 
-// The coefficients of the system depend on the size class and the energy
-// only, so the elimination factors c'_j = up_j / p_j and 1/p_j (p_j the
-// pivot) are formed once per (class, energy) pair, one lane per pair, and
-// shared by every system of that size; each (system, energy) lane then only
-// carries d'_j = (rhs_j - low_j d'_{j-1}) / p_j through its own workspace.
-__device__ __forceinline__ void spec_coefs(const SpecArgs& a, double E, double dx, double& off_re,
-                                           double& off_im, double& dia_re, double& dia_im)
+constexpr int kSpecGroup = 8;       // d' values recomputed per group
+constexpr int kSpecTile = 8;        // systems (and energies) per wavefront tile
+
+// b = M2 psi of every system (ragged, natural point order).
+__global__ void __launch_bounds__(256) spectrum_rhs_kernel(SpecArgs a)
 {
-    const double k2 = 1.0 / (dx * dx);
-    off_re = E / 12.0 + 0.5 * k2;
-    off_im = -a.eps / 12.0;
-    dia_re = E * (10.0 / 12.0) - k2;
-    dia_im = -a.eps * (10.0 / 12.0);
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int b = blockIdx.y; b < a.batch; b += gridDim.y) {
+        const SysDesc d = a.sys[b];
+        if (j >= d.n) continue;
+        const double* psi = a.psi + 2 * d.psi_off;
+        const cd p0 = ld_psi(psi, j);
+        const cd pm = j > 0 ? ld_psi(psi, j - 1) : czero();
+        const cd pp = j + 1 < d.n ? ld_psi(psi, j + 1) : czero();
+        a.rhs[d.psi_off + j] = mkc((pm.re + 10.0 * p0.re + pp.re) / 12.0,
+                                   (pm.im + 10.0 * p0.im + pp.im) / 12.0);
+    }
 }
 
+// Elimination factors of one (size class, energy) pair, one lane per pair:
+// fac[(j * pairs + pair) * 3 + {0, 1, 2}] = inv_j, m_j, -c'_j.
 __global__ void __launch_bounds__(256) spectrum_factor_kernel(SpecArgs a)
 {
     const int pair = blockIdx.x * blockDim.x + threadIdx.x;
@@ -47,8 +61,10 @@ __global__ void __launch_bounds__(256) spectrum_factor_kernel(SpecArgs a)
     const SizeClass& sc = a.classes[c];
     const int n = sc.n, C = sc.C;
     const double* v = sc.pt.v;
-    double off_re, off_im, dia_re, dia_im;
-    spec_coefs(a, a.energies[e], sc.dx, off_re, off_im, dia_re, dia_im);
+    const double k2 = 1.0 / (sc.dx * sc.dx);
+    const double E = a.energies[e];
+    const double off_re = E / 12.0 + 0.5 * k2, off_im = -a.eps / 12.0;
+    const double dia_re = E * (10.0 / 12.0) - k2, dia_im = -a.eps * (10.0 / 12.0);
     const int64_t P = a.pairs;
     cd cp = czero();
     double vm = 0.0, v0 = v[pidx(0, 0, C)];
@@ -60,71 +76,112 @@ __global__ void __launch_bounds__(256) spectrum_factor_kernel(SpecArgs a)
         const cd up = last ? czero() : mkc(off_re - vp / 12.0, off_im);
         const cd inv = cinv(cadd(dia, cscale(-1.0, cmul(low, cp))));
         cp = cmul(up, inv);
-        a.fac[2 * ((int64_t)j * P + pair)] = cp;
-        a.fac[2 * ((int64_t)j * P + pair) + 1] = inv;
+        cd* f = a.fac + 3 * ((int64_t)j * P + pair);
+        f[0] = inv;
+        f[1] = cscale(-1.0, cmul(low, inv));
+        f[2] = cscale(-1.0, cp);
         vm = v0;
         v0 = vp;
     }
 }
 
-__global__ void __launch_bounds__(256) energy_spectrum_kernel(SpecArgs a)
+// One wavefront per tile of 8 systems x 8 energies (lane = 8 s + e); the
+// wavefronts stride over the tiles.  Each lane keeps its d' group starts in
+// its own column of the workspace ([group][lane], coalesced).
+__global__ void __launch_bounds__(64) energy_spectrum_kernel(SpecArgs a)
 {
-    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane >= a.lanes) return;
-    const int64_t items = (int64_t)a.batch * a.n_energy;
+    const int lane = threadIdx.x;
+    const int64_t wave = blockIdx.x;
+    const int64_t nwaves = gridDim.x;
+    const int ts_count = (a.batch + kSpecTile - 1) / kSpecTile;
+    const int te_count = (a.n_energy + kSpecTile - 1) / kSpecTile;
+    const int64_t tiles = (int64_t)ts_count * te_count;
     const int64_t P = a.pairs;
-    for (int64_t it = lane; it < items; it += a.lanes) {
-        const int b = (int)(it / a.n_energy);
-        const int e = (int)(it - (int64_t)b * a.n_energy);
+    const int64_t ckstride = nwaves * kWave;
+    cd* ck = a.work + wave * kWave + lane;
+    for (int64_t tile = wave; tile < tiles; tile += nwaves) {
+        // energy tiles of one system tile are consecutive: neighbouring
+        // wavefronts read the same right-hand sides
+        const int te = (int)(tile % te_count), ts = (int)(tile / te_count);
+        const int s_raw = ts * kSpecTile + lane / kSpecTile;
+        const int e_raw = te * kSpecTile + lane % kSpecTile;
+        const bool valid = s_raw < a.batch && e_raw < a.n_energy;
+        const int b = a.order[min(s_raw, a.batch - 1)];
+        const int ei = min(e_raw, a.n_energy - 1);
         const SysDesc d = a.sys[b];
-        const SizeClass& sc = a.classes[d.cls];
-        const int n = sc.n, C = sc.C;
-        const double dx = sc.dx;
-        const double* v = sc.pt.v;
-        const double* psi = a.psi + 2 * d.psi_off;
-        const int64_t pair = (int64_t)d.cls * a.n_energy + e;
-        double off_re, off_im, dia_re, dia_im;
-        spec_coefs(a, a.energies[e], dx, off_re, off_im, dia_re, dia_im);
-        cd* w = a.work;
-        const int64_t L = a.lanes;
-
-        // forward elimination: d' only (c' and 1/p from the shared factors,
-        // loads of several points issued ahead of their use)
+        const int n = d.n;
+        const int64_t pair = (int64_t)d.cls * a.n_energy + ei;
+        const cd* f = a.fac + 3 * pair;
+        const int64_t fs = 3 * P;  // factor stride per point
+        const cd* rb = a.rhs + d.psi_off;
+        const int ng = (n + kSpecGroup - 1) / kSpecGroup;
+        const int nfull = n / kSpecGroup;  // groups of kSpecGroup points (no tail)
+        // forward sweep, keeping d'_{j0 - 1} of every group j0 > 0; full
+        // groups run without conditions, so their loads issue ahead
         cd dp = czero();
-        cd pm = czero(), p0 = ld_psi(psi, 0);
-        double vm = 0.0, v0 = v[pidx(0, 0, C)];
-#pragma unroll 8
-        for (int j = 0; j < n; ++j) {
-            const bool last = j + 1 == n;
-            const cd pp = last ? czero() : ld_psi(psi, j + 1);
-            const double vp = last ? 0.0 : v[pidx((j + 1) / C, (j + 1) % C, C)];
-            const cd low = j > 0 ? mkc(off_re - vm / 12.0, off_im) : czero();
-            const cd rhs = mkc((pm.re + 10.0 * p0.re + pp.re) / 12.0, (pm.im + 10.0 * p0.im + pp.im) / 12.0);
-            const cd inv = a.fac[2 * ((int64_t)j * P + pair) + 1];
-            dp = cmul(cadd(rhs, cscale(-1.0, cmul(low, dp))), inv);
-            w[(int64_t)j * L + lane] = dp;
-            pm = p0;
-            p0 = pp;
-            vm = v0;
-            v0 = vp;
+        for (int g = 0; g < ng; ++g) {
+            const int j0 = g * kSpecGroup;
+            if (g > 0) ck[(int64_t)(g - 1) * ckstride] = dp;
+            const cd* fg = f + (int64_t)j0 * fs;
+            if (g < nfull) {
+#pragma unroll
+                for (int u = 0; u < kSpecGroup; ++u)
+                    dp = cmad(ldg(fg + u * fs + 1), dp, cmul(ldg(rb + j0 + u), ldg(fg + u * fs)));
+            } else {
+                for (int u = 0; j0 + u < n; ++u)
+                    dp = cmad(ldg(fg + u * fs + 1), dp, cmul(ldg(rb + j0 + u), ldg(fg + u * fs)));
+            }
         }
-        // back substitution with |phi|^2 accumulated
-        cd phi = dp;
-        double acc = cabs2(phi);
-#pragma unroll 8
-        for (int j = n - 2; j >= 0; --j) {
-            const cd c = a.fac[2 * ((int64_t)j * P + pair)];
-            const cd dd = w[(int64_t)j * L + lane];
-            phi = cadd(dd, cscale(-1.0, cmul(c, phi)));
-            acc += cabs2(phi);
+        // backward sweep group by group: recompute the group's d' from its
+        // start value, then walk it backwards accumulating |phi|^2
+        double acc = 0.0;
+        cd phi = czero();
+        for (int g = ng - 1; g >= 0; --g) {
+            const int j0 = g * kSpecGroup;
+            const cd* fg = f + (int64_t)j0 * fs;
+            cd x = g > 0 ? ck[(int64_t)(g - 1) * ckstride] : czero();
+            if (g < nfull) {
+                cd dd[kSpecGroup];
+#pragma unroll
+                for (int u = 0; u < kSpecGroup; ++u) {
+                    x = cmad(ldg(fg + u * fs + 1), x, cmul(ldg(rb + j0 + u), ldg(fg + u * fs)));
+                    dd[u] = x;
+                }
+#pragma unroll
+                for (int u = kSpecGroup - 1; u >= 0; --u) {
+                    phi = cmad(ldg(fg + u * fs + 2), phi, dd[u]);
+                    acc = fma(phi.re, phi.re, fma(phi.im, phi.im, acc));
+                }
+            } else {
+                cd dd[kSpecGroup];
+#pragma unroll
+                for (int u = 0; u < kSpecGroup; ++u) {
+                    if (j0 + u < n)
+                        x = cmad(ldg(fg + u * fs + 1), x, cmul(ldg(rb + j0 + u), ldg(fg + u * fs)));
+                    dd[u] = x;
+                }
+#pragma unroll
+                for (int u = kSpecGroup - 1; u >= 0; --u) {
+                    if (j0 + u < n) {
+                        phi = cmad(ldg(fg + u * fs + 2), phi, dd[u]);
+                        acc = fma(phi.re, phi.re, fma(phi.im, phi.im, acc));
+                    }
+                }
+            }
         }
-        a.out[it] = a.eps / M_PI * dx * acc;
+        if (valid) a.out[(int64_t)b * a.n_energy + ei] = a.eps / M_PI * a.classes[d.cls].dx * acc;
     }
 }
 
 size_t spectrum_factor_bytes(int n_max, int64_t pairs)
 {
-    return ((size_t)n_max * (size_t)pairs * 2 * sizeof(cd) + 255) & ~size_t(255);
+    return ((size_t)n_max * (size_t)pairs * 3 * sizeof(cd) + 255) & ~size_t(255);
+}
+
+size_t spectrum_slot_bytes(int n_max)
+{
+    const int ng = (n_max + kSpecGroup - 1) / kSpecGroup;
+    return sizeof(cd) * (size_t)std::max(ng - 1, 1);
 }
 
 // Gabor transform (section "Physical Examples & tutorials", microscopic
@@ -254,8 +311,9 @@ hipError_t launch_gabor(const GaborArgs& a, hipStream_t st)
 hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st)
 {
     hipLaunchKernelGGL(spectrum_factor_kernel, dim3((a.pairs + 255) / 256), dim3(256), 0, st, a);
-    const unsigned blocks = (unsigned)((a.lanes + 255) / 256);
-    hipLaunchKernelGGL(energy_spectrum_kernel, dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(spectrum_rhs_kernel, dim3((a.n_max + 255) / 256, std::min(a.batch, 65535)),
+                       dim3(256), 0, st, a);
+    hipLaunchKernelGGL(energy_spectrum_kernel, dim3((unsigned)(a.lanes / kWave)), dim3(kWave), 0, st, a);
     return hipGetLastError();
 }
 
