@@ -97,6 +97,19 @@ typedef struct {
 tdse_status tdse_ground_state(const tdse_params* p, int32_t n, double dtau, int32_t max_iter,
                               double tol, double* psi_out, double* energy_out, void* stream);
 
+/* tdse_ground_state for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results (bitwise), but the
+ * tables and the kernel's outputs live in a static device workspace of
+ * 2 MiB that each GPU holds until the process ends, so the call makes no
+ * hipMalloc, hipFree or allocating library call.  That covers every n up
+ * to 16384; a layout needing more fails with TDSE_E_NOMEM before any launch.
+ * Calls share their GPU's workspace: the library runs calls on one GPU from
+ * threads of one process one after the other (the call is synchronous), and
+ * overlapping use of the workspace by other means races. */
+tdse_status tdse_ground_state_noalloc(const tdse_params* p, int32_t n, double dtau,
+                                      int32_t max_iter, double tol, double* psi_out,
+                                      double* energy_out, void* stream);
 
 /* Soft-core parameter a in [a_lo, a_hi] whose ground-state energy on the
  * n-point grid of spacing dx equals -ip (E_g increases with a).  Multisection:

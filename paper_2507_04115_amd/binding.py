@@ -58,6 +58,8 @@ _PROTOS = {
     "tdse_last_error": (ctypes.c_char_p, []),
     "tdse_ground_state": (_i32, [ctypes.POINTER(tdse_params), _i32, _d, _i32, _d, _vp,
                                  ctypes.POINTER(_d), _vp]),
+    "tdse_ground_state_noalloc": (_i32, [ctypes.POINTER(tdse_params), _i32, _d, _i32, _d, _vp,
+                                         ctypes.POINTER(_d), _vp]),
     "tdse_soft_core_for_ip": (_i32, [_d, _i32, _d, _d, _d, _d, _d, ctypes.POINTER(_d),
                                      ctypes.POINTER(_d)]),
     "tdse_plan_create": (_i32, [ctypes.POINTER(tdse_params), _i32, ctypes.POINTER(_i32),
@@ -213,6 +215,18 @@ def tdse_ground_state(p: tdse_params, n: int, dtau: float, max_iter: int, tol: f
     e = _d()
     _check(load().tdse_ground_state(ctypes.byref(p), n, dtau, max_iter, tol, _ptr(psi_out),
                                     ctypes.byref(e), _stream(stream)), "tdse_ground_state")
+    return e.value
+
+
+def tdse_ground_state_noalloc(p: tdse_params, n: int, dtau: float, max_iter: int, tol: float,
+                              psi_out, stream=None) -> float:
+    """tdse_ground_state without device allocations (static workspace)."""
+    _c128(psi_out)
+    _need(psi_out, n, "psi_out", True)
+    e = _d()
+    _check(load().tdse_ground_state_noalloc(ctypes.byref(p), n, dtau, max_iter, tol, _ptr(psi_out),
+                                            ctypes.byref(e), _stream(stream)),
+           "tdse_ground_state_noalloc")
     return e.value
 
 

@@ -1920,6 +1920,89 @@ tdse_status tdse_resample_field(int32_t batch, int32_t m, double dt_coarse, doub
     return TDSE_OK;
 }
 
+// ------------------------------------------------ allocation-free ground state
+// A fixed device workspace for tdse_ground_state_noalloc: the tables of one
+// size class and the ground-state kernel's outputs (about 1.6 MB at the
+// largest grid, n = 16384).  Every GPU the library runs on holds its own
+// copy of the array until the process ends.  In host code `scratch` only
+// stands in for the symbol: its device address on the current GPU comes
+// from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(2) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;                  // held for the whole call: calls on one
+char* g_scratch_ptr[kMaxDevices] = {};    // GPU from threads of this process run
+                                          // one after the other
+
+// The device address of `scratch` on the current GPU (looked up on the first
+// call on that GPU).  Called with g_scratch_mu held.
+tdse_status scratch_of_current_device(char** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TDSE_E_UNSUPPORTED, "device %d out of range", dev);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TDSE_E_DEVICE, "hipGetSymbolAddress of the static workspace failed: %s",
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return TDSE_OK;
+}
+
+}  // namespace
+
+tdse_status tdse_ground_state_noalloc(const tdse_params* p, int32_t n, double dtau,
+                                      int32_t max_iter, double tol, double* psi_out,
+                                      double* energy_out, void* stream)
+{
+    g_last_error.clear();
+    tdse_status st = check_params(p, false);
+    if (st != TDSE_OK) return st;
+    if (n < kMinN || n > kMaxN) return fail(n > kMaxN ? TDSE_E_UNSUPPORTED : TDSE_E_INVALID, "n=%d out of range", n);
+    if (!(dtau > 0.0) || max_iter < 1 || !(tol > 0.0) || !psi_out)
+        return fail(TDSE_E_INVALID, "dtau > 0, max_iter >= 1, tol > 0 and psi_out are required");
+    if (!aligned16(psi_out)) return fail(TDSE_E_INVALID, "psi_out must be 16-byte aligned");
+    const Layout L = default_layout(n);
+    const size_t need = ground_state_device_bytes(L);
+    if (need > kNoAllocScratchBytes)
+        return fail(TDSE_E_NOMEM, "n=%d needs %zu bytes of the static workspace, which holds %zu", n,
+                    need, kNoAllocScratchBytes);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    char* base = nullptr;
+    st = scratch_of_current_device(&base);
+    if (st != TDSE_OK) return st;
+    DevMem dm{base, kNoAllocScratchBytes, 0};
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    ClassSet cs;
+    std::vector<int> ns{n};
+    std::vector<Layout> lay{L};
+    std::vector<TableParams> prm{imag_time_params(p->dx, p->a, p->charge_z, dtau)};
+    st = build_classes(cs, ns, lay, prm, hs, &dm);
+    if (st == TDSE_OK) {
+        std::vector<int> one{0};
+        int64_t off = 0;
+        std::vector<double> e;
+        std::vector<int> it;
+        st = run_ground_states(cs, one, dtau, max_iter, tol, psi_out, &off, e, it, hs, &dm);
+        if (st == TDSE_OK) {
+            if (energy_out) *energy_out = e[0];
+            if (it[0] <= 0) st = fail(TDSE_E_NOCONV, "not converged after %d iterations", -it[0]);
+            else if (!std::isfinite(e[0])) st = fail(TDSE_E_NONFINITE, "non-finite energy");
+        }
+    }
+    cs.release();  // nothing to free: the tables live in the static workspace
+    // the stream has been synchronised (the energy was read back), so the
+    // workspace is free for the next call
+    return st;
+}
+
 tdse_status tdse_soft_core_for_ip(double ip, int32_t n, double dx, double dtau, double tol,
                                   double a_lo, double a_hi, double* a_out, double* e_out)
 {
