@@ -52,15 +52,19 @@ CSRC = os.path.join(ROOT, "paper_2507_04115_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+# the translation unit of the forward kernel and the headers it includes:
+# the HBM counters describe that kernel only
+FORWARD_SOURCES = ("tdse_forward.hip", "tdse_device.hpp", "tdse_internal.hpp", "tdse_kernels.hpp")
+
+
 def source_digest() -> str:
-    """sha256 over the kernel sources; HBM counters are valid only for this digest."""
+    """sha256 over the forward kernel's sources; HBM counters are valid only for this digest."""
     import hashlib
 
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in sorted(FORWARD_SOURCES):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
