@@ -87,7 +87,8 @@ __global__ void __launch_bounds__(256) spectrum_factor_kernel(SpecArgs a)
 
 // One wavefront per tile of 8 systems x 8 energies (lane = 8 s + e); the
 // wavefronts stride over the tiles.  Each lane keeps its d' group starts in
-// its own column of the workspace ([group][lane], coalesced).
+// its own column of its wavefront's block of the workspace ([group][lane],
+// coalesced).
 __global__ void __launch_bounds__(64) energy_spectrum_kernel(SpecArgs a)
 {
     const int lane = threadIdx.x;
@@ -97,8 +98,11 @@ __global__ void __launch_bounds__(64) energy_spectrum_kernel(SpecArgs a)
     const int te_count = (a.n_energy + kSpecTile - 1) / kSpecTile;
     const int64_t tiles = (int64_t)ts_count * te_count;
     const int64_t P = a.pairs;
-    const int64_t ckstride = nwaves * kWave;
-    cd* ck = a.work + wave * kWave + lane;
+    // this wavefront's group starts: [group][lane], contiguous per wavefront
+    // so that each wavefront walks its own pages of the workspace
+    const int64_t ckstride = kWave;
+    const int64_t slots = (a.n_max + kSpecGroup - 1) / kSpecGroup - 1;
+    cd* ck = a.work + wave * (slots > 0 ? slots : 1) * kWave + lane;
     for (int64_t tile = wave; tile < tiles; tile += nwaves) {
         // energy tiles of one system tile are consecutive: neighbouring
         // wavefronts read the same right-hand sides
