@@ -135,18 +135,19 @@ def bench_spectrum(torch, L, plan, w, dev, stream):
     del work
     # algorithmic HBM bytes: psi in (16 B per point and system), the shared
     # factors (48 B per point and energy), the spectrum out; plus the d'
-    # group starts the kernel keeps (2 B per point and solve, written and
+    # group starts the kernel keeps (1 B per point and solve, written and
     # read back)
     algo = 16.0 * n * w.batch + 48.0 * n * 256 + 8.0 * solves
-    ckpt = 2.0 * 2.0 * n * solves
+    ckpt = 2.0 * 1.0 * n * solves
     return {"energies": 256, "eps": 0.01, "ms": ms, "solves": solves,
             "grid_point_solves_per_s": solves * n / (ms * 1e-3),
             "algorithmic_hbm_bytes": algo, "group_start_bytes": ckpt,
             "hbm_gbs_incl_group_starts": (algo + ckpt) / (ms * 1e-3) / 1e9,
-            "note": "elimination factors per (grid size, energy) shared by the systems; "
-                    "one lane per (system, energy), tiles of 8 systems x 8 energies per "
-                    "wavefront; d' kept in registers in groups of 8 points, recomputed from "
-                    "each group's start value in the backward sweep"}
+            "note": "elimination factors per (grid size, energy) shared by the systems, "
+                    "read as scalar loads; one lane per (system, energy), one energy and 64 "
+                    "systems of one size per wavefront, M2 psi point-interleaved per size; "
+                    "d' kept in registers in groups of 16 points, recomputed from each "
+                    "group's start value in the backward sweep"}
 
 
 def bench_far_field(torch, L, ti, dev, stream):

@@ -344,10 +344,11 @@ tdse_status tdse_plan_populations(tdse_plan plan, uint64_t generation, const dou
  *             elimination factors shared by the systems of one size (48 n_max
  *             bytes per grid size and energy, n_max = the plan's largest n),
  *             then M2 psi of every system (16 bytes per point), then
- *             2 n_max bytes per (system, energy) solve in flight (the start
- *             of every 8-point group of the forward sweep, recomputed from
+ *             n_max bytes per (system, energy) solve in flight (the start
+ *             of every 16-point group of the forward sweep, recomputed from
  *             in the backward sweep), at least 64 of them; 256k keep the GPU
- *             busy.
+ *             busy.  A wavefront solves one energy for 64 systems of one
+ *             size, so a size with fewer systems leaves lanes idle.
  *             tdse_plan_energy_spectrum_work gives the size for a number of
  *             solves in flight.  Contents on return are undefined.
  * Fails with TDSE_E_INVALID, before any launch, when work is too small.

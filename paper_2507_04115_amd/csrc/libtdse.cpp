@@ -434,6 +434,11 @@ struct tdse_plan_s {
     int32_t* d_counters = nullptr;      // adjoint: launches + 2*launches (compaction); then one
                                         // kQueueInts queue per system (plain) and per forward group
     int32_t* d_ident = nullptr;
+    // electron energy distribution: the sizes in system order, their blocks
+    // of 64 systems and the length of the point-interleaved right-hand sides
+    SpecClass* d_spec = nullptr;
+    int spec_n = 0, spec_blocks = 0;
+    int64_t spec_rhs = 0;
     // graph replay; graph_state: 0 not captured yet, 1 replaying a graph,
     // 2 capture failed (or was switched off) and calls launch directly
     int graph_state = 0;
@@ -487,6 +492,7 @@ void plan_free(tdse_plan pl)
     if (pl->d_order_all) (void)hipFree(pl->d_order_all);
     if (pl->d_counters) (void)hipFree(pl->d_counters);
     if (pl->d_ident) (void)hipFree(pl->d_ident);
+    if (pl->d_spec) (void)hipFree(pl->d_spec);
     if (pl->d_adj) (void)hipFree(pl->d_adj);
     if (pl->d_store) (void)hipFree(pl->d_store);
     if (pl->d_store_off) (void)hipFree(pl->d_store_off);
@@ -1462,6 +1468,7 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
             return bail(fail(TDSE_E_DEVICE, "plan upload failed"));
     }
     std::vector<int32_t> order_all;
+    std::vector<SpecClass> spec;
     pl->launch_of_cls.assign(ncls, -1);
     const int64_t nt = p->nt;
     int64_t adj_total = 0;
@@ -1476,6 +1483,18 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         L.count = (int)csys[c].size();
         L.d_order = pl->d_order_all + order_all.size();
         L.d_order_adj = pl->d_order_all + batch + order_all.size();
+        {
+            SpecClass sp{};
+            sp.cls = c;
+            sp.n = pl->n_per[csys[c][0]];
+            sp.start = (int32_t)order_all.size();
+            sp.count = L.count;
+            sp.blk0 = pl->spec_blocks;
+            sp.rhs_off = pl->spec_rhs;
+            pl->spec_blocks += (L.count + kWave - 1) / kWave;
+            pl->spec_rhs += (int64_t)sp.n * L.count;
+            spec.push_back(sp);
+        }
         order_all.insert(order_all.end(), csys[c].begin(), csys[c].end());
         const tdse_plan_s::FwdGroup& fg = pl->fgroups[pl->fgroup_of_cls[c]];
         L.S = std::max(1, fg.threads / L.T);
@@ -1509,6 +1528,12 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     }
     std::vector<int32_t> ident(batch);
     for (int b = 0; b < batch; ++b) ident[b] = b;
+    pl->spec_n = (int)spec.size();
+    if (hipMalloc(&pl->d_spec, sizeof(SpecClass) * spec.size()) != hipSuccess)
+        return bail(fail(TDSE_E_NOMEM, "plan allocation failed"));
+    if (hipMemcpy(pl->d_spec, spec.data(), sizeof(SpecClass) * spec.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return bail(fail(TDSE_E_DEVICE, "plan upload failed"));
     if (hipMemcpy(pl->d_sys, sys.data(), sizeof(SysDesc) * batch, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(pl->d_order_all, order_all.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice) !=
             hipSuccess ||
@@ -2247,10 +2272,10 @@ tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t
     if (pairs > std::numeric_limits<int32_t>::max())
         return fail(TDSE_E_INVALID, "too many (size, energy) pairs");
     const size_t fac = spectrum_factor_bytes(n_max, pairs);
-    const size_t rhs = ((size_t)plan->psi_off[plan->batch] * sizeof(cd) + 255) & ~size_t(255);
+    const size_t rhs = ((size_t)plan->spec_rhs * sizeof(cd) + 255) & ~size_t(255);
     const size_t per_lane = spectrum_slot_bytes(n_max);
-    // tiles of 8 systems x 8 energies, one wavefront each
-    const int64_t tiles = (int64_t)((plan->batch + 7) / 8) * ((n_energy + 7) / 8);
+    // tiles of one energy x 64 systems of one size, one wavefront each
+    const int64_t tiles = (int64_t)plan->spec_blocks * n_energy;
     if (work_bytes < fac + rhs + kWave * per_lane)
         return fail(TDSE_E_INVALID,
                     "work must hold at least %zu bytes: %zu of elimination factors, %zu of right-hand "
@@ -2265,6 +2290,9 @@ tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t
     a.classes = plan->cls.d;
     a.sys = plan->d_sys;
     a.order = plan->d_order_all;
+    a.spec = plan->d_spec;
+    a.nspec = plan->spec_n;
+    a.nblocks = plan->spec_blocks;
     a.batch = plan->batch;
     a.n_energy = n_energy;
     a.n_max = n_max;
@@ -2287,7 +2315,7 @@ tdse_status tdse_plan_energy_spectrum_work(tdse_plan plan, int32_t n_energy, int
     if (n_energy < 1 || lanes < kWave) return fail(TDSE_E_INVALID, "need n_energy >= 1 and lanes >= 64");
     const int n_max = *std::max_element(plan->n_per.begin(), plan->n_per.end());
     *bytes = spectrum_factor_bytes(n_max, (int64_t)plan->ncls_real * n_energy) +
-             (((size_t)plan->psi_off[plan->batch] * sizeof(cd) + 255) & ~size_t(255)) +
+             (((size_t)plan->spec_rhs * sizeof(cd) + 255) & ~size_t(255)) +
              (size_t)((lanes + kWave - 1) / kWave * kWave) * spectrum_slot_bytes(n_max);
     return TDSE_OK;
 }

@@ -106,20 +106,36 @@ struct BandAdjArgs {
     double* accel_bar;      // [batch][nt+1]
 };
 
+// One grid size of a batch as the electron energy distribution sees it: its
+// systems are order[start .. start+count), their right-hand sides stored
+// point by point (rhs[rhs_off + j * count + k] for the k-th of them), in
+// blocks of 64 systems numbered blk0 .. blk0 + ceil(count / 64) - 1.
+struct SpecClass {
+    int32_t cls;      // size class
+    int32_t n;        // grid size
+    int32_t start;    // first position in the plan's system order
+    int32_t count;    // systems of this size
+    int32_t blk0;     // first 64-system block
+    int32_t pad_;
+    int64_t rhs_off;  // complex elements into rhs
+};
+
 // Electron energy distribution (tdse_plan_energy_spectrum).
 struct SpecArgs {
     const SizeClass* classes;
     const SysDesc* sys;
     const int32_t* order;    // systems grouped by size class
+    const SpecClass* spec;   // [nspec], ordered by blk0
+    int32_t nspec, nblocks;  // sizes, 64-system blocks over all sizes
     int32_t batch, n_energy, n_max;
     const double* psi;       // ragged complex, plan offsets
     const double* energies;  // [n_energy]
     double eps;
     double* out;             // [batch][n_energy]
-    cd* fac;                 // [n_max][pairs][3] (1/p, -low/p, -c'), pair = class * n_energy + energy
+    cd* fac;                 // [pairs][n_max][3] (1/p, -low/p, -c'), pair = class * n_energy + energy
     int32_t pairs;           // real classes * n_energy
-    cd* rhs;                 // ragged M2 psi
-    cd* work;                // [groups - 1][lanes] start values of the d' groups
+    cd* rhs;                 // M2 psi, point-interleaved per size (SpecClass)
+    cd* work;                // per wavefront: [groups - 1][64] start values of the d' groups
     int64_t lanes;           // solves in flight (a multiple of 64)
 };
 

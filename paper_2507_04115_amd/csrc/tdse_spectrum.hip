@@ -24,100 +24,202 @@
 // in reverse order: the forward sweep keeps only every kSpecGroup-th value
 // (16 / kSpecGroup bytes per point and solve, in the caller's workspace),
 // and the backward sweep recomputes each group of kSpecGroup values from
-// its start value into registers before walking it backwards.  A wavefront
-// works on a tile of 8 systems x 8 energies (systems ordered by size), so a
-// factor load serves 8 lanes and a right-hand-side load 8 lanes.
+// its start value into registers before walking it backwards.
+//
+// A wavefront solves one energy for a block of 64 systems of one size, one
+// lane each: the factors are then the same for the whole wavefront and come
+// in through scalar loads, and the right-hand sides b = M2 psi, stored point
+// by point for the systems of a size ([j][system], one row of 16 bytes per
+// system), arrive in one coalesced load per point.  So the vector memory
+// path carries only the 16 bytes per point and solve that differ between
+// lanes, twice (forward sweep, recomputation), plus the group starts.
 #include "tdse_device.hpp"
 #include "tdse_kernels.hpp"
 
 namespace tdse {
 
-constexpr int kSpecGroup = 8;       // d' values recomputed per group
-constexpr int kSpecTile = 8;        // systems (and energies) per wavefront tile
+constexpr int kSpecGroup = 16;      // d' values recomputed per group
 
-// b = M2 psi of every system (ragged, natural point order).
+// Entry of `spec` that holds 64-system block `blk` (entries ordered by blk0).
+__device__ __forceinline__ int spec_entry(const SpecClass* spec, int nspec, int blk)
+{
+    int lo = 0, hi = nspec - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (scalar_load(&spec[mid].blk0) <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// b = M2 psi of every system, point-interleaved within its size:
+// rhs[rhs_off + j * count + k] for the size's k-th system.  Lanes are
+// systems of one block, so the stores are coalesced.
 __global__ void __launch_bounds__(256) spectrum_rhs_kernel(SpecArgs a)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int b = blockIdx.y; b < a.batch; b += gridDim.y) {
-        const SysDesc d = a.sys[b];
-        if (j >= d.n) continue;
+    const int j = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    for (int blk = blockIdx.y; blk < a.nblocks; blk += gridDim.y) {
+        const SpecClass s = scalar_load(a.spec + spec_entry(a.spec, a.nspec, blk));
+        const int k = (blk - s.blk0) * kWave + threadIdx.x % kWave;
+        if (k >= s.count || j >= s.n) continue;
+        const SysDesc d = a.sys[a.order[s.start + k]];
         const double* psi = a.psi + 2 * d.psi_off;
         const cd p0 = ld_psi(psi, j);
         const cd pm = j > 0 ? ld_psi(psi, j - 1) : czero();
-        const cd pp = j + 1 < d.n ? ld_psi(psi, j + 1) : czero();
-        a.rhs[d.psi_off + j] = mkc((pm.re + 10.0 * p0.re + pp.re) / 12.0,
-                                   (pm.im + 10.0 * p0.im + pp.im) / 12.0);
+        const cd pp = j + 1 < s.n ? ld_psi(psi, j + 1) : czero();
+        a.rhs[s.rhs_off + (int64_t)j * s.count + k] =
+            mkc((pm.re + 10.0 * p0.re + pp.re) / 12.0, (pm.im + 10.0 * p0.im + pp.im) / 12.0);
     }
 }
 
-// Elimination factors of one (size class, energy) pair, one lane per pair:
-// fac[(j * pairs + pair) * 3 + {0, 1, 2}] = inv_j, m_j, -c'_j.
-__global__ void __launch_bounds__(256) spectrum_factor_kernel(SpecArgs a)
+// Elimination factors of one (size class, energy) pair per wavefront:
+// fac[(pair * n_max + j) * 3 + {0, 1, 2}] = inv_j, m_j, -c'_j, contiguous
+// along j for the scalar stream of the solve.
+//
+// The elimination is a serial chain, c'_j = up_j / (dia_j - low_j c'_{j-1})
+// from c'_{-1} = 0: a Moebius map of c'_{j-1} with the matrix
+// M_j = [[0, up_j], [-low_j, dia_j]] acting on (c', 1).  Lane l takes the
+// points of one chunk of ceil(n / 64), composes its maps into one matrix
+// (rescaled by powers of two, which changes neither the map nor any
+// rounding), a scan over the lanes composes the chunks before each one, and
+// the lane then runs the elimination itself over its chunk from the start
+// value c'_{j0-1} that the composition gives.  The chain that was 4096 steps
+// long per pair becomes 2 x 64 steps and a 6-level scan.  The potential is
+// staged in LDS in natural point order (n doubles).
+struct Moeb {
+    cd a, b, c, d;  // [[a, b], [c, d]]
+};
+__device__ __forceinline__ cd cadd2(cd x, cd y) { return mkc(x.re + y.re, x.im + y.im); }
+// x * y: the map y first, then x
+__device__ __forceinline__ Moeb moeb_mul(const Moeb& x, const Moeb& y)
 {
-    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pair >= a.pairs) return;
+    Moeb r;
+    r.a = cadd2(cmul(x.a, y.a), cmul(x.b, y.c));
+    r.b = cadd2(cmul(x.a, y.b), cmul(x.b, y.d));
+    r.c = cadd2(cmul(x.c, y.a), cmul(x.d, y.c));
+    r.d = cadd2(cmul(x.c, y.b), cmul(x.d, y.d));
+    return r;
+}
+__device__ __forceinline__ double cmaxabs(cd z) { return fmax(fabs(z.re), fabs(z.im)); }
+__device__ __forceinline__ cd cldexp(cd z, int e) { return mkc(ldexp(z.re, e), ldexp(z.im, e)); }
+// Scales the matrix by a power of two that brings its largest component near 1.
+__device__ __forceinline__ void moeb_rescale(Moeb& m)
+{
+    const double big = fmax(fmax(cmaxabs(m.a), cmaxabs(m.b)), fmax(cmaxabs(m.c), cmaxabs(m.d)));
+    if (!(big > 0.0) || !isfinite(big)) return;
+    int ex;
+    (void)frexp(big, &ex);
+    m.a = cldexp(m.a, -ex);
+    m.b = cldexp(m.b, -ex);
+    m.c = cldexp(m.c, -ex);
+    m.d = cldexp(m.d, -ex);
+}
+__device__ __forceinline__ cd shfl_up_cd(cd z, int d)
+{
+    return mkc(__shfl_up(z.re, d, kWave), __shfl_up(z.im, d, kWave));
+}
+__device__ __forceinline__ Moeb shfl_up_moeb(const Moeb& m, int d)
+{
+    Moeb r;
+    r.a = shfl_up_cd(m.a, d);
+    r.b = shfl_up_cd(m.b, d);
+    r.c = shfl_up_cd(m.c, d);
+    r.d = shfl_up_cd(m.d, d);
+    return r;
+}
+constexpr int kFacRescale = 8;  // chunk-product steps between rescalings
+
+__global__ void __launch_bounds__(kWave) spectrum_factor_kernel(SpecArgs a)
+{
+    extern __shared__ double vs[];  // V_j, natural order
+    const int pair = blockIdx.x;
+    const int lane = threadIdx.x;
     const int c = pair / a.n_energy, e = pair - c * a.n_energy;
     const SizeClass& sc = a.classes[c];
     const int n = sc.n, C = sc.C;
-    const double* v = sc.pt.v;
+    for (int j = lane; j < n; j += kWave) vs[j] = ldg(sc.pt.v + pidx(j / C, j % C, C));
+    __syncthreads();
     const double k2 = 1.0 / (sc.dx * sc.dx);
     const double E = a.energies[e];
     const double off_re = E / 12.0 + 0.5 * k2, off_im = -a.eps / 12.0;
     const double dia_re = E * (10.0 / 12.0) - k2, dia_im = -a.eps * (10.0 / 12.0);
-    const int64_t P = a.pairs;
-    cd cp = czero();
-    double vm = 0.0, v0 = v[pidx(0, 0, C)];
-    for (int j = 0; j < n; ++j) {
-        const bool last = j + 1 == n;
-        const double vp = last ? 0.0 : v[pidx((j + 1) / C, (j + 1) % C, C)];
-        const cd dia = mkc(dia_re - (10.0 / 12.0) * v0, dia_im);
-        const cd low = j > 0 ? mkc(off_re - vm / 12.0, off_im) : czero();
-        const cd up = last ? czero() : mkc(off_re - vp / 12.0, off_im);
+    // the row of the Numerov matrix at point j
+    auto row = [&](int j, cd& low, cd& dia, cd& up) {
+        dia = mkc(dia_re - (10.0 / 12.0) * vs[j], dia_im);
+        low = j > 0 ? mkc(off_re - vs[j - 1] / 12.0, off_im) : czero();
+        up = j + 1 < n ? mkc(off_re - vs[j + 1] / 12.0, off_im) : czero();
+    };
+    const int L = (n + kWave - 1) / kWave;
+    const int j0 = min(n, lane * L), j1 = min(n, j0 + L);
+    // this chunk's map
+    Moeb P{mkc(1.0, 0.0), czero(), czero(), mkc(1.0, 0.0)};
+    for (int j = j0; j < j1; ++j) {
+        cd low, dia, up;
+        row(j, low, dia, up);
+        Moeb Q;
+        Q.a = cmul(up, P.c);
+        Q.b = cmul(up, P.d);
+        Q.c = cadd2(cmul(dia, P.c), cscale(-1.0, cmul(low, P.a)));
+        Q.d = cadd2(cmul(dia, P.d), cscale(-1.0, cmul(low, P.b)));
+        P = Q;
+        if ((j - j0) % kFacRescale == kFacRescale - 1) moeb_rescale(P);
+    }
+    moeb_rescale(P);
+    // inclusive scan over the lanes: the maps of chunks 0 .. lane, composed
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const Moeb prev = shfl_up_moeb(P, d);
+        if (lane >= d) {
+            P = moeb_mul(P, prev);
+            moeb_rescale(P);
+        }
+    }
+    // c'_{j0-1}: the composed maps of the chunks before this one applied to 0
+    const cd num = shfl_up_cd(P.b, 1), den = shfl_up_cd(P.d, 1);
+    cd cp = lane > 0 ? cmul(num, cinv(den)) : czero();
+    cd* f = a.fac + 3 * ((int64_t)pair * a.n_max + j0);
+    for (int j = j0; j < j1; ++j, f += 3) {
+        cd low, dia, up;
+        row(j, low, dia, up);
         const cd inv = cinv(cadd(dia, cscale(-1.0, cmul(low, cp))));
         cp = cmul(up, inv);
-        cd* f = a.fac + 3 * ((int64_t)j * P + pair);
         f[0] = inv;
         f[1] = cscale(-1.0, cmul(low, inv));
         f[2] = cscale(-1.0, cp);
-        vm = v0;
-        v0 = vp;
     }
 }
 
-// One wavefront per tile of 8 systems x 8 energies (lane = 8 s + e); the
-// wavefronts stride over the tiles.  Each lane keeps its d' group starts in
-// its own column of its wavefront's block of the workspace ([group][lane],
+// d'_j of one lane from d'_{j-1}: factors from the scalar stream, b_j from
+// the lane's column.
+__device__ __forceinline__ cd spec_step(const cd* f, const cd* b, cd dp)
+{
+    return cmad(scalar_load(f + 1), dp, cmul(ldg(b), scalar_load(f)));
+}
+
+// One wavefront per tile (energy e, block of 64 systems of one size); the
+// wavefronts stride over the tiles, energy-major, so that the blocks of one
+// energy run side by side.  Each lane keeps its d' group starts in its own
+// column of its wavefront's block of the workspace ([group][lane],
 // coalesced).
 __global__ void __launch_bounds__(64) energy_spectrum_kernel(SpecArgs a)
 {
     const int lane = threadIdx.x;
     const int64_t wave = blockIdx.x;
     const int64_t nwaves = gridDim.x;
-    const int ts_count = (a.batch + kSpecTile - 1) / kSpecTile;
-    const int te_count = (a.n_energy + kSpecTile - 1) / kSpecTile;
-    const int64_t tiles = (int64_t)ts_count * te_count;
-    const int64_t P = a.pairs;
-    // this wavefront's group starts: [group][lane], contiguous per wavefront
-    // so that each wavefront walks its own pages of the workspace
-    const int64_t ckstride = kWave;
+    const int64_t tiles = (int64_t)a.nblocks * a.n_energy;
     const int64_t slots = (a.n_max + kSpecGroup - 1) / kSpecGroup - 1;
     cd* ck = a.work + wave * (slots > 0 ? slots : 1) * kWave + lane;
     for (int64_t tile = wave; tile < tiles; tile += nwaves) {
-        // energy tiles of one system tile are consecutive: neighbouring
-        // wavefronts read the same right-hand sides
-        const int te = (int)(tile % te_count), ts = (int)(tile / te_count);
-        const int s_raw = ts * kSpecTile + lane / kSpecTile;
-        const int e_raw = te * kSpecTile + lane % kSpecTile;
-        const bool valid = s_raw < a.batch && e_raw < a.n_energy;
-        const int b = a.order[min(s_raw, a.batch - 1)];
-        const int ei = min(e_raw, a.n_energy - 1);
-        const SysDesc d = a.sys[b];
-        const int n = d.n;
-        const int64_t pair = (int64_t)d.cls * a.n_energy + ei;
-        const cd* f = a.fac + 3 * pair;
-        const int64_t fs = 3 * P;  // factor stride per point
-        const cd* rb = a.rhs + d.psi_off;
+        const int e = (int)(tile / a.nblocks);
+        const int blk = (int)(tile - (int64_t)e * a.nblocks);
+        const SpecClass s = scalar_load(a.spec + spec_entry(a.spec, a.nspec, blk));
+        const int k = (blk - s.blk0) * kWave + lane;
+        const bool valid = k < s.count;
+        const int n = s.n;
+        // lanes past the last system repeat it (in bounds, nothing written)
+        const cd* rb = a.rhs + s.rhs_off + (valid ? k : s.count - 1);
+        const int64_t rs = s.count;  // right-hand side stride per point
+        const cd* f = a.fac + 3 * ((int64_t)s.cls * a.n_energy + e) * a.n_max;
         const int ng = (n + kSpecGroup - 1) / kSpecGroup;
         const int nfull = n / kSpecGroup;  // groups of kSpecGroup points (no tail)
         // forward sweep, keeping d'_{j0 - 1} of every group j0 > 0; full
@@ -125,15 +227,14 @@ __global__ void __launch_bounds__(64) energy_spectrum_kernel(SpecArgs a)
         cd dp = czero();
         for (int g = 0; g < ng; ++g) {
             const int j0 = g * kSpecGroup;
-            if (g > 0) ck[(int64_t)(g - 1) * ckstride] = dp;
-            const cd* fg = f + (int64_t)j0 * fs;
+            if (g > 0) ck[(int64_t)(g - 1) * kWave] = dp;
+            const cd* fg = f + 3 * (int64_t)j0;
+            const cd* bg = rb + j0 * rs;
             if (g < nfull) {
 #pragma unroll
-                for (int u = 0; u < kSpecGroup; ++u)
-                    dp = cmad(ldg(fg + u * fs + 1), dp, cmul(ldg(rb + j0 + u), ldg(fg + u * fs)));
+                for (int u = 0; u < kSpecGroup; ++u) dp = spec_step(fg + 3 * u, bg + u * rs, dp);
             } else {
-                for (int u = 0; j0 + u < n; ++u)
-                    dp = cmad(ldg(fg + u * fs + 1), dp, cmul(ldg(rb + j0 + u), ldg(fg + u * fs)));
+                for (int u = 0; j0 + u < n; ++u) dp = spec_step(fg + 3 * u, bg + u * rs, dp);
             }
         }
         // backward sweep group by group: recompute the group's d' from its
@@ -142,38 +243,39 @@ __global__ void __launch_bounds__(64) energy_spectrum_kernel(SpecArgs a)
         cd phi = czero();
         for (int g = ng - 1; g >= 0; --g) {
             const int j0 = g * kSpecGroup;
-            const cd* fg = f + (int64_t)j0 * fs;
-            cd x = g > 0 ? ck[(int64_t)(g - 1) * ckstride] : czero();
+            const cd* fg = f + 3 * (int64_t)j0;
+            const cd* bg = rb + j0 * rs;
+            cd x = g > 0 ? ck[(int64_t)(g - 1) * kWave] : czero();
+            cd dd[kSpecGroup];
             if (g < nfull) {
-                cd dd[kSpecGroup];
 #pragma unroll
                 for (int u = 0; u < kSpecGroup; ++u) {
-                    x = cmad(ldg(fg + u * fs + 1), x, cmul(ldg(rb + j0 + u), ldg(fg + u * fs)));
+                    x = spec_step(fg + 3 * u, bg + u * rs, x);
                     dd[u] = x;
                 }
 #pragma unroll
                 for (int u = kSpecGroup - 1; u >= 0; --u) {
-                    phi = cmad(ldg(fg + u * fs + 2), phi, dd[u]);
+                    phi = cmad(scalar_load(fg + 3 * u + 2), phi, dd[u]);
                     acc = fma(phi.re, phi.re, fma(phi.im, phi.im, acc));
                 }
             } else {
-                cd dd[kSpecGroup];
 #pragma unroll
                 for (int u = 0; u < kSpecGroup; ++u) {
-                    if (j0 + u < n)
-                        x = cmad(ldg(fg + u * fs + 1), x, cmul(ldg(rb + j0 + u), ldg(fg + u * fs)));
+                    if (j0 + u < n) x = spec_step(fg + 3 * u, bg + u * rs, x);
                     dd[u] = x;
                 }
 #pragma unroll
                 for (int u = kSpecGroup - 1; u >= 0; --u) {
                     if (j0 + u < n) {
-                        phi = cmad(ldg(fg + u * fs + 2), phi, dd[u]);
+                        phi = cmad(scalar_load(fg + 3 * u + 2), phi, dd[u]);
                         acc = fma(phi.re, phi.re, fma(phi.im, phi.im, acc));
                     }
                 }
             }
         }
-        if (valid) a.out[(int64_t)b * a.n_energy + ei] = a.eps / M_PI * a.classes[d.cls].dx * acc;
+        if (valid)
+            a.out[(int64_t)a.order[s.start + k] * a.n_energy + e] =
+                a.eps / M_PI * a.classes[s.cls].dx * acc;
     }
 }
 
@@ -314,8 +416,12 @@ hipError_t launch_gabor(const GaborArgs& a, hipStream_t st)
 
 hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL(spectrum_factor_kernel, dim3((a.pairs + 255) / 256), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(spectrum_rhs_kernel, dim3((a.n_max + 255) / 256, std::min(a.batch, 65535)),
+    const size_t vbytes = sizeof(double) * (size_t)a.n_max;
+    if (vbytes > (size_t)kMaxLds) return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spectrum_factor_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    hipLaunchKernelGGL(spectrum_factor_kernel, dim3(a.pairs), dim3(kWave), vbytes, st, a);
+    hipLaunchKernelGGL(spectrum_rhs_kernel, dim3((a.n_max + 3) / 4, std::min(a.nblocks, 65535)),
                        dim3(256), 0, st, a);
     hipLaunchKernelGGL(energy_spectrum_kernel, dim3((unsigned)(a.lanes / kWave)), dim3(kWave), 0, st, a);
     return hipGetLastError();

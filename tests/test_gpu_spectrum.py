@@ -53,6 +53,37 @@ def test_energy_spectrum_matches_oracle(lib, torch_dev, lanes):
     plan.close()
 
 
+@pytest.mark.parametrize("lanes", [None, 64])
+def test_energy_spectrum_blocks_of_many_systems(lib, torch_dev, lanes):
+    """Sizes with more systems than a wavefront has lanes (a full block, a
+    ragged second block) next to a size with a few: every system against the
+    oracle, also with one wavefront of lanes striding over every tile."""
+    torch, dev = torch_dev
+    ns = [200] * 70 + [333] * 5 + [128] * 64
+    dx, eps = 0.2, 0.05
+    p = lib.make_params(dx, 0.05, A, 10)
+    plan = lib.Plan(p, ns)
+    psis = [ti.random_state(n, 500 + i, width=min(6.0, n * dx / 8), k0=0.3, dx=dx)
+            for i, n in enumerate(ns)]
+    psi = torch.tensor(np.concatenate([_c2d(x) for x in psis]), device=dev)
+    energies = np.linspace(-0.6, 1.5, 7)
+    E = torch.tensor(energies, device=dev)
+    out = torch.empty(len(ns), len(energies), dtype=torch.float64, device=dev)
+    nbytes = lib.tdse_plan_energy_spectrum_work(plan, len(energies), lanes or 65536)
+    work = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+    print(f"energy spectrum blocks: {len(ns)} systems, work lanes={lanes}", flush=True)
+    lib.tdse_plan_energy_spectrum(plan, psi, E, eps, out, work)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    worst = 0.0
+    for b, n in enumerate(ns):
+        ref = oracle.energy_spectrum(psis[b], energies, eps, dx, A)
+        worst = max(worst, np.max(np.abs(got[b] - ref)) / np.max(ref))
+    print(f"  max err / max P = {worst:.3e}", flush=True)
+    assert worst < 1e-10
+    plan.close()
+
+
 def test_eigenstate_lorentzian_and_small_workspace(lib, torch_dev):
     torch, dev = torch_dev
     n, dx, eps = 512, 0.2, 1e-3
