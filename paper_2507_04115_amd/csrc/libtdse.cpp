@@ -518,9 +518,13 @@ constexpr int kTabOrder[3] = {kTabLds, kTabOmLds, kTabGlobal};
 // Systems per workgroup and table placement for a class: as many systems as
 // fit in 1024 lanes whose registers and LDS fit one workgroup per CU, point
 // tables in LDS whenever they fit.  Returns false if nothing fits.
-bool choose_packing(int C, int T, int count, bool adjoint, int* S_out, int* tab_out, int* occ_out)
+bool choose_packing(int C, int T, int count, bool adjoint, int* S_out, int* tab_out, int* occ_out,
+                    bool stored = false)
 {
     int smax = std::max(1, std::min(1024 / T, count));
+    // the adjoint prefers workgroups of at most 512 threads, whose instances
+    // have twice the registers (TDSE_ADJ_WIDE=1: up to 1024, experiments)
+    if (adjoint && T <= 512 && !env_int("TDSE_ADJ_WIDE", 0)) smax = std::max(1, std::min(512 / T, count));
     const int fs = env_int("TDSE_PACK_S", 0);          // experiment overrides
     const int fl = env_int("TDSE_PACK_LDS", -1);
     if (fs > 0) smax = std::min(smax, fs);
@@ -531,7 +535,7 @@ bool choose_packing(int C, int T, int count, bool adjoint, int* S_out, int* tab_
         for (int S = smax; S >= 1; --S) {
             const size_t sh = adjoint ? adjoint_smem_bytes(C, T, S, lds) : fwd_smem(C, T, S, tab);
             if (sh > (size_t)kMaxLds) continue;
-            const int occ = adjoint ? adjoint_occupancy(C, T, S, lds) : fwd_occupancy(C, T, S, tab);
+            const int occ = adjoint ? adjoint_occupancy(C, T, S, lds, stored) : fwd_occupancy(C, T, S, tab);
             if (occ >= 1) {
                 *S_out = S;
                 *tab_out = tab;
@@ -956,7 +960,7 @@ tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int coun
 {
     *rate = 0.0;
     int S = 1, occ = 0, tab = kTabGlobal;
-    if (!choose_packing(L.C, L.T, count, true, &S, &tab, &occ)) return TDSE_OK;
+    if (!choose_packing(L.C, L.T, count, true, &S, &tab, &occ, stored)) return TDSE_OK;
     const bool lds = tab == kTabLds;
     const int P = std::max(1, std::min(count, S * occ * num_cus()));
     const int nt = kProbeSteps, K = 16;
@@ -1108,9 +1112,18 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, bool 
         const int smax = std::max(1, std::min(1024 / L.T, count));
         for (int tab : kTabOrder) {
             if (!forward_tab_supported(C, tab)) continue;
+            // the two widest packings that fit, and the widest one of the
+            // narrow instances (at most 512 threads) when they differ
+            std::vector<int> cand;
+            for (int S = smax; S >= 1 && cand.size() < 2; --S)
+                if (fwd_occupancy(C, L.T, S, tab) >= 1) cand.push_back(S);
+            const int sn = std::min(512 / L.T, count);
+            if (sn >= 1 && forward_narrow(C, sn * L.T) &&
+                std::find(cand.begin(), cand.end(), sn) == cand.end() &&
+                fwd_occupancy(C, L.T, sn, tab) >= 1)
+                cand.push_back(sn);
             int tried = 0;
-            for (int S = smax; S >= 1 && tried < 2; --S) {
-                if (fwd_occupancy(C, L.T, S, tab) < 1) continue;
+            for (int S : cand) {
                 double r = 0.0;
                 tdse_status rc = probe_forward(p, n, L, S, tab, count, st, &r);
                 if (rc != TDSE_OK) return rc;
@@ -1119,7 +1132,10 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, bool 
                     std::fprintf(stderr, "[tdse autotune] n=%d C=%d T=%d S=%d tab=%d: %.4e grid-point-steps/s\n",
                                  n, C, L.T, S, tab, r);
                 if (r <= 0.0) continue;
-                const double cost = 1.0 / r + adj_cost;
+                // narrow instances (2 waves per SIMD) come out of the short
+                // probe up to 5 % better than over whole runs (focus workload:
+                // +5 % in the probe, -4 % over the run): they must win by 6 %
+                const double cost = (forward_narrow(C, S * L.T) ? 1.06 : 1.0) / r + adj_cost;
                 // fewer systems per workgroup (tried after more) must win by
                 // more than the probe's noise: over whole runs the wider
                 // workgroup, which shares its staged tables, was 1.5 % faster
@@ -1504,7 +1520,7 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         if (adjoint_k > 0) {
             int aocc = 0;
             int atab = kTabGlobal;
-            if (!choose_packing(L.C, L.T, L.count, true, &L.aS, &atab, &aocc))
+            if (!choose_packing(L.C, L.T, L.count, true, &L.aS, &atab, &aocc, store))
                 return bail(fail(TDSE_E_UNSUPPORTED, "adjoint layout C=%d T=%d does not fit", L.C, L.T));
             L.alds = atab == kTabLds;
             L.agrid = std::min((L.count + L.aS - 1) / L.aS, aocc * num_cus());
@@ -1641,7 +1657,7 @@ tdse_status tdse_plan_kernel_info(tdse_plan plan, int32_t n, int32_t* workgroup_
     if (grid) *grid = g.grid;
     if (workgroups_per_cu) *workgroups_per_cu = forward_occupancy(g.C, g.threads, g.smem, g.tab);
     if (lds_bytes) *lds_bytes = (int32_t)g.smem;
-    if (vgprs) *vgprs = forward_vgprs(g.C, g.tab, ab);
+    if (vgprs) *vgprs = forward_vgprs(g.C, g.tab, ab, g.threads);
     return TDSE_OK;
 }
 

@@ -191,14 +191,21 @@ __device__ __forceinline__ void source_grad_streamed(cd (&kap)[C], cd& kgl, cd& 
 // kernel, the costate is parked in the slot while a segment is recomputed
 // and psi^i is read point by point at every chunk length, which leaves room
 // for the pivot factors in registers up to 8 points per lane.
-template <int C, bool LDSTAB, bool AB = false, bool REV = false>
-__global__ void __launch_bounds__(1024) adjoint_kernel(FwdArgs a)
+// NARROW: workgroups of at most 512 threads (2 waves per SIMD, 256
+// registers per lane) instead of 1024 (4 waves, 128).  The adjoint holds the
+// costate, the pivot factors and the recomputed state together; at 128
+// registers the 8-point layout spilled about 80 of them per lane.
+template <int C, bool LDSTAB, bool AB = false, bool REV = false, bool NARROW = false>
+__global__ void __launch_bounds__(NARROW ? 512 : 1024) adjoint_kernel(FwdArgs a)
 {
-    // the costate doubles the chunk state: pivot factors stay in registers
-    // only for 4 points per lane; from 16 points the costate is parked in the
-    // slot while a segment is recomputed, and psi^i is read point by point
-    constexpr bool kAdjQRegs = REV ? C <= 8 : C <= 4;
-    constexpr bool kStream = REV || C >= 16;
+    // the costate doubles the chunk state: at 128 registers the pivot factors
+    // stay in registers only for 4 points per lane, and from 16 points (or in
+    // the reverse-only sweep) the costate is parked in the slot while a
+    // segment is recomputed and psi^i is read point by point.  The narrow
+    // instances (256 registers) keep q in registers up to 8 points and load
+    // psi^i ahead of the costate step, so its latency overlaps the step.
+    constexpr bool kAdjQRegs = (REV || NARROW) ? C <= 8 : C <= 4;
+    constexpr bool kStream = (REV && !NARROW) || C >= 16;
     extern __shared__ double smem_raw[];
     const SizeClass sc = uniform_load(a.classes + a.cls);
     const int T = sc.T, W = T / kWave, np = C * T;
@@ -445,39 +452,53 @@ size_t adjoint_smem_bytes(int C, int T, int S, bool lds_tables)
            16;
 }
 
-template <int C, bool L>
+template <int C, bool L, bool REV, bool NARROW>
 static int occ_adj(int threads, size_t sh)
 {
     int nb = 0;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(adjoint_kernel<C, L>),
+    void (*k)(FwdArgs) = adjoint_kernel<C, L, false, REV, NARROW>;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     hipFuncAttributes fa;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(adjoint_kernel<C, L>)) != hipSuccess ||
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k)) != hipSuccess ||
         threads > fa.maxThreadsPerBlock)
         return 0;  // beyond the kernel's launch bounds
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, adjoint_kernel<C, L>, threads, sh) !=
-        hipSuccess)
-        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, threads, sh) != hipSuccess) return 0;
     return nb;
 }
 
-int adjoint_occupancy(int C, int T, int S, bool lds_tables)
+template <bool REV, bool NARROW>
+static int adjoint_occupancy_t(int C, int th, size_t sh, bool lds_tables)
 {
-    const size_t sh = adjoint_smem_bytes(C, T, S, lds_tables);
-    if (sh > (size_t)kMaxLds) return 0;
-    const int th = S * T;
     switch (C * 2 + (lds_tables ? 1 : 0)) {
-        case 8: return occ_adj<4, false>(th, sh);
-        case 9: return occ_adj<4, true>(th, sh);
-        case 16: return occ_adj<8, false>(th, sh);
-        case 17: return occ_adj<8, true>(th, sh);
-        case 32: return occ_adj<16, false>(th, sh);
-        case 33: return occ_adj<16, true>(th, sh);
+        case 8: return occ_adj<4, false, REV, NARROW>(th, sh);
+        case 9: return occ_adj<4, true, REV, NARROW>(th, sh);
+        case 16: return occ_adj<8, false, REV, NARROW>(th, sh);
+        case 17: return occ_adj<8, true, REV, NARROW>(th, sh);
+        case 32: return occ_adj<16, false, REV, NARROW>(th, sh);
+        case 33: return occ_adj<16, true, REV, NARROW>(th, sh);
         default: return 0;
     }
 }
 
-template <bool REV>
+bool adjoint_narrow(int threads) { return threads <= 512; }
+
+int adjoint_occupancy(int C, int T, int S, bool lds_tables, bool stored)
+{
+    const size_t sh = adjoint_smem_bytes(C, T, S, lds_tables);
+    if (sh > (size_t)kMaxLds) return 0;
+    const int th = S * T;
+    // a plan with stored checkpoints launches both instances with one
+    // packing: the reverse-only one bounds it
+    if (adjoint_narrow(th)) {
+        if (stored && adjoint_occupancy_t<true, true>(C, th, sh, lds_tables) < 1) return 0;
+        return adjoint_occupancy_t<false, true>(C, th, sh, lds_tables);
+    }
+    if (stored && adjoint_occupancy_t<true, false>(C, th, sh, lds_tables) < 1) return 0;
+    return adjoint_occupancy_t<false, false>(C, th, sh, lds_tables);
+}
+
+template <bool REV, bool NARROW>
 static hipError_t launch_adjoint_t(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
                                    hipStream_t st)
 {
@@ -488,14 +509,14 @@ static hipError_t launch_adjoint_t(int C, bool lds_tables, const FwdArgs& a, int
     // the 256 on-axis systems of the full focal volume (N = 8192), so that
     // layout always forms them.
     switch (C * 4 + (lds_tables ? 2 : 0) + (a.ab && C > 8 ? 1 : 0)) {
-        case 16: hipLaunchKernelGGL((adjoint_kernel<4, false, false, REV>), dim3(grid), b, sh, st, a); break;
-        case 18: hipLaunchKernelGGL((adjoint_kernel<4, true, false, REV>), dim3(grid), b, sh, st, a); break;
-        case 32: hipLaunchKernelGGL((adjoint_kernel<8, false, false, REV>), dim3(grid), b, sh, st, a); break;
-        case 34: hipLaunchKernelGGL((adjoint_kernel<8, true, false, REV>), dim3(grid), b, sh, st, a); break;
-        case 64: hipLaunchKernelGGL((adjoint_kernel<16, false, false, REV>), dim3(grid), b, sh, st, a); break;
-        case 65: hipLaunchKernelGGL((adjoint_kernel<16, false, true, REV>), dim3(grid), b, sh, st, a); break;
-        case 66: hipLaunchKernelGGL((adjoint_kernel<16, true, false, REV>), dim3(grid), b, sh, st, a); break;
-        case 67: hipLaunchKernelGGL((adjoint_kernel<16, true, true, REV>), dim3(grid), b, sh, st, a); break;
+        case 16: hipLaunchKernelGGL((adjoint_kernel<4, false, false, REV, NARROW>), dim3(grid), b, sh, st, a); break;
+        case 18: hipLaunchKernelGGL((adjoint_kernel<4, true, false, REV, NARROW>), dim3(grid), b, sh, st, a); break;
+        case 32: hipLaunchKernelGGL((adjoint_kernel<8, false, false, REV, NARROW>), dim3(grid), b, sh, st, a); break;
+        case 34: hipLaunchKernelGGL((adjoint_kernel<8, true, false, REV, NARROW>), dim3(grid), b, sh, st, a); break;
+        case 64: hipLaunchKernelGGL((adjoint_kernel<16, false, false, REV, NARROW>), dim3(grid), b, sh, st, a); break;
+        case 65: hipLaunchKernelGGL((adjoint_kernel<16, false, true, REV, NARROW>), dim3(grid), b, sh, st, a); break;
+        case 66: hipLaunchKernelGGL((adjoint_kernel<16, true, false, REV, NARROW>), dim3(grid), b, sh, st, a); break;
+        case 67: hipLaunchKernelGGL((adjoint_kernel<16, true, true, REV, NARROW>), dim3(grid), b, sh, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -504,8 +525,12 @@ static hipError_t launch_adjoint_t(int C, bool lds_tables, const FwdArgs& a, int
 hipError_t launch_adjoint(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
                           hipStream_t st)
 {
-    if (a.mode == kAdjReverseOnly) return launch_adjoint_t<true>(C, lds_tables, a, T, S, grid, st);
-    return launch_adjoint_t<false>(C, lds_tables, a, T, S, grid, st);
+    const bool nar = adjoint_narrow(S * T);
+    if (a.mode == kAdjReverseOnly)
+        return nar ? launch_adjoint_t<true, true>(C, lds_tables, a, T, S, grid, st)
+                   : launch_adjoint_t<true, false>(C, lds_tables, a, T, S, grid, st);
+    return nar ? launch_adjoint_t<false, true>(C, lds_tables, a, T, S, grid, st)
+               : launch_adjoint_t<false, false>(C, lds_tables, a, T, S, grid, st);
 }
 
 // Reorders the systems of one launch so that rows with a non-zero abar come

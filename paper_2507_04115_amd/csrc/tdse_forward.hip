@@ -51,9 +51,19 @@ constexpr int kFwdPlain = 0;
 constexpr int kFwdPop = 1;
 constexpr int kFwdStore = 2;
 
-template <int C, int TAB, bool AB = false, int X = kFwdPlain>
-__global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
+// NARROW: workgroups of at most 512 threads, 2 waves per SIMD with 256
+// registers per lane instead of 4 with 128.  At 8 points per lane the wide
+// instances spill about 20 registers per lane; at 16 the narrow ones also
+// keep the pivot factors in registers, as the shorter chunks do.
+template <int C, bool NARROW>
+struct FwdQRegs {
+    static constexpr bool value = NARROW ? C <= 16 : QInRegs<C>::value;
+};
+
+template <int C, int TAB, bool AB = false, int X = kFwdPlain, bool NARROW = false>
+__global__ void __launch_bounds__(NARROW ? 512 : 1024) forward_kernel(FwdArgs a)
 {
+    constexpr bool QREG = FwdQRegs<C, NARROW>::value;
     constexpr bool POP = X == kFwdPop;
     constexpr bool STORE = X == kFwdStore;
     constexpr int NV = POP ? 6 : 3;                   // ring values per wavefront and sample
@@ -144,10 +154,10 @@ __global__ void __launch_bounds__(1024) forward_kernel(FwdArgs a)
         cd gl = (active && s > 0 && s - 1 < n) ? ld_psi(src, s - 1) : czero();
         cd gr = (active && s + C < n) ? ld_psi(src, s + C) : czero();
 
-        LaneFactors<C, QInRegs<C>::value, AB> f;
+        LaneFactors<C, QREG, AB> f;
         {
             const StepView<TAB> sv = step_view<TAB>(clsp, wsys, tab);
-            f = load_factors<C, QInRegs<C>::value, AB>(sv.sc, sv.lc);
+            f = load_factors<C, QREG, AB>(sv.sc, sv.lc);
             if constexpr (POP)
                 observe_pop<C>(v, sv.tb, T, sv.lc, sv.xs, dx, n_pop, phi, a.pop_radius, sm.ring);
             else
@@ -333,21 +343,23 @@ hipError_t launch_reset_counters(int32_t* counters, int n, hipStream_t st)
 
 bool layout_supported(int C) { return C == 4 || C == 8 || C == 12 || C == 16; }
 
-template <int C, int TAB>
+template <int C, int TAB, bool NARROW = false>
 static int occ_fwd(int threads, size_t sh)
 {
     int nb = 0;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(forward_kernel<C, TAB>),
+    void (*k)(FwdArgs) = forward_kernel<C, TAB, false, kFwdPlain, NARROW>;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     hipFuncAttributes fa;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(forward_kernel<C, TAB>)) != hipSuccess ||
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k)) != hipSuccess ||
         threads > fa.maxThreadsPerBlock)
         return 0;  // beyond the kernel's launch bounds
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, forward_kernel<C, TAB>, threads, sh) !=
-        hipSuccess)
-        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, threads, sh) != hipSuccess) return 0;
     return nb;
 }
+
+// Layouts with narrow instances, used for workgroups of at most 512 threads.
+bool forward_narrow(int C, int threads) { return (C == 8 || C == 16) && threads <= 512; }
 
 // Instantiated layouts: C in {4, 8, 12, 16} with tables in global memory or
 // in LDS; om alone in LDS only for 12 and 16 points per lane (the grids whose
@@ -362,6 +374,16 @@ bool forward_tab_supported(int C, int tab)
 int forward_occupancy(int C, int threads, size_t smem, int tab)
 {
     if (smem > (size_t)kMaxLds || threads < kWave || threads > 1024 || threads % kWave) return 0;
+    if (forward_narrow(C, threads)) {
+        switch (C * 4 + tab) {
+            case 32: return occ_fwd<8, kTabGlobal, true>(threads, smem);
+            case 33: return occ_fwd<8, kTabLds, true>(threads, smem);
+            case 64: return occ_fwd<16, kTabGlobal, true>(threads, smem);
+            case 65: return occ_fwd<16, kTabLds, true>(threads, smem);
+            case 66: return occ_fwd<16, kTabOmLds, true>(threads, smem);
+            default: return 0;
+        }
+    }
     switch (C * 4 + tab) {
         case 16: return occ_fwd<4, kTabGlobal>(threads, smem);
         case 17: return occ_fwd<4, kTabLds>(threads, smem);
@@ -377,17 +399,27 @@ int forward_occupancy(int C, int threads, size_t smem, int tab)
     }
 }
 
-template <int C, int TAB, bool AB>
+template <int C, int TAB, bool AB, bool NARROW = false>
 static int regs_fwd()
 {
     hipFuncAttributes fa;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(forward_kernel<C, TAB, AB>)) != hipSuccess)
-        return 0;
+    void (*k)(FwdArgs) = forward_kernel<C, TAB, AB, kFwdPlain, NARROW>;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k)) != hipSuccess) return 0;
     return fa.numRegs;
 }
 
-int forward_vgprs(int C, int tab, bool ab)
+int forward_vgprs(int C, int tab, bool ab, int threads)
 {
+    if (forward_narrow(C, threads)) {
+        switch (C * 4 + tab) {
+            case 32: return regs_fwd<8, kTabGlobal, false, true>();
+            case 33: return regs_fwd<8, kTabLds, false, true>();
+            case 64: return regs_fwd<16, kTabGlobal, false, true>();
+            case 65: return regs_fwd<16, kTabLds, false, true>();
+            case 66: return regs_fwd<16, kTabOmLds, false, true>();
+            default: return 0;
+        }
+    }
     if (C >= 12 && ab) {
         switch (C * 4 + tab) {
             case 48: return regs_fwd<12, kTabGlobal, true>();
@@ -419,6 +451,18 @@ static hipError_t launch_forward_t(int C, int tab, const FwdArgs& a, int threads
                                    int grid, hipStream_t st)
 {
     const dim3 b(threads);
+    // narrow instances hold q in registers and form the elimination factors
+    if (forward_narrow(C, threads)) {
+        switch (C * 4 + tab) {
+            case 32: hipLaunchKernelGGL((forward_kernel<8, kTabGlobal, false, X, true>), dim3(grid), b, smem, st, a); break;
+            case 33: hipLaunchKernelGGL((forward_kernel<8, kTabLds, false, X, true>), dim3(grid), b, smem, st, a); break;
+            case 64: hipLaunchKernelGGL((forward_kernel<16, kTabGlobal, false, X, true>), dim3(grid), b, smem, st, a); break;
+            case 65: hipLaunchKernelGGL((forward_kernel<16, kTabLds, false, X, true>), dim3(grid), b, smem, st, a); break;
+            case 66: hipLaunchKernelGGL((forward_kernel<16, kTabOmLds, false, X, true>), dim3(grid), b, smem, st, a); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     // 12 and 16 points per lane: elimination factors from their tables
     // (a.ab) or formed from q and om
     if (C >= 12 && a.ab) {

@@ -214,13 +214,22 @@ size_t sub_smem_bytes(int W);
 // when it does not fit or the combination is not instantiated).
 bool forward_tab_supported(int C, int tab);
 int forward_occupancy(int C, int threads, size_t smem, int tab);
-// Vector registers per lane of the forward kernel instance (0 if not instantiated).
-int forward_vgprs(int C, int tab, bool ab);
+// Vector registers per lane of the forward kernel instance launched with
+// `threads` per workgroup (0 if not instantiated).
+int forward_vgprs(int C, int tab, bool ab, int threads);
+// Whether workgroups of `threads` run the narrow instance (at most 512
+// threads, 256 registers per lane, pivot factors in registers).
+bool forward_narrow(int C, int threads);
 hipError_t launch_forward(int C, int tab, const FwdArgs& a, int threads, size_t smem, int grid,
                           hipStream_t st);
 
 size_t adjoint_smem_bytes(int C, int T, int S, bool lds_tables);
-int adjoint_occupancy(int C, int T, int S, bool lds_tables);
+// Workgroups per CU of the adjoint kernel; `stored`: the packing must also
+// fit the reverse-only instance (plans with stored checkpoints).
+int adjoint_occupancy(int C, int T, int S, bool lds_tables, bool stored);
+// Workgroups of at most 512 threads run the instances with 256 registers per
+// lane (2 waves per SIMD); wider ones those with 128 (4 waves per SIMD).
+bool adjoint_narrow(int threads);
 hipError_t launch_adjoint(int C, bool lds_tables, const FwdArgs& a, int T, int S, int grid,
                           hipStream_t st);
 
