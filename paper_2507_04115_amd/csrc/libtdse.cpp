@@ -967,7 +967,9 @@ tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int coun
     const int grid = std::min((P + S - 1) / S, occ * num_cus());
     const int64_t rec = 2 * (int64_t)(L.C + 2) * L.T;
     const int64_t ck = rec * (nt / K + 1) + ((nt + 2) & ~int64_t(1));  // checkpoints + norm row
-    const int64_t slot = (stored ? rec : rec + ck) + 2 * (int64_t)L.C * L.T * (K + 1);
+    // the two-chain reverse sweep (narrow, up to 8 points) keeps two segment buffers
+    const int nbuf = (stored && adjoint_narrow(S * L.T) && L.C <= 8) ? 2 : 1;
+    const int64_t slot = (stored ? rec : rec + ck) + nbuf * 2 * (int64_t)L.C * L.T * (K + 1);
     const size_t b_store = stored ? sizeof(double) * (size_t)ck * P : 0;
     const size_t b_soff = stored ? ((sizeof(int64_t) * (size_t)P + 255) & ~size_t(255)) : 0;
     ClassSet cs;
@@ -1530,7 +1532,10 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
             const int64_t ck = rec * nseg + ((nt + 2) & ~int64_t(1));  // checkpoints + norm row
             // a slot holds the segment states and one parked costate record, and
             // the checkpoints unless they are stored per system
-            L.slot_doubles = recs * (adjoint_k + 1) + rec + (store ? 0 : ck);
+            // the two-chain reverse sweep (narrow, up to 8 points per lane)
+            // keeps a second segment buffer after the parked costate
+            const int nbuf = (store && adjoint_narrow(L.aS * L.T) && L.C <= 8) ? 2 : 1;
+            L.slot_doubles = nbuf * recs * (adjoint_k + 1) + rec + (store ? 0 : ck);
             L.work_off = adj_total;
             adj_total += L.slot_doubles * (int64_t)L.agrid * L.aS;
             if (store)

@@ -184,6 +184,214 @@ __device__ __forceinline__ void source_grad_streamed(cd (&kap)[C], cd& kgl, cd& 
     }
 }
 
+// ------------------------------------------------------------ two chains
+// The reverse-only sweep advances two independent Crank-Nicolson chains at
+// once: the costate of one segment and the recomputation of the segment
+// before it.  They share the lane layout, the tables and the carry window
+// products, and each carry scan takes one barrier for both, so the two
+// chains' instructions interleave in one stream (twice the independent work
+// per wavefront at 2 waves per SIMD).  scan_fwd2, scan_bwd2 and cn_apply2
+// are scan_fwd, scan_bwd and cn_apply applied to both chains, operation for
+// operation, so each chain's results are bitwise those of the single form.
+__device__ __forceinline__ void scan_fwd2(cd& z1, cd& z2, cd a0, cd a1, cd aw, const SizeClass& sc,
+                                          const LaneCtx& lc, cd* lds1, cd* lds2, cd& out1,
+                                          cd& out2)
+{
+    const unsigned off = 16u * (unsigned)lc.t;
+    if (sc.levels > 0) {
+        z1 = cmad(a0, wave_shr1(z1), z1);
+        z2 = cmad(a0, wave_shr1(z2), z2);
+    }
+    if (sc.levels > 1) {
+        z1 = cmad(a1, wave_shr1(wave_shr1(z1)), z1);
+        z2 = cmad(a1, wave_shr1(wave_shr1(z2)), z2);
+    }
+    for (int lev = 2; lev < sc.levels; ++lev) {
+        const int d = 1 << lev;
+        const cd zs1 = shfl_up_c(z1, d), zs2 = shfl_up_c(z2, d);
+        const cd p = ld_lane(sc.lt.pa + lev * sc.T, off);
+        if (lc.lane >= d) {
+            z1 = cmad(p, zs1, z1);
+            z2 = cmad(p, zs2, z2);
+        }
+    }
+    cd prev1 = czero(), prev2 = czero();
+    if (lc.W > 1 && lc.lane == kWave - 1) {
+        lds1[lc.wave] = z1;
+        lds2[lc.wave] = z2;
+    }
+    __syncthreads();
+    if (lc.W > 1) {
+        const int v0 = max(0, lc.wave - sc.xwaves);
+        if (v0 < lc.wave) {
+            prev1 = lds1[v0];
+            prev2 = lds2[v0];
+            for (int w = v0 + 1; w < lc.wave; ++w) {
+                const cd pw = ldg(sc.lt.pw + w * kWave + kWave - 1);
+                prev1 = cmad(pw, prev1, lds1[w]);
+                prev2 = cmad(pw, prev2, lds2[w]);
+            }
+        }
+        z1 = cmad(aw, prev1, z1);
+        z2 = cmad(aw, prev2, z2);
+    }
+    out1 = wave_shr1_keep(z1, prev1);
+    out2 = wave_shr1_keep(z2, prev2);
+}
+
+__device__ __forceinline__ void scan_bwd2(cd& y1, cd& y2, cd b0, cd b1, cd bw, const SizeClass& sc,
+                                          const LaneCtx& lc, cd* lds1, cd* lds2, cd& out1,
+                                          cd& out2)
+{
+    const unsigned off = 16u * (unsigned)lc.t;
+    if (sc.levels > 0) {
+        y1 = cmad(b0, wave_shl1(y1), y1);
+        y2 = cmad(b0, wave_shl1(y2), y2);
+    }
+    if (sc.levels > 1) {
+        y1 = cmad(b1, wave_shl1(wave_shl1(y1)), y1);
+        y2 = cmad(b1, wave_shl1(wave_shl1(y2)), y2);
+    }
+    for (int lev = 2; lev < sc.levels; ++lev) {
+        const int d = 1 << lev;
+        const cd ys1 = shfl_down_c(y1, d), ys2 = shfl_down_c(y2, d);
+        const cd p = ld_lane(sc.lt.qb + lev * sc.T, off);
+        if (lc.lane + d < kWave) {
+            y1 = cmad(p, ys1, y1);
+            y2 = cmad(p, ys2, y2);
+        }
+    }
+    cd next1 = czero(), next2 = czero();
+    if (lc.W > 1 && lc.lane == 0) {
+        lds1[lc.wave] = y1;
+        lds2[lc.wave] = y2;
+    }
+    __syncthreads();
+    if (lc.W > 1) {
+        const int v1 = min(lc.W - 1, lc.wave + sc.xwaves);
+        if (v1 > lc.wave) {
+            next1 = lds1[v1];
+            next2 = lds2[v1];
+            for (int w = v1 - 1; w > lc.wave; --w) {
+                const cd qw = ldg(sc.lt.qw + w * kWave);
+                next1 = cmad(qw, next1, lds1[w]);
+                next2 = cmad(qw, next2, lds2[w]);
+            }
+        }
+        y1 = cmad(bw, next1, y1);
+        y2 = cmad(bw, next2, y2);
+    }
+    out1 = wave_shl1_keep(y1, next1);
+    out2 = wave_shl1_keep(y2, next2);
+}
+
+// cn_apply (real time, q in registers) on two chunk states.
+template <int C, class TV, class LF>
+__device__ __forceinline__ void cn_apply2(cd (&v1)[C], cd& gl1, cd& gr1, cd (&v2)[C], cd& gl2,
+                                          cd& gr2, const LF& f, const TV& tb, const SizeClass& sc,
+                                          const LaneCtx& lc, const RhsCoef rc, cd* lf1, cd* lb1,
+                                          cd* lf2, cd* lb2)
+{
+    static_assert(LF::kRegs, "two chains need the pivot factors in registers");
+    constexpr bool RT = true;
+    const int b0 = lc.b0;
+    const unsigned off = 16u * (unsigned)lc.t;
+    const double oml = tb.om(lc.il());
+    const double omr = tb.om(lc.ir());
+    cd a0 = czero(), a1 = czero(), aw = czero();
+    // A. right-hand sides in place, chunk-end values with zero carry-in
+    cd ze1 = czero(), ze2 = czero();
+    {
+        double om_p = oml;
+        double om_c = tb.om(b0);
+        cd gp1 = gfac<RT>(oml, gl1), gp2 = gfac<RT>(oml, gl2);
+        cd gc1 = gfac<RT>(om_c, v1[0]), gc2 = gfac<RT>(om_c, v2[0]);
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            if (k == C / 2) {
+                if (sc.levels > 0) a0 = ld_lane(sc.lt.pa, off);
+                if (sc.levels > 1) a1 = ld_lane(sc.lt.pa + sc.T, off);
+                if (lc.lane < (1 << sc.levels)) aw = ld_lane(sc.lt.pw, off);
+            }
+            const double om_n = (k + 1 < C) ? tb.om(b0 + 64 * (k + 1)) : omr;
+            const cd al = f.template alpha<RT>(k, om_p, sc, lc);
+            const cd gn1 = gfac<RT>(om_n, (k + 1 < C) ? v1[k + 1] : gr1);
+            const cd gn2 = gfac<RT>(om_n, (k + 1 < C) ? v2[k + 1] : gr2);
+            const cd gh1 = gfac<RT>(om_c + rc.dofs10, v1[k]);
+            const cd gh2 = gfac<RT>(om_c + rc.dofs10, v2[k]);
+            const cd r1 = mkc(fma(10.0, gh1.re, gp1.re + gn1.re), fma(10.0, gh1.im, gp1.im + gn1.im));
+            const cd r2 = mkc(fma(10.0, gh2.re, gp2.re + gn2.re), fma(10.0, gh2.im, gp2.im + gn2.im));
+            v1[k] = r1;
+            v2[k] = r2;
+            ze1 = (k == 0) ? r1 : cmad(al, ze1, r1);
+            ze2 = (k == 0) ? r2 : cmad(al, ze2, r2);
+            gp1 = gc1;
+            gc1 = gn1;
+            gp2 = gc2;
+            gc2 = gn2;
+            om_p = om_c;
+            om_c = om_n;
+            point_fence(ze1, ze2);
+        }
+    }
+    cd cf1, cf2;
+    scan_fwd2(ze1, ze2, a0, a1, aw, sc, lc, lf1, lf2, cf1, cf2);
+    cd b0c = czero(), b1c = czero(), bw = czero();
+    if (sc.levels > 0) b0c = ld_lane(sc.lt.qb, off);
+    if (sc.levels > 1) b1c = ld_lane(sc.lt.qb + sc.T, off);
+    if (lc.lane > kWave - 1 - (1 << sc.levels)) bw = ld_lane(sc.lt.qw, off);
+    // B. forward recurrences from the exact carries, w = q z
+    {
+        cd z1 = cf1, z2 = cf2;
+        double om_p = oml;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const cd al = f.template alpha<RT>(k, om_p, sc, lc);
+            const cd qk = f.q(k, sc, lc);
+            z1 = cmad(al, z1, v1[k]);
+            z2 = cmad(al, z2, v2[k]);
+            v1[k] = cmul(qk, z1);
+            v2[k] = cmul(qk, z2);
+            if (k + 1 < C) om_p = tb.om(b0 + 64 * k);
+            point_fence(v1[k], v2[k]);
+        }
+    }
+    // C. chunk-start values with zero carry-in
+    cd yb1 = v1[C - 1], yb2 = v2[C - 1];
+#pragma unroll
+    for (int k = C - 2; k >= 0; --k) {
+        const cd be = f.template beta<RT>(k, tb.om(b0 + 64 * (k + 1)), sc, lc);
+        yb1 = cmad(be, yb1, v1[k]);
+        yb2 = cmad(be, yb2, v2[k]);
+        point_fence(yb1, yb2);
+    }
+    cd cb1, cb2;
+    scan_bwd2(yb1, yb2, b0c, b1c, bw, sc, lc, lb1, lb2, cb1, cb2);
+    // D. backward recurrences from the exact carries
+    double om_0;
+    {
+        cd y1 = cb1, y2 = cb2;
+        double om_n = omr;
+#pragma unroll
+        for (int k = C - 1; k >= 0; --k) {
+            const cd be = f.template beta<RT>(k, om_n, sc, lc);
+            y1 = cmad(be, y1, v1[k]);
+            y2 = cmad(be, y2, v2[k]);
+            v1[k] = y1;
+            v2[k] = y2;
+            om_n = tb.om(b0 + 64 * k);
+            point_fence(y1, y2);
+        }
+        om_0 = om_n;
+    }
+    const cd ql = f.ql(sc, lc);
+    const cd e0 = elim<RT>(om_0, ql);
+    gl1 = cmad(ql, cf1, cmul(e0, v1[0]));
+    gl2 = cmad(ql, cf2, cmul(e0, v2[0]));
+    gr1 = cb1;
+    gr2 = cb2;
+}
+
 }  // namespace
 
 // REV: the reverse sweep alone (tdse_adjoint_batch_stored: the checkpoints
@@ -206,6 +414,9 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) adjoint_kernel(FwdArgs a)
     // psi^i ahead of the costate step, so its latency overlaps the step.
     constexpr bool kAdjQRegs = (REV || NARROW) ? C <= 8 : C <= 4;
     constexpr bool kStream = (REV && !NARROW) || C >= 16;
+    // the narrow reverse-only sweep runs the costate and the recomputation
+    // as two chains in one instruction stream (two segment buffers)
+    constexpr bool kDual = REV && NARROW && C <= 8;
     extern __shared__ double smem_raw[];
     const SizeClass sc = uniform_load(a.classes + a.cls);
     const int T = sc.T, W = T / kWave, np = C * T;
@@ -333,6 +544,110 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) adjoint_kernel(FwdArgs a)
 #pragma unroll
         for (int k = 0; k < C; ++k) kap[k] = czero();
         cd kgl = czero(), kgr = czero();
+        if constexpr (kDual) {
+        // ---- two chains: while the costate runs backwards through segment
+        // sidx (read from one segment buffer), the segment before it is
+        // recomputed into the other.  In the reverse-only sweep the ring
+        // holds one value per wavefront and sample (the gradient partials),
+        // so its upper part carries the second chain's carry slots.
+        cd* const lf2 = reinterpret_cast<cd*>(ring + kRing * W);
+        cd* const lb2 = lf2 + W;
+        double* const seg2 = kbuf + np2;
+        auto buf = [&](int sx) { return (sx & 1) ? seg2 : seg; };
+        if (wg_need) {
+            // the last segment is recomputed alone
+            const int sl = nseg - 1;
+            const int s0l = sl * K, s1l = min(s0l + K, nt);
+            load_state<C>(ckpt + np2 * sl, T, loff, v, gl, gr);
+            store_chunk<C>(buf(sl), T, loff, v);
+            for (int i = s0l; i < s1l; ++i) {
+                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
+                forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
+                                sm.lds_f, sm.lds_b);
+                store_chunk<C>(buf(sl) + nps * (i - s0l + 1), T, loff, v);
+            }
+            {
+                // kappa^nt = 2 abar_nt dx (V' + E_nt) conj(psi^nt), psi^nt = v
+                // with the ghosts of its stored record
+                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
+                __syncthreads();
+                chunk_ghosts<C>(reinterpret_cast<const cd*>(buf(sl) + nps * (s1l - s0l)), T, t, loff,
+                                gl, gr);
+                add_source<C>(kap, kgl, kgr, v, gl, gr, 2.0 * abar[nt] * dx, erow[nt], sv.tb, T,
+                              sv.lc);
+                if (nt > 0) grad_partial<C>(kap, v, sv.xs, dx, sv.lc, ring + ((nt - 1) % kRing) * W);
+                if (nt > 0 && (nt - 1) % kFlush == 0) {
+                    __syncthreads();
+                    if (active && need_grad)
+                        flush_grad(nt - 1, nt - 1, t, T, ring, W, a.dt, abar, n_row, g_row, flag);
+                }
+            }
+            // one costate step i: kappa <- U (D_i kappa) + source(psi^i), and
+            // the partial of grad_{i-1}; psi^i read from its record first
+            auto costate_tail = [&](int i, int s0, const double* bc) {
+                const double e = erow[i];
+                const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
+                cd pv[C], pgl, pgr;
+                load_chunk<C>(bc + nps * (i - s0), T, t, loff, pv, pgl, pgr);
+                phase_mask<C, !kAdjQRegs>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc, sv.lc);
+                cn_apply<C, true>(kap, kgl, kgr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
+                add_source<C>(kap, kgl, kgr, pv, pgl, pgr, 2.0 * abar[i] * dx, e, sv.tb, T, sv.lc);
+                if (i > 0) grad_partial<C>(kap, pv, sv.xs, dx, sv.lc, ring + ((i - 1) % kRing) * W);
+            };
+            auto grad_flush = [&](int i) {
+                if (i > 0 && (i - 1) % kFlush == 0) {
+                    __syncthreads();
+                    if (active && need_grad)
+                        flush_grad(i - 1, min(i - 1 + kFlush - 1, nt - 1), t, T, ring, W, a.dt,
+                                   abar, n_row, g_row, flag);
+                }
+            };
+            for (int sidx = sl; sidx >= 0; --sidx) {
+                const int s0 = sidx * K, s1 = min(s0 + K, nt);
+                const int ncost = s1 - s0;           // costate steps of segment sidx
+                const int nrec = sidx > 0 ? K : 0;   // recompute steps of segment sidx - 1
+                const int r0 = s0 - K;
+                const double* const bc = buf(sidx);
+                double* const br = buf(sidx + 1);    // the other buffer
+                if (nrec > 0) {
+                    load_state<C>(ckpt + np2 * (sidx - 1), T, loff, v, gl, gr);
+                    store_chunk<C>(br, T, loff, v);
+                }
+                const int both = min(ncost, nrec);
+                for (int it = 0; it < both; ++it) {
+                    const int i = s1 - 1 - it, ir = r0 + it;
+                    const double e = erow[i];
+                    const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
+                    cd pv[C], pgl, pgr;
+                    load_chunk<C>(bc + nps * (i - s0), T, t, loff, pv, pgl, pgr);
+                    phase_mask<C, !kAdjQRegs>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc,
+                                              sv.lc);
+                    cn_apply2<C>(kap, kgl, kgr, v, gl, gr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f,
+                                 sm.lds_b, lf2, lb2);
+                    phase_mask<C, !kAdjQRegs>(v, gl, gr, erow[ir], a.dt, sv.xl, dx, f.mflags, sv.sc,
+                                              sv.lc);
+                    store_chunk<C>(br + nps * (it + 1), T, loff, v);
+                    add_source<C>(kap, kgl, kgr, pv, pgl, pgr, 2.0 * abar[i] * dx, e, sv.tb, T,
+                                  sv.lc);
+                    if (i > 0)
+                        grad_partial<C>(kap, pv, sv.xs, dx, sv.lc, ring + ((i - 1) % kRing) * W);
+                    grad_flush(i);
+                }
+                // the costate alone (segment 0 has no segment before it)
+                for (int it = both; it < ncost; ++it) {
+                    costate_tail(s1 - 1 - it, s0, bc);
+                    grad_flush(s1 - 1 - it);
+                }
+                // the recomputation alone (after a last segment shorter than K)
+                for (int it = both; it < nrec; ++it) {
+                    const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
+                    forward_step<C>(v, gl, gr, f, erow[r0 + it], a.dt, sv.xl, sv.tb, sv.sc, sv.lc,
+                                    sv.rc, sm.lds_f, sm.lds_b);
+                    store_chunk<C>(br + nps * (it + 1), T, loff, v);
+                }
+            }
+        }
+        } else {
         bool started = false;
         for (int sidx = wg_need ? nseg - 1 : -1; sidx >= 0; --sidx) {
             const int s0 = sidx * K;
@@ -410,6 +725,7 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) adjoint_kernel(FwdArgs a)
                 }
             }
         }
+        }  // single chain
         if (active && !need_grad && a.mode != kAdjForwardOnly)
             for (int i = t; i <= nt; i += T) g_row[i] = 0.0;
         __syncthreads();
