@@ -343,6 +343,27 @@ def energy_spectrum(psi, energies, eps, dx, a, z=1.0):
     return out
 
 
+def energy_integral(energies, spectrum, e_lo):
+    """int_{E >= e_lo} P(E) dE by the trapezoid rule over the grid points
+    E_e >= e_lo (section "Analysing the Time-Dependent Electron Energy
+    Density": integrated over the energies above the ionisation threshold,
+    e_lo = 0, the distribution of psi(t) gives the time-dependent ionisation
+    probability).  energies increasing; spectrum [..., n_energy]."""
+    e = np.asarray(energies, np.float64)
+    p = np.asarray(spectrum, np.float64)
+    total = np.zeros(p.shape[:-1])
+    for q in range(len(e) - 1):
+        if e[q] >= e_lo and e[q + 1] >= e_lo:
+            total = total + 0.5 * (e[q + 1] - e[q]) * (p[..., q] + p[..., q + 1])
+    return total
+
+
+def ionisation_probability(psi, energies, eps, dx, a, z=1.0):
+    """The time-dependent ionisation probability of a state: its energy
+    distribution integrated over E >= 0 on the given grid."""
+    return energy_integral(energies, energy_spectrum(psi, energies, eps, dx, a, z), 0.0)
+
+
 # --------------------------------------------------------------------------
 # driver-field resampling (Fourier zero-padding)
 # --------------------------------------------------------------------------
