@@ -362,6 +362,22 @@ tdse_status tdse_plan_energy_spectrum(tdse_plan plan, const double* psi, int32_t
 tdse_status tdse_plan_energy_spectrum_work(tdse_plan plan, int32_t n_energy, int64_t lanes,
                                            size_t* bytes);
 
+/* Integral of energy distributions over E >= e_lo by the trapezoid rule
+ * over the grid points at or above e_lo (section "Analysing the
+ * Time-Dependent Electron Energy Density": with e_lo = 0 the distribution
+ * of psi(t) integrates to the time-dependent ionisation probability; over
+ * the whole grid, to the norm up to the Lorentzian tails):
+ *   out[b] = sum over e with E_e >= e_lo and E_{e+1} >= e_lo of
+ *            (E_{e+1} - E_e) (P[b][e] + P[b][e+1]) / 2
+ *   energies dev [n_energy], increasing (not checked: it is device data);
+ *   spectrum dev [batch][n_energy] (e.g. from tdse_plan_energy_spectrum);
+ *   out dev [batch]
+ * Fails with TDSE_E_INVALID before any launch for batch < 1, n_energy < 2,
+ * a non-finite e_lo other than -inf, or a NULL pointer.  Asynchronous on
+ * `stream`; allocates nothing. */
+tdse_status tdse_energy_integral(int32_t batch, int32_t n_energy, const double* energies,
+                                 const double* spectrum, double e_lo, double* out, void* stream);
+
 /* Gabor transform of the source term (section "Physical Examples &
  * tutorials", the microscopic analysis: a joint time-frequency picture of
  * the dipole acceleration):

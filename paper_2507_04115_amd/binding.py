@@ -89,6 +89,7 @@ _PROTOS = {
     "tdse_plan_stored_state": (_i32, [_vp, ctypes.c_uint64, _i32, _vp, _vp]),
     "tdse_plan_populations": (_i32, [_vp, ctypes.c_uint64, _vp, _d, _vp, _vp, _vp]),
     "tdse_gabor": (_i32, [_i32, _i32, _d, _vp, _i32, _vp, _i32, _vp, _d, _vp, _vp]),
+    "tdse_energy_integral": (_i32, [_i32, _i32, _vp, _vp, _d, _vp, _vp]),
     "tdse_resample_field": (_i32, [_i32, _i32, _d, _d, _i32, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "tdse_band_dft": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
     "tdse_band_dft_adjoint": (_i32, [_i32, _i32, _d, _d, _d, _d, _vp, _vp, _vp]),
@@ -516,6 +517,17 @@ def tdse_gabor(accel, dt: float, t_centres, omegas, sigma: float, out, stream=No
     _check(load().tdse_gabor(batch, n1 - 1, float(dt), _ptr(accel), int(t_centres.numel()),
                              _ptr(t_centres), int(omegas.numel()), _ptr(omegas), float(sigma),
                              _ptr(out), _stream(stream)), "tdse_gabor")
+
+
+def tdse_energy_integral(energies, spectrum, e_lo: float, out, stream=None):
+    """out[b] = trapezoid integral of spectrum[b] over the grid points E >= e_lo
+    (e_lo = 0: the ionisation probability); see include/libtdse.h."""
+    _f64(energies, spectrum, out)
+    n_e = int(energies.numel())
+    batch = int(out.numel())
+    _need(spectrum, batch * n_e, "spectrum")
+    _check(load().tdse_energy_integral(batch, n_e, _ptr(energies), _ptr(spectrum), float(e_lo),
+                                       _ptr(out), _stream(stream)), "tdse_energy_integral")
 
 
 def tdse_plan_stored_state(plan: Plan, generation: int, index: int, psi_out, stream=None):

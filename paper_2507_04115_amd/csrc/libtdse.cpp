@@ -2341,6 +2341,19 @@ tdse_status tdse_plan_energy_spectrum_work(tdse_plan plan, int32_t n_energy, int
     return TDSE_OK;
 }
 
+tdse_status tdse_energy_integral(int32_t batch, int32_t n_energy, const double* energies,
+                                 const double* spectrum, double e_lo, double* out, void* stream)
+{
+    g_last_error.clear();
+    if (batch < 1 || n_energy < 2) return fail(TDSE_E_INVALID, "need batch >= 1 and n_energy >= 2");
+    if (std::isnan(e_lo) || e_lo == std::numeric_limits<double>::infinity())
+        return fail(TDSE_E_INVALID, "e_lo must be finite or -inf");
+    if (!energies || !spectrum || !out) return fail(TDSE_E_INVALID, "energies, spectrum and out are required");
+    HIP_TRY(launch_energy_integral(batch, n_energy, energies, spectrum, e_lo, out,
+                                   reinterpret_cast<hipStream_t>(stream)));
+    return TDSE_OK;
+}
+
 tdse_status tdse_gabor(int32_t batch, int32_t nt, double dt, const double* accel, int32_t n_tc,
                        const double* t_centres, int32_t n_w, const double* omegas, double sigma,
                        double* out, void* stream)

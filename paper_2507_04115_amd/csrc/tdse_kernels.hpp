@@ -192,6 +192,8 @@ hipError_t launch_energy_spectrum(const SpecArgs& a, hipStream_t st);
 size_t spectrum_factor_bytes(int n_max, int64_t pairs);
 size_t spectrum_slot_bytes(int n_max);
 hipError_t launch_gabor(const GaborArgs& a, hipStream_t st);
+hipError_t launch_energy_integral(int batch, int n_energy, const double* energies,
+                                  const double* spectrum, double e_lo, double* out, hipStream_t st);
 hipError_t launch_populations(const PopArgs& a, hipStream_t st);
 hipError_t launch_stored_state(const SizeClass* classes, const SysDesc* sys, int batch, int n_max,
                                const double* store, const int64_t* store_off, int index,

@@ -279,6 +279,34 @@ __global__ void __launch_bounds__(64) energy_spectrum_kernel(SpecArgs a)
     }
 }
 
+// Trapezoid integral of each row of a spectrum over the grid points at or
+// above e_lo: one wavefront per row, lanes striding over the intervals, a
+// fixed-order wave sum.
+__global__ void __launch_bounds__(kWave) energy_integral_kernel(int32_t n_energy,
+                                                                const double* energies,
+                                                                const double* spectrum,
+                                                                double e_lo, double* out)
+{
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const double* p = spectrum + (int64_t)b * n_energy;
+    double acc = 0.0;
+    for (int q = lane; q + 1 < n_energy; q += kWave) {
+        const double e0 = energies[q], e1 = energies[q + 1];
+        if (e0 >= e_lo && e1 >= e_lo) acc = fma(0.5 * (e1 - e0), p[q] + p[q + 1], acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == kSumLane) out[b] = acc;
+}
+
+hipError_t launch_energy_integral(int batch, int n_energy, const double* energies,
+                                  const double* spectrum, double e_lo, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(energy_integral_kernel, dim3(batch), dim3(kWave), 0, st, n_energy, energies,
+                       spectrum, e_lo, out);
+    return hipGetLastError();
+}
+
 size_t spectrum_factor_bytes(int n_max, int64_t pairs)
 {
     return ((size_t)n_max * (size_t)pairs * 3 * sizeof(cd) + 255) & ~size_t(255);

@@ -114,3 +114,16 @@ def test_resample_validation_before_any_launch():
     for args in bad:
         assert f(*args) == L.TDSE_E_INVALID, args
         assert lib.tdse_last_error().decode()
+
+
+def test_energy_integral_validation_before_any_launch():
+    """tdse_energy_integral refuses an empty batch, a grid of one point, a
+    NaN or +inf threshold and NULL arrays on the host."""
+    lib = L.load()
+    f = lib.tdse_energy_integral
+    assert f(0, 8, 16, 16, 0.0, 16, None) == L.TDSE_E_INVALID
+    assert f(2, 1, 16, 16, 0.0, 16, None) == L.TDSE_E_INVALID
+    assert f(2, 8, 16, 16, float("nan"), 16, None) == L.TDSE_E_INVALID
+    assert f(2, 8, 16, 16, float("inf"), 16, None) == L.TDSE_E_INVALID
+    assert f(2, 8, None, 16, 0.0, 16, None) == L.TDSE_E_INVALID
+    assert "required" in lib.tdse_last_error().decode()

@@ -84,6 +84,52 @@ def test_energy_spectrum_blocks_of_many_systems(lib, torch_dev, lanes):
     plan.close()
 
 
+def test_energy_integral_and_ionisation_probability(lib, torch_dev):
+    """tdse_energy_integral of device spectra against the oracle's trapezoid
+    rule on the same values (threshold inside the grid, at -inf and above
+    it), and the ionisation probability of propagated states end to end
+    against the oracle's (spectrum and integral both on the CPU)."""
+    torch, dev = torch_dev
+    ns = [300, 512, 300]
+    dx, dt, eps = 0.2, 0.05, 0.05
+    nt = 400
+    p = lib.make_params(dx, dt, A, nt, mask_fraction=0.2)
+    plan = lib.Plan(p, ns)
+    rng = np.random.default_rng(4)
+    efield = 0.06 * np.sin(0.25 * np.arange(nt + 1) * dt)[None, :] * (1.0 + 0.3 * rng.random((3, 1)))
+    E = torch.tensor(efield, device=dev)
+    acc = torch.empty_like(E)
+    pf = torch.empty(2 * sum(ns), dtype=torch.float64, device=dev)
+    lib.tdse_propagate_batch(plan, E, None, acc, psi_final=pf)
+    energies = np.linspace(-0.7, 2.5, 161)
+    Eg = torch.tensor(energies, device=dev)
+    spec = torch.empty(len(ns), len(energies), dtype=torch.float64, device=dev)
+    nbytes = lib.tdse_plan_energy_spectrum_work(plan, len(energies), 65536)
+    work = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+    lib.tdse_plan_energy_spectrum(plan, pf, Eg, eps, spec, work)
+    out = torch.empty(len(ns), dtype=torch.float64, device=dev)
+    sp = None
+    for e_lo in (0.0, -np.inf, 0.3, 5.0):
+        lib.tdse_energy_integral(Eg, spec, e_lo, out)
+        torch.cuda.synchronize()
+        sp = spec.cpu().numpy()
+        ref = oracle.energy_integral(energies, sp, e_lo)
+        got = out.cpu().numpy()
+        print(f"energy integral e_lo={e_lo}: {got}", flush=True)
+        assert np.allclose(got, ref, rtol=1e-13, atol=1e-300)
+    lib.tdse_energy_integral(Eg, spec, 0.0, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    psi_f = pf.cpu().numpy().view(np.complex128)
+    off = np.concatenate([[0], np.cumsum(ns)])
+    for b, n in enumerate(ns):
+        ref = oracle.ionisation_probability(psi_f[off[b]:off[b + 1]], energies, eps, dx, A)
+        print(f"  n={n}: ionisation probability {got[b]:.6e} (oracle on the GPU state {ref:.6e})", flush=True)
+        assert abs(got[b] - ref) <= 1e-10 * abs(ref) + 1e-15
+        assert 0.0 < got[b] < 1.0
+    plan.close()
+
+
 def test_eigenstate_lorentzian_and_small_workspace(lib, torch_dev):
     torch, dev = torch_dev
     n, dx, eps = 512, 0.2, 1e-3
