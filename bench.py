@@ -202,6 +202,13 @@ def cpu_model() -> dict:
                           ("Thread(s) per core", "threads_per_core"), ("CPU(s)", "cpus")):
             if key in kv:
                 info[name] = int(kv[key])
+        # the rest of lscpu's identification (the model name alone can be generic)
+        for key, name in (("Vendor ID", "vendor"), ("CPU family", "family"), ("Model", "model_id"),
+                          ("Stepping", "stepping"), ("CPU max MHz", "max_mhz"),
+                          ("L3 cache", "l3_cache"), ("Hypervisor vendor", "hypervisor"),
+                          ("Architecture", "arch")):
+            if key in kv:
+                info[name] = kv[key]
     except Exception:
         pass
     try:
@@ -580,12 +587,13 @@ def main():
         # largest grid, and rows spread over the batch; one per thread
         by_n = np.argsort(np.asarray(w.n_per), kind="stable")
         picks = {int(np.argmax(w.e0)), int(by_n[0]), int(by_n[-1])}
-        picks |= set(np.linspace(0, w.batch - 1, nth).round().astype(int).tolist())
-        rows = np.array(sorted(picks))[:max(nth, 3)]
-        # over a bounded number of segments: about ten seconds per system on
-        # one core at the oracle's rate of a few 1e7 grid-point-steps/s
+        n_rows = min(w.batch, max(32, nth))
+        picks |= set(np.linspace(0, w.batch - 1, n_rows).round().astype(int).tolist())
+        rows = np.array(sorted(picks))[:max(n_rows, 3)]
+        # over a bounded number of segments: about ten seconds of CPU time per
+        # thread at the oracle's rate of a few 1e7 grid-point-steps/s per core
         n_max = max(w.n_per[r] for r in rows)
-        budget = 4.0e8 / n_max
+        budget = 4.0e8 * nth / (len(rows) * n_max)
         cseg, steps_cpu = 0, 0
         while cseg < solve.nseg and (cseg == 0 or steps_cpu + solve.lens[cseg] <= budget):
             steps_cpu += solve.lens[cseg]
@@ -618,11 +626,13 @@ def main():
                                "sample": f"{len(rows)} systems of the same batch (the hottest, the "
                                          f"smallest and largest grid, the rest spread over it), "
                                          f"first {steps_cpu} of {w.nt} steps "
-                                         f"({cseg} of {solve.nseg} segments), one system per "
-                                         f"thread on {nth} threads, {t_cpu:.1f} s",
+                                         f"({cseg} of {solve.nseg} segments), the systems spread "
+                                         f"over {nth} threads, {t_cpu:.1f} s",
                                "single_core_value": float(w.n_per[rows[0]]) * st1 / t1,
                                "cpu": cpu,
-                               "full_workload_estimate_s": float(sum(w.n_per)) * w.nt / (ps_cpu / t_cpu)}
+                               "full_workload_estimate_s": float(sum(w.n_per)) * w.nt / (ps_cpu / t_cpu),
+                               "full_workload_estimate": "extrapolated linearly in grid-point-steps "
+                                                         "from the sample's rate"}
         got = solve.series(rows.tolist(), cseg)
         errs = [float(np.linalg.norm(got[i] - ref["accel"][i]) / np.linalg.norm(ref["accel"][i]))
                 for i in range(len(rows))]

@@ -446,6 +446,49 @@ def test_table_placement_does_not_change_results(lib, torch_dev, monkeypatch):
         plan_f.close()
 
 
+def test_narrow_instances_match_wide_bitwise(lib, torch_dev, monkeypatch):
+    """Workgroups of at most 512 threads run the narrow forward instances
+    (256 registers per lane; at 16 points per lane with q in registers and
+    the elimination factors formed from it).  Packed into 1024-thread
+    workgroups instead, the same systems run the wide instances: plain and
+    population outputs bitwise equal, and within the bar of the oracle."""
+    torch, dev = torch_dev
+    dx, dt, nt = 0.2, 0.05, 300
+    for C, count, narrow_s in ((8, 6, "2"), (16, 8, "4")):
+        ns = [2000] * count
+        efield = ti.sin2_pulse(np.linspace(0.05, 0.08, count), 0.057, 1, dt, nt=nt)
+        monkeypatch.setenv("TDSE_LAYOUT_C", str(C))
+        monkeypatch.delenv("TDSE_PACK_S", raising=False)
+        plan_w, out_w = _run_forward(lib, torch, dev, ns, efield, dx, dt, A_AR)
+        monkeypatch.setenv("TDSE_PACK_S", narrow_s)
+        plan_n, out_n = _run_forward(lib, torch, dev, ns, efield, dx, dt, A_AR)
+        monkeypatch.delenv("TDSE_PACK_S")
+        monkeypatch.delenv("TDSE_LAYOUT_C")
+        kw, kn = plan_w.kernel_info(2000), plan_n.kernel_info(2000)
+        print(f"C={C}: wide {kw.workgroup_lanes} lanes {kw.vgprs} VGPRs, "
+              f"narrow {kn.workgroup_lanes} lanes {kn.vgprs} VGPRs", flush=True)
+        assert plan_n.layout(2000).points_per_lane == C
+        assert kw.workgroup_lanes == 1024 and kn.workgroup_lanes == 512
+        assert kn.vgprs > 128
+        for key in ("accel", "xexp", "norm", "psi_final"):
+            assert np.array_equal(out_n[key], out_w[key]), key
+        assert np.all(out_n["status"] == 0)
+        # the population variant of the same kernels
+        pops = []
+        for plan in (plan_w, plan_n):
+            E = _to_dev(torch, dev, efield)
+            acc, gs, vol = (torch.empty_like(E) for _ in range(3))
+            lib.tdse_propagate_batch_populations(plan, E, None, acc, 5.0, gs, vol)
+            torch.cuda.synchronize()
+            pops.append([t.cpu().numpy() for t in (acc, gs, vol)])
+        for x, y in zip(*pops):
+            assert np.array_equal(x, y)
+        ref = oracle_side.propagate(efield[0], 2000, dx, dt, A_AR, mask_frac=0.1)
+        assert rel(out_n["accel"][0], ref["accel"]) < TOL_ACC
+        plan_w.close()
+        plan_n.close()
+
+
 def test_elimination_factor_source_does_not_change_results(lib, torch_dev, monkeypatch):
     """Layouts without q in registers (16 points per lane forward, 8 and 16
     in the adjoint) read alpha and beta from their tables, or form them from
