@@ -218,6 +218,47 @@ def cpu_model() -> dict:
     return info
 
 
+def adjoint_cpu_leg(wa, g_gpu, h_lo, h_hi, cpu_threads=0) -> dict:
+    """The oracle's gradient of the same loss for a bounded sample of the
+    adjoint workload's systems, one system per thread, each from the
+    oracle's own soft-core fit, ground state, forward pass and loss gradient
+    (no value of the GPU path goes in), timed, and compared with the GPU
+    gradient rows of those systems."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    cpu = cpu_model()
+    nth = cpu_threads or max(1, min(16, cpu["threads_available"]))
+    rows = sorted({int(np.argmax(wa.e0))} |
+                  set(np.linspace(0, wa.batch - 1, nth).round().astype(int).tolist()))[:nth]
+    n = wa.n_per[0]
+    a_ref = oracle.soft_core_for_ip(wa.ip, 2048, wa.dx, dtau=1.0)[0]
+    psi0 = oracle.ground_state(n, wa.dx, a_ref, dtau=1.0, tol=1e-14)[0]
+    e_rows = np.ascontiguousarray(wa.efield(rows=rows))
+    kw = dict(mask_frac=wa.mask_frac, mask_pow=wa.mask_pow)
+
+    def one(i):
+        accel = oracle.propagate(e_rows[i], psi0, wa.dx, wa.dt, a_ref, **kw)["accel"]
+        _, ab = oracle.harmonic_yield(accel[None, :], wa.dt, wa.omega, h_lo, h_hi)
+        g, _ = oracle.adjoint(e_rows[i], psi0, ab[0], wa.dx, wa.dt, a_ref, k=256, **kw)
+        return g
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(nth) as ex:
+        gs = list(ex.map(one, range(len(rows))))
+    t = time.perf_counter() - t0
+    errs = [float(np.linalg.norm(g_gpu[r] - gs[i]) / np.linalg.norm(gs[i])) for i, r in enumerate(rows)]
+    return {"cpu_baseline": {"kind": "oracle", "systems": len(rows), "cores": nth, "seconds": t,
+                             "time_per_gradient_s_extrapolated": t * wa.batch / len(rows),
+                             "extrapolation": "linear in the number of systems (one per thread)",
+                             "sample": f"{len(rows)} systems of the batch (the hottest and the rest "
+                                       f"spread over it), whole pulse ({wa.nt} steps): forward, "
+                                       f"loss gradient and adjoint each, one system per thread"},
+            "parity": {"grad_rel_l2_max": max(errs), "systems_checked": len(rows),
+                       "tolerance": 1e-9,
+                       "oracle_side": "own soft-core fit, ground state, forward and loss gradient"}}
+
+
 def seg_lengths(nt: int, nseg: int):
     """Lengths of nseg consecutive time segments covering nt steps."""
     nseg = max(1, min(nseg, nt)) if nt > 0 else 1
@@ -558,6 +599,13 @@ def main():
                                        "frac_hbm": by_a * 1e-9 / HBM_PEAK_GBS}}
         log(f"adjoint: {ms[True] * 1e-3:.3f} s per gradient with stored checkpoints, "
             f"{ms[False] * 1e-3:.3f} s recomputing them ({wa.batch} systems)")
+        if not args.no_cpu and args.adjoint_workload == "adjoint":
+            out["adjoint"].update(adjoint_cpu_leg(wa, grad.cpu().numpy(), h_lo, h_hi,
+                                                  args.cpu_threads))
+            log(f"adjoint, cpu oracle: {out['adjoint']['cpu_baseline']['seconds']:.1f} s for "
+                f"{out['adjoint']['cpu_baseline']['systems']} systems on "
+                f"{out['adjoint']['cpu_baseline']['cores']} threads; gradient parity max rel-L2 "
+                f"{out['adjoint']['parity']['grad_rel_l2_max']:.2e}")
         plan_a.close()
 
     # ------------------------------------------------- energy distribution
