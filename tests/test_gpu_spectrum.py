@@ -209,6 +209,47 @@ def test_stored_states_along_a_propagation(lib, torch_dev):
     plan.close()
 
 
+def test_time_dependent_ionisation_from_stored_states(lib, torch_dev):
+    """The time-dependent ionisation probability along a pulse: the states a
+    storing forward pass keeps every K steps, their energy distributions and
+    the integral over E >= 0, each on the device, against the oracle's
+    ionisation probability of its own state after the same number of steps."""
+    torch, dev = torch_dev
+    ns = [300, 420]
+    dx, dt, om, nc, K, eps = 0.4, 0.05, 0.25, 2, 37, 0.05
+    nt = ti.n_steps(om, nc, dt)
+    efield = ti.sin2_pulse(np.array([0.12, 0.09]), om, nc, dt, nt=nt)
+    p = lib.make_params(dx, dt, 1.1, nt, mask_fraction=0.2)
+    plan = lib.Plan(p, ns, adjoint_k=K, options=lib.TDSE_OPT_STORE_CHECKPOINTS)
+    E = torch.tensor(efield, device=dev)
+    lib.tdse_propagate_batch(plan, E, None, torch.empty_like(E))
+    gen = plan.checkpoint_generation()
+    off = plan.psi_offsets()
+    energies = np.linspace(-0.8, 2.0, 113)
+    Eg = torch.tensor(energies, device=dev)
+    spec = torch.empty(len(ns), len(energies), dtype=torch.float64, device=dev)
+    work = torch.empty(lib.tdse_plan_energy_spectrum_work(plan, len(energies), 4096) // 8,
+                       dtype=torch.float64, device=dev)
+    prob = torch.empty(len(ns), dtype=torch.float64, device=dev)
+    psi = torch.empty(2 * sum(ns), dtype=torch.float64, device=dev)
+    for index in (0, (nt // K) // 2, nt // K):
+        lib.tdse_plan_stored_state(plan, gen, index, psi)
+        lib.tdse_plan_energy_spectrum(plan, psi, Eg, eps, spec, work)
+        lib.tdse_energy_integral(Eg, spec, 0.0, prob)
+        torch.cuda.synchronize()
+        got = prob.cpu().numpy()
+        for b, n in enumerate(ns):
+            psi0 = oracle_side.ground_state(n, dx, 1.1)  # the oracle's own
+            steps = index * K
+            st = psi0 if steps == 0 else oracle.propagate(
+                efield[b, :steps + 1], psi0, dx, dt, 1.1, mask_frac=0.2, want_psi=True)["psi_final"]
+            ref = oracle.ionisation_probability(st, energies, eps, dx, 1.1)
+            print(f"  step {steps} n={n}: ionisation probability {got[b]:.6e} (oracle {ref:.6e})",
+                  flush=True)
+            assert abs(got[b] - ref) <= 1e-9 * abs(ref) + 1e-15
+    plan.close()
+
+
 def test_populations_along_a_propagation(lib, torch_dev):
     """Ground-state and volumetric populations of every stored state against
     the oracle's populations of the oracle's state after the same number of
