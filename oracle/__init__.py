@@ -22,7 +22,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_PATH = os.path.join(_HERE, "libtdse_ref.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -44,15 +44,15 @@ def _load():
         _b.build()
     lib = ctypes.CDLL(_LIB_PATH)
     d, i = ctypes.c_double, ctypes.c_int
-    lib.ref_grid.argtypes = [i, d, d, d, _dp, _dp, _dp]
-    lib.ref_mask.argtypes = [i, d, d, d, _dp]
-    lib.ref_propagate.argtypes = [i, d, d, d, d, d, d, i, _dp, _dp, _dp, _dp, _dp, _dp]
-    lib.ref_propagate_batch.argtypes = [i, _ip, _i64p, d, d, d, d, d, d, i, _dp, _dp, _dp,
+    lib.tdse_ref_grid.argtypes = [i, d, d, d, _dp, _dp, _dp]
+    lib.tdse_ref_mask.argtypes = [i, d, d, d, _dp]
+    lib.tdse_ref_propagate.argtypes = [i, d, d, d, d, d, d, i, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.tdse_ref_propagate_batch.argtypes = [i, _ip, _i64p, d, d, d, d, d, d, i, _dp, _dp, _dp,
                                         _dp, _dp, i]
-    lib.ref_ground_state.argtypes = [i, d, d, d, d, i, d, _dp, _dp, _ip]
-    lib.ref_soft_core_for_ip.argtypes = [d, i, d, d, d, i, d, d, d, _dp, _dp]
-    lib.ref_adjoint.argtypes = [i, d, d, d, d, d, d, i, _dp, _dp, _dp, i, _dp, _dp]
-    lib.ref_step.argtypes = [i, d, d, d, d, d, d, d, _dp]
+    lib.tdse_ref_ground_state.argtypes = [i, d, d, d, d, i, d, _dp, _dp, _ip]
+    lib.tdse_ref_soft_core_for_ip.argtypes = [d, i, d, d, d, i, d, d, d, _dp, _dp]
+    lib.tdse_ref_adjoint.argtypes = [i, d, d, d, d, d, d, i, _dp, _dp, _dp, i, _dp, _dp]
+    lib.tdse_ref_step.argtypes = [i, d, d, d, d, d, d, d, _dp]
     _lib = lib
     return lib
 
@@ -84,13 +84,13 @@ def grid(n, dx, a=1.0, z=1.0):
     x = np.empty(n)
     v = np.empty(n)
     dv = np.empty(n)
-    _check(_load().ref_grid(n, dx, a, z, _ptr(x), _ptr(v), _ptr(dv)), "ref_grid")
+    _check(_load().tdse_ref_grid(n, dx, a, z, _ptr(x), _ptr(v), _ptr(dv)), "tdse_ref_grid")
     return x, v, dv
 
 
 def mask(n, dx, frac=0.1, power=0.125):
     m = np.empty(n)
-    _check(_load().ref_mask(n, dx, frac, power, _ptr(m)), "ref_mask")
+    _check(_load().tdse_ref_mask(n, dx, frac, power, _ptr(m)), "tdse_ref_mask")
     return m
 
 
@@ -102,8 +102,8 @@ def step(psi, dx, dt, a, z, e, mask_frac=0.0, mask_pow=0.125):
     """One Crank-Nicolson + field step psi^(i) -> psi^(i+1) with E(t_i) = e."""
     n = len(psi)
     out = _c128(psi, n).copy()
-    _check(_load().ref_step(n, dx, dt, a, z, mask_frac, mask_pow, e,
-                            out.ctypes.data_as(_dp)), "ref_step")
+    _check(_load().tdse_ref_step(n, dx, dt, a, z, mask_frac, mask_pow, e,
+                            out.ctypes.data_as(_dp)), "tdse_ref_step")
     return out
 
 
@@ -119,10 +119,10 @@ def propagate(efield, psi0, dx, dt, a, z=1.0, mask_frac=0.1, mask_pow=0.125,
     xe = np.empty(nt + 1)
     nr = np.empty(nt + 1)
     pf = np.empty(n, dtype=np.complex128) if want_psi else None
-    st = _load().ref_propagate(n, dx, dt, a, z, mask_frac, mask_pow, nt, _ptr(efield),
+    st = _load().tdse_ref_propagate(n, dx, dt, a, z, mask_frac, mask_pow, nt, _ptr(efield),
                                psi0.ctypes.data_as(_dp), _ptr(acc), _ptr(xe), _ptr(nr),
                                pf.ctypes.data_as(_dp) if pf is not None else None)
-    _check(st, "ref_propagate")
+    _check(st, "tdse_ref_propagate")
     out = {"accel": acc, "xexp": xe, "norm": nr}
     if want_psi:
         out["psi_final"] = pf
@@ -142,11 +142,11 @@ def propagate_batch(efield, psi0_list, dx, dt, a, z=1.0, mask_frac=0.1, mask_pow
     acc = np.empty((batch, ntp1))
     xe = np.empty((batch, ntp1))
     nr = np.empty((batch, ntp1))
-    st = _load().ref_propagate_batch(batch, n_per.ctypes.data_as(_ip), off.ctypes.data_as(_i64p),
+    st = _load().tdse_ref_propagate_batch(batch, n_per.ctypes.data_as(_ip), off.ctypes.data_as(_i64p),
                                      dx, dt, a, z, mask_frac, mask_pow, ntp1 - 1, _ptr(efield),
                                      psi0.ctypes.data_as(_dp), _ptr(acc), _ptr(xe), _ptr(nr),
                                      nthreads)
-    _check(st, "ref_propagate_batch")
+    _check(st, "tdse_ref_propagate_batch")
     return {"accel": acc, "xexp": xe, "norm": nr}
 
 
@@ -159,9 +159,9 @@ def ground_state(n, dx, a, z=1.0, dtau=1.0, max_iter=20000, tol=1e-13):
     psi = np.empty(n, dtype=np.complex128)
     e = ctypes.c_double()
     it = ctypes.c_int()
-    st = _load().ref_ground_state(n, dx, a, z, dtau, max_iter, tol, psi.ctypes.data_as(_dp),
+    st = _load().tdse_ref_ground_state(n, dx, a, z, dtau, max_iter, tol, psi.ctypes.data_as(_dp),
                                   ctypes.byref(e), ctypes.byref(it))
-    _check(st, "ref_ground_state")
+    _check(st, "tdse_ref_ground_state")
     return psi, e.value, it.value
 
 
@@ -171,9 +171,9 @@ def soft_core_for_ip(ip, n, dx, dtau=1.0, gs_tol=1e-13, gs_max_iter=20000, tol=1
     Returns (a, E_g(a))."""
     a = ctypes.c_double()
     e = ctypes.c_double()
-    st = _load().ref_soft_core_for_ip(ip, n, dx, dtau, gs_tol, gs_max_iter, tol, a_lo, a_hi,
+    st = _load().tdse_ref_soft_core_for_ip(ip, n, dx, dtau, gs_tol, gs_max_iter, tol, a_lo, a_hi,
                                       ctypes.byref(a), ctypes.byref(e))
-    _check(st, "ref_soft_core_for_ip")
+    _check(st, "tdse_ref_soft_core_for_ip")
     return a.value, e.value
 
 
@@ -193,9 +193,9 @@ def adjoint(efield, psi0, abar, dx, dt, a, z=1.0, mask_frac=0.1, mask_pow=0.125,
     psi0 = _c128(psi0, n)
     grad = np.empty(nt + 1)
     acc = np.empty(nt + 1)
-    st = _load().ref_adjoint(n, dx, dt, a, z, mask_frac, mask_pow, nt, _ptr(efield),
+    st = _load().tdse_ref_adjoint(n, dx, dt, a, z, mask_frac, mask_pow, nt, _ptr(efield),
                              psi0.ctypes.data_as(_dp), _ptr(abar), k, _ptr(grad), _ptr(acc))
-    _check(st, "ref_adjoint")
+    _check(st, "tdse_ref_adjoint")
     return grad, acc
 
 

@@ -1,4 +1,4 @@
-"""Builds the CPU oracle shared library ``oracle/liboracle.so`` with gcc.
+"""Builds the CPU oracle shared library ``oracle/libtdse_ref.so`` with gcc.
 
 Test infrastructure only (see ``oracle/__init__.py``).
 """
@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tdse_ref.c")
-LIB = os.path.join(HERE, "liboracle.so")
+LIB = os.path.join(HERE, "libtdse_ref.so")
 
 
 def build(verbose: bool = False) -> str:

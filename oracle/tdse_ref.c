@@ -66,7 +66,7 @@ static const double kPi = 3.14159265358979323846264338327950288;
 
 /* x_j = (j - (n-1)/2) dx;  V_j = -z / sqrt(x_j^2 + a^2);
  * dV_j = dV/dx = z x_j (x_j^2 + a^2)^(-3/2).  (Eq. SC potential.) */
-int ref_grid(int n, double dx, double a, double z, double* x, double* v, double* dv)
+int tdse_ref_grid(int n, double dx, double a, double z, double* x, double* v, double* dv)
 {
     if (n < 3 || !(dx > 0.0)) return REF_EINVAL;
     for (int j = 0; j < n; ++j) {
@@ -85,7 +85,7 @@ int ref_grid(int n, double dx, double a, double z, double* x, double* v, double*
  * cos(pi/2 (|x|-x_a)/(x_max-x_a))^power between x_a and x_max, and 0 at
  * |x| >= x_max (the two outermost points).  frac <= 0 disables the mask (all
  * ones); frac must stay below 1/2. */
-int ref_mask(int n, double dx, double frac, double power, double* m)
+int tdse_ref_mask(int n, double dx, double frac, double power, double* m)
 {
     if (n < 3 || !(dx > 0.0) || !(frac < 0.5)) return REF_EINVAL;
     double xmax = 0.5 * (double)(n - 1) * dx;
@@ -276,8 +276,8 @@ static int ctx_init(ref_ctx* c, int n, double dx, double dt, double a, double z,
         ctx_free(c);
         return REF_ENOMEM;
     }
-    ref_grid(n, dx, a, z, c->x, c->v, c->dv);
-    ref_mask(n, dx, mask_frac, mask_pow, c->m);
+    tdse_ref_grid(n, dx, a, z, c->x, c->v, c->dv);
+    tdse_ref_mask(n, dx, mask_frac, mask_pow, c->m);
     build_cn(n, dx, c->v, I * (0.5 * dt), &c->L, &c->R);
     return REF_OK;
 }
@@ -297,7 +297,7 @@ static void step_forward(ref_ctx* c, double e, cplx* psi)
 /* psi0, psi_final: interleaved (re, im), n complex values.  efield: nt+1
  * samples E(t_i), t_i = i dt.  accel (required), xexp, norm: nt+1 samples;
  * xexp, norm, psi_final may be NULL. */
-int ref_propagate(int n, double dx, double dt, double a, double z, double mask_frac,
+int tdse_ref_propagate(int n, double dx, double dt, double a, double z, double mask_frac,
                   double mask_pow, int nt, const double* efield, const double* psi0,
                   double* accel, double* xexp, double* norm, double* psi_final)
 {
@@ -350,7 +350,7 @@ static void* batch_worker(void* arg)
         pthread_mutex_unlock(&job->lock);
         if (p >= job->batch) break;
         size_t row = (size_t)p * (size_t)(job->nt + 1);
-        int st = ref_propagate(job->n_per[p], job->dx, job->dt, job->a, job->z, job->mask_frac,
+        int st = tdse_ref_propagate(job->n_per[p], job->dx, job->dt, job->a, job->z, job->mask_frac,
                                job->mask_pow, job->nt, job->efield + row,
                                job->psi0 + 2 * job->psi_off[p], job->accel + row,
                                job->xexp ? job->xexp + row : NULL,
@@ -364,7 +364,7 @@ static void* batch_worker(void* arg)
     return NULL;
 }
 
-int ref_propagate_batch(int batch, const int* n_per, const int64_t* psi_off, double dx,
+int tdse_ref_propagate_batch(int batch, const int* n_per, const int64_t* psi_off, double dx,
                         double dt, double a, double z, double mask_frac, double mask_pow, int nt,
                         const double* efield, const double* psi0, double* accel, double* xexp,
                         double* norm, int nthreads)
@@ -409,7 +409,7 @@ static double dx_norm2(int n, double dx, const cplx* psi)
 /* psi_out: interleaved complex (imaginary parts are zero); energy_out:
  * Rayleigh quotient dx <psi, H psi>.  Returns REF_ENOCONV when max_iter
  * iterations do not bring the change of the normalised iterate below tol. */
-int ref_ground_state(int n, double dx, double a, double z, double dtau, int max_iter,
+int tdse_ref_ground_state(int n, double dx, double a, double z, double dtau, int max_iter,
                      double tol, double* psi_out, double* energy_out, int* iters_out)
 {
     if (n < 3 || !(dx > 0.0) || !(dtau > 0.0) || max_iter < 1 || !psi_out) return REF_EINVAL;
@@ -426,7 +426,7 @@ int ref_ground_state(int n, double dx, double a, double z, double dtau, int max_
         st = REF_ENOMEM;
         goto done;
     }
-    ref_grid(n, dx, a, z, x, v, NULL);
+    tdse_ref_grid(n, dx, a, z, x, v, NULL);
     build_cn(n, dx, v, 0.5 * dtau, &L, &R);
     for (int j = 0; j < n; ++j) {
         m2sub[j] = 1.0 / 12.0;
@@ -482,7 +482,7 @@ done:
 /* Soft-core parameter: bisection on a in [a_lo, a_hi] for E_g(a) = -ip
  * (E_g increases with a).  Stops when |E_g(a) + ip| < tol or after 100
  * halvings. */
-int ref_soft_core_for_ip(double ip, int n, double dx, double dtau, double gs_tol,
+int tdse_ref_soft_core_for_ip(double ip, int n, double dx, double dtau, double gs_tol,
                          int gs_max_iter, double tol, double a_lo, double a_hi, double* a_out,
                          double* e_out)
 {
@@ -490,9 +490,9 @@ int ref_soft_core_for_ip(double ip, int n, double dx, double dtau, double gs_tol
     double* psi = (double*)malloc(sizeof(double) * 2 * (size_t)n);
     if (!psi) return REF_ENOMEM;
     double e_lo, e_hi, e_mid = 0.0, mid = a_lo;
-    int st = ref_ground_state(n, dx, a_lo, 1.0, dtau, gs_max_iter, gs_tol, psi, &e_lo, NULL);
+    int st = tdse_ref_ground_state(n, dx, a_lo, 1.0, dtau, gs_max_iter, gs_tol, psi, &e_lo, NULL);
     if (st == REF_OK)
-        st = ref_ground_state(n, dx, a_hi, 1.0, dtau, gs_max_iter, gs_tol, psi, &e_hi, NULL);
+        st = tdse_ref_ground_state(n, dx, a_hi, 1.0, dtau, gs_max_iter, gs_tol, psi, &e_hi, NULL);
     if (st != REF_OK) goto done;
     if (!(e_lo < -ip && e_hi > -ip)) {
         st = REF_EINVAL;
@@ -501,7 +501,7 @@ int ref_soft_core_for_ip(double ip, int n, double dx, double dtau, double gs_tol
     st = REF_ENOCONV;
     for (int k = 0; k < 100; ++k) {
         mid = 0.5 * (a_lo + a_hi);
-        int s2 = ref_ground_state(n, dx, mid, 1.0, dtau, gs_max_iter, gs_tol, psi, &e_mid, NULL);
+        int s2 = tdse_ref_ground_state(n, dx, mid, 1.0, dtau, gs_max_iter, gs_tol, psi, &e_mid, NULL);
         if (s2 != REF_OK) {
             st = s2;
             break;
@@ -537,7 +537,7 @@ done:
  *   grad_nt = abar_nt n_nt.
  * Forward states are recomputed segment by segment from checkpoints stored
  * every `k` steps (k = 1 stores every state).  accel_out may be NULL. */
-int ref_adjoint(int n, double dx, double dt, double a, double z, double mask_frac,
+int tdse_ref_adjoint(int n, double dx, double dt, double a, double z, double mask_frac,
                 double mask_pow, int nt, const double* efield, const double* psi0,
                 const double* abar, int k, double* grad, double* accel_out)
 {
@@ -625,7 +625,7 @@ done:
 /* Single step (exposed for the dense-matrix pin)                             */
 /* ------------------------------------------------------------------------ */
 
-int ref_step(int n, double dx, double dt, double a, double z, double mask_frac, double mask_pow,
+int tdse_ref_step(int n, double dx, double dt, double a, double z, double mask_frac, double mask_pow,
              double e, double* psi)
 {
     ref_ctx c;

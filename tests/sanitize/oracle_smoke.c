@@ -8,24 +8,24 @@
 #include <stdio.h>
 #include <stdlib.h>
 
-int ref_grid(int n, double dx, double a, double z, double* x, double* v, double* dv);
-int ref_mask(int n, double dx, double frac, double power, double* m);
-int ref_propagate(int n, double dx, double dt, double a, double z, double mask_frac,
+int tdse_ref_grid(int n, double dx, double a, double z, double* x, double* v, double* dv);
+int tdse_ref_mask(int n, double dx, double frac, double power, double* m);
+int tdse_ref_propagate(int n, double dx, double dt, double a, double z, double mask_frac,
                   double mask_pow, int nt, const double* efield, const double* psi0,
                   double* accel, double* xexp, double* norm, double* psi_final);
-int ref_propagate_batch(int batch, const int* n_per, const int64_t* psi_off, double dx,
+int tdse_ref_propagate_batch(int batch, const int* n_per, const int64_t* psi_off, double dx,
                         double dt, double a, double z, double mask_frac, double mask_pow, int nt,
                         const double* efield, const double* psi0, double* accel, double* xexp,
                         double* norm, int nthreads);
-int ref_ground_state(int n, double dx, double a, double z, double dtau, int max_iter,
+int tdse_ref_ground_state(int n, double dx, double a, double z, double dtau, int max_iter,
                      double tol, double* psi_out, double* energy_out, int* iters_out);
-int ref_soft_core_for_ip(double ip, int n, double dx, double dtau, double gs_tol,
+int tdse_ref_soft_core_for_ip(double ip, int n, double dx, double dtau, double gs_tol,
                          int gs_max_iter, double tol, double a_lo, double a_hi, double* a_out,
                          double* e_out);
-int ref_adjoint(int n, double dx, double dt, double a, double z, double mask_frac,
+int tdse_ref_adjoint(int n, double dx, double dt, double a, double z, double mask_frac,
                 double mask_pow, int nt, const double* efield, const double* psi0,
                 const double* abar, int k, double* grad, double* accel_out);
-int ref_step(int n, double dx, double dt, double a, double z, double mask_frac, double mask_pow,
+int tdse_ref_step(int n, double dx, double dt, double a, double z, double mask_frac, double mask_pow,
              double e, double* psi);
 
 #define CHECK(cond)                                                   \
@@ -44,19 +44,19 @@ int main(void)
     double* v = malloc(sizeof(double) * n);
     double* dv = malloc(sizeof(double) * n);
     double* m = malloc(sizeof(double) * n);
-    CHECK(ref_grid(n, dx, a, 1.0, x, v, dv) == 0);
-    CHECK(ref_mask(n, dx, 0.1, 0.125, m) == 0);
+    CHECK(tdse_ref_grid(n, dx, a, 1.0, x, v, dv) == 0);
+    CHECK(tdse_ref_mask(n, dx, 0.1, 0.125, m) == 0);
     CHECK(m[0] == 0.0 && m[n - 1] == 0.0 && m[n / 2] == 1.0);
-    CHECK(ref_mask(n, dx, 0.5, 0.125, m) != 0);   /* fraction out of range */
-    CHECK(ref_grid(2, dx, a, 1.0, x, v, dv) != 0);  /* too few points */
+    CHECK(tdse_ref_mask(n, dx, 0.5, 0.125, m) != 0);   /* fraction out of range */
+    CHECK(tdse_ref_grid(2, dx, a, 1.0, x, v, dv) != 0);  /* too few points */
 
     double* psi = malloc(sizeof(double) * 2 * n);
     double e = 0.0;
     int it = 0;
-    CHECK(ref_ground_state(n, dx, a, 1.0, 1.0, 20000, 1e-12, psi, &e, &it) == 0);
+    CHECK(tdse_ref_ground_state(n, dx, a, 1.0, 1.0, 20000, 1e-12, psi, &e, &it) == 0);
     CHECK(e < 0.0 && it > 0);
     double a_fit = 0.0, e_fit = 0.0;
-    CHECK(ref_soft_core_for_ip(0.5792, 64, 0.4, 1.0, 1e-12, 20000, 1e-9, 0.5, 3.0, &a_fit, &e_fit) == 0);
+    CHECK(tdse_ref_soft_core_for_ip(0.5792, 64, 0.4, 1.0, 1e-12, 20000, 1e-9, 0.5, 3.0, &a_fit, &e_fit) == 0);
     CHECK(fabs(e_fit + 0.5792) < 1e-9);
 
     double* ef = malloc(sizeof(double) * (nt + 1));
@@ -69,17 +69,17 @@ int main(void)
     double* xe = malloc(sizeof(double) * (nt + 1));
     double* nr = malloc(sizeof(double) * (nt + 1));
     double* pf = malloc(sizeof(double) * 2 * n);
-    CHECK(ref_propagate(n, dx, dt, a, 1.0, 0.1, 0.125, nt, ef, psi, acc, xe, nr, pf) == 0);
-    CHECK(ref_propagate(n, dx, dt, a, 1.0, 0.1, 0.125, nt, ef, psi, acc, NULL, NULL, NULL) == 0);
-    CHECK(ref_propagate(n, dx, dt, a, 1.0, 0.1, 0.125, 0, ef, psi, acc, xe, nr, pf) == 0);
+    CHECK(tdse_ref_propagate(n, dx, dt, a, 1.0, 0.1, 0.125, nt, ef, psi, acc, xe, nr, pf) == 0);
+    CHECK(tdse_ref_propagate(n, dx, dt, a, 1.0, 0.1, 0.125, nt, ef, psi, acc, NULL, NULL, NULL) == 0);
+    CHECK(tdse_ref_propagate(n, dx, dt, a, 1.0, 0.1, 0.125, 0, ef, psi, acc, xe, nr, pf) == 0);
     double* step_psi = malloc(sizeof(double) * 2 * n);
     for (int j = 0; j < 2 * n; ++j) step_psi[j] = psi[j];
-    CHECK(ref_step(n, dx, dt, a, 1.0, 0.1, 0.125, 0.07, step_psi) == 0);
+    CHECK(tdse_ref_step(n, dx, dt, a, 1.0, 0.1, 0.125, 0.07, step_psi) == 0);
 
     double* grad = malloc(sizeof(double) * (nt + 1));
     for (int k = 1; k <= nt + 2; k += 5)
-        CHECK(ref_adjoint(n, dx, dt, a, 1.0, 0.1, 0.125, nt, ef, psi, abar, k, grad, acc) == 0);
-    CHECK(ref_adjoint(n, dx, dt, a, 1.0, 0.1, 0.125, nt, ef, psi, abar, 0, grad, acc) != 0);
+        CHECK(tdse_ref_adjoint(n, dx, dt, a, 1.0, 0.1, 0.125, nt, ef, psi, abar, k, grad, acc) == 0);
+    CHECK(tdse_ref_adjoint(n, dx, dt, a, 1.0, 0.1, 0.125, nt, ef, psi, abar, 0, grad, acc) != 0);
 
     /* ragged batch on several threads, offsets with gaps */
     const int batch = 5;
@@ -96,11 +96,11 @@ int main(void)
     double* accb = malloc(sizeof(double) * batch * (nt + 1));
     double* xeb = malloc(sizeof(double) * batch * (nt + 1));
     double* nrb = malloc(sizeof(double) * batch * (nt + 1));
-    CHECK(ref_propagate_batch(batch, ns, off, dx, dt, a, 1.0, 0.1, 0.125, nt, efb, buf, accb, xeb,
+    CHECK(tdse_ref_propagate_batch(batch, ns, off, dx, dt, a, 1.0, 0.1, 0.125, nt, efb, buf, accb, xeb,
                               nrb, 3) == 0);
-    CHECK(ref_propagate_batch(batch, ns, off, dx, dt, a, 1.0, 0.1, 0.125, nt, efb, buf, accb, NULL,
+    CHECK(tdse_ref_propagate_batch(batch, ns, off, dx, dt, a, 1.0, 0.1, 0.125, nt, efb, buf, accb, NULL,
                               NULL, 8) == 0);
-    CHECK(ref_propagate_batch(batch, ns, off, dx, dt, a, 1.0, 0.1, 0.125, nt, efb, buf, accb, xeb,
+    CHECK(tdse_ref_propagate_batch(batch, ns, off, dx, dt, a, 1.0, 0.1, 0.125, nt, efb, buf, accb, xeb,
                               nrb, 0) != 0);
 
     free(x); free(v); free(dv); free(m); free(psi); free(ef); free(abar); free(acc); free(xe);

@@ -223,7 +223,7 @@ def test_propagate_batch_equals_single_propagations():
     lib = oracle._load()
     n_per = np.array(ns, np.int32)
     dp = ctypes.POINTER(ctypes.c_double)
-    st = lib.ref_propagate_batch(len(ns), n_per.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+    st = lib.tdse_ref_propagate_batch(len(ns), n_per.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                  off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), dx, dt, a,
                                  1.0, 0.1, 0.125, nt, efield.ctypes.data_as(dp),
                                  buf.ctypes.data_as(dp), acc.ctypes.data_as(dp),
