@@ -1124,12 +1124,10 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, bool 
                 std::find(cand.begin(), cand.end(), sn) == cand.end() &&
                 fwd_occupancy(C, L.T, sn, tab) >= 1)
                 cand.push_back(sn);
-            int tried = 0;
             for (int S : cand) {
                 double r = 0.0;
                 tdse_status rc = probe_forward(p, n, L, S, tab, count, st, &r);
                 if (rc != TDSE_OK) return rc;
-                ++tried;
                 if (env_int("TDSE_TUNE_LOG", 0))
                     std::fprintf(stderr, "[tdse autotune] n=%d C=%d T=%d S=%d tab=%d: %.4e grid-point-steps/s\n",
                                  n, C, L.T, S, tab, r);
