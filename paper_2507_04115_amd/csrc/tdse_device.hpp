@@ -568,16 +568,19 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
     {
         double om_p = oml;
         double om_c = tb.om(b0);
+        double om_n = C > 1 ? tb.om(b0 + 64) : omr;
         cd g_p = gfac<RT>(oml, gl);
         cd g_c = gfac<RT>(om_c, v[0]);
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            if (k == (LF::kRegs ? C / 2 : C - 1)) {
+            if (k == (LF::kRegs ? 3 * C / 4 : C - 1)) {
                 if (sc.levels > 0) a0 = ld_lane(sc.lt.pa, off);
                 if (sc.levels > 1) a1 = ld_lane(sc.lt.pa + sc.T, off);
                 if (lc.lane < (1 << sc.levels)) aw = ld_lane(sc.lt.pw, off);
             }
-            const double om_n = (k + 1 < C) ? tb.om(b0 + 64 * (k + 1)) : omr;
+            // om of the point after next, issued one point ahead of its use
+            const double om_nn = (k + 2 < C) ? tb.om(b0 + 64 * (k + 2)) : omr;
+            TDSE_POINT_FENCE();
             const cd g_n = gfac<RT>(om_n, (k + 1 < C) ? v[k + 1] : gr);
             const cd gh = gfac<RT>(om_c + rc.dofs10, v[k]);
             const cd r = mkc(fma(10.0, gh.re, g_p.re + g_n.re), fma(10.0, gh.im, g_p.im + g_n.im));
@@ -587,6 +590,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
             g_c = g_n;
             om_p = om_c;
             om_c = om_n;
+            om_n = om_nn;
             point_fence(r, ze);
         }
     }
@@ -600,6 +604,7 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         if (lc.lane > kWave - 1 - (1 << sc.levels)) bw = ld_lane(sc.lt.qw, off);
     };
     if constexpr (LF::kRegs) load_bwd_windows();
+    double om_last;  // om_{C-1}, read by sweep B for sweep C
     // B. forward recurrence from the exact carry, w = q z.  When q is read
     // from memory, each sweep hides the chunk base from the optimiser so
     // that it reloads its factors rather than keeping earlier sweeps' values
@@ -611,11 +616,17 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         double om_p = oml;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
+            // om_k for the next point (at the last point, om_{C-1} for sweep
+            // C), issued ahead of this point's work so that its LDS latency
+            // overlaps it
+            const double om_k = tb.om(lcb.b0 + 64 * k);
+            TDSE_POINT_FENCE();
             z = cmad(f.template alpha<RT>(k, om_p, sc, lcb), z, v[k]);
             v[k] = cmul(f.q(k, sc, lcb), z);
-            if (k + 1 < C) om_p = tb.om(lcb.b0 + 64 * k);
+            om_p = om_k;
             point_fence(v[k]);
         }
+        om_last = om_p;
     }
     // C. chunk-start value of y with zero carry-in
     cd yb = v[C - 1];
@@ -623,10 +634,14 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         LaneCtx lcc = lc;
         if constexpr (!LF::kRegs) lcc.b0 = opaque(lc.b0);
         const int bc = lcc.b0;
+        double om_n = LF::kOm ? om_last : 0.0;
 #pragma unroll
         for (int k = C - 2; k >= 0; --k) {
-            const double om_n = LF::kOm ? tb.om(bc + 64 * (k + 1)) : 0.0;
+            // om_k for the next point, issued one point ahead
+            const double om_k = (LF::kOm && k > 0) ? tb.om(bc + 64 * k) : 0.0;
+            TDSE_POINT_FENCE();
             yb = cmad(f.template beta<RT>(k, om_n, sc, lcc), yb, v[k]);
+            om_n = om_k;
             point_fence(yb);
         }
     }
@@ -641,9 +656,12 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         double om_n = omr;
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
+            // om_k for the next point (om_0 for the ghost), issued ahead
+            const double om_k = tb.om(lcd.b0 + 64 * k);
+            TDSE_POINT_FENCE();
             y = cmad(f.template beta<RT>(k, om_n, sc, lcd), y, v[k]);
             v[k] = y;
-            om_n = tb.om(lcd.b0 + 64 * k);
+            om_n = om_k;
             point_fence(y);
         }
         om_0 = om_n;
@@ -833,12 +851,17 @@ __device__ __forceinline__ void observe(const cd (&v)[C], const TV& tb, int T,
                                         const LaneCtx& lc, double xs, double dx, double* slot)
 {
     double sn = 0.0, sk = 0.0, sv = 0.0;
+    double dv = tb.dv(lc.b0);
 #pragma unroll
     for (int k = 0; k < C; ++k) {
+        // dV/dx of the next point, issued one point ahead of its use
+        const double dv_n = k + 1 < C ? tb.dv(lc.b0 + 64 * (k + 1)) : 0.0;
+        TDSE_POINT_FENCE();
         const double p = cabs2(v[k]);
         sn += p;
         sk = fma((double)k, p, sk);
-        sv = fma(tb.dv(lc.b0 + 64 * k), p, sv);
+        sv = fma(dv, p, sv);
+        dv = dv_n;
         point_fence(sv, sn);
     }
     double sx = fma(xs, sn, dx * sk);
