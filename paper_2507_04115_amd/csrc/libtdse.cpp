@@ -748,11 +748,12 @@ std::string tune_key_text(const std::string& arch, const TuneKey& k)
 int fwd_occupancy(int C, int T, int S, int tab);
 
 // A cached choice is used only if it is a layout the plan could have picked.
-bool choice_fits(int n, bool adjoint, const TuneChoice& c)
+bool choice_fits(int n, bool adjoint, bool shared, const TuneChoice& c)
 {
     if (!layout_supported(c.C) || (adjoint && c.C == 12)) return false;
     const Layout L = layout_for(n, c.C);
     if (L.T != c.T || L.T > 1024 || c.S < 1 || c.S * c.T > 1024) return false;
+    if (shared && forward_narrow(c.C, c.S * c.T)) return false;
     if (!forward_tab_supported(c.C, c.tab)) return false;
     if (!(c.rate > 0.0) || !std::isfinite(c.rate)) return false;
     return fwd_occupancy(c.C, c.T, c.S, c.tab) >= 1;
@@ -799,7 +800,7 @@ bool parse_choice(const std::string& line, TuneChoice* out)
 }
 
 // The cached choice for `key`, if the file holds a valid one.
-bool tune_file_lookup(const TuneKey& key, int n, bool adjoint, TuneChoice* out)
+bool tune_file_lookup(const TuneKey& key, int n, bool adjoint, bool shared, TuneChoice* out)
 {
     const std::string path = tune_file();
     if (path.empty()) return false;
@@ -808,7 +809,7 @@ bool tune_file_lookup(const TuneKey& key, int n, bool adjoint, TuneChoice* out)
     auto it = lines.find(tune_key_text(device_arch(), key));
     if (it == lines.end()) return false;
     TuneChoice c;
-    if (!parse_choice(it->second, &c) || !choice_fits(n, adjoint, c)) return false;
+    if (!parse_choice(it->second, &c) || !choice_fits(n, adjoint, shared, c)) return false;
     *out = c;
     return true;
 }
@@ -1073,11 +1074,20 @@ tdse_status probe_adjoint(const tdse_params* p, int n, const Layout& L, int coun
 
 // For plans with the adjoint the score is the time of one forward and one
 // adjoint pass per grid-point-step, with the adjoint's own default packing.
+// shared: the plan holds several sizes, whose classes share 1024-lane
+// workgroups (one persistent launch per lane layout); only candidates that
+// run the wide instances are probed there.  Narrow packings are kept by
+// single-size plans only: in a plan of several sizes a narrow choice for
+// some of them split the forward pass into launches of both instance
+// families, which measured 15 % slower than one family on the uneven
+// workload although the per-size probes favoured the mix.
 tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, bool stored,
-                     hipStream_t st, TuneChoice* out)
+                     bool shared, hipStream_t st, TuneChoice* out)
 {
     // the count field of the key also says which adjoint path the plan takes
-    const int kc = adjoint ? (stored ? -(count + (1 << 29)) : -count) : count;
+    // and whether its classes share workgroups
+    int kc = adjoint ? (stored ? -(count + (1 << 29)) : -count) : count;
+    if (shared) kc = kc >= 0 ? kc + (1 << 28) : kc - (1 << 28);
     const TuneKey key{n, kc, p->dx, p->dt, p->a, p->charge_z, p->mask_fraction, p->mask_power};
     {
         std::lock_guard<std::mutex> g(g_tune_mutex);
@@ -1087,7 +1097,7 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, bool 
             return TDSE_OK;
         }
         TuneChoice c;
-        if (tune_file_lookup(key, n, adjoint, &c)) {
+        if (tune_file_lookup(key, n, adjoint, shared, &c)) {
             g_tune_cache[key] = c;
             *out = c;
             return TDSE_OK;
@@ -1118,9 +1128,10 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, bool 
             // narrow instances (at most 512 threads) when they differ
             std::vector<int> cand;
             for (int S = smax; S >= 1 && cand.size() < 2; --S)
-                if (fwd_occupancy(C, L.T, S, tab) >= 1) cand.push_back(S);
+                if (fwd_occupancy(C, L.T, S, tab) >= 1 && !(shared && forward_narrow(C, S * L.T)))
+                    cand.push_back(S);
             const int sn = std::min(512 / L.T, count);
-            if (sn >= 1 && forward_narrow(C, sn * L.T) &&
+            if (!shared && sn >= 1 && forward_narrow(C, sn * L.T) &&
                 std::find(cand.begin(), cand.end(), sn) == cand.end() &&
                 fwd_occupancy(C, L.T, sn, tab) >= 1)
                 cand.push_back(sn);
@@ -1298,7 +1309,7 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
     for (int c = 0; c < ncls; ++c) {
         if (tune) {
             st = autotune(p, ns[c], ccount[c], adjoint_k > 0,
-                          (options & TDSE_OPT_STORE_CHECKPOINTS) != 0, s0, &tuned[c]);
+                          (options & TDSE_OPT_STORE_CHECKPOINTS) != 0, ncls > 1, s0, &tuned[c]);
             if (st != TDSE_OK) return bail(st);
             lay[c] = {tuned[c].C, tuned[c].T};
         } else {
