@@ -304,6 +304,7 @@ __device__ __forceinline__ void cn_apply2(cd (&v1)[C], cd& gl1, cd& gr1, cd (&v2
     {
         double om_p = oml;
         double om_c = tb.om(b0);
+        double om_n = C > 1 ? tb.om(b0 + 64) : omr;
         cd gp1 = gfac<RT>(oml, gl1), gp2 = gfac<RT>(oml, gl2);
         cd gc1 = gfac<RT>(om_c, v1[0]), gc2 = gfac<RT>(om_c, v2[0]);
 #pragma unroll
@@ -313,7 +314,9 @@ __device__ __forceinline__ void cn_apply2(cd (&v1)[C], cd& gl1, cd& gr1, cd (&v2
                 if (sc.levels > 1) a1 = ld_lane(sc.lt.pa + sc.T, off);
                 if (lc.lane < (1 << sc.levels)) aw = ld_lane(sc.lt.pw, off);
             }
-            const double om_n = (k + 1 < C) ? tb.om(b0 + 64 * (k + 1)) : omr;
+            // om of the point after next, issued one point ahead of its use
+            const double om_nn = (k + 2 < C) ? tb.om(b0 + 64 * (k + 2)) : omr;
+            TDSE_POINT_FENCE();
             const cd al = f.template alpha<RT>(k, om_p, sc, lc);
             const cd gn1 = gfac<RT>(om_n, (k + 1 < C) ? v1[k + 1] : gr1);
             const cd gn2 = gfac<RT>(om_n, (k + 1 < C) ? v2[k + 1] : gr2);
@@ -331,6 +334,7 @@ __device__ __forceinline__ void cn_apply2(cd (&v1)[C], cd& gl1, cd& gr1, cd (&v2
             gc2 = gn2;
             om_p = om_c;
             om_c = om_n;
+            om_n = om_nn;
             point_fence(ze1, ze2);
         }
     }
@@ -340,30 +344,41 @@ __device__ __forceinline__ void cn_apply2(cd (&v1)[C], cd& gl1, cd& gr1, cd (&v2
     if (sc.levels > 0) b0c = ld_lane(sc.lt.qb, off);
     if (sc.levels > 1) b1c = ld_lane(sc.lt.qb + sc.T, off);
     if (lc.lane > kWave - 1 - (1 << sc.levels)) bw = ld_lane(sc.lt.qw, off);
-    // B. forward recurrences from the exact carries, w = q z
+    // B. forward recurrences from the exact carries, w = q z; each point
+    // issues the next one's om load first (at the last point sweep C's)
+    double om_last;
     {
         cd z1 = cf1, z2 = cf2;
         double om_p = oml;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
+            const double om_k = tb.om(b0 + 64 * k);
+            TDSE_POINT_FENCE();
             const cd al = f.template alpha<RT>(k, om_p, sc, lc);
             const cd qk = f.q(k, sc, lc);
             z1 = cmad(al, z1, v1[k]);
             z2 = cmad(al, z2, v2[k]);
             v1[k] = cmul(qk, z1);
             v2[k] = cmul(qk, z2);
-            if (k + 1 < C) om_p = tb.om(b0 + 64 * k);
+            om_p = om_k;
             point_fence(v1[k], v2[k]);
         }
+        om_last = om_p;
     }
-    // C. chunk-start values with zero carry-in
+    // C. chunk-start values with zero carry-in (om one point ahead)
     cd yb1 = v1[C - 1], yb2 = v2[C - 1];
+    {
+        double om_n = om_last;
 #pragma unroll
-    for (int k = C - 2; k >= 0; --k) {
-        const cd be = f.template beta<RT>(k, tb.om(b0 + 64 * (k + 1)), sc, lc);
-        yb1 = cmad(be, yb1, v1[k]);
-        yb2 = cmad(be, yb2, v2[k]);
-        point_fence(yb1, yb2);
+        for (int k = C - 2; k >= 0; --k) {
+            const double om_k = k > 0 ? tb.om(b0 + 64 * k) : 0.0;
+            TDSE_POINT_FENCE();
+            const cd be = f.template beta<RT>(k, om_n, sc, lc);
+            yb1 = cmad(be, yb1, v1[k]);
+            yb2 = cmad(be, yb2, v2[k]);
+            om_n = om_k;
+            point_fence(yb1, yb2);
+        }
     }
     cd cb1, cb2;
     scan_bwd2(yb1, yb2, b0c, b1c, bw, sc, lc, lb1, lb2, cb1, cb2);
@@ -374,12 +389,14 @@ __device__ __forceinline__ void cn_apply2(cd (&v1)[C], cd& gl1, cd& gr1, cd (&v2
         double om_n = omr;
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
+            const double om_k = tb.om(b0 + 64 * k);  // the next point's (om_0 last)
+            TDSE_POINT_FENCE();
             const cd be = f.template beta<RT>(k, om_n, sc, lc);
             y1 = cmad(be, y1, v1[k]);
             y2 = cmad(be, y2, v2[k]);
             v1[k] = y1;
             v2[k] = y2;
-            om_n = tb.om(b0 + 64 * k);
+            om_n = om_k;
             point_fence(y1, y2);
         }
         om_0 = om_n;
