@@ -571,6 +571,9 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         double om_n = C > 1 ? tb.om(b0 + 64) : omr;
         cd g_p = gfac<RT>(oml, gl);
         cd g_c = gfac<RT>(om_c, v[0]);
+        // elimination factors read from their table: the next point's is
+        // issued one point ahead (its L2 latency overlaps this point)
+        cd al_c = czero();
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             if (k == (LF::kRegs ? 3 * C / 4 : C - 1)) {
@@ -580,17 +583,23 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
             }
             // om of the point after next, issued one point ahead of its use
             const double om_nn = (k + 2 < C) ? tb.om(b0 + 64 * (k + 2)) : omr;
+            cd al_n = czero();
+            if constexpr (LF::kTabAB) {
+                if (k + 1 < C) al_n = f.template alpha<RT>(k + 1, 0.0, sc, lc);
+            }
             TDSE_POINT_FENCE();
             const cd g_n = gfac<RT>(om_n, (k + 1 < C) ? v[k + 1] : gr);
             const cd gh = gfac<RT>(om_c + rc.dofs10, v[k]);
             const cd r = mkc(fma(10.0, gh.re, g_p.re + g_n.re), fma(10.0, gh.im, g_p.im + g_n.im));
             v[k] = r;
-            ze = (k == 0) ? r : cmad(f.template alpha<RT>(k, om_p, sc, lc), ze, r);
+            if constexpr (LF::kTabAB) ze = (k == 0) ? r : cmad(al_c, ze, r);
+            else ze = (k == 0) ? r : cmad(f.template alpha<RT>(k, om_p, sc, lc), ze, r);
             g_p = g_c;
             g_c = g_n;
             om_p = om_c;
             om_c = om_n;
             om_n = om_nn;
+            al_c = al_n;
             point_fence(r, ze);
         }
     }
@@ -614,16 +623,32 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         if constexpr (!LF::kRegs) lcb.b0 = opaque(lc.b0);
         cd z = cf;
         double om_p = oml;
+        // factors read from memory (alpha from its table, q): the next
+        // point's issued one point ahead
+        cd al_c = czero(), q_c = czero();
+        if constexpr (LF::kTabAB) al_c = f.template alpha<RT>(0, 0.0, sc, lcb);
+        if constexpr (!LF::kRegs) q_c = f.q(0, sc, lcb);
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             // om_k for the next point (at the last point, om_{C-1} for sweep
             // C), issued ahead of this point's work so that its LDS latency
             // overlaps it
             const double om_k = tb.om(lcb.b0 + 64 * k);
+            cd al_n = czero(), q_n = czero();
+            if constexpr (LF::kTabAB) {
+                if (k + 1 < C) al_n = f.template alpha<RT>(k + 1, 0.0, sc, lcb);
+            }
+            if constexpr (!LF::kRegs) {
+                if (k + 1 < C) q_n = f.q(k + 1, sc, lcb);
+            }
             TDSE_POINT_FENCE();
-            z = cmad(f.template alpha<RT>(k, om_p, sc, lcb), z, v[k]);
-            v[k] = cmul(f.q(k, sc, lcb), z);
+            if constexpr (LF::kTabAB) z = cmad(al_c, z, v[k]);
+            else z = cmad(f.template alpha<RT>(k, om_p, sc, lcb), z, v[k]);
+            if constexpr (LF::kRegs) v[k] = cmul(f.q(k, sc, lcb), z);
+            else v[k] = cmul(q_c, z);
             om_p = om_k;
+            al_c = al_n;
+            q_c = q_n;
             point_fence(v[k]);
         }
         om_last = om_p;
@@ -635,13 +660,22 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         if constexpr (!LF::kRegs) lcc.b0 = opaque(lc.b0);
         const int bc = lcc.b0;
         double om_n = LF::kOm ? om_last : 0.0;
+        cd be_c = czero();
+        if constexpr (LF::kTabAB) be_c = f.template beta<RT>(C - 2, 0.0, sc, lcc);
 #pragma unroll
         for (int k = C - 2; k >= 0; --k) {
-            // om_k for the next point, issued one point ahead
+            // om_k (or the table's beta_{k-1}) for the next point, issued one
+            // point ahead
             const double om_k = (LF::kOm && k > 0) ? tb.om(bc + 64 * k) : 0.0;
+            cd be_n = czero();
+            if constexpr (LF::kTabAB) {
+                if (k > 0) be_n = f.template beta<RT>(k - 1, 0.0, sc, lcc);
+            }
             TDSE_POINT_FENCE();
-            yb = cmad(f.template beta<RT>(k, om_n, sc, lcc), yb, v[k]);
+            if constexpr (LF::kTabAB) yb = cmad(be_c, yb, v[k]);
+            else yb = cmad(f.template beta<RT>(k, om_n, sc, lcc), yb, v[k]);
             om_n = om_k;
+            be_c = be_n;
             point_fence(yb);
         }
     }
@@ -654,14 +688,23 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         if constexpr (!LF::kRegs) lcd.b0 = opaque(lc.b0);
         cd y = cb;
         double om_n = omr;
+        cd be_c = czero();
+        if constexpr (LF::kTabAB) be_c = f.template beta<RT>(C - 1, 0.0, sc, lcd);
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
-            // om_k for the next point (om_0 for the ghost), issued ahead
+            // om_k for the next point (om_0 for the ghost) and the table's
+            // beta_{k-1}, issued ahead
             const double om_k = tb.om(lcd.b0 + 64 * k);
+            cd be_n = czero();
+            if constexpr (LF::kTabAB) {
+                if (k > 0) be_n = f.template beta<RT>(k - 1, 0.0, sc, lcd);
+            }
             TDSE_POINT_FENCE();
-            y = cmad(f.template beta<RT>(k, om_n, sc, lcd), y, v[k]);
+            if constexpr (LF::kTabAB) y = cmad(be_c, y, v[k]);
+            else y = cmad(f.template beta<RT>(k, om_n, sc, lcd), y, v[k]);
             v[k] = y;
             om_n = om_k;
+            be_c = be_n;
             point_fence(y);
         }
         om_0 = om_n;
@@ -690,7 +733,21 @@ __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e,
     gl = cmul(ph, gl);
     if (mflags & 2) gl = cscale(ldg(sc.pt.m + lc.il()), gl);
     ph = cmul(ph, w1);
-    if (BRANCHLESS) {
+    if constexpr (BRANCHLESS && C <= 12) {
+        // the next point's absorber value (L2) issued one point ahead (at 16
+        // points per lane the extra live value costs more spills than the
+        // latency it hides: 14 % slower at N = 16384)
+        double m_c = ldg(sc.pt.m + lc.b0);
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const double m_n = k + 1 < C ? ldg(sc.pt.m + lc.b0 + 64 * (k + 1)) : 0.0;
+            TDSE_POINT_FENCE();
+            v[k] = cscale(m_c, cmul(ph, v[k]));
+            ph = cmul(ph, w1);
+            m_c = m_n;
+            point_fence(v[k], ph);
+        }
+    } else if constexpr (BRANCHLESS) {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             v[k] = cscale(ldg(sc.pt.m + lc.b0 + 64 * k), cmul(ph, v[k]));
