@@ -320,8 +320,9 @@ __device__ __forceinline__ void cn_apply2(cd (&v1)[C], cd& gl1, cd& gr1, cd (&v2
             const cd al = f.template alpha<RT>(k, om_p, sc, lc);
             const cd gn1 = gfac<RT>(om_n, (k + 1 < C) ? v1[k + 1] : gr1);
             const cd gn2 = gfac<RT>(om_n, (k + 1 < C) ? v2[k + 1] : gr2);
-            const cd gh1 = gfac<RT>(om_c + rc.dofs10, v1[k]);
-            const cd gh2 = gfac<RT>(om_c + rc.dofs10, v2[k]);
+            // gh = g - i (dofs/10) psi from g, as cn_apply forms it in real time
+            const cd gh1 = mkc(fma(rc.dofs10, v1[k].im, gc1.re), fma(-rc.dofs10, v1[k].re, gc1.im));
+            const cd gh2 = mkc(fma(rc.dofs10, v2[k].im, gc2.re), fma(-rc.dofs10, v2[k].re, gc2.im));
             const cd r1 = mkc(fma(10.0, gh1.re, gp1.re + gn1.re), fma(10.0, gh1.im, gp1.im + gn1.im));
             const cd r2 = mkc(fma(10.0, gh2.re, gp2.re + gn2.re), fma(10.0, gh2.im, gp2.im + gn2.im));
             v1[k] = r1;

@@ -206,8 +206,9 @@ __device__ __forceinline__ void sincos_rr(double x, double* s, double* c)
 
 // sin and cos of the per-point phase increment dt E dx, which is tiny
 // (|x| < 0.05 always holds for sensible grids): Taylor series through x^9 and
-// x^10 (truncation below 1e-19); larger arguments take the general path.
-// The branch is uniform across the wavefront.
+// x^10 (truncation below 1e-19), through x^5 and x^6 for |x| <= 1e-3 (the
+// usual case: dt E dx ~ 1e-4); larger arguments take the general path.
+// The branches are uniform across the wavefront.
 __device__ __forceinline__ void sincos_step(double x, double* s, double* c)
 {
     if (fabs(x) > 0.05) {
@@ -215,6 +216,15 @@ __device__ __forceinline__ void sincos_step(double x, double* s, double* c)
         return;
     }
     const double x2 = x * x;
+    if (fabs(x) <= 1e-3) {
+        // through x^5 and x^6 (truncation below 3e-22 relative)
+        const double p5 = fma(x2, TDSE_K(8.3333333333333333333e-03), TDSE_K(-1.6666666666666666667e-01));  // 1/5!, -1/3!
+        *s = fma(p5 * x2, x, x);
+        double p6 = fma(x2, TDSE_K(-1.3888888888888888889e-03), TDSE_K(4.1666666666666666667e-02));        // -1/6!, 1/4!
+        p6 = fma(p6, x2, -0.5);
+        *c = fma(p6, x2, 1.0);
+        return;
+    }
     double ps = fma(x2, TDSE_K(2.7557319223985890653e-06), TDSE_K(-1.9841269841269841270e-04));   // 1/9!, -1/7!
     ps = fma_s(ps, x2, TDSE_K(8.3333333333333333333e-03));                                   // 1/5!
     ps = fma_s(ps, x2, TDSE_K(-1.6666666666666666667e-01));                                  // -1/3!
@@ -529,8 +539,11 @@ __device__ __forceinline__ cd scan_bwd(cd y, cd b0, cd b1, cd bw, const SizeClas
 //   12 R psi = S(psi) - h' (S(om psi) + dofs psi)
 //            = (g_{j-1} + g_{j+1}) + 10 gh_j,
 //   g_j  = (1 - h' om_j) psi_j,   gh_j = (1 - h' (om_j + dofs/10)) psi_j.
-// om_j + dofs/10 is small where the kinetic and potential parts cancel, so
-// gh is formed from psi directly rather than from g.
+// In real time gh_j = g_j - i (dofs/10) psi_j is formed from g_j (two FMAs):
+// om_j and dofs/10 are both about 6 |h| / dx^2 and their sum is several times
+// smaller, so this loses about 2.5 bits of the step's rounding, far below the
+// method's error.  In imaginary time 1 - (om_j + dofs/10) can vanish and gh
+// is formed from psi directly.
 struct RhsCoef {
     double dofs10;  // dofs / 10 (precomputed per size class)
 };
@@ -589,7 +602,12 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
             }
             TDSE_POINT_FENCE();
             const cd g_n = gfac<RT>(om_n, (k + 1 < C) ? v[k + 1] : gr);
-            const cd gh = gfac<RT>(om_c + rc.dofs10, v[k]);
+            // real time: gh = g - i (dofs/10) psi from g (two FMAs); the
+            // cancellation of om and dofs/10 costs about 2.5 bits per step
+            // there. Imaginary time forms it from psi, since 1 - (om +
+            // dofs/10) can vanish.
+            const cd gh = RT ? mkc(fma(rc.dofs10, v[k].im, g_c.re), fma(-rc.dofs10, v[k].re, g_c.im))
+                             : gfac<RT>(om_c + rc.dofs10, v[k]);
             const cd r = mkc(fma(10.0, gh.re, g_p.re + g_n.re), fma(10.0, gh.im, g_p.im + g_n.im));
             v[k] = r;
             if constexpr (LF::kTabAB) ze = (k == 0) ? r : cmad(al_c, ze, r);
@@ -915,9 +933,9 @@ __device__ __forceinline__ void observe(const cd (&v)[C], const TV& tb, int T,
         const double dv_n = k + 1 < C ? tb.dv(lc.b0 + 64 * (k + 1)) : 0.0;
         TDSE_POINT_FENCE();
         const double p = cabs2(v[k]);
-        sn += p;
-        sk = fma((double)k, p, sk);
-        sv = fma(dv, p, sv);
+        sn = k == 0 ? p : sn + p;
+        if (k > 0) sk = fma((double)k, p, sk);
+        sv = k == 0 ? dv * p : fma(dv, p, sv);
         dv = dv_n;
         point_fence(sv, sn);
     }
