@@ -574,7 +574,8 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
     const unsigned off = 16u * (unsigned)lc.t;
     const double oml = tb.om(lc.il());
     const double omr = tb.om(lc.ir());
-    // window products of the forward scan, loaded halfway through sweep A
+    // window products of the forward scan, loaded three quarters of the way
+    // through sweep A (at its last point where q is read from memory)
     cd a0 = czero(), a1 = czero(), aw = czero();
     // A. right-hand side in place, chunk-end value of z with zero carry-in
     cd ze = czero();
