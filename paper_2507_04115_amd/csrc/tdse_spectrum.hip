@@ -241,11 +241,15 @@ __global__ void __launch_bounds__(64) energy_spectrum_kernel(SpecArgs a)
         // start value, then walk it backwards accumulating |phi|^2
         double acc = 0.0;
         cd phi = czero();
+        // each group's start value is read one group ahead, so that its
+        // memory latency overlaps the group before it
+        cd x_next = ng > 1 ? ck[(int64_t)(ng - 2) * kWave] : czero();
         for (int g = ng - 1; g >= 0; --g) {
             const int j0 = g * kSpecGroup;
             const cd* fg = f + 3 * (int64_t)j0;
             const cd* bg = rb + j0 * rs;
-            cd x = g > 0 ? ck[(int64_t)(g - 1) * kWave] : czero();
+            cd x = x_next;
+            x_next = g > 1 ? ck[(int64_t)(g - 2) * kWave] : czero();
             cd dd[kSpecGroup];
             if (g < nfull) {
 #pragma unroll
