@@ -133,6 +133,29 @@ def test_forward_single_2048_full_pulse(lib, torch_dev):
     assert rel(out["norm"][0], ref["norm"]) < TOL_ACC
 
 
+def test_phase_increment_branches_match_oracle(lib, torch_dev):
+    """The per-point phase increment dt E dx takes a short series for
+    |dt E dx| <= 1e-3, a longer one up to 0.05 and the reduced-range sincos
+    beyond: fields ramping through all three ranges (dt = 0.05, dx = 0.2:
+    E up to 0.05, 1.0 and 8.0) against the oracle, which evaluates
+    exp(-i dt E x_j) point by point."""
+    torch, dev = torch_dev
+    ns = [1024, 2048, 1500]
+    dx, dt, nt = 0.2, 0.05, 300
+    ramp = np.linspace(0.0, 1.0, nt + 1)
+    efield = np.stack([0.05 * ramp, 1.0 * ramp, 8.0 * ramp])
+    print(f"phase increment branches ns={ns} nt={nt} |dt E dx| up to "
+          f"{[float(dt * e * dx) for e in (0.05, 1.0, 8.0)]}", flush=True)
+    _, out = _run_forward(lib, torch, dev, ns, efield, dx, dt, A_AR)
+    assert np.all(out["status"] == 0)
+    for b, n in enumerate(ns):
+        ref = oracle_side.propagate(efield[b], n, dx, dt, A_AR, mask_frac=0.1)
+        r = rel(out["accel"][b], ref["accel"])
+        print(f"  system {b}: accel rel-L2 {r:.3e}", flush=True)
+        assert r < TOL_ACC
+        assert rel(out["norm"][b], ref["norm"]) < TOL_ACC
+
+
 def test_plan_ground_state_matches_oracle(lib, torch_dev):
     torch, dev = torch_dev
     p = lib.make_params(0.2, 0.05, A_AR, 10)
