@@ -164,8 +164,10 @@ __device__ __forceinline__ double fma_s(double a, double b, double k)
 
 // sin and cos of x by Cody-Waite reduction to |r| <= pi/4 (x = k pi/2 + r,
 // pi/2 split into a 32-bit head and two tails so k*head is exact for
-// |k| < 2^20) and the Taylor series of sin r and cos r through r^17 and r^16
-// (truncation below 4e-18 on |r| <= pi/4), evaluated by Horner in r^2.
+// |k| < 2^20), then sin r = r + r^3 S(r^2) and cos r = 1 - r^2/2 + r^4 C(r^2)
+// with S and C of degree 5: Chebyshev fits on r^2 in [0, (pi/4)^2] (the
+// script csrc/sincos_coefficients.py derives them and checks the error:
+// below 8e-17 for sin and 1.3e-16 for cos in double, i.e. rounding).
 __device__ __forceinline__ void sincos_rr(double x, double* s, double* c)
 {
     const double two_over_pi = TDSE_K(0.63661977236758134308);
@@ -177,25 +179,20 @@ __device__ __forceinline__ void sincos_rr(double x, double* s, double* c)
     r = fma(-k, p2, r);
     r = fma(-k, p3, r);
     const double r2 = r * r;
-    // sin r = r (1 - r^2/3! + r^4/5! - ... + r^16/17!)
-    double ps = TDSE_K(2.8114572543455207632e-15);                       // 1/17!
-    ps = fma_s(ps, r2, TDSE_K(-7.6471637318198164759e-13));                 // -1/15!
-    ps = fma_s(ps, r2, TDSE_K(1.6059043836821614599e-10));                  // 1/13!
-    ps = fma_s(ps, r2, TDSE_K(-2.5052108385441718775e-08));                 // -1/11!
-    ps = fma_s(ps, r2, TDSE_K(2.7557319223985890653e-06));                  // 1/9!
-    ps = fma_s(ps, r2, TDSE_K(-1.9841269841269841270e-04));                 // -1/7!
-    ps = fma_s(ps, r2, TDSE_K(8.3333333333333333333e-03));                  // 1/5!
-    ps = fma_s(ps, r2, TDSE_K(-1.6666666666666666667e-01));                 // -1/3!
+    double ps = TDSE_K(1.5918129294866608e-10);
+    ps = fma_s(ps, r2, TDSE_K(-2.5051131845003624e-08));
+    ps = fma_s(ps, r2, TDSE_K(2.755731610255244e-06));
+    ps = fma_s(ps, r2, TDSE_K(-0.00019841269836758574));
+    ps = fma_s(ps, r2, TDSE_K(0.008333333333330948));
+    ps = fma_s(ps, r2, TDSE_K(-0.16666666666666666));
     const double sr = fma(ps * r2, r, r);
-    // cos r = 1 - r^2/2! + r^4/4! - ... + r^16/16!
-    double pc = TDSE_K(4.7794773323873852974e-14);                       // 1/16!
-    pc = fma_s(pc, r2, TDSE_K(-1.1470745597729724714e-11));                 // -1/14!
-    pc = fma_s(pc, r2, TDSE_K(2.0876756987868098979e-09));                  // 1/12!
-    pc = fma_s(pc, r2, TDSE_K(-2.7557319223985890653e-07));                 // -1/10!
-    pc = fma_s(pc, r2, TDSE_K(2.4801587301587301587e-05));                  // 1/8!
-    pc = fma_s(pc, r2, TDSE_K(-1.3888888888888888889e-03));                 // -1/6!
-    pc = fma_s(pc, r2, TDSE_K(4.1666666666666666667e-02));                  // 1/4!
-    pc = fma(pc, r2, -0.5);                                       // -1/2!
+    double pc = TDSE_K(-1.1382632425521717e-11);
+    pc = fma_s(pc, r2, TDSE_K(2.08761462684032e-09));
+    pc = fma_s(pc, r2, TDSE_K(-2.7557317271729793e-07));
+    pc = fma_s(pc, r2, TDSE_K(2.480158729876569e-05));
+    pc = fma_s(pc, r2, TDSE_K(-0.0013888888888887398));
+    pc = fma_s(pc, r2, TDSE_K(0.041666666666666664));
+    pc = fma(pc, r2, -0.5);
     const double cr = fma(pc, r2, 1.0);
     const int q = ((int)k) & 3;
     const double ss = (q & 1) ? cr : sr;
