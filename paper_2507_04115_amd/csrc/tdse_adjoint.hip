@@ -524,8 +524,8 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) adjoint_kernel(FwdArgs a)
             if (i % K == 0) store_state<C>(ckpt + np2 * (i / K), T, loff, v, gl, gr);
             observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, ring + (i % kRing) * W * 3);
             if (i == nt) break;
-            forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
-                            sm.lds_f, sm.lds_b);
+            forward_step<C>(v, gl, gr, f, erow[i], RatioNow{erow[i], a.dt, sv.sc.dx}, a.dt, sv.xl,
+                            sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
             if ((i + 1) % kFlush == 0) {
                 __syncthreads();
                 if (flushed == 0) n0 = ring_norm0(ring, W, dx);
@@ -580,8 +580,8 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) adjoint_kernel(FwdArgs a)
             store_chunk<C>(buf(sl), T, loff, v);
             for (int i = s0l; i < s1l; ++i) {
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
-                forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
-                                sm.lds_f, sm.lds_b);
+                forward_step<C>(v, gl, gr, f, erow[i], RatioNow{erow[i], a.dt, sv.sc.dx}, a.dt,
+                                sv.xl, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
                 store_chunk<C>(buf(sl) + nps * (i - s0l + 1), T, loff, v);
             }
             {
@@ -607,7 +607,8 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) adjoint_kernel(FwdArgs a)
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 cd pv[C], pgl, pgr;
                 load_chunk<C>(bc + nps * (i - s0), T, t, loff, pv, pgl, pgr);
-                phase_mask<C, !kAdjQRegs>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc, sv.lc);
+                phase_mask<C, !kAdjQRegs>(kap, kgl, kgr, e, a.dt, sv.xl, phase_ratio(e, a.dt, dx),
+                                          f.mflags, sv.sc, sv.lc);
                 cn_apply<C, true>(kap, kgl, kgr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
                 add_source<C>(kap, kgl, kgr, pv, pgl, pgr, 2.0 * abar[i] * dx, e, sv.tb, T, sv.lc);
                 if (i > 0) grad_partial<C>(kap, pv, sv.xs, dx, sv.lc, ring + ((i - 1) % kRing) * W);
@@ -638,11 +639,12 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) adjoint_kernel(FwdArgs a)
                     const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                     cd pv[C], pgl, pgr;
                     load_chunk<C>(bc + nps * (i - s0), T, t, loff, pv, pgl, pgr);
-                    phase_mask<C, !kAdjQRegs>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc,
-                                              sv.lc);
+                    phase_mask<C, !kAdjQRegs>(kap, kgl, kgr, e, a.dt, sv.xl,
+                                              phase_ratio(e, a.dt, dx), f.mflags, sv.sc, sv.lc);
                     cn_apply2<C>(kap, kgl, kgr, v, gl, gr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f,
                                  sm.lds_b, lf2, lb2);
-                    phase_mask<C, !kAdjQRegs>(v, gl, gr, erow[ir], a.dt, sv.xl, dx, f.mflags, sv.sc,
+                    phase_mask<C, !kAdjQRegs>(v, gl, gr, erow[ir], a.dt, sv.xl,
+                                              phase_ratio(erow[ir], a.dt, dx), f.mflags, sv.sc,
                                               sv.lc);
                     store_chunk<C>(br + nps * (it + 1), T, loff, v);
                     add_source<C>(kap, kgl, kgr, pv, pgl, pgr, 2.0 * abar[i] * dx, e, sv.tb, T,
@@ -659,8 +661,9 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) adjoint_kernel(FwdArgs a)
                 // the recomputation alone (after a last segment shorter than K)
                 for (int it = both; it < nrec; ++it) {
                     const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
-                    forward_step<C>(v, gl, gr, f, erow[r0 + it], a.dt, sv.xl, sv.tb, sv.sc, sv.lc,
-                                    sv.rc, sm.lds_f, sm.lds_b);
+                    forward_step<C>(v, gl, gr, f, erow[r0 + it],
+                                    RatioNow{erow[r0 + it], a.dt, sv.sc.dx}, a.dt, sv.xl, sv.tb,
+                                    sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
                     store_chunk<C>(br + nps * (it + 1), T, loff, v);
                 }
             }
@@ -682,8 +685,8 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) adjoint_kernel(FwdArgs a)
             store_chunk<C>(seg, T, loff, v);
             for (int i = s0; i < s1; ++i) {
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
-                forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
-                                sm.lds_f, sm.lds_b);
+                forward_step<C>(v, gl, gr, f, erow[i], RatioNow{erow[i], a.dt, sv.sc.dx}, a.dt,
+                                sv.xl, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
                 store_chunk<C>(seg + nps * (i - s0 + 1), T, loff, v);
             }
             if constexpr (kStream) load_state<C>(kbuf, T, loff, kap, kgl, kgr);
@@ -721,7 +724,8 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) adjoint_kernel(FwdArgs a)
                 const StepView<LDSTAB> sv = step_view<LDSTAB>(clsp, wsys, smem_raw);
                 // psi^i is loaded first: its latency overlaps the costate step
                 if constexpr (!kStream) load_chunk<C>(seg + nps * (i - s0), T, t, loff, v, gl, gr);
-                phase_mask<C, !kAdjQRegs>(kap, kgl, kgr, e, a.dt, sv.xl, dx, f.mflags, sv.sc, sv.lc);
+                phase_mask<C, !kAdjQRegs>(kap, kgl, kgr, e, a.dt, sv.xl, phase_ratio(e, a.dt, dx),
+                                          f.mflags, sv.sc, sv.lc);
                 cn_apply<C, true>(kap, kgl, kgr, f, sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
                 // + 2 abar_i dx (V' + E_i) conj(psi^i), and the partial of
                 // grad_{i-1} from kappa^i and psi^i

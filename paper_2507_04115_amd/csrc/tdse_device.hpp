@@ -233,6 +233,15 @@ __device__ __forceinline__ void sincos_step(double x, double* s, double* c)
     *c = fma(pc, x2, 1.0);
 }
 
+// exp(-i dt e dx): the ratio of the field phase factors of neighbouring grid
+// points in a step at field e.
+__device__ __forceinline__ cd phase_ratio(double e, double dt, double dx)
+{
+    double s, c;
+    sincos_step(-dt * e * dx, &s, &c);
+    return mkc(c, s);
+}
+
 // ------------------------------------------------------------ wavefront ops
 // DPP moves of the two halves of a double; lanes without a source (or in a
 // masked row) read 0.  Controls: row_shr:n = 0x110+n, wave_shl:1 = 0x130,
@@ -732,20 +741,19 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
 
 // Field substep exp(-i dt E x_j) and absorber m_j on the chunk and its two
 // ghost points (x_{s-1} = xl).  The phase advances along the chunk by
-// multiplication with exp(-i dt E dx); each lane starts from its own sincos.
+// multiplication with w1 = exp(-i dt E dx) (phase_ratio); each lane starts
+// from its own sincos.
 // BRANCHLESS: the absorber factor is applied to every point (1 away from
 // the edges); used where a branch would make the two paths' results meet in
 // different registers and cost spills of the chunk.
 template <int C, bool BRANCHLESS>
 __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e, double dt,
-                                           double xl, double dx, int mflags,
+                                           double xl, const cd w1, int mflags,
                                            const SizeClass& sc, const LaneCtx& lc)
 {
-    double s0, c0, s1, c1;
+    double s0, c0;
     sincos_rr(-dt * e * xl, &s0, &c0);
-    sincos_step(-dt * e * dx, &s1, &c1);
     cd ph = mkc(c0, s0);
-    const cd w1 = mkc(c1, s1);
     gl = cmul(ph, gl);
     if (mflags & 2) gl = cscale(ldg(sc.pt.m + lc.il()), gl);
     ph = cmul(ph, w1);
@@ -789,16 +797,29 @@ __device__ __forceinline__ void phase_mask(cd (&v)[C], cd& gl, cd& gr, double e,
     if (mflags & 4) gr = cscale(ldg(sc.pt.m + lc.ir()), gr);
 }
 
+// Where forward_step takes the step's phase ratio from, after the solve (so
+// after its barriers): computed in place, or read from the subgroup's LDS
+// block that fill_ratios wrote ahead.
+struct RatioNow {
+    double e, dt, dx;
+    __device__ __forceinline__ cd operator()() const { return phase_ratio(e, dt, dx); }
+};
+struct RatioLds {
+    const cd* p;
+    __device__ __forceinline__ cd operator()() const { return *p; }
+};
+
 // One full step psi^(i) -> psi^(i+1) (CN right-hand side, partitioned solve,
 // ghost rebuild, field phase and absorber).
-template <int C, class TV, class LF>
+template <int C, class TV, class LF, class RF>
 __device__ __forceinline__ void forward_step(cd (&v)[C], cd& gl, cd& gr, const LF& f,
-                                             double e, double dt, double xl, const TV& tb,
-                                             const SizeClass& sc, const LaneCtx& lc,
-                                             const RhsCoef rc, cd* lds_f, cd* lds_b)
+                                             double e, const RF ratio, double dt, double xl,
+                                             const TV& tb, const SizeClass& sc,
+                                             const LaneCtx& lc, const RhsCoef rc, cd* lds_f,
+                                             cd* lds_b)
 {
     cn_apply<C, true, TV>(v, gl, gr, f, tb, sc, lc, rc, lds_f, lds_b);
-    phase_mask<C, !LF::kRegs>(v, gl, gr, e, dt, xl, sc.dx, f.mflags, sc, lc);
+    phase_mask<C, !LF::kRegs>(v, gl, gr, e, dt, xl, ratio(), f.mflags, sc, lc);
 }
 
 // Copies the om and dV/dx tables of a size class into LDS: 16 bytes per
@@ -894,12 +915,14 @@ __device__ __forceinline__ StepView<TAB> step_view(const SizeClass* cls, int wsy
 
 // ------------------------------------------------------------ time-loop helpers
 // Per-subgroup LDS block: forward and backward carry slots, two reduction
-// slot arrays, the observables ring, a few flags.
+// slot arrays, the phase ratios of the next kFlush steps, the observables
+// ring, a few flags.
 struct SubSmem {
     cd* lds_f;
     cd* lds_b;
     double* red0;
     double* red1;
+    cd* ratio;
     double* ring;
     int* misc;
 };
@@ -911,7 +934,8 @@ __device__ __forceinline__ SubSmem carve_sub(char* base, int W)
     s.lds_b = s.lds_f + kMaxWaves;
     s.red0 = reinterpret_cast<double*>(s.lds_b + kMaxWaves);
     s.red1 = s.red0 + kMaxWaves;
-    s.ring = s.red1 + kMaxWaves;
+    s.ratio = reinterpret_cast<cd*>(s.red1 + kMaxWaves);
+    s.ring = reinterpret_cast<double*>(s.ratio + kFlush);
     s.misc = reinterpret_cast<int*>(s.ring + kRing * W * 3);
     return s;
 }

@@ -30,12 +30,23 @@ constexpr int kHwRegXccId = 20;
 
 size_t sub_smem_bytes(int W)
 {
-    size_t b = sizeof(cd) * 2 * kMaxWaves + sizeof(double) * 2 * kMaxWaves +
+    size_t b = sizeof(cd) * 2 * kMaxWaves + sizeof(double) * 2 * kMaxWaves + sizeof(cd) * kFlush +
                sizeof(double) * kRing * W * 3 + 4 * sizeof(int);
     return (b + 15) & ~size_t(15);
 }
 
 // -------------------------------------------------------------- forward
+// Phase ratios of steps [i0, i0 + F) below nt into the subgroup's LDS block,
+// one step per lane of its first wavefront: the per-step sincos of
+// phase_ratio runs once per F steps instead of once per step.  Written after
+// a barrier that follows every read of the previous block; the step's solve
+// takes two more barriers before its phase reads them.
+__device__ __forceinline__ void fill_ratios(cd* ratio, const double* erow, int i0, int nt, int F,
+                                            double dt, double dx, int wsys, int lane)
+{
+    if (wsys == 0 && lane < F && i0 + lane < nt) ratio[lane] = phase_ratio(erow[i0 + lane], dt, dx);
+}
+
 // Persistent: each workgroup takes bins from the run of its XCD, then from
 // the other runs (a.queue).  A bin is a set of
 // systems of one lane layout that together fill the workgroup's lanes (plus a
@@ -163,6 +174,7 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) forward_kernel(FwdArgs a)
             else
                 observe<C>(v, sv.tb, T, sv.lc, sv.xs, dx, sm.ring);
         }
+        fill_ratios(sm.ratio, erow, 0, nt, FLUSH, a.dt, dx, wsys, tid & (kWave - 1));
         __syncthreads();
         double n0 = 0.0;
         for (int w = 0; w < W; ++w) n0 += sm.ring[w * NV + 2];
@@ -176,13 +188,14 @@ __global__ void __launch_bounds__(NARROW ? 512 : 1024) forward_kernel(FwdArgs a)
                     store_state<C>(a.store + uniform_load(a.store_off + p) + np2 * (size_t)(i / K),
                                    sv.sc.T, 16u * (unsigned)sv.lc.t, v, gl, gr);
             }
-            forward_step<C>(v, gl, gr, f, erow[i], a.dt, sv.xl, sv.tb, sv.sc, sv.lc, sv.rc,
-                            sm.lds_f, sm.lds_b);
+            forward_step<C>(v, gl, gr, f, erow[i], RatioLds{sm.ratio + i % FLUSH}, a.dt, sv.xl,
+                            sv.tb, sv.sc, sv.lc, sv.rc, sm.lds_f, sm.lds_b);
             if ((i + 1) % FLUSH == 0) {
                 __syncthreads();
                 if (active)
                     flush<POP>(i + 1 - FLUSH, i, t, T, sm.ring, W, dx, erow, acc_row, x_row, n_row,
                                n0, sm.misc + 1, gs_row, vol_row, STORE ? st_norm : nullptr);
+                fill_ratios(sm.ratio, erow, i + 1, nt, FLUSH, a.dt, dx, wsys, tid & (kWave - 1));
                 flushed = i + 1;
             }
             double* slot = sm.ring + ((i + 1) % RING) * W * NV;
