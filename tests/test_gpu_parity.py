@@ -245,13 +245,15 @@ def test_invalid_arguments_are_refused_before_any_launch(lib, torch_dev):
     plan.close()
 
 
-@pytest.mark.parametrize("nt", [0, 1, 5])
+@pytest.mark.parametrize("nt", [0, 1, 5, 32, 33])
 def test_degenerate_lengths_and_layout_boundaries(lib, torch_dev, nt):
-    """Propagations of 0, 1 and 5 steps (checkpoint interval longer than the
-    run, and one checkpoint per step) on the smallest grid and on both sides
-    of every layout boundary (4 | 8 points per lane at 512, 8 | 16 at 8192):
-    outputs, final states and gradients, recomputed and from stored
-    checkpoints, against the oracle."""
+    """Propagations of 0, 1, 5, 32 and 33 steps (checkpoint interval longer
+    than the run, and one checkpoint per step; 32 and 33 end exactly on and
+    one step past a block of the forward kernel's 32-step output flush and
+    phase-ratio fill) on the smallest grid and on both sides of every layout
+    boundary (4 | 8 points per lane at 512, 8 | 16 at 8192): outputs, final
+    states and gradients, recomputed and from stored checkpoints, against the
+    oracle."""
     torch, dev = torch_dev
     ns = [16, 17, 511, 512, 513, 8192, 8193]
     dx, dt, a = 0.4, 0.05, 1.1
