@@ -580,6 +580,12 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
     const unsigned off = 16u * (unsigned)lc.t;
     const double oml = tb.om(lc.il());
     const double omr = tb.om(lc.ir());
+    // points ahead of its use at which a factor read from memory (L2) is
+    // issued: one in sweeps A and B, whose per-point work covers it and where
+    // a second point's factors would be spilled; three in sweeps C and D,
+    // which do one complex FMA per point (N = 9216-16384: +2-3 %)
+    constexpr int kAhead = 1;
+    constexpr int kAheadBwd = 3;
     // window products of the forward scan, loaded three quarters of the way
     // through sweep A (at its last point where q is read from memory)
     cd a0 = czero(), a1 = czero(), aw = czero();
@@ -591,9 +597,13 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         double om_n = C > 1 ? tb.om(b0 + 64) : omr;
         cd g_p = gfac<RT>(oml, gl);
         cd g_c = gfac<RT>(om_c, v[0]);
-        // elimination factors read from their table: the next point's is
-        // issued one point ahead (its L2 latency overlaps this point)
-        cd al_c = czero();
+        // elimination factors read from their table (L2): issued kAhead
+        // points ahead of their use
+        cd al[C];
+        if constexpr (LF::kTabAB) {
+#pragma unroll
+            for (int j = 1; j < kAhead && j < C; ++j) al[j] = f.template alpha<RT>(j, 0.0, sc, lc);
+        }
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             if (k == (LF::kRegs ? 3 * C / 4 : C - 1)) {
@@ -603,9 +613,8 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
             }
             // om of the point after next, issued one point ahead of its use
             const double om_nn = (k + 2 < C) ? tb.om(b0 + 64 * (k + 2)) : omr;
-            cd al_n = czero();
             if constexpr (LF::kTabAB) {
-                if (k + 1 < C) al_n = f.template alpha<RT>(k + 1, 0.0, sc, lc);
+                if (k + kAhead < C) al[k + kAhead] = f.template alpha<RT>(k + kAhead, 0.0, sc, lc);
             }
             TDSE_POINT_FENCE();
             const cd g_n = gfac<RT>(om_n, (k + 1 < C) ? v[k + 1] : gr);
@@ -617,14 +626,13 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
                              : gfac<RT>(om_c + rc.dofs10, v[k]);
             const cd r = mkc(fma(10.0, gh.re, g_p.re + g_n.re), fma(10.0, gh.im, g_p.im + g_n.im));
             v[k] = r;
-            if constexpr (LF::kTabAB) ze = (k == 0) ? r : cmad(al_c, ze, r);
+            if constexpr (LF::kTabAB) ze = (k == 0) ? r : cmad(al[k], ze, r);
             else ze = (k == 0) ? r : cmad(f.template alpha<RT>(k, om_p, sc, lc), ze, r);
             g_p = g_c;
             g_c = g_n;
             om_p = om_c;
             om_c = om_n;
             om_n = om_nn;
-            al_c = al_n;
             point_fence(r, ze);
         }
     }
@@ -648,32 +656,30 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         if constexpr (!LF::kRegs) lcb.b0 = opaque(lc.b0);
         cd z = cf;
         double om_p = oml;
-        // factors read from memory (alpha from its table, q): the next
-        // point's issued one point ahead
-        cd al_c = czero(), q_c = czero();
-        if constexpr (LF::kTabAB) al_c = f.template alpha<RT>(0, 0.0, sc, lcb);
-        if constexpr (!LF::kRegs) q_c = f.q(0, sc, lcb);
+        // factors read from memory (alpha from its table, q): issued kAhead
+        // points ahead of their use
+        cd al[C], qm[C];
+#pragma unroll
+        for (int j = 0; j < kAhead && j < C; ++j) {
+            if constexpr (LF::kTabAB) al[j] = f.template alpha<RT>(j, 0.0, sc, lcb);
+            if constexpr (!LF::kRegs) qm[j] = f.q(j, sc, lcb);
+        }
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             // om_k for the next point (at the last point, om_{C-1} for sweep
             // C), issued ahead of this point's work so that its LDS latency
             // overlaps it
             const double om_k = tb.om(lcb.b0 + 64 * k);
-            cd al_n = czero(), q_n = czero();
-            if constexpr (LF::kTabAB) {
-                if (k + 1 < C) al_n = f.template alpha<RT>(k + 1, 0.0, sc, lcb);
-            }
-            if constexpr (!LF::kRegs) {
-                if (k + 1 < C) q_n = f.q(k + 1, sc, lcb);
+            if (k + kAhead < C) {
+                if constexpr (LF::kTabAB) al[k + kAhead] = f.template alpha<RT>(k + kAhead, 0.0, sc, lcb);
+                if constexpr (!LF::kRegs) qm[k + kAhead] = f.q(k + kAhead, sc, lcb);
             }
             TDSE_POINT_FENCE();
-            if constexpr (LF::kTabAB) z = cmad(al_c, z, v[k]);
+            if constexpr (LF::kTabAB) z = cmad(al[k], z, v[k]);
             else z = cmad(f.template alpha<RT>(k, om_p, sc, lcb), z, v[k]);
             if constexpr (LF::kRegs) v[k] = cmul(f.q(k, sc, lcb), z);
-            else v[k] = cmul(q_c, z);
+            else v[k] = cmul(qm[k], z);
             om_p = om_k;
-            al_c = al_n;
-            q_c = q_n;
             point_fence(v[k]);
         }
         om_last = om_p;
@@ -685,22 +691,24 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         if constexpr (!LF::kRegs) lcc.b0 = opaque(lc.b0);
         const int bc = lcc.b0;
         double om_n = LF::kOm ? om_last : 0.0;
-        cd be_c = czero();
-        if constexpr (LF::kTabAB) be_c = f.template beta<RT>(C - 2, 0.0, sc, lcc);
+        // the table's beta issued kAheadBwd points ahead of its use
+        cd be[C];
+        if constexpr (LF::kTabAB) {
+#pragma unroll
+            for (int j = C - 2; j > C - 2 - kAheadBwd && j >= 0; --j)
+                be[j] = f.template beta<RT>(j, 0.0, sc, lcc);
+        }
 #pragma unroll
         for (int k = C - 2; k >= 0; --k) {
-            // om_k (or the table's beta_{k-1}) for the next point, issued one
-            // point ahead
+            // om_k for the next point, issued one point ahead
             const double om_k = (LF::kOm && k > 0) ? tb.om(bc + 64 * k) : 0.0;
-            cd be_n = czero();
             if constexpr (LF::kTabAB) {
-                if (k > 0) be_n = f.template beta<RT>(k - 1, 0.0, sc, lcc);
+                if (k - kAheadBwd >= 0) be[k - kAheadBwd] = f.template beta<RT>(k - kAheadBwd, 0.0, sc, lcc);
             }
             TDSE_POINT_FENCE();
-            if constexpr (LF::kTabAB) yb = cmad(be_c, yb, v[k]);
+            if constexpr (LF::kTabAB) yb = cmad(be[k], yb, v[k]);
             else yb = cmad(f.template beta<RT>(k, om_n, sc, lcc), yb, v[k]);
             om_n = om_k;
-            be_c = be_n;
             point_fence(yb);
         }
     }
@@ -713,23 +721,25 @@ __device__ __forceinline__ void cn_apply(cd (&v)[C], cd& gl, cd& gr, const LF& f
         if constexpr (!LF::kRegs) lcd.b0 = opaque(lc.b0);
         cd y = cb;
         double om_n = omr;
-        cd be_c = czero();
-        if constexpr (LF::kTabAB) be_c = f.template beta<RT>(C - 1, 0.0, sc, lcd);
+        cd be[C];
+        if constexpr (LF::kTabAB) {
+#pragma unroll
+            for (int j = C - 1; j > C - 1 - kAheadBwd && j >= 0; --j)
+                be[j] = f.template beta<RT>(j, 0.0, sc, lcd);
+        }
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
-            // om_k for the next point (om_0 for the ghost) and the table's
-            // beta_{k-1}, issued ahead
+            // om_k for the next point (om_0 for the ghost), issued ahead; the
+            // table's beta kAheadBwd points ahead
             const double om_k = tb.om(lcd.b0 + 64 * k);
-            cd be_n = czero();
             if constexpr (LF::kTabAB) {
-                if (k > 0) be_n = f.template beta<RT>(k - 1, 0.0, sc, lcd);
+                if (k - kAheadBwd >= 0) be[k - kAheadBwd] = f.template beta<RT>(k - kAheadBwd, 0.0, sc, lcd);
             }
             TDSE_POINT_FENCE();
-            if constexpr (LF::kTabAB) y = cmad(be_c, y, v[k]);
+            if constexpr (LF::kTabAB) y = cmad(be[k], y, v[k]);
             else y = cmad(f.template beta<RT>(k, om_n, sc, lcd), y, v[k]);
             v[k] = y;
             om_n = om_k;
-            be_c = be_n;
             point_fence(y);
         }
         om_0 = om_n;
