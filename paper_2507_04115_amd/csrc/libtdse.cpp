@@ -853,7 +853,8 @@ tdse_status probe_forward(const tdse_params* p, int n, const Layout& L, int S, i
     if (occ < 1 || smem > (size_t)kMaxLds || count < S) return TDSE_OK;
     const int nb = std::max(1, std::min(count / S, occ * num_cus()));
     const int P = nb * S;
-    const int nt = kProbeSteps;
+    const int ps = env_int("TDSE_PROBE_STEPS", 0);  // experiment override
+    const int nt = ps > 0 ? ps : kProbeSteps;
     ClassSet cs;
     tdse_status rc = build_classes(cs, {n}, {L}, {real_time_params(p)}, st);
     if (rc != TDSE_OK) {
@@ -1105,6 +1106,7 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, bool 
     }
     TuneChoice best;
     double best_cost = 0.0;  // seconds per grid-point-step (forward [+ adjoint])
+    int best_waves = 0;      // wavefronts the best candidate keeps resident per CU
     for (int C : {4, 8, 12, 16}) {
         const Layout L = layout_for(n, C);
         if (L.T > 1024 || !layout_supported(C)) continue;
@@ -1153,8 +1155,22 @@ tdse_status autotune(const tdse_params* p, int n, int count, bool adjoint, bool 
                 // on the focus workload, while its 128-step probes came out
                 // up to 1.5 % either way
                 const bool narrower = best_cost > 0.0 && C == best.C && tab == best.tab && S < best.S;
-                if (best_cost == 0.0 || cost < best_cost * (narrower ? 0.97 : 1.0)) {
+                // candidates within 2 % of each other are a tie, which goes
+                // to the one keeping more wavefronts resident per CU: at
+                // N = 12288 the 12-point layout (16 wavefronts) and the
+                // 16-point one (12) probe within 1-2 % of each other either
+                // way round, while over whole runs the first is 4 % faster
+                const int waves = fwd_occupancy(C, L.T, S, tab) * S * L.T / kWave;
+                bool take;
+                if (best_cost == 0.0)
+                    take = true;
+                else if (waves != best_waves && std::fabs(cost - best_cost) < 0.02 * best_cost)
+                    take = waves > best_waves;
+                else
+                    take = cost < best_cost * (narrower ? 0.97 : 1.0);
+                if (take) {
                     best_cost = cost;
+                    best_waves = waves;
                     best = TuneChoice{C, L.T, S, tab, r};
                 }
             }
