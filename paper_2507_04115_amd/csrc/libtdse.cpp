@@ -463,8 +463,12 @@ struct tdse_plan_s {
         size_t smem = 0;  // LDS bytes per workgroup
         int nbins = 0, grid = 0;
         BinDesc* d_bins = nullptr;
+        double est = 0.0;   // estimated time of the group run alone (any unit)
+        bool fills = true;  // its grid takes every workgroup slot of the GPU
+        int branch = 0;     // graph branch stream the group is launched on
     };
     std::vector<FwdGroup> fgroups;
+    std::vector<int> fgroup_launch_order;  // longest estimated group first
     std::vector<int> fgroup_of_cls;
     BinDesc* d_bins = nullptr;             // every group's bins, then one bin per system (plain)
     std::vector<int> plain_threads;        // per system
@@ -1439,7 +1443,14 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
             return bail(fail(TDSE_E_UNSUPPORTED, "forward workgroup of %d lanes with %zu B of LDS does not fit",
                              fg.threads, fg.smem));
         fg.grid = std::min(fg.nbins, occ * num_cus());
+        fg.fills = fg.nbins >= occ * num_cus();
         pl->fgroups.push_back(fg);
+    }
+    // each group's time alone: its grid points over the rate its classes
+    // reached when tuned (grid-point-steps per second), else its grid points
+    for (int c = 0; c < ncls; ++c) {
+        const double rate = (tune && tuned[c].rate > 0.0) ? tuned[c].rate : 1.0;
+        pl->fgroups[pl->fgroup_of_cls[c]].est += (double)ccount[c] * (double)ns[c] / rate;
     }
     pl->plain_threads.assign(batch, 0);
     pl->plain_smem.assign(batch, 0);
@@ -1587,8 +1598,26 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
             hipSuccess)
         return bail(fail(TDSE_E_DEVICE, "plan upload failed"));
 
-    // graph branches (forward groups run concurrently)
+    // graph branches (forward groups run concurrently).  A persistent launch
+    // whose grid takes every workgroup slot keeps its CUs until its queue is
+    // empty, so launches that come after it start on the CUs its workgroups
+    // leave.  Launch order: first the groups whose grids leave slots free
+    // (they run beside the others from the start), then the rest by
+    // decreasing time per bin, so that the last launch, whose end no other
+    // work can fill, has the shortest bins.  Branches in launch order.
     const int nbr = std::min<int>(4, ng);
+    {
+        std::vector<int> order(ng);
+        for (int g = 0; g < ng; ++g) order[g] = g;
+        auto per_bin = [&](int g) { return pl->fgroups[g].est / std::max(1, pl->fgroups[g].nbins); };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            const bool fx = pl->fgroups[x].fills, fy = pl->fgroups[y].fills;
+            if (fx != fy) return !fx;
+            return per_bin(x) > per_bin(y);
+        });
+        for (int i = 0; i < ng; ++i) pl->fgroups[order[i]].branch = i % std::max(nbr, 1);
+        pl->fgroup_launch_order = order;
+    }
     for (int i = 0; i < nbr; ++i) {
         hipStream_t s;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
@@ -1752,8 +1781,8 @@ static tdse_status enqueue_forward(tdse_plan pl, const FwdArgs& base, hipStream_
     const int nb = (int)pl->branch.size();
     HIP_TRY(hipEventRecord(pl->ev[0], st));
     for (int b = 0; b < nb; ++b) HIP_TRY(hipStreamWaitEvent(pl->branch[b], pl->ev[0], 0));
-    for (int g = 0; g < ng; ++g) {
-        tdse_status rc = one(g, pl->branch[g % nb]);
+    for (int g : pl->fgroup_launch_order) {
+        tdse_status rc = one(g, pl->branch[pl->fgroups[g].branch % nb]);
         if (rc != TDSE_OK) return rc;
     }
     for (int b = 0; b < nb; ++b) {
