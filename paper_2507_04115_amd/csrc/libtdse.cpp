@@ -468,7 +468,7 @@ struct tdse_plan_s {
         int branch = 0;     // graph branch stream the group is launched on
     };
     std::vector<FwdGroup> fgroups;
-    std::vector<int> fgroup_launch_order;  // longest estimated group first
+    std::vector<int> fgroup_launch_order;  // small grids, then by decreasing time per bin
     std::vector<int> fgroup_of_cls;
     BinDesc* d_bins = nullptr;             // every group's bins, then one bin per system (plain)
     std::vector<int> plain_threads;        // per system
@@ -1599,12 +1599,13 @@ tdse_status tdse_plan_create(const tdse_params* p, int32_t batch, const int32_t*
         return bail(fail(TDSE_E_DEVICE, "plan upload failed"));
 
     // graph branches (forward groups run concurrently).  A persistent launch
-    // whose grid takes every workgroup slot keeps its CUs until its queue is
-    // empty, so launches that come after it start on the CUs its workgroups
-    // leave.  Launch order: first the groups whose grids leave slots free
-    // (they run beside the others from the start), then the rest by
-    // decreasing time per bin, so that the last launch, whose end no other
-    // work can fill, has the shortest bins.  Branches in launch order.
+    // whose grid takes every workgroup slot can hold its CUs until its queue
+    // is empty: a small grid launched after it waited for them (the uneven
+    // batch's 37-workgroup group, 11 % on the whole solve).  Launch order:
+    // first the groups whose grids leave slots free, then the rest by
+    // decreasing time per bin, so that the longest bins start first and the
+    // last launch to end, which no other work can overlap, has the shortest.
+    // Branches in launch order.
     const int nbr = std::min<int>(4, ng);
     {
         std::vector<int> order(ng);
